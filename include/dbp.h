@@ -1,0 +1,118 @@
+/* dbp.h -- C ABI of the MI355X decentralized baseband processing library.
+ *
+ * Method: K. Li, R. Sharan, Y. Chen, T. Goldstein, J. R. Cavallaro, C. Studer,
+ * "Decentralized Baseband Processing for Massive MU-MIMO Systems",
+ * arXiv:1702.04458.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex data is interleaved single precision (re, im) -- "complex64".
+ * - H is the UPLINK channel in layout [n_sc][B][U] (row b = antenna b,
+ *   column u = user u), row-major.  Cluster c owns rows c*S .. c*S+S-1 with
+ *   S = B / C (the row partition of Section II-A2).  The downlink channel is
+ *   taken in place as H^d = H^T (channel reciprocity, Section II-B1).
+ * - All array arguments are DEVICE pointers owned by the caller; the library
+ *   never frees, retains or reallocates them, and never writes outside the
+ *   documented output arrays.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *   stream-ordered and asynchronous: they return after enqueueing the work,
+ *   without a host synchronisation.
+ * - Argument errors are detected on the host BEFORE any device work is queued
+ *   and return DBP_ERR_INVALID or DBP_ERR_UNSUPPORTED; nothing is written then.
+ *   A launch failure returns DBP_ERR_DEVICE.  dbp_last_error() gives a
+ *   human-readable reason for the last failure on the calling thread.
+ * - Results are deterministic: for fixed inputs and parameters every output
+ *   bit is independent of the launch shape and of other work on the device.
+ */
+#ifndef DBP_H_
+#define DBP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DBP_OK 0
+#define DBP_ERR_INVALID 1      /* malformed arguments                            */
+#define DBP_ERR_UNSUPPORTED 2  /* valid for the method, not built for the GPU     */
+#define DBP_ERR_NOMEM 3        /* device memory or serving budget exhausted       */
+#define DBP_ERR_DEVICE 4       /* HIP runtime or launch failure                   */
+#define DBP_ERR_BUSY 5         /* serving queue full                              */
+#define DBP_ERR_NOTFOUND 6     /* unknown serving ticket                          */
+
+/* Regularizer g(s) of the equalization problem (E0), Section III-A. */
+#define DBP_REG_MMSE 0   /* g = N0/(2 Es) ||s||^2, proximal step (E2-MMSE)     */
+#define DBP_REG_ZF 1     /* g = 0, proximal step (E2-ZF)                      */
+#define DBP_REG_BOX 2    /* indicator of the QAM bounding box, (E2-BOX)        */
+
+/* Arithmetic of the preprocessing (Gram matrix and its regularised inverse). */
+#define DBP_PREC_FP32 0        /* everything in FP32                                     */
+#define DBP_PREC_MIXED_FP16 1  /* Gram on FP16 MFMA (FP32 accumulate) + FP32 refinement */
+#define DBP_PREC_MIXED_BF16 2  /* Gram on BF16 MFMA (FP32 accumulate) + FP32 refinement */
+
+const char* dbp_version(void);
+const char* dbp_strerror(int status);
+/* Reason for the most recent failed call on this thread ("" if none). */
+const char* dbp_last_error(void);
+
+/* Decentralized ADMM-based data detection: Algorithm 1 (Section III-C) with
+ * the U x U closed form of step (E1) (eq. StepE1variant1), the consensus of
+ * Lemma 1 and the proximal steps (E2-MMSE / E2-ZF / E2-BOX).
+ *
+ *   H      [n_sc][B][U] complex64   uplink channel (shared by all n_sym symbols)
+ *   y      [n_sc][n_sym][B] complex64  receive vectors
+ *   s_hat  [n_sc][n_sym][U] complex64  output: s^(T) of Algorithm 1
+ *   hard   [n_sc][n_sym][U] uint8 or NULL  output: nearest unit-energy square
+ *          QAM point per entry, as index iI + L*iQ (L = sqrt(qam); level i of a
+ *          dimension is (2i - (L-1)) / sqrt(2 (qam-1) / 3); ties go up)
+ *   T      number of estimates s^(1..T) (T - 1 ADMM iterations after the
+ *          initial consensus), T >= 1
+ *   rho    ADMM penalty > 0;  gamma  dual step > 0 (the paper uses 1)
+ *   N0     noise variance >= 0 (MMSE);  Es  symbol energy > 0
+ *   reg    DBP_REG_*;  qam  4, 16 or 64 (slicer and BOX radius)
+ *   prec   DBP_PREC_*
+ * Requires B % C == 0, S = B / C >= U (the U x U branch, S > U in the paper;
+ * at S = U the S x S and U x U branches coincide), U in {8, 16, 32, 64},
+ * C <= 16, n_sc >= 0 (0 is a no-op), n_sym >= 1.
+ */
+int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard,
+                    int n_sc, int n_sym, int B, int U, int C, int T,
+                    float rho, float gamma, float N0, float Es,
+                    int reg, int qam, int prec, void* stream);
+
+/* Decentralized conjugate-gradient data detection: Algorithm 2 (Section
+ * III-D) with the broadcast-w variant (every cluster keeps its own x, r, p).
+ * The CG regulariser is N0/Es for DBP_REG_MMSE and 0 for DBP_REG_ZF; T >= 1
+ * CG iterations.  x_hat [n_sc][n_sym][U] complex64; hard as above.
+ * Requires B % C == 0, U in {8, 16, 32, 64}, C <= 16.
+ */
+int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard,
+                  int n_sc, int n_sym, int B, int U, int C, int T,
+                  float N0, float Es, int reg, int qam, void* stream);
+
+/* Decentralized ADMM-based beamforming: Algorithm 3 (Section IV-C),
+ * epsilon = 0, S x S branch (A_c = H_c^H H_c + rho^-1 I_S with the downlink
+ * cluster channel H_c = (H^u_c)^T read from the uplink-layout H).
+ *
+ *   s      [n_sc][n_sym][U] complex64  precoding targets
+ *   x      [n_sc][n_sym][B] complex64  output [x_1; ...; x_C]
+ *   beta   [n_sc][n_sym] float or NULL  output common gain (1 without budgets)
+ *   P_cluster  [C] float DEVICE array of per-cluster transmit-energy budgets,
+ *          or NULL.  When given, x is scaled by
+ *          beta = min(1, min_c sqrt(P_c / ||x_c||^2)) so that every cluster
+ *          meets its budget while H^d x = beta * H^d x_unscaled stays
+ *          interference-free.
+ *   T      number of x-updates (T - 1 consensus steps), T >= 1
+ * Requires B % C == 0, S = B / C <= U, U in {8, 16, 32, 64}, C <= 16.
+ */
+int dbp_precode_admm(const void* H, const void* s, void* x, float* beta,
+                     const float* P_cluster, int n_sc, int n_sym, int B, int U,
+                     int C, int T, float rho, float gamma, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBP_H_ */

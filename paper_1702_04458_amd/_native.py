@@ -1,0 +1,51 @@
+"""ctypes loader for ``libdbp.so`` (argument marshalling only).
+
+The library is built in-tree by ``paper_1702_04458_amd.build``.  If it is
+missing, loading raises: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdbp.so")
+
+# Entry points declared in include/dbp.h: (name, restype, argtypes)
+_vp, _i, _f, _u8p, _fp = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p
+SIGNATURES = {
+    "dbp_version": (ctypes.c_char_p, []),
+    "dbp_strerror": (ctypes.c_char_p, [_i]),
+    "dbp_last_error": (ctypes.c_char_p, []),
+    "dbp_detect_admm": (_i, [_vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i, _i, _vp]),
+    "dbp_detect_cg": (_i, [_vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i, _vp]),
+    "dbp_precode_admm": (_i, [_vp, _vp, _vp, _fp, _fp, _i, _i, _i, _i, _i, _i, _f, _f, _vp]),
+}
+
+_lib = None
+
+
+class DbpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1702_04458_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code: int) -> None:
+    if code != 0:
+        L = lib()
+        raise DbpError(code, f"{L.dbp_strerror(code).decode()}: {L.dbp_last_error().decode()}")

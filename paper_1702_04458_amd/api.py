@@ -1,0 +1,105 @@
+"""Python binding over the C ABI (``include/dbp.h``).
+
+Argument marshalling only: every step of detection and precoding runs in the
+HIP library.  torch provides device memory and the stream; inputs must be
+contiguous complex64 CUDA (HIP) tensors already resident on the device.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _native
+
+REG = {"mmse": 0, "zf": 1, "box": 2}
+PREC = {"fp32": 0, "fp16": 1, "bf16": 2, "mixed_fp16": 1, "mixed_bf16": 2}
+
+
+def _dev(t: torch.Tensor, name: str, dtype=torch.complex64) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes_ptr(s.cuda_stream)
+
+
+def ctypes_ptr(v):
+    return v if v else None
+
+
+def _shapes(H, y):
+    if H.dim() != 3:
+        raise ValueError("H must be [n_sc, B, U]")
+    n_sc, B, U = H.shape
+    if y.dim() == 2:
+        y = y.unsqueeze(1)
+    if y.dim() != 3 or y.shape[0] != n_sc or y.shape[2] != B:
+        raise ValueError("y must be [n_sc, n_sym, B] (or [n_sc, B])")
+    return n_sc, y.shape[1], B, U, y
+
+
+def detect(H, y, N0, C, rho=1.0, T=5, *, algo="admm", reg="mmse", qam=16, Es=1.0, gamma=1.0,
+           prec="fp32", hard=True, out=None, stream=None):
+    """Decentralized uplink detection.
+
+    ``algo="admm"`` runs Algorithm 1 (``rho`` is the ADMM penalty),
+    ``algo="cg"`` runs Algorithm 2 (regulariser N0/Es, ``rho`` unused).
+    Returns ``(s_hat [n_sc, n_sym, U] complex64, hard [n_sc, n_sym, U] uint8 or None)``.
+    """
+    _dev(H, "H")
+    _dev(y, "y")
+    n_sc, n_sym, B, U, y = _shapes(H, y)
+    if out is None:
+        s_hat = torch.empty((n_sc, n_sym, U), dtype=torch.complex64, device=H.device)
+        hd = torch.empty((n_sc, n_sym, U), dtype=torch.uint8, device=H.device) if hard else None
+    else:
+        s_hat, hd = out
+    L = _native.lib()
+    st = _stream(stream)
+    hp = hd.data_ptr() if hd is not None else None
+    if algo == "admm":
+        code = L.dbp_detect_admm(H.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hp, n_sc, n_sym, B, U, C, T,
+                                 float(rho), float(gamma), float(N0), float(Es), REG[reg], qam, PREC[prec], st)
+    elif algo == "cg":
+        code = L.dbp_detect_cg(H.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hp, n_sc, n_sym, B, U, C, T,
+                               float(N0), float(Es), REG[reg], qam, st)
+    else:
+        raise ValueError(algo)
+    _native.check(code)
+    return s_hat, hd
+
+
+def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, P_cluster=None, out=None, stream=None):
+    """Decentralized ADMM beamforming (Algorithm 3, epsilon = 0).
+
+    ``H`` is the uplink-layout channel [n_sc, B, U]; ``s`` the targets
+    [n_sc, n_sym, U] (or [n_sc, U]).  ``P_cluster`` optional device float32
+    tensor [C] of per-cluster budgets.  Returns ``(x [n_sc, n_sym, B], beta [n_sc, n_sym])``.
+    """
+    _dev(H, "H")
+    _dev(s, "s")
+    n_sc, B, U = H.shape
+    if s.dim() == 2:
+        s = s.unsqueeze(1)
+    n_sym = s.shape[1]
+    if s.shape[0] != n_sc or s.shape[2] != U:
+        raise ValueError("s must be [n_sc, n_sym, U]")
+    if P_cluster is not None:
+        _dev(P_cluster, "P_cluster", torch.float32)
+    if out is None:
+        x = torch.empty((n_sc, n_sym, B), dtype=torch.complex64, device=H.device)
+        beta = torch.empty((n_sc, n_sym), dtype=torch.float32, device=H.device)
+    else:
+        x, beta = out
+    L = _native.lib()
+    code = L.dbp_precode_admm(H.data_ptr(), s.data_ptr(), x.data_ptr(), beta.data_ptr(),
+                              P_cluster.data_ptr() if P_cluster is not None else None,
+                              n_sc, n_sym, B, U, C, T, float(rho), float(gamma), _stream(stream))
+    _native.check(code)
+    return x, beta

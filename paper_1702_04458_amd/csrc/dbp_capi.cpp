@@ -1,0 +1,222 @@
+// C ABI entry points: host-side validation, launch planning and dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/dbp.h"
+#include "dbp_launch.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int ok() {
+  g_last_error.clear();
+  return DBP_OK;
+}
+
+bool supported_u(int U) { return U == 8 || U == 16 || U == 32 || U == 64; }
+
+int qam_side(int qam) {
+  switch (qam) {
+    case 4: return 2;
+    case 16: return 4;
+    case 64: return 8;
+  }
+  return 0;
+}
+
+// Launch plan: a lane group of U lanes per (subcarrier, cluster) problem,
+// P = 64 / U problems per wave, the Cp >= C (power of two) cluster slots of a
+// subcarrier in one workgroup.
+struct Plan {
+  int Cp, nw, scpb;
+};
+
+Plan make_plan(int U, int C) {
+  Plan p;
+  const int P = 64 / U;
+  p.Cp = 1;
+  while (p.Cp < C) p.Cp <<= 1;
+  if (p.Cp >= P) {
+    const int wps = p.Cp / P;
+    p.nw = wps > 4 ? wps : 4;
+    p.scpb = p.nw / wps;
+  } else {
+    p.nw = 4;
+    p.scpb = 4 * (P / p.Cp);
+  }
+  return p;
+}
+
+int common_shape(const char* who, int n_sc, int n_sym, int B, int U, int C, int T) {
+  if (n_sc < 0) return fail(DBP_ERR_INVALID, "%s: n_sc must be >= 0", who);
+  if (n_sym < 1) return fail(DBP_ERR_INVALID, "%s: n_sym must be >= 1", who);
+  if (B < 1 || U < 1 || C < 1) return fail(DBP_ERR_INVALID, "%s: B, U, C must be >= 1", who);
+  if (B % C) return fail(DBP_ERR_INVALID, "%s: B=%d is not a multiple of C=%d", who, B, C);
+  if (U > B) return fail(DBP_ERR_INVALID, "%s: U=%d exceeds B=%d", who, U, B);
+  if (T < 1) return fail(DBP_ERR_INVALID, "%s: T must be >= 1", who);
+  if (!supported_u(U)) return fail(DBP_ERR_UNSUPPORTED, "%s: U=%d not built (8, 16, 32, 64)", who, U);
+  if (C > 16) return fail(DBP_ERR_UNSUPPORTED, "%s: C=%d > 16 clusters per subcarrier not built", who, C);
+  // all cluster groups of one subcarrier share a workgroup of at most 8 waves
+  int Cp = 1;
+  while (Cp < C) Cp <<= 1;
+  if (Cp > 8 * (64 / U))
+    return fail(DBP_ERR_UNSUPPORTED, "%s: C=%d clusters of U=%d users exceed one 512-lane workgroup", who, C, U);
+  return DBP_OK;
+}
+
+int device_status(const char* who, hipError_t e) {
+  if (e != hipSuccess) return fail(DBP_ERR_DEVICE, "%s: %s", who, hipGetErrorString(e));
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dbp_version(void) { return "dbp-mi355x 0.1 (gfx950)"; }
+
+const char* dbp_strerror(int status) {
+  switch (status) {
+    case DBP_OK: return "ok";
+    case DBP_ERR_INVALID: return "invalid argument";
+    case DBP_ERR_UNSUPPORTED: return "unsupported configuration";
+    case DBP_ERR_NOMEM: return "out of memory / budget";
+    case DBP_ERR_DEVICE: return "device error";
+    case DBP_ERR_BUSY: return "busy";
+    case DBP_ERR_NOTFOUND: return "not found";
+  }
+  return "unknown status";
+}
+
+const char* dbp_last_error(void) { return g_last_error.c_str(); }
+
+int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, int n_sc, int n_sym, int B, int U,
+                    int C, int T, float rho, float gamma, float N0, float Es, int reg, int qam, int prec,
+                    void* stream) {
+  const char* who = "dbp_detect_admm";
+  int st = common_shape(who, n_sc, n_sym, B, U, C, T);
+  if (st) return st;
+  if (!(rho > 0.f) || !std::isfinite(rho)) return fail(DBP_ERR_INVALID, "%s: rho must be > 0", who);
+  if (!(gamma > 0.f) || !std::isfinite(gamma)) return fail(DBP_ERR_INVALID, "%s: gamma must be > 0", who);
+  if (!(N0 >= 0.f) || !std::isfinite(N0)) return fail(DBP_ERR_INVALID, "%s: N0 must be >= 0", who);
+  if (!(Es > 0.f) || !std::isfinite(Es)) return fail(DBP_ERR_INVALID, "%s: Es must be > 0", who);
+  if (reg < DBP_REG_MMSE || reg > DBP_REG_BOX) return fail(DBP_ERR_INVALID, "%s: reg=%d", who, reg);
+  const int L = qam_side(qam);
+  if (!L) return fail(DBP_ERR_INVALID, "%s: qam=%d not in {4,16,64}", who, qam);
+  if (prec < DBP_PREC_FP32 || prec > DBP_PREC_MIXED_BF16) return fail(DBP_ERR_INVALID, "%s: prec=%d", who, prec);
+  if (n_sc > 0 && (!H || !y || !s_hat)) return fail(DBP_ERR_INVALID, "%s: null H, y or s_hat", who);
+  const int S = B / C;
+  if (S < U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d < U=%d (S x S branch) not built", who, S, U);
+  if (prec != DBP_PREC_FP32) return fail(DBP_ERR_UNSUPPORTED, "%s: mixed precision not built yet", who);
+  if (n_sc == 0) return ok();
+
+  const Plan pl = make_plan(U, C);
+  dbp::UlArgs a{};
+  a.H = static_cast<const dbp::c32*>(H);
+  a.y = static_cast<const dbp::c32*>(y);
+  a.shat = static_cast<dbp::c32*>(s_hat);
+  a.hard = hard;
+  a.n_sc = n_sc;
+  a.n_sym = n_sym;
+  a.B = B;
+  a.C = C;
+  a.Cp = pl.Cp;
+  a.S = S;
+  a.T = T;
+  a.sc_per_block = pl.scpb;
+  a.reg = reg;
+  a.L = L;
+  a.rho = rho;
+  a.gamma = gamma;
+  const double nu = (reg == DBP_REG_MMSE) ? (double)N0 / ((double)rho * (double)Es) : 0.0;
+  a.inv_den = (float)(1.0 / (nu + C));
+  a.invC = (float)(1.0 / C);
+  a.box_r = (float)((L - 1) / std::sqrt(2.0 * (qam - 1) / 3.0));
+  a.kappa = (float)std::sqrt(2.0 * (qam - 1) / 3.0);
+  return device_status(who, dbp::launch_admm_ul_f32(a, U, pl.nw, static_cast<hipStream_t>(stream)));
+}
+
+int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int n_sc, int n_sym, int B, int U,
+                  int C, int T, float N0, float Es, int reg, int qam, void* stream) {
+  const char* who = "dbp_detect_cg";
+  int st = common_shape(who, n_sc, n_sym, B, U, C, T);
+  if (st) return st;
+  if (!(N0 >= 0.f) || !std::isfinite(N0)) return fail(DBP_ERR_INVALID, "%s: N0 must be >= 0", who);
+  if (!(Es > 0.f) || !std::isfinite(Es)) return fail(DBP_ERR_INVALID, "%s: Es must be > 0", who);
+  if (reg != DBP_REG_MMSE && reg != DBP_REG_ZF)
+    return fail(DBP_ERR_INVALID, "%s: CG needs a quadratic regularizer (MMSE or ZF)", who);
+  const int L = qam_side(qam);
+  if (!L) return fail(DBP_ERR_INVALID, "%s: qam=%d not in {4,16,64}", who, qam);
+  if (n_sc > 0 && (!H || !y || !x_hat)) return fail(DBP_ERR_INVALID, "%s: null H, y or x_hat", who);
+  if (n_sc == 0) return ok();
+  const Plan pl = make_plan(U, C);
+  dbp::UlArgs a{};
+  a.H = static_cast<const dbp::c32*>(H);
+  a.y = static_cast<const dbp::c32*>(y);
+  a.shat = static_cast<dbp::c32*>(x_hat);
+  a.hard = hard;
+  a.n_sc = n_sc;
+  a.n_sym = n_sym;
+  a.B = B;
+  a.C = C;
+  a.Cp = pl.Cp;
+  a.S = B / C;
+  a.T = T;
+  a.sc_per_block = pl.scpb;
+  a.reg = reg;
+  a.L = L;
+  a.rho = (reg == DBP_REG_MMSE) ? (float)((double)N0 / (double)Es) : 0.f;
+  a.gamma = 1.f;
+  a.kappa = (float)std::sqrt(2.0 * (qam - 1) / 3.0);
+  return device_status(who, dbp::launch_dcg_ul_f32(a, U, pl.nw, static_cast<hipStream_t>(stream)));
+}
+
+int dbp_precode_admm(const void* H, const void* s, void* x, float* beta, const float* P_cluster, int n_sc,
+                     int n_sym, int B, int U, int C, int T, float rho, float gamma, void* stream) {
+  const char* who = "dbp_precode_admm";
+  int st = common_shape(who, n_sc, n_sym, B, U, C, T);
+  if (st) return st;
+  if (!(rho > 0.f) || !std::isfinite(rho)) return fail(DBP_ERR_INVALID, "%s: rho must be > 0", who);
+  if (!(gamma > 0.f) || !std::isfinite(gamma)) return fail(DBP_ERR_INVALID, "%s: gamma must be > 0", who);
+  if (n_sc > 0 && (!H || !s || !x)) return fail(DBP_ERR_INVALID, "%s: null H, s or x", who);
+  const int S = B / C;
+  if (S > U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d > U=%d (U x U branch) not built", who, S, U);
+  if (n_sc == 0) return ok();
+  const Plan pl = make_plan(U, C);
+  dbp::DlArgs a{};
+  a.H = static_cast<const dbp::c32*>(H);
+  a.s = static_cast<const dbp::c32*>(s);
+  a.x = static_cast<dbp::c32*>(x);
+  a.beta = beta;
+  a.P = P_cluster;
+  a.n_sc = n_sc;
+  a.n_sym = n_sym;
+  a.B = B;
+  a.C = C;
+  a.Cp = pl.Cp;
+  a.S = S;
+  a.T = T;
+  a.sc_per_block = pl.scpb;
+  a.rho = rho;
+  a.gamma = gamma;
+  a.invC = (float)(1.0 / C);
+  a.f0 = (float)std::fmax((double)U / B, 1.0 / C);
+  return device_status(who, dbp::launch_admm_dl_f32(a, U, pl.nw, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,149 @@
+// Device-side building blocks shared by the detection and precoding kernels.
+//
+// Layout convention used throughout: a "problem" is one (subcarrier, antenna
+// cluster) pair.  A problem owns a group of G = 64 / P consecutive lanes of a
+// wave64 (P problems per wave); lane u of the group owns row u of every
+// G x G matrix of that problem and entry u of every length-G vector.  Matrices
+// live in registers (one row per lane, fully unrolled loops so that row slots
+// are compile-time register indices); vectors that another lane needs are
+// broadcast through a per-wave LDS scratch line.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dbp {
+
+struct c32 {
+  float re, im;
+};
+
+__device__ __forceinline__ c32 cz() { return c32{0.f, 0.f}; }
+__device__ __forceinline__ c32 cadd(c32 a, c32 b) { return c32{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ c32 csub(c32 a, c32 b) { return c32{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ c32 cscale(c32 a, float f) { return c32{a.re * f, a.im * f}; }
+__device__ __forceinline__ c32 cmul(c32 a, c32 b) {
+  return c32{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc += x * y
+__device__ __forceinline__ void cmac(c32& acc, c32 x, c32 y) {
+  acc.re = fmaf(x.re, y.re, acc.re);
+  acc.re = fmaf(-x.im, y.im, acc.re);
+  acc.im = fmaf(x.re, y.im, acc.im);
+  acc.im = fmaf(x.im, y.re, acc.im);
+}
+// acc += conj(x) * y
+__device__ __forceinline__ void cmacc(c32& acc, c32 x, c32 y) {
+  acc.re = fmaf(x.re, y.re, acc.re);
+  acc.re = fmaf(x.im, y.im, acc.re);
+  acc.im = fmaf(x.re, y.im, acc.im);
+  acc.im = fmaf(-x.im, y.re, acc.im);
+}
+// acc -= x * y
+__device__ __forceinline__ void cmsub(c32& acc, c32 x, c32 y) {
+  acc.re = fmaf(-x.re, y.re, acc.re);
+  acc.re = fmaf(x.im, y.im, acc.re);
+  acc.im = fmaf(-x.re, y.im, acc.im);
+  acc.im = fmaf(-x.im, y.re, acc.im);
+}
+
+// Completes this wave's outstanding LDS operations and stops the compiler from
+// moving memory accesses across this point.  LDS instructions of one wave are
+// executed in order, so after this a lane sees what other lanes of the same
+// wave wrote before it.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Reads N consecutive complex values starting at p (16-byte aligned, N even)
+// into r[0..N-1] with 128-bit LDS loads.
+template <int N>
+__device__ __forceinline__ void lds_read_vec(const c32* p, c32* r) {
+  const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    float4 v = q[i];
+    r[2 * i] = c32{v.x, v.y};
+    r[2 * i + 1] = c32{v.z, v.w};
+  }
+}
+
+// Sum over the G lanes of a group (G a power of two, groups aligned); every
+// lane of the group receives the identical value (the butterfly adds the same
+// pair of operands on both partners at every level).
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ float group_min(float v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// In-place inversion of the Hermitian positive definite matrix whose row u is
+// held by lane u of the group (A[v] = M[u][v]), by Gauss-Jordan elimination
+// without pivoting (the pivots of an HPD matrix are positive Schur
+// complements).  Only the first n pivots are swept: a block-diagonal
+// [M_n 0; 0 I] stays block-diagonal, so groups may pad a smaller system with
+// identity rows.  Row k of the partially swept matrix equals the conjugate of
+// column k with the sign flipped on already-swept columns, so a single column
+// broadcast per step suffices.
+template <int G>
+__device__ __forceinline__ void gj_invert(c32 (&A)[G], int u, int n, c32* line, int gbase) {
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    if (k < n) {
+      line[gbase + u] = A[k];
+      wave_lds_sync();
+      c32 col[G];
+      lds_read_vec<G>(line + gbase, col);
+      wave_lds_sync();
+      const float p = 1.0f / col[k].re;
+      const bool me = (u == k);
+      const c32 m = c32{A[k].re * p, A[k].im * p};
+#pragma unroll
+      for (int v = 0; v < G; ++v) {
+        if (v == k) continue;
+        // row k entry v
+        c32 rk = (v < k) ? c32{-col[v].re, col[v].im} : c32{col[v].re, -col[v].im};
+        c32 upd = A[v];
+        cmsub(upd, m, rk);
+        A[v] = me ? cscale(rk, p) : upd;
+      }
+      A[k] = me ? c32{p, 0.f} : c32{-m.re, -m.im};
+    }
+  }
+}
+
+// out = M q for the group matrix M (row u in A), q distributed one entry per
+// lane; the first n entries of q are used.
+template <int G>
+__device__ __forceinline__ c32 group_matvec(const c32 (&A)[G], c32 q, int u, c32* line, int gbase) {
+  line[gbase + u] = q;
+  wave_lds_sync();
+  c32 qv[G];
+  lds_read_vec<G>(line + gbase, qv);
+  wave_lds_sync();
+  c32 acc0 = cz(), acc1 = cz();
+#pragma unroll
+  for (int v = 0; v < G; v += 2) {
+    cmac(acc0, A[v], qv[v]);
+    cmac(acc1, A[v + 1], qv[v + 1]);
+  }
+  (void)u;
+  return cadd(acc0, acc1);
+}
+
+// Nearest-point slicing of one real dimension of a unit-energy square QAM
+// (L levels, kappa = sqrt(2 (M - 1) / 3)): i = clamp(floor((kappa x + L) / 2)),
+// ties to the upper level.  The products and sums are rounded individually so
+// the decision is reproducible on any IEEE single-precision implementation.
+__device__ __forceinline__ int slice_dim(float x, float kappa, int L) {
+  float t = __fadd_rn(__fmul_rn(x, kappa), (float)L);
+  float f = floorf(t * 0.5f);
+  f = fminf(fmaxf(f, 0.f), (float)(L - 1));
+  return (int)f;
+}
+
+}  // namespace dbp

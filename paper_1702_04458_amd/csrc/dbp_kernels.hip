@@ -1,0 +1,421 @@
+// HIP kernels for decentralized uplink detection and downlink precoding on gfx950.
+//
+// Method: Li et al., "Decentralized Baseband Processing for Massive MU-MIMO
+// Systems" (arXiv:1702.04458).  Algorithm 1 (decentralized ADMM detection,
+// U x U branch, eq. StepE1variant1), Algorithm 2 (decentralized CG detection,
+// eqs. CGiteration / CGdecentralization) and Algorithm 3 (decentralized ADMM
+// beamforming, S x S branch).  On one GPU the antenna clusters are a batch
+// axis: each (subcarrier, cluster) problem is a lane group of a wave64, the
+// clusters of one subcarrier sit in one workgroup, and the consensus sum of the
+// paper's fusion node is an LDS reduction in fixed cluster order (so every
+// result is independent of how the work is tiled).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dbp_device.h"
+#include "dbp_launch.h"
+
+namespace dbp {
+
+constexpr int kStageRows = 8;   // rows of H_c staged per pass through LDS
+
+// LDS carve-up shared by the kernels (all offsets in c32 units):
+//   stage[nw][kStageRows][64]   staged H rows (one slot per lane)
+//   ystage[nw][kStageRows][8]   staged y entries (one per problem of the wave)
+//   line[nw][64]                per-wave broadcast line
+//   cons[2][nw][64]             double-buffered consensus slots (one per lane)
+//   aux[nw][64]                 per-problem scalars (precoder power scaling)
+struct Smem {
+  c32* stage;
+  c32* ystage;
+  c32* line;
+  c32* cons;
+  c32* aux;
+};
+
+__device__ __forceinline__ Smem carve(c32* base, int nw) {
+  Smem s;
+  s.stage = base;
+  s.ystage = s.stage + nw * kStageRows * 64;
+  s.line = s.ystage + nw * kStageRows * 8;
+  s.cons = s.line + nw * 64;
+  s.aux = s.cons + 2 * nw * 64;
+  return s;
+}
+
+size_t smem_bytes(int nw) { return sizeof(c32) * (size_t)nw * (kStageRows * 64 + kStageRows * 8 + 64 + 128 + 64); }
+
+// One pass over the S rows of H_c (and of y_c for symbol n): accumulates the
+// Gram row A[v] += conj(H[s][u]) H[s][v] when WITH_GRAM, and always
+// hy = sum_s conj(H[s][u]) y[s] (row u of H_c^H y_c).
+template <int G, bool WITH_GRAM>
+__device__ __forceinline__ c32 cluster_pass(const c32* __restrict__ H, const c32* __restrict__ y, c32 (&A)[G],
+                                            int k, int c, int n, int u, int g, int lane, int wave, bool active,
+                                            int B, int S, int U, int n_sym, const Smem& sm) {
+  constexpr int R = kStageRows;
+  c32 hy = cz();
+  c32* stage = sm.stage + wave * R * 64;
+  c32* yst = sm.ystage + wave * R * 8;
+  const c32* Hk = H + (size_t)k * B * U + (size_t)c * S * U;
+  const c32* yk = y + ((size_t)k * n_sym + n) * B + (size_t)c * S;
+  for (int s0 = 0; s0 < S; s0 += R) {
+    c32 h[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int s = s0 + r;
+      h[r] = (active && s < S) ? Hk[(size_t)s * U + u] : cz();
+      if (WITH_GRAM) stage[r * 64 + lane] = h[r];
+    }
+    if (u < R) {
+      const int s = s0 + u;
+      yst[u * 8 + g] = (active && s < S) ? yk[s] : cz();
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (WITH_GRAM) {
+#pragma unroll
+        for (int v0 = 0; v0 < G; v0 += 8) {
+          c32 row[8];
+          lds_read_vec<8>(stage + r * 64 + g * G + v0, row);
+#pragma unroll
+          for (int v = 0; v < 8; ++v) cmacc(A[v0 + v], h[r], row[v]);
+        }
+      }
+      cmacc(hy, h[r], yst[r * 8 + g]);
+    }
+    wave_lds_sync();
+  }
+  return hy;
+}
+
+// Consensus: every lane of cluster c writes its entry of w_c into its slot;
+// after the barrier each lane sums the C clusters of its subcarrier in cluster
+// order 1..C (identical sum on every cluster, as if broadcast by the fusion
+// node).
+__device__ __forceinline__ c32 consensus(c32 wc, int buf, int ls, int G, int u, int C, int Cp, const Smem& sm,
+                                         int slot, int nw) {
+  c32* cb = sm.cons + buf * nw * 64;
+  cb[slot] = wc;
+  __syncthreads();
+  c32 w = cz();
+  const c32* src = cb + (size_t)ls * Cp * G + u;
+  for (int cc = 0; cc < C; ++cc) w = cadd(w, src[cc * G]);
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1, U x U branch (S >= U), FP32.  Group size G = U.
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
+  constexpr int P = 64 / G;
+  extern __shared__ float4 smem_raw[];
+  const int nw = blockDim.x >> 6;
+  Smem sm = carve(reinterpret_cast<c32*>(smem_raw), nw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane / G, u = lane % G;
+  const int lp = wave * P + g;
+  const int ls = lp / a.Cp, c = lp % a.Cp;
+  const int k = blockIdx.x * a.sc_per_block + ls;
+  const bool active = (k < a.n_sc) && (c < a.C);
+  const int slot = wave * 64 + lane;
+  c32* line = sm.line + wave * 64;
+  const int gbase = g * G;
+
+  // Preprocessing (Alg. 1, S > U branch): B_c = H_c^H H_c + rho I, B_c^{-1}.
+  c32 A[G];
+#pragma unroll
+  for (int v = 0; v < G; ++v) A[v] = cz();
+  c32 hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G,
+                                  a.n_sym, sm);
+#pragma unroll
+  for (int v = 0; v < G; ++v)
+    if (v == u) A[v].re += a.rho;
+  gj_invert<G>(A, u, G, line, gbase);
+
+  int buf = 0;
+  for (int n = 0; n < a.n_sym; ++n) {
+    c32 hy = hy0;
+    if (n > 0) hy = cluster_pass<G, false>(a.H, a.y, A, k, c, n, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
+    // y_c^reg = B_c^{-1} H_c^H y_c; z = y^reg; lambda = 0
+    const c32 yreg = group_matvec<G>(A, hy, u, line, gbase);
+    c32 z = yreg, lam = cz();
+    c32 w = consensus(active ? z : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+    buf ^= 1;
+    c32 s;
+    if (a.reg == 2) {
+      c32 v = cscale(w, a.invC);
+      s = c32{fminf(fmaxf(v.re, -a.box_r), a.box_r), fminf(fmaxf(v.im, -a.box_r), a.box_r)};
+    } else {
+      s = cscale(w, a.inv_den);
+    }
+    for (int t = 2; t <= a.T; ++t) {
+      lam.re = fmaf(a.gamma, z.re - s.re, lam.re);
+      lam.im = fmaf(a.gamma, z.im - s.im, lam.im);
+      const c32 q = csub(s, lam);
+      const c32 bq = group_matvec<G>(A, q, u, line, gbase);
+      z = c32{fmaf(a.rho, bq.re, yreg.re), fmaf(a.rho, bq.im, yreg.im)};
+      w = consensus(active ? cadd(z, lam) : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+      buf ^= 1;
+      if (a.reg == 2) {
+        c32 v = cscale(w, a.invC);
+        s = c32{fminf(fmaxf(v.re, -a.box_r), a.box_r), fminf(fmaxf(v.im, -a.box_r), a.box_r)};
+      } else {
+        s = cscale(w, a.inv_den);
+      }
+    }
+    if (active && c == 0) {
+      const size_t o = ((size_t)k * a.n_sym + n) * G + u;
+      a.shat[o] = s;
+      if (a.hard) {
+        const int iI = slice_dim(s.re, a.kappa, a.L), iQ = slice_dim(s.im, a.kappa, a.L);
+        a.hard[o] = (uint8_t)(iI + a.L * iQ);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2 (decentralized CG), FP32.  Each cluster keeps its own copy of
+// x, r, p (the broadcast-w variant) and contributes w_c = H_c^H H_c p through
+// its local Gram G_c held in registers (one matvec per iteration).
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
+  constexpr int P = 64 / G;
+  extern __shared__ float4 smem_raw[];
+  const int nw = blockDim.x >> 6;
+  Smem sm = carve(reinterpret_cast<c32*>(smem_raw), nw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane / G, u = lane % G;
+  const int lp = wave * P + g;
+  const int ls = lp / a.Cp, c = lp % a.Cp;
+  const int k = blockIdx.x * a.sc_per_block + ls;
+  const bool active = (k < a.n_sc) && (c < a.C);
+  const int slot = wave * 64 + lane;
+  c32* line = sm.line + wave * 64;
+  const int gbase = g * G;
+
+  c32 A[G];
+#pragma unroll
+  for (int v = 0; v < G; ++v) A[v] = cz();
+  c32 hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
+
+  int buf = 0;
+  for (int n = 0; n < a.n_sym; ++n) {
+    c32 hy = hy0;
+    if (n > 0) hy = cluster_pass<G, false>(a.H, a.y, A, k, c, n, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
+    // y^MRC = sum_c H_c^H y_c (consensus); r = p = y^MRC; x = 0
+    c32 r = consensus(active ? hy : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+    buf ^= 1;
+    c32 pv = r, x = cz();
+    float rr = group_sum<G>(r.re * r.re + r.im * r.im);
+    for (int t = 1; t <= a.T; ++t) {
+      const c32 wc = group_matvec<G>(A, pv, u, line, gbase);
+      const c32 w = consensus(active ? wc : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+      buf ^= 1;
+      const c32 e = c32{fmaf(a.rho, pv.re, w.re), fmaf(a.rho, pv.im, w.im)};
+      const float pe = group_sum<G>(pv.re * e.re + pv.im * e.im);
+      const float alpha = (rr > 0.f) ? rr / pe : 0.f;
+      x.re = fmaf(alpha, pv.re, x.re);
+      x.im = fmaf(alpha, pv.im, x.im);
+      r.re = fmaf(-alpha, e.re, r.re);
+      r.im = fmaf(-alpha, e.im, r.im);
+      const float rr_new = group_sum<G>(r.re * r.re + r.im * r.im);
+      const float beta = (rr > 0.f) ? rr_new / rr : 0.f;
+      pv.re = fmaf(beta, pv.re, r.re);
+      pv.im = fmaf(beta, pv.im, r.im);
+      rr = rr_new;
+    }
+    if (active && c == 0) {
+      const size_t o = ((size_t)k * a.n_sym + n) * G + u;
+      a.shat[o] = x;
+      if (a.hard) {
+        const int iI = slice_dim(x.re, a.kappa, a.L), iQ = slice_dim(x.im, a.kappa, a.L);
+        a.hard[o] = (uint8_t)(iI + a.L * iQ);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 3 (decentralized ADMM beamforming, epsilon = 0), S x S branch
+// (S <= U), FP32.  Group size G = U.  The downlink cluster channel is
+// H_c = (Hu_c)^T with Hu_c the S x U uplink block (reciprocity), read in place
+// from the uplink layout.  Lane u holds column u of Hu_c (entries Hu_c[a][u],
+// a < S) for m_c = H_c x_c; lane a < S holds row a of Hu_c for H_c^H v and
+// row a of A_c^{-1}.
+// ---------------------------------------------------------------------------
+template <int G, int SG>
+__global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
+  constexpr int P = 64 / G;
+  extern __shared__ float4 smem_raw[];
+  const int nw = blockDim.x >> 6;
+  Smem sm = carve(reinterpret_cast<c32*>(smem_raw), nw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane / G, u = lane % G;
+  const int lp = wave * P + g;
+  const int ls = lp / a.Cp, c = lp % a.Cp;
+  const int k = blockIdx.x * a.sc_per_block + ls;
+  const bool active = (k < a.n_sc) && (c < a.C);
+  const int slot = wave * 64 + lane;
+  c32* line = sm.line + wave * 64;
+  const int gbase = g * G;
+  const int S = a.S;
+  const c32* Hk = a.H + (size_t)k * a.B * G + (size_t)c * S * G;
+
+  c32 hcol[SG], hrow[G], A[SG];
+#pragma unroll
+  for (int i = 0; i < SG; ++i) {
+    hcol[i] = (active && i < S) ? Hk[(size_t)i * G + u] : cz();
+    A[i] = cz();
+  }
+#pragma unroll
+  for (int i = 0; i < G; ++i) hrow[i] = (active && u < S) ? Hk[(size_t)u * G + i] : cz();
+  // A_c = H_c^H H_c + rho^{-1} I_S with (H_c^H H_c)[a][b] = sum_u conj(Hu[a][u]) Hu[b][u].
+  // Row b of Hu_c is broadcast from the stage buffer of this wave.
+  {
+    c32* stage = sm.stage + wave * kStageRows * 64;   // needs G*G/64*... rows: stage one row at a time
+    for (int b = 0; b < S; ++b) {
+      // lane u of the group publishes Hu[b][u] = hcol[b]
+      c32 hb = cz();
+#pragma unroll
+      for (int i = 0; i < SG; ++i)
+        if (i == b) hb = hcol[i];
+      stage[lane] = hb;
+      wave_lds_sync();
+      c32 acc = cz();
+#pragma unroll
+      for (int v0 = 0; v0 < G; v0 += 8) {
+        c32 row[8];
+        lds_read_vec<8>(stage + gbase + v0, row);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) cmacc(acc, hrow[v0 + v], row[v]);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < SG; ++i)
+        if (i == b) A[i] = (u < S) ? acc : cz();
+    }
+  }
+  const float irho = 1.0f / a.rho;
+#pragma unroll
+  for (int v = 0; v < SG; ++v)
+    if (v == u) A[v].re += (u < S) ? irho : 1.0f;
+  gj_invert<SG>(A, u, S, line, gbase);
+
+  int buf = 0;
+  for (int n = 0; n < a.n_sym; ++n) {
+    const size_t vo = ((size_t)k * a.n_sym + n);
+    const c32 s = (k < a.n_sc) ? a.s[vo * G + u] : cz();
+    c32 z = cscale(s, a.f0), lam = cz();
+    // x_c = A_c^{-1} H_c^H (z + lambda), entry a held by lane a < S
+    auto apply = [&](c32 v) -> c32 {
+      line[gbase + u] = v;
+      wave_lds_sync();
+      c32 acc = cz();
+#pragma unroll
+      for (int v0 = 0; v0 < G; v0 += 8) {
+        c32 vv[8];
+        lds_read_vec<8>(line + gbase + v0, vv);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cmacc(acc, hrow[v0 + i], vv[i]);
+      }
+      wave_lds_sync();
+      return group_matvec<SG>(A, (u < S) ? acc : cz(), u, line, gbase);
+    };
+    c32 x = apply(z);
+    for (int t = 2; t <= a.T; ++t) {
+      // m_c = H_c x_c: m[u] = sum_a Hu[a][u] x[a]
+      line[gbase + u] = x;
+      wave_lds_sync();
+      c32 m = cz();
+#pragma unroll
+      for (int v0 = 0; v0 < SG; v0 += 8) {
+        c32 xv[8];
+        lds_read_vec<8>(line + gbase + v0, xv);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cmac(m, hcol[v0 + i], xv[i]);
+      }
+      wave_lds_sync();
+      const c32 wc = csub(m, lam);
+      const c32 w = consensus(active ? wc : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+      buf ^= 1;
+      z = c32{fmaf(a.invC, s.re - w.re, wc.re), fmaf(a.invC, s.im - w.im, wc.im)};
+      lam.re = fmaf(-a.gamma, m.re - z.re, lam.re);
+      lam.im = fmaf(-a.gamma, m.im - z.im, lam.im);
+      x = apply(cadd(z, lam));
+    }
+    // optional common power scaling: beta = min(1, min_c sqrt(P_c / ||x_c||^2))
+    float beta = 1.0f;
+    if (a.P) {
+      const float e = group_sum<G>((u < S) ? (x.re * x.re + x.im * x.im) : 0.f);
+      float ratio = 1.0f;
+      if (active && e > 0.f) ratio = fminf(1.0f, sqrtf(a.P[c] / e));
+      c32* ab = sm.aux;
+      if (u == 0) ab[wave * 64 + g] = c32{ratio, 0.f};
+      __syncthreads();
+      // problems of subcarrier ls occupy local problem indices ls*Cp .. ls*Cp+C-1
+      for (int cc = 0; cc < a.C; ++cc) {
+        const int q = ls * a.Cp + cc;
+        beta = fminf(beta, ab[(q / P) * 64 + (q % P)].re);
+      }
+      __syncthreads();
+    }
+    if (active && u < S) a.x[vo * a.B + (size_t)c * S + u] = cscale(x, beta);
+    if (active && c == 0 && u == 0 && a.beta) a.beta[vo] = beta;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename K, typename Args>
+static hipError_t launch(K kernel, const Args& a, int nw, hipStream_t st) {
+  const int nblocks = (a.n_sc + a.sc_per_block - 1) / a.sc_per_block;
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(64 * nw), smem_bytes(nw), st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st) {
+  switch (U) {
+    case 8: return launch(admm_ul_f32<8>, a, nw, st);
+    case 16: return launch(admm_ul_f32<16>, a, nw, st);
+    case 32: return launch(admm_ul_f32<32>, a, nw, st);
+    case 64: return launch(admm_ul_f32<64>, a, nw, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st) {
+  switch (U) {
+    case 8: return launch(dcg_ul_f32<8>, a, nw, st);
+    case 16: return launch(dcg_ul_f32<16>, a, nw, st);
+    case 32: return launch(dcg_ul_f32<32>, a, nw, st);
+    case 64: return launch(dcg_ul_f32<64>, a, nw, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st) {
+  const int S = a.S;
+  switch (U) {
+    case 8: return launch(admm_dl_f32<8, 8>, a, nw, st);
+    case 16:
+      return S <= 8 ? launch(admm_dl_f32<16, 8>, a, nw, st) : launch(admm_dl_f32<16, 16>, a, nw, st);
+    case 32:
+      if (S <= 8) return launch(admm_dl_f32<32, 8>, a, nw, st);
+      if (S <= 16) return launch(admm_dl_f32<32, 16>, a, nw, st);
+      return launch(admm_dl_f32<32, 32>, a, nw, st);
+    case 64:
+      if (S <= 8) return launch(admm_dl_f32<64, 8>, a, nw, st);
+      if (S <= 16) return launch(admm_dl_f32<64, 16>, a, nw, st);
+      if (S <= 32) return launch(admm_dl_f32<64, 32>, a, nw, st);
+      return launch(admm_dl_f32<64, 64>, a, nw, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dbp

@@ -1,0 +1,44 @@
+// Kernel argument blocks and launcher declarations (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dbp {
+
+struct c32;
+
+struct UlArgs {
+  const c32* H;       // [n_sc][B][U]
+  const c32* y;       // [n_sc][n_sym][B]
+  c32* shat;          // [n_sc][n_sym][U]
+  uint8_t* hard;      // [n_sc][n_sym][U] or null
+  int n_sc, n_sym, B, C, Cp, S, T;
+  int sc_per_block;
+  int reg;            // 0 MMSE, 1 ZF, 2 BOX
+  int L;              // QAM levels per dimension
+  float rho;          // ADMM penalty (Alg. 1) or N0/Es regulariser (Alg. 2)
+  float gamma;
+  float inv_den;      // 1 / (N0/(rho Es) + C)  (MMSE), 1 / C (ZF)
+  float invC;
+  float box_r;
+  float kappa;
+};
+
+struct DlArgs {
+  const c32* H;       // [n_sc][B][U] uplink layout
+  const c32* s;       // [n_sc][n_sym][U]
+  c32* x;             // [n_sc][n_sym][B]
+  float* beta;        // [n_sc][n_sym] or null
+  const float* P;     // [C] device per-cluster budgets or null
+  int n_sc, n_sym, B, C, Cp, S, T;
+  int sc_per_block;
+  float rho, gamma, invC, f0;
+};
+
+size_t smem_bytes(int nw);
+hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
+hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
+hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st);
+
+}  // namespace dbp

@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+declared in include/dbp.h, and rejects malformed arguments before touching the
+device (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1702_04458_amd import _native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dbp.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_native.LIB_PATH), reason="libdbp.so not built")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dbp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = ctypes.CDLL(_native.LIB_PATH)
+    syms = declared_symbols()
+    assert len(syms) >= 6
+    for s in syms:
+        assert hasattr(lib, s), s
+    # and the binding knows every declared entry point
+    assert set(syms) <= set(_native.SIGNATURES)
+
+
+def test_version_and_strerror():
+    L = _native.lib()
+    assert b"gfx950" in L.dbp_version()
+    for code in range(7):
+        assert L.dbp_strerror(code)
+
+
+def _admm(**kw):
+    args = dict(H=1, y=1, s=1, hard=None, n_sc=4, n_sym=1, B=64, U=8, C=4, T=3, rho=1.0, gamma=1.0,
+                N0=0.1, Es=1.0, reg=0, qam=4, prec=0)
+    args.update(kw)
+    L = _native.lib()
+    return L.dbp_detect_admm(args["H"], args["y"], args["s"], args["hard"], args["n_sc"], args["n_sym"],
+                             args["B"], args["U"], args["C"], args["T"], args["rho"], args["gamma"],
+                             args["N0"], args["Es"], args["reg"], args["qam"], args["prec"], None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(B=63), 1), (dict(U=128, B=64), 1), (dict(T=0), 1), (dict(rho=0.0), 1), (dict(rho=-1.0), 1),
+    (dict(N0=-1.0), 1), (dict(Es=0.0), 1), (dict(gamma=0.0), 1), (dict(qam=8), 1), (dict(reg=7), 1),
+    (dict(prec=9), 1), (dict(H=None), 1), (dict(y=None), 1), (dict(s=None), 1), (dict(n_sc=-1), 1),
+    (dict(n_sym=0), 1), (dict(U=12, B=96, C=4), 2), (dict(B=64, C=8, U=16), 2), (dict(C=32, B=512), 2),
+    (dict(rho=float("nan")), 1),
+])
+def test_detect_admm_rejects(kw, code):
+    assert _admm(**kw) == code
+    assert _native.lib().dbp_last_error()
+
+
+def test_detect_admm_empty_is_noop():
+    assert _admm(n_sc=0, H=None, y=None, s=None) == 0
+
+
+def test_detect_cg_rejects():
+    L = _native.lib()
+    base = [1, 1, 1, None, 4, 1, 64, 8, 4, 3, 0.1, 1.0, 0, 4, None]
+    assert L.dbp_detect_cg(*base[:12], 2, 4, None) == 1            # BOX is not quadratic
+    assert L.dbp_detect_cg(1, 1, 1, None, 4, 1, 64, 8, 3, 3, 0.1, 1.0, 0, 4, None) == 1   # B % C
+    assert L.dbp_detect_cg(1, 1, None, None, 4, 1, 64, 8, 4, 3, 0.1, 1.0, 0, 4, None) == 1
+
+
+def test_precode_rejects():
+    L = _native.lib()
+    ok = [1, 1, 1, None, None, 4, 1, 256, 32, 16, 5, 1.0, 1.0, None]
+    bad_S = list(ok)
+    bad_S[8] = 4          # C = 4 -> S = 64 > U = 32 (U x U branch)
+    assert L.dbp_precode_admm(*bad_S) == 2
+    bad_rho = list(ok)
+    bad_rho[11] = 0.0
+    assert L.dbp_precode_admm(*bad_rho) == 1
+    bad_ptr = list(ok)
+    bad_ptr[2] = None
+    assert L.dbp_precode_admm(*bad_ptr) == 1

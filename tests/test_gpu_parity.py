@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars (FP32 path):
+* soft outputs: frame-level relative Frobenius error ||gpu - oracle|| / ||oracle||
+  <= 1e-5, and every vector within 1e-4 relative;
+* hard decisions: the kernel's decision equals the FP32 slicer applied to the
+  kernel's own soft output bit for bit, and equals the oracle's FP64 decision on
+  every symbol whose oracle soft value is farther than a guard band (1e-3 in
+  kappa-scaled units) from a decision threshold; at most 1e-4 of all symbols may
+  sit inside the guard band and differ.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import dbp_oracle as O
+from paper_1702_04458_amd import inputs
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1702_04458_amd import api  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def rel_err(gpu, ref):
+    return float(np.linalg.norm(gpu - ref) / np.linalg.norm(ref))
+
+
+def per_vec_rel(gpu, ref):
+    num = np.linalg.norm(gpu - ref, axis=-1)
+    den = np.linalg.norm(ref, axis=-1)
+    return float(np.max(num / np.maximum(den, 1e-30)))
+
+
+def threshold_gap(x, M):
+    """Distance of the oracle value to the nearest decision threshold, in the
+    slicer's units t = (kappa x + L) / 2 (thresholds at t = 1 .. L-1)."""
+    L = int(math.sqrt(M))
+    kappa = math.sqrt(2 * (M - 1) / 3)
+
+    def gap(v):
+        t = (kappa * v + L) / 2
+        return np.abs(t - np.clip(np.round(t), 1, L - 1))
+    return np.minimum(gap(x.real), gap(x.imag))
+
+
+def check_hard(shat, hard, ref, M, guard=1e-3):
+    assert np.array_equal(hard, O.slice_qam_f32(shat, M)), "kernel slicer differs from FP32 slicer"
+    ref_hard = O.slice_qam(ref, M)
+    diff = hard != ref_hard
+    near = threshold_gap(ref, M) < guard
+    assert not np.any(diff & ~near), f"{int(np.sum(diff & ~near))} hard decisions differ away from thresholds"
+    assert np.sum(diff) <= max(1, 1e-4 * diff.size)
+
+
+def run_detect(fr, C, T, algo, reg="mmse", rho=1.0, sel=None):
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    s, h = api.detect(H, y, fr.N0, C, rho, T, algo=algo, reg=reg, qam=fr.qam)
+    torch.cuda.synchronize()
+    s, h = s.cpu().numpy(), h.cpu().numpy()
+    return s, h
+
+
+def oracle_detect(fr, C, T, algo, reg="mmse", rho=1.0, sel=None):
+    Hs = fr.H if sel is None else fr.H[sel]
+    ys = fr.y if sel is None else fr.y[sel]
+    box_r = O.box_radius(fr.qam)
+    if algo == "admm":
+        return O.admm_ul_frame(Hs, ys, C, rho, T, fr.N0, reg=reg, box_r=box_r)
+    return O.dcg_ul_frame(Hs, ys, C, T, fr.N0, reg=reg)
+
+
+# -- configuration 1: B=64, C=4, U=8, 16 subcarriers, QPSK, 10 dB, rho=1, T=3, 4 seeds
+@pytest.mark.parametrize("seed", range(4))
+def test_cfg1_admm(seed):
+    say(f"[gpu] cfg1 admm seed={seed}")
+    fr = inputs.uplink_frame(inputs.frame_seed(1, seed, 10), 16, 64, 8, 4, 10.0)
+    s, h = run_detect(fr, 4, 3, "admm")
+    ref = oracle_detect(fr, 4, 3, "admm")
+    assert rel_err(s, ref) <= 1e-5
+    assert per_vec_rel(s, ref) <= 1e-4
+    check_hard(s, h, ref, 4)
+
+
+# -- configuration 2: B=128, C=8, U=16, 16-QAM, SNR 0..20, T=5; ADMM and DCG side by side.
+# 75 subcarriers (a ragged tail of the 2-subcarrier workgroups) per SNR point.
+@pytest.mark.parametrize("snr", [0, 5, 10, 15, 20])
+@pytest.mark.parametrize("algo", ["admm", "cg"])
+def test_cfg2(snr, algo):
+    say(f"[gpu] cfg2 {algo} snr={snr}")
+    fr = inputs.uplink_frame(inputs.frame_seed(2, 0, snr), 75, 128, 16, 16, float(snr))
+    s, h = run_detect(fr, 8, 5, algo)
+    ref = oracle_detect(fr, 8, 5, algo)
+    assert rel_err(s, ref) <= 1e-5
+    assert per_vec_rel(s, ref) <= 1e-4
+    check_hard(s, h, ref, 16)
+
+
+def test_cfg2_full_size_sampled():
+    """1200 subcarriers in one launch; the oracle checks a sample of them."""
+    say("[gpu] cfg2 full size sampled")
+    fr = inputs.uplink_frame(inputs.frame_seed(2, 1, 10), 1200, 128, 16, 16, 10.0)
+    rng = np.random.default_rng(0)
+    sel = np.sort(rng.choice(1200, 48, replace=False))
+    for algo in ("admm", "cg"):
+        s, h = run_detect(fr, 8, 5, algo)
+        ref = oracle_detect(fr, 8, 5, algo, sel=sel)
+        assert rel_err(s[sel], ref) <= 1e-5
+        check_hard(s[sel], h[sel], ref, 16)
+
+
+# -- headline shape: B=256, U=32, 64-QAM, 25 dB, T=5, C=8 (S=32) and C=4 (S=64)
+@pytest.mark.parametrize("C", [8, 4])
+def test_headline_shape(C):
+    say(f"[gpu] headline C={C}")
+    fr = inputs.uplink_frame(inputs.frame_seed(6, C, 25), 41, 256, 32, 64, 25.0)
+    s, h = run_detect(fr, C, 5, "admm")
+    ref = oracle_detect(fr, C, 5, "admm")
+    assert rel_err(s, ref) <= 1e-5
+    assert per_vec_rel(s, ref) <= 1e-4
+    check_hard(s, h, ref, 64)
+
+
+# -- configuration 4 shape (B=512, C=8, U=64), FP32 path, i.i.d. and correlated
+@pytest.mark.parametrize("corr", [0.0, 0.7])
+def test_cfg4_shape_fp32(corr):
+    say(f"[gpu] cfg4 fp32 corr={corr}")
+    fr = inputs.uplink_frame(inputs.frame_seed(4, 0, 25), 9, 512, 64, 64, 25.0, corr=corr)
+    s, h = run_detect(fr, 8, 5, "admm")
+    ref = oracle_detect(fr, 8, 5, "admm")
+    assert rel_err(s, ref) <= 1e-5
+    check_hard(s, h, ref, 64)
+
+
+@pytest.mark.parametrize("reg", ["zf", "box"])
+def test_other_regularisers(reg):
+    say(f"[gpu] reg={reg}")
+    fr = inputs.uplink_frame(inputs.frame_seed(7, 0, 15), 21, 64, 8, 16, 15.0)
+    s, h = run_detect(fr, 4, 4, "admm", reg=reg)
+    ref = oracle_detect(fr, 4, 4, "admm", reg=reg)
+    assert rel_err(s, ref) <= 1e-5
+    check_hard(s, h, ref, 16)
+
+
+def test_cg_zf():
+    say("[gpu] cg zf")
+    fr = inputs.uplink_frame(inputs.frame_seed(7, 1, 15), 13, 64, 8, 16, 15.0)
+    s, h = run_detect(fr, 4, 4, "cg", reg="zf")
+    ref = oracle_detect(fr, 4, 4, "cg", reg="zf")
+    assert rel_err(s, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("B,U,C", [(64, 16, 4), (128, 32, 4), (512, 64, 8), (128, 8, 16), (96, 8, 3)])
+@pytest.mark.parametrize("algo", ["admm", "cg"])
+def test_shapes(B, U, C, algo):
+    say(f"[gpu] shape B={B} U={U} C={C} {algo}")
+    fr = inputs.uplink_frame(inputs.frame_seed(8, B + U + C, 10), 11, B, U, 16, 10.0)
+    s, h = run_detect(fr, C, 3, algo)
+    ref = oracle_detect(fr, C, 3, algo)
+    assert rel_err(s, ref) <= 1e-5
+
+
+def test_multi_symbol_reuse():
+    """N_sym = 3 receive vectors share one channel (and one factorisation)."""
+    say("[gpu] n_sym=3")
+    fr = inputs.uplink_frame(inputs.frame_seed(9, 0, 10), 10, 128, 16, 16, 10.0, n_sym=3)
+    for algo in ("admm", "cg"):
+        s, h = run_detect(fr, 8, 4, algo)
+        ref = oracle_detect(fr, 8, 4, algo)
+        assert rel_err(s, ref) <= 1e-5
+
+
+def test_T1_and_C1():
+    say("[gpu] T=1, C=1")
+    fr = inputs.uplink_frame(inputs.frame_seed(9, 1, 10), 7, 32, 8, 4, 10.0)
+    for C, T in ((1, 1), (1, 4), (4, 1)):
+        s, _ = run_detect(fr, C, T, "admm")
+        assert rel_err(s, oracle_detect(fr, C, T, "admm")) <= 1e-5
+        s, _ = run_detect(fr, C, T, "cg")
+        assert rel_err(s, oracle_detect(fr, C, T, "cg")) <= 1e-5
+
+
+def test_empty_batch():
+    H = torch.zeros((0, 64, 8), dtype=torch.complex64, device=DEV)
+    y = torch.zeros((0, 1, 64), dtype=torch.complex64, device=DEV)
+    s, h = api.detect(H, y, 0.1, 4, 1.0, 3)
+    assert s.shape == (0, 1, 8)
+
+
+def test_launch_shape_independence():
+    """Same inputs as one batch or split in pieces give identical bits."""
+    say("[gpu] tiling independence")
+    fr = inputs.uplink_frame(inputs.frame_seed(10, 0, 10), 33, 128, 16, 16, 10.0)
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    full, _ = api.detect(H, y, fr.N0, 8, 1.0, 5)
+    parts = [api.detect(H[i:i + 7].contiguous(), y[i:i + 7].contiguous(), fr.N0, 8, 1.0, 5)[0] for i in range(0, 33, 7)]
+    torch.cuda.synchronize()
+    assert torch.equal(full, torch.cat(parts))
+
+
+# -- configuration 3: downlink B=256, C=16 (S=16), U=32, 64-QAM targets, T=5, power budgets
+@pytest.mark.parametrize("budget", [False, True])
+def test_cfg3_precode(budget):
+    say(f"[gpu] cfg3 precode budget={budget}")
+    B, U, C = 256, 32, 16
+    fr = inputs.downlink_frame(inputs.frame_seed(3, 0, 0), 37, B, U, 64)
+    H, s = to_dev(fr.H), to_dev(fr.s)
+    P = None
+    Pc = [(B // C) / B * U * 1.0] * C
+    if budget:
+        P = torch.tensor(Pc, dtype=torch.float32, device=DEV)
+    x, beta = api.precode(H, s, C, 1.0, 5, P_cluster=P)
+    torch.cuda.synchronize()
+    x, beta = x.cpu().numpy(), beta.cpu().numpy()
+    ref = O.admm_dl_frame(fr.H, fr.s, C, 1.0, 5)
+    if budget:
+        refb = np.zeros_like(beta, dtype=np.float64)
+        for k in range(ref.shape[0]):
+            ref[k, 0], refb[k, 0] = O.power_scale(ref[k, 0], C, Pc)
+        assert np.abs(beta - refb).max() <= 1e-5
+        assert np.any(refb < 1.0)
+    else:
+        assert np.all(beta == 1.0)
+    assert rel_err(x, ref) <= 1e-5
+    assert per_vec_rel(x, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("B,U,C", [(64, 8, 8), (128, 16, 8), (256, 32, 8), (64, 16, 8), (256, 64, 8)])
+def test_precode_shapes(B, U, C):
+    say(f"[gpu] precode B={B} U={U} C={C}")
+    fr = inputs.downlink_frame(inputs.frame_seed(11, B + U, C), 9, B, U, 16)
+    x, _ = api.precode(to_dev(fr.H), to_dev(fr.s), C, 1.0, 4)
+    torch.cuda.synchronize()
+    ref = O.admm_dl_frame(fr.H, fr.s, C, 1.0, 4)
+    assert rel_err(x.cpu().numpy(), ref) <= 1e-5
