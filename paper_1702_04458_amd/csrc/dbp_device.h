@@ -82,37 +82,48 @@ __device__ __forceinline__ float group_min(float v) {
 }
 
 // In-place inversion of the Hermitian positive definite matrix whose row u is
-// held by lane u of the group (A[v] = M[u][v]), by Gauss-Jordan elimination
-// without pivoting (the pivots of an HPD matrix are positive Schur
-// complements).  Only the first n pivots are swept: a block-diagonal
-// [M_n 0; 0 I] stays block-diagonal, so groups may pad a smaller system with
-// identity rows.  Row k of the partially swept matrix equals the conjugate of
-// column k with the sign flipped on already-swept columns, so a single column
-// broadcast per step suffices.
+// held by lane u of the group, by Gauss-Jordan elimination without pivoting
+// (the pivots of an HPD matrix are positive Schur complements).  Block-diagonal
+// padding [M 0; 0 I] stays block-diagonal, so groups may pad a smaller system
+// with identity rows.
+//
+// Register layout is rotated so that every register index is a compile-time
+// constant while the pivot loop stays rolled: before step k, slot j of a row
+// holds column (k + j) mod G; the pivot column is always slot 0, and after the
+// step the row shifts left by one slot with the new pivot-column entry
+// appended.  After G steps the natural order is restored.
+//
+// Row k of the partially swept matrix is the conjugate of column k, with the
+// sign flipped on columns already swept; each lane publishes its entry of the
+// pivot column already conjugated and signed, at the rotated position of the
+// column it stands for, so one broadcast line per step gives row k in slot
+// order.
 template <int G>
-__device__ __forceinline__ void gj_invert(c32 (&A)[G], int u, int n, c32* line, int gbase) {
-#pragma unroll
+__device__ __forceinline__ void gj_invert(c32 (&A)[G], int u, c32* line, int gbase) {
   for (int k = 0; k < G; ++k) {
-    if (k < n) {
-      line[gbase + u] = A[k];
-      wave_lds_sync();
-      c32 col[G];
-      lds_read_vec<G>(line + gbase, col);
-      wave_lds_sync();
-      const float p = 1.0f / col[k].re;
-      const bool me = (u == k);
-      const c32 m = c32{A[k].re * p, A[k].im * p};
+    const float sg = (u < k) ? -1.f : 1.f;
+    // lanes past the matrix (a group wider than G) must not publish
+    if (u < G) line[gbase + ((u - k) & (G - 1))] = c32{sg * A[0].re, -sg * A[0].im};
+    wave_lds_sync();
+    const float p = 1.0f / line[gbase].re;
+    const bool me = (u == k);
+    const c32 m = me ? c32{-p, 0.f} : c32{A[0].re * p, A[0].im * p};
+    const c32 pivot_new = me ? c32{p, 0.f} : c32{-m.re, -m.im};
 #pragma unroll
-      for (int v = 0; v < G; ++v) {
-        if (v == k) continue;
-        // row k entry v
-        c32 rk = (v < k) ? c32{-col[v].re, col[v].im} : c32{col[v].re, -col[v].im};
-        c32 upd = A[v];
-        cmsub(upd, m, rk);
-        A[v] = me ? cscale(rk, p) : upd;
+    for (int j0 = 0; j0 < G; j0 += 8) {
+      c32 rk[8];
+      lds_read_vec<8>(line + gbase + j0, rk);
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const int j = j0 + jj;
+        if (j == 0) continue;
+        c32 base = me ? cz() : A[j];
+        cmsub(base, m, rk[jj]);
+        A[j - 1] = base;
       }
-      A[k] = me ? c32{p, 0.f} : c32{-m.re, -m.im};
     }
+    A[G - 1] = pivot_new;
+    wave_lds_sync();
   }
 }
 

@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
 #pragma unroll
   for (int v = 0; v < G; ++v)
     if (v == u) A[v].re += a.rho;
-  gj_invert<G>(A, u, G, line, gbase);
+  gj_invert<G>(A, u, line, gbase);
 
   int buf = 0;
   for (int n = 0; n < a.n_sym; ++n) {
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
 #pragma unroll
   for (int v = 0; v < SG; ++v)
     if (v == u) A[v].re += (u < S) ? irho : 1.0f;
-  gj_invert<SG>(A, u, S, line, gbase);
+  gj_invert<SG>(A, u, line, gbase);
 
   int buf = 0;
   for (int n = 0; n < a.n_sym; ++n) {
