@@ -151,7 +151,22 @@ def main():
     ap.add_argument("--frames", type=int, default=0, help="distinct resident frames (0: enough for >= 2 GB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--n-sc", type=int, default=0, help="subcarriers per step (default: one 1200-subcarrier frame)")
+    ap.add_argument("--T", type=int, default=0, help="override the iteration count of the workload")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="run only a plain device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_bytes:
+        import torch
+
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes, "launches": max(1, args.steps)}), flush=True)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -163,6 +178,10 @@ def main():
     from paper_1702_04458_amd import api
 
     algo, B, U, C, qam, snr, T, n_sc = WORKLOADS[args.workload]
+    if args.n_sc:
+        n_sc = args.n_sc
+    if args.T:
+        T = args.T
     bytes_vec = algorithmic_bytes(algo, B, U, C)
     flops_vec = algorithmic_flops(algo, B, U, C, T)
     frame_bytes = n_sc * (8 * B * U + 8 * B)

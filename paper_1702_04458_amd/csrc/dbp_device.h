@@ -133,15 +133,18 @@ template <int G>
 __device__ __forceinline__ c32 group_matvec(const c32 (&A)[G], c32 q, int u, c32* line, int gbase) {
   line[gbase + u] = q;
   wave_lds_sync();
-  c32 qv[G];
-  lds_read_vec<G>(line + gbase, qv);
-  wave_lds_sync();
   c32 acc0 = cz(), acc1 = cz();
 #pragma unroll
-  for (int v = 0; v < G; v += 2) {
-    cmac(acc0, A[v], qv[v]);
-    cmac(acc1, A[v + 1], qv[v + 1]);
+  for (int v0 = 0; v0 < G; v0 += 8) {
+    c32 qv[8];
+    lds_read_vec<8>(line + gbase + v0, qv);
+#pragma unroll
+    for (int v = 0; v < 8; v += 2) {
+      cmac(acc0, A[v0 + v], qv[v]);
+      cmac(acc1, A[v0 + v + 1], qv[v + 1]);
+    }
   }
+  wave_lds_sync();
   (void)u;
   return cadd(acc0, acc1);
 }

@@ -89,6 +89,169 @@ __device__ __forceinline__ c32 cluster_pass(const c32* __restrict__ H, const c32
   return hy;
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Regularised inverse on the matrix cores, for the two Gram matrices of a wave
+// held in the 32x32 accumulator layout (lane l: column l%32, rows
+// 8(r/4) + 4(l/32) + r%4).  Gauss-Jordan elimination of the HPD matrix
+// B = G + rho I, where every pivot step k is a complex rank-1 update
+// S -= m (x) row_k, issued as two v_mfma_f32_32x32x2f32 (real part with
+// operands [-Re m, Im m] x [Re row; Im row], imaginary part with
+// [-Re m, -Im m] x [Im row; Re row]).  The multipliers m_i = B[i][k] / B[k][k]
+// come from row k through the signed Hermitian symmetry of the partially swept
+// matrix (entry (i, k) is the conjugate of entry (k, i), negated when exactly
+// one of i, k has been swept).  The swept pivot column is not rewritten: each
+// column carries a scale factor sigma_j (true = stored * sigma_j), and the new
+// column k is the old one times -1/B[k][k], so only sigma_k changes.  Row k is
+// rescaled in place.  The result is multiplied out by sigma at the end.
+__device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)[2], int lane, float rho) {
+  const int h = lane >> 5, col = lane & 31;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r / 4) + 4 * h + (r % 4);
+    const float add = (i == col) ? rho : 0.f;
+    re[0][r] += add;
+    re[1][r] += add;
+  }
+  const float hs = h ? 1.f : -1.f;
+  float sig[2] = {1.f, 1.f};
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const int rr = 4 * (k / 8) + (k % 4);   // register holding row k
+    const int hk = (k / 4) & 1;             // lane half holding row k
+    const bool isk = (col == k);
+    const bool rowk_here = (h == hk);
+    // multiplier sign: -1 for swept rows (col < k), 0 for the pivot row itself
+    const float f = (col < k) ? -1.f : (isk ? 0.f : 1.f);
+    const float mk = isk ? 0.f : 1.f;
+    const float g = (rowk_here && isk) ? -1.f : 0.f;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const float sr = re[p][rr], si = im[p][rr];
+      // row k at column col, arranged for the operands: lanes < 32 get
+      // (first, second) = (Re, Im), lanes >= 32 get (Im, Re)
+      const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(sr), __float_as_uint(si), false, false);
+      const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(si), __float_as_uint(sr), false, false);
+      const float first = __uint_as_float(fs[hk]);
+      const float second = __uint_as_float(sf[hk]);
+      const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sr), k + 32 * hk));
+      const float pv = __builtin_amdgcn_rcpf(d);
+      const float c = f * pv * sig[p];          // m_col = c * conj(stored row k entry)
+      const float Are = -c * first;             // lanes < 32: -Re m, lanes >= 32: Im m
+      const float Aim = (hs * c) * first;       // lanes < 32: -Re m, lanes >= 32: -Im m
+      const float Bre = mk * first, Bim = mk * second;
+      // row k <- row k / B[k][k]; the diagonal becomes 1/B[k][k], stored as -1
+      // under sigma_k = -1/B[k][k]
+      const float fr = rowk_here ? pv * mk : 1.f;
+      re[p][rr] = fmaf(sr, fr, g);
+      im[p][rr] = si * fr;
+      re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are, Bre, re[p], 0, 0, 0);
+      im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim, Bim, im[p], 0, 0, 0);
+      sig[p] = isk ? -pv : sig[p];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      re[p][r] *= sig[p];
+      im[p][r] *= sig[p];
+    }
+  }
+}
+
+// Gram matrices of the two problems of a wave (U = 32, P = 2) on the matrix
+// cores with v_mfma_f32_32x32x2f32, K running over pairs of antenna rows:
+//   Re G = sum_s Hr[s]^T Hr[s] + Hi[s]^T Hi[s],
+//   Im G = sum_s Hr[s]^T Hi[s] - Hi[s]^T Hr[s].
+// For the Gram of one problem lane l supplies H[s0 + l/32][l%32] as both the A
+// and the B operand.  The 32x32 result leaves lane l holding column l%32 for
+// rows 8(r/4) + 4(l/32) + r%4 (r = 0..15); by Hermitian symmetry that is row
+// l%32 conjugated, for half h = l/32 of the columns.  With INVERT the
+// accumulators are replaced by (G + rho I)^{-1} on the matrix cores first.
+// One exchange between lanes l and l^32 then gives every lane the full row of
+// its own problem (lane-row layout, problem = l/32).  Returns row u of
+// H_c^H y_c for symbol 0.
+template <bool INVERT>
+__device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave) {
+  const int h = lane >> 5, col = lane & 31;
+  f32x16 re[2], im[2];
+  c32 hyp[2];
+  const c32* Hp[2];
+  const c32* yp[2];
+  bool act[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int lp = wave * 2 + p;
+    const int ls = lp / a.Cp, c = lp % a.Cp;
+    const int k = blockIdx.x * a.sc_per_block + ls;
+    act[p] = (k < a.n_sc) && (c < a.C);
+    Hp[p] = a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32;
+    yp[p] = a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S;
+    re[p] = f32x16{};
+    im[p] = f32x16{};
+    hyp[p] = cz();
+  }
+  // Software pipeline: the loads of the next CH row pairs are in flight while
+  // the MFMAs of the current ones run.
+  constexpr int CH = 2;
+  c32 hv[2][CH], yv[2][CH], hn[2][CH], yn[2][CH];
+  auto fetch = [&](int s0, c32 (&hd)[2][CH], c32 (&yd)[2][CH]) {
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int s = s0 + 2 * q + h;
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const bool ok = act[p] && s < a.S;
+        hd[p][q] = ok ? Hp[p][(size_t)s * 32 + col] : cz();
+        yd[p][q] = ok ? yp[p][s] : cz();
+      }
+    }
+  };
+  fetch(0, hv, yv);
+  for (int s0 = 0; s0 < a.S; s0 += 2 * CH) {
+    if (s0 + 2 * CH < a.S) fetch(s0 + 2 * CH, hn, yn);
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const c32 x = hv[p][q];
+        re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, x.re, re[p], 0, 0, 0);
+        re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, x.im, re[p], 0, 0, 0);
+        im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, x.im, im[p], 0, 0, 0);
+        im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(-x.im, x.re, im[p], 0, 0, 0);
+        cmacc(hyp[p], x, yv[p][q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        hv[p][q] = hn[p][q];
+        yv[p][q] = yn[p][q];
+      }
+  }
+  if (INVERT) gj_invert_mfma_u32(re, im, lane, a.rho);
+  // exchange halves: lanes < 32 keep problem 0, lanes >= 32 keep problem 1
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m0 = 8 * (r / 4) + (r % 4);      // column of this slot in half 0
+    const float sr = h ? re[0][r] : re[1][r];
+    const float si = h ? im[0][r] : im[1][r];
+    const float tr = __shfl_xor(sr, 32, 64);
+    const float ti = __shfl_xor(si, 32, 64);
+    const float h0r = h ? tr : re[0][r], h0i = h ? ti : im[0][r];
+    const float h1r = h ? re[1][r] : tr, h1i = h ? im[1][r] : ti;
+    A[m0] = c32{h0r, -h0i};
+    A[m0 + 4] = c32{h1r, -h1i};
+  }
+  const c32 send = h ? hyp[0] : hyp[1];
+  const c32 got = c32{__shfl_xor(send.re, 32, 64), __shfl_xor(send.im, 32, 64)};
+  const c32 mine = h ? hyp[1] : hyp[0];
+  // rows of parity 0 first, then parity 1 (same order on every lane)
+  return h ? cadd(got, mine) : cadd(mine, got);
+}
+
 // Consensus: every lane of cluster c writes its entry of w_c into its slot;
 // after the barrier each lane sums the C clusters of its subcarrier in cluster
 // order 1..C (identical sum on every cluster, as if broadcast by the fusion
@@ -127,12 +290,16 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   c32 A[G];
 #pragma unroll
   for (int v = 0; v < G; ++v) A[v] = cz();
-  c32 hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G,
-                                  a.n_sym, sm);
+  c32 hy0;
+  if constexpr (G == 32) {
+    hy0 = gram_mfma_u32<true>(a, A, lane, wave);
+  } else {
+    hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 #pragma unroll
-  for (int v = 0; v < G; ++v)
-    if (v == u) A[v].re += a.rho;
-  gj_invert<G>(A, u, line, gbase);
+    for (int v = 0; v < G; ++v)
+      if (v == u) A[v].re += a.rho;
+    gj_invert<G>(A, u, line, gbase);
+  }
 
   int buf = 0;
   for (int n = 0; n < a.n_sym; ++n) {
@@ -200,7 +367,11 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   c32 A[G];
 #pragma unroll
   for (int v = 0; v < G; ++v) A[v] = cz();
-  c32 hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
+  c32 hy0;
+  if constexpr (G == 32)
+    hy0 = gram_mfma_u32<false>(a, A, lane, wave);
+  else
+    hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 
   int buf = 0;
   for (int n = 0; n < a.n_sym; ++n) {
