@@ -91,11 +91,11 @@ def make_frames(n_frames, algo, B, U, qam, snr_db, n_sc, seed):
     return frames, N0
 
 
-def run_step(api, frame, algo, C, T, N0, qam, out):
+def run_step(api, frame, algo, C, T, N0, qam, out, prec="fp32", factor=None):
     if algo == "dl":
         api.precode(frame[0], frame[1], C, 1.0, T, out=out)
     else:
-        api.detect(frame[0], frame[1], N0, C, 1.0, T, algo=algo, qam=qam, out=out)
+        api.detect(frame[0], frame[1], N0, C, 1.0, T, algo=algo, qam=qam, out=out, prec=prec, factor=factor)
 
 
 def _oracle_worker(args):
@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--n-sc", type=int, default=0, help="subcarriers per step (default: one 1200-subcarrier frame)")
     ap.add_argument("--T", type=int, default=0, help="override the iteration count of the workload")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--factor", default=None, choices=["auto", "fp32", "fp64"])
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run only a plain device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -198,7 +200,7 @@ def main():
     torch.cuda.synchronize()
 
     for i in range(args.warmup):
-        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out)
+        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out, args.prec, args.factor)
     torch.cuda.synchronize()
     print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
@@ -211,7 +213,7 @@ def main():
     start_all.record(stream)
     for i in range(args.steps):
         ev[i][0].record(stream)
-        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out)
+        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out, args.prec, args.factor)
         ev[i][1].record(stream)
     end_all.record(stream)
     torch.cuda.synchronize()
@@ -262,7 +264,7 @@ def main():
             "workload": args.workload,
             "algorithm": {"admm": "Algorithm 1 (ADMM-UL)", "cg": "Algorithm 2 (CG-UL)", "dl": "Algorithm 3 (ADMM-DL)"}[algo],
             "B": B, "U": U, "C": C, "S": B // C, "n_sc": n_sc, "n_sym": 1, "T": T, "rho": 1.0, "qam": qam,
-            "snr_db": snr, "precision": "fp32", "frames_resident": n_frames,
+            "snr_db": snr, "precision": args.prec, "factor": args.factor or "auto", "frames_resident": n_frames,
             "p50_frame_latency_us": round(p50 * 1e3, 2), "p99_frame_latency_us": round(p99 * 1e3, 2),
         },
         "roofline": roof,

@@ -12,6 +12,7 @@ from . import _native
 
 REG = {"mmse": 0, "zf": 1, "box": 2}
 PREC = {"fp32": 0, "fp16": 1, "bf16": 2, "mixed_fp16": 1, "mixed_bf16": 2}
+FACTOR = {None: 0, "auto": 0, "fp32": 0x10, "fp64": 0x20}
 
 
 def _dev(t: torch.Tensor, name: str, dtype=torch.complex64) -> torch.Tensor:
@@ -45,11 +46,13 @@ def _shapes(H, y):
 
 
 def detect(H, y, N0, C, rho=1.0, T=5, *, algo="admm", reg="mmse", qam=16, Es=1.0, gamma=1.0,
-           prec="fp32", hard=True, out=None, stream=None):
+           prec="fp32", factor=None, hard=True, out=None, stream=None):
     """Decentralized uplink detection.
 
     ``algo="admm"`` runs Algorithm 1 (``rho`` is the ADMM penalty),
     ``algo="cg"`` runs Algorithm 2 (regulariser N0/Es, ``rho`` unused).
+    ``prec`` selects the Gram arithmetic ("fp32", "fp16", "bf16"); in the mixed
+    modes ``factor`` ("auto", "fp32", "fp64") selects the inverse's precision.
     Returns ``(s_hat [n_sc, n_sym, U] complex64, hard [n_sc, n_sym, U] uint8 or None)``.
     """
     _dev(H, "H")
@@ -65,7 +68,8 @@ def detect(H, y, N0, C, rho=1.0, T=5, *, algo="admm", reg="mmse", qam=16, Es=1.0
     hp = hd.data_ptr() if hd is not None else None
     if algo == "admm":
         code = L.dbp_detect_admm(H.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hp, n_sc, n_sym, B, U, C, T,
-                                 float(rho), float(gamma), float(N0), float(Es), REG[reg], qam, PREC[prec], st)
+                                 float(rho), float(gamma), float(N0), float(Es), REG[reg], qam,
+                                 PREC[prec] | FACTOR[factor], st)
     elif algo == "cg":
         code = L.dbp_detect_cg(H.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hp, n_sc, n_sym, B, U, C, T,
                                float(N0), float(Es), REG[reg], qam, st)

@@ -118,11 +118,17 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
   if (reg < DBP_REG_MMSE || reg > DBP_REG_BOX) return fail(DBP_ERR_INVALID, "%s: reg=%d", who, reg);
   const int L = qam_side(qam);
   if (!L) return fail(DBP_ERR_INVALID, "%s: qam=%d not in {4,16,64}", who, qam);
-  if (prec < DBP_PREC_FP32 || prec > DBP_PREC_MIXED_BF16) return fail(DBP_ERR_INVALID, "%s: prec=%d", who, prec);
+  const int gram_prec = prec & 0xF, factor = prec & ~0xF;
+  if (gram_prec < DBP_PREC_FP32 || gram_prec > DBP_PREC_MIXED_BF16 ||
+      (factor != 0 && factor != DBP_FACTOR_FP32 && factor != DBP_FACTOR_FP64))
+    return fail(DBP_ERR_INVALID, "%s: prec=%d", who, prec);
   if (n_sc > 0 && (!H || !y || !s_hat)) return fail(DBP_ERR_INVALID, "%s: null H, y or s_hat", who);
   const int S = B / C;
   if (S < U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d < U=%d (S x S branch) not built", who, S, U);
-  if (prec != DBP_PREC_FP32) return fail(DBP_ERR_UNSUPPORTED, "%s: mixed precision not built yet", who);
+  if (gram_prec != DBP_PREC_FP32 && U != 32)
+    return fail(DBP_ERR_UNSUPPORTED, "%s: mixed precision is built for U=32 only", who);
+  if (gram_prec == DBP_PREC_FP32 && factor == DBP_FACTOR_FP64)
+    return fail(DBP_ERR_UNSUPPORTED, "%s: FP64 inverse is built for the mixed modes only", who);
   if (n_sc == 0) return ok();
 
   const Plan pl = make_plan(U, C);
@@ -148,7 +154,11 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
   a.invC = (float)(1.0 / C);
   a.box_r = (float)((L - 1) / std::sqrt(2.0 * (qam - 1) / 3.0));
   a.kappa = (float)std::sqrt(2.0 * (qam - 1) / 3.0);
-  return device_status(who, dbp::launch_admm_ul_f32(a, U, pl.nw, static_cast<hipStream_t>(stream)));
+  hipStream_t st_ = static_cast<hipStream_t>(stream);
+  if (gram_prec == DBP_PREC_FP32) return device_status(who, dbp::launch_admm_ul_f32(a, U, pl.nw, st_));
+  // FP64 inverse for poorly conditioned regularised Grams (aspect ratio U/S > 0.8)
+  const bool f64 = (factor == DBP_FACTOR_FP64) || (factor == 0 && 5 * U > 4 * S);
+  return device_status(who, dbp::launch_admm_ul_mixed(a, U, gram_prec, f64, pl.nw, st_));
 }
 
 int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int n_sc, int n_sym, int B, int U,

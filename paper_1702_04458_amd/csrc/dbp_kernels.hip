@@ -252,6 +252,223 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
   return h ? cadd(got, mine) : cadd(mine, got);
 }
 
+// ---------------------------------------------------------------------------
+// Mixed precision preprocessing for U = 32: the Gram on FP16 / BF16 matrix
+// cores with FP32 accumulation.  Each problem's H_c is scaled by a power of two
+// 2^e chosen from its largest entry (so its half-precision image uses the top
+// of the format; exact, undone on the FP32 Gram), then split as
+// H = H_hi + H_lo with H_hi = half(H) and H_lo = half(H - H_hi).  The Gram is
+// refined to near FP32 accuracy by accumulating the correction products:
+//   G ~ H_hi^H H_hi + H_hi^H H_lo + H_lo^H H_hi
+// (the dropped H_lo^H H_lo term is below FP32 rounding for FP16).  Every
+// v_mfma_f32_32x32x16 covers 16 real rows: lane l supplies column l%32 of the
+// 8 rows 8(l/32) .. 8(l/32)+7 of its 16-row chunk as both the A and the B
+// operand; the result uses the same 32x32 accumulator layout as the FP32 path.
+// ---------------------------------------------------------------------------
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename HT>
+struct HalfMma;
+template <>
+struct HalfMma<_Float16> {
+  typedef f16x8 V;
+  static __device__ __forceinline__ f32x16 mma(V x, V y, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, c, 0, 0, 0);
+  }
+};
+template <>
+struct HalfMma<__bf16> {
+  typedef bf16x8 V;
+  static __device__ __forceinline__ f32x16 mma(V x, V y, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <typename HT>
+__device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2], f32x16 (&im)[2], c32 (&hyp)[2],
+                                               int lane, int wave) {
+  typedef typename HalfMma<HT>::V V;
+  const int h = lane >> 5, col = lane & 31;
+  const c32* Hp[2];
+  const c32* yp[2];
+  bool act[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int lp = wave * 2 + p;
+    const int ls = lp / a.Cp, c = lp % a.Cp;
+    const int k = blockIdx.x * a.sc_per_block + ls;
+    act[p] = (k < a.n_sc) && (c < a.C);
+    Hp[p] = a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32;
+    yp[p] = a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S;
+    re[p] = f32x16{};
+    im[p] = f32x16{};
+    hyp[p] = cz();
+  }
+  // pass 1: largest |Re|, |Im| of each problem -> scale exponent
+  int ex[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    float m = 0.f;
+    for (int s0 = 0; s0 < a.S; s0 += 16) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int s = s0 + 8 * h + t;
+        const c32 v = (act[p] && s < a.S) ? Hp[p][(size_t)s * 32 + col] : cz();
+        m = fmaxf(m, fmaxf(fabsf(v.re), fabsf(v.im)));
+      }
+    }
+    m = wave_max(m);
+    int x = 0;
+    if (m > 0.f) frexpf(m, &x);      // m < 2^x
+    ex[p] = 14 - x;                  // scaled entries stay below 2^14
+  }
+  // pass 2: split and accumulate
+  for (int s0 = 0; s0 < a.S; s0 += 16) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      c32 v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int s = s0 + 8 * h + t;
+        const bool ok = act[p] && s < a.S;
+        v[t] = ok ? Hp[p][(size_t)s * 32 + col] : cz();
+        const c32 yv = ok ? yp[p][s] : cz();
+        cmacc(hyp[p], v[t], yv);
+      }
+      V rh, rl, ih, il, nih, nil;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float xr = ldexpf(v[t].re, ex[p]), xi = ldexpf(v[t].im, ex[p]);
+        const HT hr = (HT)xr, hi = (HT)xi;
+        rh[t] = hr;
+        rl[t] = (HT)(xr - (float)hr);
+        ih[t] = hi;
+        il[t] = (HT)(xi - (float)hi);
+        nih[t] = -ih[t];
+        nil[t] = -il[t];
+      }
+      // Re G = Hr^T Hr + Hi^T Hi
+      re[p] = HalfMma<HT>::mma(rh, rh, re[p]);
+      re[p] = HalfMma<HT>::mma(rh, rl, re[p]);
+      re[p] = HalfMma<HT>::mma(rl, rh, re[p]);
+      re[p] = HalfMma<HT>::mma(ih, ih, re[p]);
+      re[p] = HalfMma<HT>::mma(ih, il, re[p]);
+      re[p] = HalfMma<HT>::mma(il, ih, re[p]);
+      // Im G = Hr^T Hi - Hi^T Hr
+      im[p] = HalfMma<HT>::mma(rh, ih, im[p]);
+      im[p] = HalfMma<HT>::mma(rh, il, im[p]);
+      im[p] = HalfMma<HT>::mma(rl, ih, im[p]);
+      im[p] = HalfMma<HT>::mma(nih, rh, im[p]);
+      im[p] = HalfMma<HT>::mma(nih, rl, im[p]);
+      im[p] = HalfMma<HT>::mma(nil, rh, im[p]);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      re[p][r] = ldexpf(re[p][r], -2 * ex[p]);
+      im[p][r] = ldexpf(im[p][r], -2 * ex[p]);
+    }
+  }
+}
+
+// Accumulator layout -> lane-row layout (lanes < 32: problem 0, >= 32: problem 1)
+__device__ __forceinline__ void acc_to_rows_u32(const f32x16 (&re)[2], const f32x16 (&im)[2], c32 (&A)[32], int h) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m0 = 8 * (r / 4) + (r % 4);
+    const float sr = h ? re[0][r] : re[1][r];
+    const float si = h ? im[0][r] : im[1][r];
+    const float tr = __shfl_xor(sr, 32, 64);
+    const float ti = __shfl_xor(si, 32, 64);
+    const float h0r = h ? tr : re[0][r], h0i = h ? ti : im[0][r];
+    const float h1r = h ? re[1][r] : tr, h1i = h ? im[1][r] : ti;
+    A[m0] = c32{h0r, -h0i};
+    A[m0 + 4] = c32{h1r, -h1i};
+  }
+}
+
+__device__ __forceinline__ c32 combine_hy(const c32 (&hyp)[2], int h) {
+  const c32 send = h ? hyp[0] : hyp[1];
+  const c32 got = c32{__shfl_xor(send.re, 32, 64), __shfl_xor(send.im, 32, 64)};
+  const c32 mine = h ? hyp[1] : hyp[0];
+  return h ? cadd(got, mine) : cadd(mine, got);
+}
+
+// Regularised inverse in FP64 on the VALU (lane-row layout, rotated
+// Gauss-Jordan as in gj_invert), for the poorly conditioned case U/S > 0.8.
+struct c64 {
+  double re, im;
+};
+
+template <int G>
+__device__ __forceinline__ void gj_invert64(c64 (&A)[G], int u, c64* line) {
+  for (int k = 0; k < G; ++k) {
+    const double sg = (u < k) ? -1.0 : 1.0;
+    line[(u - k) & (G - 1)] = c64{sg * A[0].re, -sg * A[0].im};
+    wave_lds_sync();
+    const double p = 1.0 / line[0].re;
+    const bool me = (u == k);
+    const c64 m = me ? c64{-p, 0.0} : c64{A[0].re * p, A[0].im * p};
+    const c64 pivot_new = me ? c64{p, 0.0} : c64{-m.re, -m.im};
+#pragma unroll
+    for (int j0 = 0; j0 < G; j0 += 4) {
+      c64 rk[4];
+      const double2* q = reinterpret_cast<const double2*>(line + j0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double2 t = q[i];
+        rk[i] = c64{t.x, t.y};
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = j0 + jj;
+        if (j == 0) continue;
+        c64 base = me ? c64{0.0, 0.0} : A[j];
+        base.re = fma(-m.re, rk[jj].re, base.re);
+        base.re = fma(m.im, rk[jj].im, base.re);
+        base.im = fma(-m.re, rk[jj].im, base.im);
+        base.im = fma(-m.im, rk[jj].re, base.im);
+        A[j - 1] = base;
+      }
+    }
+    A[G - 1] = pivot_new;
+    wave_lds_sync();
+  }
+}
+
+// Mixed-precision Gram + regularised inverse for U = 32; returns row u of
+// H_c^H y_c and leaves row u of (G + rho I)^{-1} in A.
+template <typename HT, bool F64>
+__device__ __forceinline__ c32 gram_inv_mixed_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave, c64* line64) {
+  const int h = lane >> 5;
+  f32x16 re[2], im[2];
+  c32 hyp[2];
+  gram_split_u32<HT>(a, re, im, hyp, lane, wave);
+  if (!F64) {
+    gj_invert_mfma_u32(re, im, lane, a.rho);
+    acc_to_rows_u32(re, im, A, h);
+  } else {
+    acc_to_rows_u32(re, im, A, h);
+    const int u = lane & 31;
+    c64 D[32];
+#pragma unroll
+    for (int v = 0; v < 32; ++v) D[v] = c64{(double)A[v].re + ((v == u) ? (double)a.rho : 0.0), (double)A[v].im};
+    gj_invert64<32>(D, u, line64 + h * 32);
+#pragma unroll
+    for (int v = 0; v < 32; ++v) A[v] = c32{(float)D[v].re, (float)D[v].im};
+  }
+  return combine_hy(hyp, h);
+}
+
 // Consensus: every lane of cluster c writes its entry of w_c into its slot;
 // after the barrier each lane sums the C clusters of its subcarrier in cluster
 // order 1..C (identical sum on every cluster, as if broadcast by the fusion
@@ -270,7 +487,9 @@ __device__ __forceinline__ c32 consensus(c32 wc, int buf, int ls, int G, int u, 
 // ---------------------------------------------------------------------------
 // Algorithm 1, U x U branch (S >= U), FP32.  Group size G = U.
 // ---------------------------------------------------------------------------
-template <int G>
+// MODE: 0 FP32; 1 / 2 mixed FP16 / BF16 Gram with an FP32 (MFMA) inverse;
+// 3 / 4 the same with an FP64 inverse.  Mixed modes exist for U = 32 only.
+template <int G, int MODE>
 __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   constexpr int P = 64 / G;
   extern __shared__ float4 smem_raw[];
@@ -291,8 +510,12 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
 #pragma unroll
   for (int v = 0; v < G; ++v) A[v] = cz();
   c32 hy0;
-  if constexpr (G == 32) {
+  if constexpr (G == 32 && MODE == 0) {
     hy0 = gram_mfma_u32<true>(a, A, lane, wave);
+  } else if constexpr (G == 32 && (MODE == 1 || MODE == 3)) {
+    hy0 = gram_inv_mixed_u32<_Float16, MODE == 3>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
+  } else if constexpr (G == 32 && (MODE == 2 || MODE == 4)) {
+    hy0 = gram_inv_mixed_u32<__bf16, MODE == 4>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
   } else {
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 #pragma unroll
@@ -552,12 +775,18 @@ static hipError_t launch(K kernel, const Args& a, int nw, hipStream_t st) {
 
 hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st) {
   switch (U) {
-    case 8: return launch(admm_ul_f32<8>, a, nw, st);
-    case 16: return launch(admm_ul_f32<16>, a, nw, st);
-    case 32: return launch(admm_ul_f32<32>, a, nw, st);
-    case 64: return launch(admm_ul_f32<64>, a, nw, st);
+    case 8: return launch(admm_ul_f32<8, 0>, a, nw, st);
+    case 16: return launch(admm_ul_f32<16, 0>, a, nw, st);
+    case 32: return launch(admm_ul_f32<32, 0>, a, nw, st);
+    case 64: return launch(admm_ul_f32<64, 0>, a, nw, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, bool f64, int nw, hipStream_t st) {
+  if (U != 32) return hipErrorInvalidValue;
+  if (half == 1) return f64 ? launch(admm_ul_f32<32, 3>, a, nw, st) : launch(admm_ul_f32<32, 1>, a, nw, st);
+  return f64 ? launch(admm_ul_f32<32, 4>, a, nw, st) : launch(admm_ul_f32<32, 2>, a, nw, st);
 }
 
 hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st) {

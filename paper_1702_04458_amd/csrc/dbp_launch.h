@@ -38,6 +38,7 @@ struct DlArgs {
 
 size_t smem_bytes(int nw);
 hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
+hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, bool f64, int nw, hipStream_t st);
 hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
 hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st);
 

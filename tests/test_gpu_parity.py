@@ -251,3 +251,48 @@ def test_precode_shapes(B, U, C):
     torch.cuda.synchronize()
     ref = O.admm_dl_frame(fr.H, fr.s, C, 1.0, 4)
     assert rel_err(x.cpu().numpy(), ref) <= 1e-5
+
+
+# -- mixed precision (split FP16 / BF16 Gram on the matrix cores), U = 32.
+# Bar: frame-level relative error <= 1e-3 and hard decisions as above; the FP16
+# split is expected to be close to the FP32 path, BF16 looser.
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("C,factor", [(8, "auto"), (8, "fp32"), (4, "auto"), (4, "fp64")])
+def test_mixed_headline_shape(prec, C, factor):
+    say(f"[gpu] mixed prec={prec} C={C} factor={factor}")
+    fr = inputs.uplink_frame(inputs.frame_seed(6, 10 + C, 25), 41, 256, 32, 64, 25.0)
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    s, h = api.detect(H, y, fr.N0, C, 1.0, 5, qam=64, prec=prec, factor=factor)
+    torch.cuda.synchronize()
+    s, h = s.cpu().numpy(), h.cpu().numpy()
+    ref = O.admm_ul_frame(fr.H, fr.y, C, 1.0, 5, fr.N0)
+    err = rel_err(s, ref)
+    say(f"    rel_err={err:.2e}")
+    assert err <= (1e-5 if prec == "fp16" else 1e-3)
+    check_hard(s, h, ref, 64)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_mixed_correlated_channel(prec):
+    say(f"[gpu] mixed correlated prec={prec}")
+    fr = inputs.uplink_frame(inputs.frame_seed(4, 1, 25), 23, 256, 32, 64, 25.0, corr=0.7)
+    s, h = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, 8, 1.0, 5, qam=64, prec=prec)
+    torch.cuda.synchronize()
+    ref = O.admm_ul_frame(fr.H, fr.y, 8, 1.0, 5, fr.N0)
+    assert rel_err(s.cpu().numpy(), ref) <= 1e-3
+    check_hard(s.cpu().numpy(), h.cpu().numpy(), ref, 64)
+
+
+@pytest.mark.parametrize("prec,factor", [("fp32", None), ("fp16", "auto"), ("bf16", "fp32")])
+def test_power_of_two_scaling_bit_exact(prec, factor):
+    """(H, y, N0, rho) -> (2^k H, 2^k y, 4^k N0, 4^k rho) leaves the output bits
+    unchanged: every step scales exactly, including the mixed path's
+    per-cluster power-of-two normalisation."""
+    say(f"[gpu] scaling invariance prec={prec}")
+    fr = inputs.uplink_frame(inputs.frame_seed(12, 0, 15), 17, 256, 32, 64, 15.0)
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    s0, h0 = api.detect(H, y, fr.N0, 8, 1.0, 5, qam=64, prec=prec, factor=factor)
+    s1, h1 = api.detect(H * 4.0, y * 4.0, fr.N0 * 16.0, 8, 16.0, 5, qam=64, prec=prec, factor=factor)
+    torch.cuda.synchronize()
+    assert torch.equal(s0, s1)
+    assert torch.equal(h0, h1)
