@@ -142,6 +142,176 @@ def cpu_baseline(algo, B, U, C, qam, snr, T, budget_s=12.0):
                       f"{workers} worker processes x {budget_s:.0f} s, FP64 numpy oracle; wall {wall:.1f} s"}
 
 
+def serve_bench(loads=(0.25, 0.5, 0.7, 0.85, 0.95), frames_per_load=300, pool=40, n_slots=8,
+                budget_gb=32.0, seed=99, log=sys.stderr):
+    """Continuous-batching serving run: Poisson arrivals of uplink frames whose
+    (B, U, C) is uniform over the valid triples with U <= S = B/C, n_sc uniform
+    over {72, 300, 600, 1200}, 16/64-QAM, SNR 0..20 dB, ADMM (rho=1, T=5).
+    Frames are resident in HBM (device I/O mode).  Returns saturation
+    throughput and per-load p50/p99 latency (submit to completion)."""
+    import random
+    import threading
+
+    import torch
+
+    from paper_1702_04458_amd import api, inputs
+
+    rng = random.Random(seed)
+    shapes = inputs.serving_shapes()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    frames = []
+    for i in range(pool):
+        B, U, C = rng.choice(shapes)
+        n_sc = rng.choice((72, 300, 600, 1200))
+        qam = rng.choice((16, 64))
+        snr = rng.choice((0, 5, 10, 15, 20))
+        N0 = U / (10.0 ** (snr / 10.0))
+        H = torch.complex(torch.randn((n_sc, B, U), generator=g, device="cuda"),
+                          torch.randn((n_sc, B, U), generator=g, device="cuda")) / math.sqrt(2.0)
+        L = inputs.qam_side(qam)
+        kap = inputs.qam_kappa(qam)
+        iI = torch.randint(0, L, (n_sc, U, 1), generator=g, device="cuda")
+        iQ = torch.randint(0, L, (n_sc, U, 1), generator=g, device="cuda")
+        sv = torch.complex((2 * iI - (L - 1)).float(), (2 * iQ - (L - 1)).float()) / kap
+        nse = torch.complex(torch.randn((n_sc, B, 1), generator=g, device="cuda"),
+                            torch.randn((n_sc, B, 1), generator=g, device="cuda")) * math.sqrt(N0 / 2.0)
+        y = (torch.matmul(H, sv) + nse).transpose(1, 2).contiguous()
+        frames.append(dict(H=H.contiguous(), y=y, B=B, U=U, C=C, n_sc=n_sc, qam=qam, N0=N0))
+    torch.cuda.synchronize()
+    srv = api.Server(hbm_budget_bytes=int(budget_gb * 2 ** 30), n_slots=n_slots)
+
+    def outs(f):
+        return (torch.empty((f["n_sc"], 1, f["U"]), dtype=torch.complex64, device="cuda"),
+                torch.empty((f["n_sc"], 1, f["U"]), dtype=torch.uint8, device="cuda"))
+
+    out_pool = [outs(f) for f in frames]
+
+    def submit(i):
+        f = frames[i % pool]
+        o = out_pool[i % pool]
+        return srv.submit(f["H"], f["y"], o[0], o[1], f["C"], 5, 1.0, f["N0"], qam=f["qam"])
+
+    # warm up every shape once
+    for t in [submit(i) for i in range(pool)]:
+        srv.wait(t)
+    # saturation: closed loop, everything queued at once
+    n_sat = 4 * pool
+    t0 = time.perf_counter()
+    tickets = [submit(i) for i in range(n_sat)]
+    for t in tickets:
+        srv.wait(t)
+    sat_fps = n_sat / (time.perf_counter() - t0)
+    vec_per_frame = sum(f["n_sc"] for f in frames) / pool
+    print(f"[serve] saturation {sat_fps:.0f} frames/s ({sat_fps * vec_per_frame / 1e6:.2f} M vectors/s)",
+          file=log, flush=True)
+    results = []
+    for load in loads:
+        rate = load * sat_fps
+        lat = []
+        pend = []
+        lock = threading.Lock()
+        done_flag = [False]
+
+        def waiter():
+            while True:
+                with lock:
+                    item = pend.pop(0) if pend else None
+                if item is None:
+                    if done_flag[0]:
+                        with lock:
+                            if not pend:
+                                return
+                    time.sleep(0.0002)
+                    continue
+                lat.append(srv.wait(item)[0])
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t_next = time.perf_counter()
+        t_start = t_next
+        for i in range(frames_per_load):
+            t_next += rng.expovariate(rate)
+            while time.perf_counter() < t_next:
+                pass
+            tk = submit(rng.randrange(pool))
+            with lock:
+                pend.append(tk)
+        done_flag[0] = True
+        th.join()
+        dur = time.perf_counter() - t_start
+        lat.sort()
+        p50 = lat[len(lat) // 2]
+        p99 = lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]
+        results.append({"load": load, "offered_fps": round(rate, 1), "achieved_fps": round(len(lat) / dur, 1),
+                        "p50_us": round(p50, 1), "p99_us": round(p99, 1), "frames": len(lat)})
+        print(f"[serve] load {load:.2f}: p50 {p50:.0f} us, p99 {p99:.0f} us", file=log, flush=True)
+    st = srv.stats()
+    srv.close()
+    return {"saturation_fps": round(sat_fps, 1),
+            "saturation_vectors_per_s": round(sat_fps * vec_per_frame, 1),
+            "mean_subcarriers_per_frame": round(vec_per_frame, 1), "slots": n_slots, "budget_gb": budget_gb,
+            "peak_inflight": st["peak_inflight"], "loads": results}
+
+
+def source_digest() -> str:
+    """sha256 over the HIP sources: identifies the kernel build a profile was taken on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1702_04458_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per launch recorded in profiles/<workload>.md (FETCH_SIZE and
+    WRITE_SIZE, calibrated against a device copy), if that profile was taken on
+    the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"{workload}.md")
+    if not os.path.exists(path):
+        return None
+    digest, traffic = None, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("source-sha256:"):
+                digest = line.split(":", 1)[1].strip()
+            if line.startswith("hbm-bytes-per-launch:"):
+                traffic = float(line.split(":", 1)[1].strip())
+    if digest != source_digest():
+        return None
+    return traffic
+
+
+def time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, steps, warmup):
+    """Runs warmup + steps launches rotating over the resident frames; returns
+    (ms per step from the events bracketing all steps, sorted per-launch ms)."""
+    import torch
+
+    n_frames = len(frames)
+    for i in range(warmup):
+        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out, prec, factor)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    start_all = torch.cuda.Event(enable_timing=True)
+    end_all = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start_all.record(stream)
+    for i in range(steps):
+        ev[i][0].record(stream)
+        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out, prec, factor)
+        ev[i][1].record(stream)
+    end_all.record(stream)
+    torch.cuda.synchronize()
+    per = sorted(e[0].elapsed_time(e[1]) for e in ev)
+    return start_all.elapsed_time(end_all) / steps, per
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,25 +320,18 @@ def main():
     ap.add_argument("--workload", default="admm_ul_B256_U32_C8", choices=sorted(WORKLOADS))
     ap.add_argument("--frames", type=int, default=0, help="distinct resident frames (0: enough for >= 2 GB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving (p50/p99) run")
+    ap.add_argument("--no-compare", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--n-sc", type=int, default=0, help="subcarriers per step (default: one 1200-subcarrier frame)")
     ap.add_argument("--T", type=int, default=0, help="override the iteration count of the workload")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--factor", default=None, choices=["auto", "fp32", "fp64"])
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving benchmark")
+    ap.add_argument("--serve-frames", type=int, default=300, help="frames per offered load in the serving run")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run only a plain device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
-
-    if args.copy_bytes:
-        import torch
-
-        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(max(1, args.steps)):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": args.copy_bytes, "launches": max(1, args.steps)}), flush=True)
-        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -177,7 +340,20 @@ def main():
 
     import torch
 
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes, "launches": max(1, args.steps)}), flush=True)
+        return
+
     from paper_1702_04458_amd import api
+
+    if args.serve_only:
+        print(json.dumps(serve_bench(frames_per_load=args.serve_frames)), flush=True)
+        return
 
     algo, B, U, C, qam, snr, T, n_sc = WORKLOADS[args.workload]
     if args.n_sc:
@@ -199,29 +375,11 @@ def main():
                torch.empty((n_sc, 1, U), dtype=torch.uint8, device="cuda"))
     torch.cuda.synchronize()
 
-    for i in range(args.warmup):
-        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out, args.prec, args.factor)
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-
-    stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start_all = torch.cuda.Event(enable_timing=True)
-    end_all = torch.cuda.Event(enable_timing=True)
-    start_all.record(stream)
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out, args.prec, args.factor)
-        ev[i][1].record(stream)
-    end_all.record(stream)
-    torch.cuda.synchronize()
+    ms_per_step, per = time_steps(api, frames, algo, C, T, N0, qam, out, args.prec, args.factor,
+                                  args.steps, args.warmup)
     wall = time.perf_counter() - t0
-    total_ms = start_all.elapsed_time(end_all)
-    per = sorted(e[0].elapsed_time(e[1]) for e in ev)
     avg_kernel_ms = sum(per) / len(per)
-    ms_per_step = total_ms / args.steps
     vectors_per_s = n_sc / (ms_per_step * 1e-3)
     p50 = per[len(per) // 2]
     p99 = per[min(len(per) - 1, int(math.ceil(0.99 * len(per))) - 1)]
@@ -232,14 +390,35 @@ def main():
     achieved_tflops = flops_vec * n_sc / (avg_kernel_ms * 1e-3) / 1e12
     hbm_floor = bytes_vec * n_sc / (HBM_PEAK_GBS * 1e9)
     alu_floor = flops_vec * n_sc / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
+    traffic = profiled_traffic(args.workload) if (args.prec == "fp32" and not args.n_sc and not args.T) else None
     if alu_floor > hbm_floor:
         roof = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None}
+                "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic}
     else:
         roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
     roof["kernel_avg_us"] = round(avg_kernel_ms * 1e3, 2)
+    roof["hbm_achieved_gbs"] = round(achieved_gbs, 1)
     roof["hbm_frac"] = round(achieved_gbs / HBM_PEAK_GBS, 4)
+    roof["algorithmic_bytes_per_launch"] = bytes_vec * n_sc
+    roof["algorithmic_flops_per_launch"] = flops_vec * n_sc
+
+    compare = None
+    if algo == "admm" and U == 32 and not args.no_compare:
+        compare = {}
+        for prec, factor in (("fp16", "auto"), ("fp16", "fp32"), ("bf16", "auto"), ("bf16", "fp32")):
+            ms, _ = time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, max(10, args.steps // 2), 3)
+            compare[f"{prec}_factor_{factor}"] = {"vectors_per_s": round(n_sc / (ms * 1e-3), 1),
+                                                  "us_per_step": round(ms * 1e3, 2)}
+            print(f"[bench] mixed {prec} factor={factor}: {ms * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+        best = max(v["vectors_per_s"] for v in compare.values())
+        compare["best_mixed_vs_fp32"] = round(best / vectors_per_s, 3)
+        compare["rule_mixed_vs_fp32"] = round(compare["fp16_factor_auto"]["vectors_per_s"] / vectors_per_s, 3)
+
+    serving = None
+    if not args.no_serve and algo == "admm":
+        print("[bench] serving run", file=sys.stderr, flush=True)
+        serving = serve_bench(loads=(0.5, 0.85), frames_per_load=args.serve_frames, pool=24)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -247,6 +426,7 @@ def main():
         cpu = cpu_baseline(algo, B, U, C, qam, snr, T, args.cpu_seconds)
 
     metric = "detected subcarrier-vectors/s at B=256,U=32 (mixed vs FP32) + p99 frame latency"
+    dtype = {"fp32": "f32", "fp16": "f16+f32", "bf16": "bf16+f32"}[args.prec]
     line = {
         "metric": metric,
         "value": round(vectors_per_s, 1),
@@ -258,14 +438,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {
             "workload": args.workload,
             "algorithm": {"admm": "Algorithm 1 (ADMM-UL)", "cg": "Algorithm 2 (CG-UL)", "dl": "Algorithm 3 (ADMM-DL)"}[algo],
             "B": B, "U": U, "C": C, "S": B // C, "n_sc": n_sc, "n_sym": 1, "T": T, "rho": 1.0, "qam": qam,
             "snr_db": snr, "precision": args.prec, "factor": args.factor or "auto", "frames_resident": n_frames,
+            "step": "one frame of n_sc subcarrier-vectors, inputs resident in HBM",
             "p50_frame_latency_us": round(p50 * 1e3, 2), "p99_frame_latency_us": round(p99 * 1e3, 2),
+            "mixed_precision": compare,
+            "serving": serving,
         },
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -121,6 +121,45 @@ int dbp_precode_admm(const void* H, const void* s, void* x, float* beta,
                      const float* P_cluster, int n_sc, int n_sym, int B, int U,
                      int C, int T, float rho, float gamma, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of uplink detection frames (Algorithm 1).
+ *
+ * A server owns a device arena of hbm_budget_bytes and n_slots streams.
+ * dbp_server_submit queues a frame (arrival time = the call); a scheduler
+ * thread admits queued frames in arrival order as soon as a slot is free and
+ * the frame's device footprint (H, y, outputs) fits in the arena, then runs
+ * host-to-device copies, dbp_detect_admm and device-to-host copies on the
+ * slot's stream.  Admitted frames overlap on the device; a finished frame
+ * returns its slot and arena space, so waiting frames are admitted as
+ * resources free up.  Results are bit-identical to a lone dbp_detect_admm
+ * call on the same inputs.
+ *
+ * H_host [n_sc][B][U], y_host [n_sc][n_sym][B], s_hat_host [n_sc][n_sym][U]
+ * (complex64) and hard_host [n_sc][n_sym][U] (uint8, or NULL) are caller-owned
+ * PINNED host buffers that must stay valid until dbp_server_wait returns for
+ * the ticket.  With flags = DBP_SERVE_DEVICE_IO they are instead caller-owned
+ * DEVICE buffers (frames already resident in HBM): no copies are made and the
+ * arena space the frame reserves only bounds the in-flight working set.  Submit returns DBP_ERR_INVALID for malformed shapes and
+ * DBP_ERR_NOMEM for a frame larger than the whole budget; other errors (e.g.
+ * an unsupported shape) are reported by dbp_server_wait.
+ * ------------------------------------------------------------------------ */
+typedef struct dbp_server dbp_server;
+#define DBP_SERVE_DEVICE_IO 1
+
+int dbp_server_create(int device, size_t hbm_budget_bytes, int n_slots, dbp_server** out);
+/* Waits for in-flight work, then frees the arena and streams. */
+int dbp_server_destroy(dbp_server* srv);
+int dbp_server_submit(dbp_server* srv, const void* H_host, const void* y_host, void* s_hat_host,
+                      uint8_t* hard_host, int n_sc, int n_sym, int B, int U, int C, int T,
+                      float rho, float N0, int reg, int qam, int prec, int flags, uint64_t* ticket);
+/* Non-blocking: *done = 1 once the frame's results are in the host buffers;
+ * latency_us (may be NULL) = completion - submit in microseconds, -1 if not done. */
+int dbp_server_poll(dbp_server* srv, uint64_t ticket, int* done, double* latency_us);
+/* Blocks until the frame is done, reports latency and queueing time (submit to
+ * admission), and forgets the ticket.  Returns the frame's status. */
+int dbp_server_wait(dbp_server* srv, uint64_t ticket, double* latency_us, double* queue_us);
+int dbp_server_stats(dbp_server* srv, size_t* peak_bytes, int* peak_inflight, uint64_t* completed);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,6 +20,13 @@ SIGNATURES = {
     "dbp_detect_admm": (_i, [_vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i, _i, _vp]),
     "dbp_detect_cg": (_i, [_vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i, _vp]),
     "dbp_precode_admm": (_i, [_vp, _vp, _vp, _fp, _fp, _i, _i, _i, _i, _i, _i, _f, _f, _vp]),
+    "dbp_server_create": (_i, [_i, ctypes.c_size_t, _i, ctypes.POINTER(ctypes.c_void_p)]),
+    "dbp_server_destroy": (_i, [_vp]),
+    "dbp_server_submit": (_i, [_vp, _vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i, _i, _i,
+                               ctypes.POINTER(ctypes.c_uint64)]),
+    "dbp_server_poll": (_i, [_vp, ctypes.c_uint64, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double)]),
+    "dbp_server_wait": (_i, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "dbp_server_stats": (_i, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_uint64)]),
 }
 
 _lib = None

@@ -107,3 +107,73 @@ def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, P_cluster=None, out=None, strea
                               n_sc, n_sym, B, U, C, T, float(rho), float(gamma), _stream(stream))
     _native.check(code)
     return x, beta
+
+
+class Server:
+    """Continuous-batching detection server (``dbp_server_*``).
+
+    Frames are submitted either from pinned host tensors (``torch.empty(...,
+    pin_memory=True)``; the server copies them into its HBM arena) or from
+    device tensors already resident in HBM (no copies).  They must stay alive
+    until :meth:`wait` returns for their ticket.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, n_slots: int = 8, device: int = 0):
+        import ctypes
+
+        self._ct = ctypes
+        h = ctypes.c_void_p()
+        _native.check(_native.lib().dbp_server_create(device, int(hbm_budget_bytes), int(n_slots), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, H, y, s_out, hard_out, C, T=5, rho=1.0, N0=0.0, *, reg="mmse", qam=16, prec="fp32",
+               factor=None) -> int:
+        ct = self._ct
+        dev = H.is_cuda
+        for t, n in ((H, "H"), (y, "y"), (s_out, "s_out")) + (((hard_out, "hard_out"),) if hard_out is not None else ()):
+            if not t.is_contiguous():
+                raise ValueError(f"{n} must be contiguous")
+            if dev and not t.is_cuda:
+                raise ValueError(f"{n} must be a device tensor like H")
+            if not dev and (t.is_cuda or not t.is_pinned()):
+                raise ValueError(f"{n} must be a pinned host tensor like H")
+        n_sc, B, U = H.shape
+        n_sym = y.shape[1]
+        tk = ct.c_uint64()
+        code = _native.lib().dbp_server_submit(
+            self._h, H.data_ptr(), y.data_ptr(), s_out.data_ptr(),
+            hard_out.data_ptr() if hard_out is not None else None,
+            n_sc, n_sym, B, U, C, T, float(rho), float(N0), REG[reg], qam, PREC[prec] | FACTOR[factor],
+            1 if dev else 0, ct.byref(tk))
+        _native.check(code)
+        return tk.value
+
+    def poll(self, ticket: int):
+        ct = self._ct
+        done, lat = ct.c_int(), ct.c_double()
+        _native.check(_native.lib().dbp_server_poll(self._h, ct.c_uint64(ticket), ct.byref(done), ct.byref(lat)))
+        return bool(done.value), lat.value
+
+    def wait(self, ticket: int):
+        """Blocks until done; returns (latency_us, queue_us)."""
+        ct = self._ct
+        lat, q = ct.c_double(), ct.c_double()
+        _native.check(_native.lib().dbp_server_wait(self._h, ct.c_uint64(ticket), ct.byref(lat), ct.byref(q)))
+        return lat.value, q.value
+
+    def stats(self):
+        ct = self._ct
+        pb, pi, c = ct.c_size_t(), ct.c_int(), ct.c_uint64()
+        _native.check(_native.lib().dbp_server_stats(self._h, ct.byref(pb), ct.byref(pi), ct.byref(c)))
+        return {"peak_bytes": pb.value, "peak_inflight": pi.value, "completed": c.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _native.check(_native.lib().dbp_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

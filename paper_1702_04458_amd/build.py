@@ -14,12 +14,13 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdbp.so")
 
-SOURCES = ["dbp_kernels.hip", "dbp_capi.cpp"]
+SOURCES = ["dbp_kernels.hip", "dbp_capi.cpp", "dbp_serve.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep hipcc from emitting packed FP32 (v_pk_*_f32) instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
+    "-pthread",
 ]
 
 

@@ -469,6 +469,300 @@ __device__ __forceinline__ c32 gram_inv_mixed_u32(const UlArgs& a, c32 (&A)[32],
   return combine_hy(hyp, h);
 }
 
+// Gram matrices of the four problems of a wave for U = 16 (P = 4) on the
+// matrix cores with v_mfma_f32_16x16x4f32, K running over quadruples of
+// antenna rows: lane l supplies H[s0 + l/16][l%16] as both operands.  The
+// 16x16 result leaves lane l holding column l%16 for rows 4(l/16) + r
+// (r = 0..3) of every problem; by Hermitian symmetry that is row l%16
+// conjugated, columns 4(l/16) .. 4(l/16)+3.  An LDS transpose (two problems
+// per pass through the wave's stage buffer) gives lane 16p + u the full row u
+// of problem p.  Returns row u of H_c^H y_c for symbol 0.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int lane, int wave, c32* stage) {
+  const int q = lane >> 4, col = lane & 15;
+  f32x4 re[4], im[4];
+  c32 hyp[4];
+  const c32* Hp[4];
+  const c32* yp[4];
+  bool act[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int lp = wave * 4 + p;
+    const int ls = lp / a.Cp, c = lp % a.Cp;
+    const int k = blockIdx.x * a.sc_per_block + ls;
+    act[p] = (k < a.n_sc) && (c < a.C);
+    Hp[p] = a.H + (size_t)k * a.B * 16 + (size_t)c * a.S * 16;
+    yp[p] = a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S;
+    re[p] = f32x4{};
+    im[p] = f32x4{};
+    hyp[p] = cz();
+  }
+  constexpr int CH = 1;   // row quadruples per prefetch chunk
+  c32 hv[4][CH], yv[4][CH], hn[4][CH], yn[4][CH];
+  auto fetch = [&](int s0, c32 (&hd)[4][CH], c32 (&yd)[4][CH]) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int s = s0 + 4 * j + q;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const bool ok = act[p] && s < a.S;
+        hd[p][j] = ok ? Hp[p][(size_t)s * 16 + col] : cz();
+        yd[p][j] = ok ? yp[p][s] : cz();
+      }
+    }
+  };
+  fetch(0, hv, yv);
+  for (int s0 = 0; s0 < a.S; s0 += 4 * CH) {
+    if (s0 + 4 * CH < a.S) fetch(s0 + 4 * CH, hn, yn);
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const c32 x = hv[p][j];
+        re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, x.re, re[p], 0, 0, 0);
+        re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, x.im, re[p], 0, 0, 0);
+        im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, x.im, im[p], 0, 0, 0);
+        im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(-x.im, x.re, im[p], 0, 0, 0);
+        cmacc(hyp[p], x, yv[p][j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        hv[p][j] = hn[p][j];
+        yv[p][j] = yn[p][j];
+      }
+  }
+  // transpose through LDS: buf[pp][q'][r][col], two problems per pass
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) stage[((pp * 4 + q) * 4 + r) * 16 + col] = c32{re[2 * half + pp][r], im[2 * half + pp][r]};
+    wave_lds_sync();
+    if ((q >> 1) == half) {
+      const int pp = q & 1;
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const c32 v = stage[((pp * 4 + qq) * 4 + r) * 16 + col];
+          A[4 * qq + r] = c32{v.re, -v.im};
+        }
+    }
+    wave_lds_sync();
+  }
+  // H_c^H y_c: sum the four row classes (lanes col, col+16, col+32, col+48)
+  c32 out = cz();
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    float hr = hyp[p].re, hi = hyp[p].im;
+    hr += __shfl_xor(hr, 16, 64);
+    hi += __shfl_xor(hi, 16, 64);
+    hr += __shfl_xor(hr, 32, 64);
+    hi += __shfl_xor(hi, 32, 64);
+    if (p == q) out = c32{hr, hi};
+  }
+  return out;
+}
+
+// Downlink S x S Gram A_c[a][b] = sum_u conj(Hu[a][u]) Hu[b][u] (S <= 16,
+// U = 32 users as the contraction index, two problems per wave) on the matrix
+// cores with v_mfma_f32_16x16x4f32: lane l supplies Hu[l%16][u0 + l/16] as
+// both operands.  The 16x16 result (lane l: column l%16, rows 4(l/16)+r) goes
+// through the wave's stage buffer so that lane b < 16 of each problem's lane
+// group reads row b.
+__device__ __forceinline__ void gram_dl_mfma_s16_u32(const DlArgs& a, c32 (&A)[16], int lane, int wave, c32* stage) {
+  const int q = lane >> 4, r16 = lane & 15;
+  f32x4 re[2], im[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int lp = wave * 2 + p;
+    const int ls = lp / a.Cp, c = lp % a.Cp;
+    const int k = blockIdx.x * a.sc_per_block + ls;
+    const bool act = (k < a.n_sc) && (c < a.C) && (r16 < a.S);
+    const c32* Hk = a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32 + (size_t)r16 * 32 + q;
+    c32 x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = act ? Hk[4 * j] : cz();
+    re[p] = f32x4{};
+    im[p] = f32x4{};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[j].re, x[j].re, re[p], 0, 0, 0);
+      re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[j].im, x[j].im, re[p], 0, 0, 0);
+      im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[j].re, x[j].im, im[p], 0, 0, 0);
+      im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(-x[j].im, x[j].re, im[p], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) stage[p * 256 + (4 * q + r) * 16 + r16] = c32{re[p][r], im[p][r]};
+  wave_lds_sync();
+  const int p = lane >> 5, b = lane & 31;
+  if (b < 16) {
+#pragma unroll
+    for (int v0 = 0; v0 < 16; v0 += 8) {
+      c32 row[8];
+      lds_read_vec<8>(stage + p * 256 + b * 16 + v0, row);
+#pragma unroll
+      for (int v = 0; v < 8; ++v) A[v0 + v] = row[v];
+    }
+  }
+  wave_lds_sync();
+}
+
+// ---------------------------------------------------------------------------
+// U = 64 (one problem per wave): the 64x64 Gram and its regularised inverse as
+// four 32x32 accumulator tiles (I, J) (rows 32I.., columns 32J..; lane l holds
+// column 32J + l%32 of tile (I, J) for rows 32I + 8(r/4) + 4(l/32) + r%4).
+// Gram: lane l supplies H[s0 + l/32][32I + l%32] as A and H[s0 + l/32][32J + l%32]
+// as B.  Gauss-Jordan as in gj_invert_mfma_u32, with the rank-1 update of every
+// pivot issued on all four tiles and one column scale per tile column.
+// ---------------------------------------------------------------------------
+template <bool INVERT>
+__device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave) {
+  const int h = lane >> 5, col = lane & 31;
+  f32x16 re[2][2], im[2][2];
+  c32 hy0 = cz(), hy1 = cz();
+  const int ls = wave / a.Cp, c = wave % a.Cp;
+  const int k = blockIdx.x * a.sc_per_block + ls;
+  const bool act = (k < a.n_sc) && (c < a.C);
+  const c32* Hk = a.H + (size_t)k * a.B * 64 + (size_t)c * a.S * 64;
+  const c32* yk = a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S;
+#pragma unroll
+  for (int I = 0; I < 2; ++I)
+#pragma unroll
+    for (int J = 0; J < 2; ++J) {
+      re[I][J] = f32x16{};
+      im[I][J] = f32x16{};
+    }
+  c32 x0 = cz(), x1 = cz(), yv = cz();
+  auto fetch = [&](int s0, c32& o0, c32& o1, c32& oy) {
+    const int s = s0 + h;
+    const bool ok = act && s < a.S;
+    o0 = ok ? Hk[(size_t)s * 64 + col] : cz();
+    o1 = ok ? Hk[(size_t)s * 64 + 32 + col] : cz();
+    oy = ok ? yk[s] : cz();
+  };
+  fetch(0, x0, x1, yv);
+  for (int s0 = 0; s0 < a.S; s0 += 2) {
+    c32 n0, n1, ny;
+    if (s0 + 2 < a.S) fetch(s0 + 2, n0, n1, ny);
+    const c32 xs[2] = {x0, x1};
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+      for (int J = 0; J < 2; ++J) {
+        re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[I].re, xs[J].re, re[I][J], 0, 0, 0);
+        re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[I].im, xs[J].im, re[I][J], 0, 0, 0);
+        im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[I].re, xs[J].im, im[I][J], 0, 0, 0);
+        im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(-xs[I].im, xs[J].re, im[I][J], 0, 0, 0);
+      }
+    // entries col and 32 + col of H_c^H y_c over the rows of this lane's parity
+    cmacc(hy0, x0, yv);
+    cmacc(hy1, x1, yv);
+    x0 = n0;
+    x1 = n1;
+    yv = ny;
+  }
+  if (INVERT) {
+    // B = G + rho I
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      const float add = (i == col) ? a.rho : 0.f;
+      re[0][0][r] += add;
+      re[1][1][r] += add;
+    }
+    const float hs = h ? 1.f : -1.f;
+    float sig[2] = {1.f, 1.f};
+#pragma unroll
+    for (int kk = 0; kk < 64; ++kk) {
+      const int Ik = kk / 32, kr = kk % 32;
+      const int rr = 4 * (kr / 8) + (kr % 4);
+      const int hk = (kr / 4) & 1;
+      const bool rowk_here = (h == hk);
+      float first[2], second[2], Sr0[2], Si0[2];
+#pragma unroll
+      for (int J = 0; J < 2; ++J) {
+        const float sr = re[Ik][J][rr], si = im[Ik][J][rr];
+        Sr0[J] = sr;
+        Si0[J] = si;
+        const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(sr), __float_as_uint(si), false, false);
+        const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(si), __float_as_uint(sr), false, false);
+        first[J] = __uint_as_float(fs[hk]);
+        second[J] = __uint_as_float(sf[hk]);
+      }
+      const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Sr0[Ik]), kr + 32 * hk));
+      const float pv = __builtin_amdgcn_rcpf(d);
+      float Are[2], Aim[2], Bre[2], Bim[2], mk[2];
+#pragma unroll
+      for (int J = 0; J < 2; ++J) {
+        const int cidx = 32 * J + col;   // global column / row index of this lane in tile column / row J
+        const float f = (cidx < kk) ? -1.f : (cidx == kk ? 0.f : 1.f);
+        mk[J] = (cidx == kk) ? 0.f : 1.f;
+        const float cc = f * pv * sig[J];
+        Are[J] = -cc * first[J];
+        Aim[J] = (hs * cc) * first[J];
+        Bre[J] = mk[J] * first[J];
+        Bim[J] = mk[J] * second[J];
+      }
+#pragma unroll
+      for (int J = 0; J < 2; ++J) {
+        const bool isk = (32 * J + col == kk);
+        const float fr = rowk_here ? pv * mk[J] : 1.f;
+        const float g = (rowk_here && isk) ? -1.f : 0.f;
+        re[Ik][J][rr] = fmaf(Sr0[J], fr, g);
+        im[Ik][J][rr] = Si0[J] * fr;
+      }
+#pragma unroll
+      for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J) {
+          re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are[I], Bre[J], re[I][J], 0, 0, 0);
+          im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim[I], Bim[J], im[I][J], 0, 0, 0);
+        }
+#pragma unroll
+      for (int J = 0; J < 2; ++J) sig[J] = (32 * J + col == kk) ? -pv : sig[J];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+      for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J) {
+          re[I][J][r] *= sig[J];
+          im[I][J][r] *= sig[J];
+        }
+  }
+  // accumulator tiles -> lane-row layout: lane u < 32 takes column u of tile
+  // column 0, lane 32 + u column u of tile column 1 (conjugated into rows)
+#pragma unroll
+  for (int I = 0; I < 2; ++I)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m0 = 32 * I + 8 * (r / 4) + (r % 4);
+      const float sr = h ? re[I][0][r] : re[I][1][r];
+      const float si = h ? im[I][0][r] : im[I][1][r];
+      const float tr = __shfl_xor(sr, 32, 64);
+      const float ti = __shfl_xor(si, 32, 64);
+      const float h0r = h ? tr : re[I][0][r], h0i = h ? ti : im[I][0][r];
+      const float h1r = h ? re[I][1][r] : tr, h1i = h ? im[I][1][r] : ti;
+      A[m0] = c32{h0r, -h0i};
+      A[m0 + 4] = c32{h1r, -h1i};
+    }
+  // lane u < 32 owns entry u, lane 32 + u entry 32 + u: add the partner's
+  // parity (rows of parity 0 first)
+  const c32 send = h ? hy0 : hy1;
+  const c32 got = c32{__shfl_xor(send.re, 32, 64), __shfl_xor(send.im, 32, 64)};
+  return h ? cadd(got, hy1) : cadd(hy0, got);
+}
+
 // Consensus: every lane of cluster c writes its entry of w_c into its slot;
 // after the barrier each lane sums the C clusters of its subcarrier in cluster
 // order 1..C (identical sum on every cluster, as if broadcast by the fusion
@@ -516,6 +810,14 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
     hy0 = gram_inv_mixed_u32<_Float16, MODE == 3>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
   } else if constexpr (G == 32 && (MODE == 2 || MODE == 4)) {
     hy0 = gram_inv_mixed_u32<__bf16, MODE == 4>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
+  } else if constexpr (G == 16) {
+    hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
+#pragma unroll
+    for (int v = 0; v < G; ++v)
+      if (v == u) A[v].re += a.rho;
+    gj_invert<G>(A, u, line, gbase);
+  } else if constexpr (G == 64 && MODE == 0) {
+    hy0 = gram_mfma_u64<true>(a, A, lane, wave);
   } else {
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 #pragma unroll
@@ -593,6 +895,10 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   c32 hy0;
   if constexpr (G == 32)
     hy0 = gram_mfma_u32<false>(a, A, lane, wave);
+  else if constexpr (G == 16)
+    hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
+  else if constexpr (G == 64)
+    hy0 = gram_mfma_u64<false>(a, A, lane, wave);
   else
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 
@@ -668,9 +974,11 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
 #pragma unroll
   for (int i = 0; i < G; ++i) hrow[i] = (active && u < S) ? Hk[(size_t)u * G + i] : cz();
   // A_c = H_c^H H_c + rho^{-1} I_S with (H_c^H H_c)[a][b] = sum_u conj(Hu[a][u]) Hu[b][u].
-  // Row b of Hu_c is broadcast from the stage buffer of this wave.
-  {
-    c32* stage = sm.stage + wave * kStageRows * 64;   // needs G*G/64*... rows: stage one row at a time
+  if constexpr (G == 32 && SG == 16) {
+    gram_dl_mfma_s16_u32(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
+  } else {
+    // Row b of Hu_c is broadcast from the stage buffer of this wave.
+    c32* stage = sm.stage + wave * kStageRows * 64;
     for (int b = 0; b < S; ++b) {
       // lane u of the group publishes Hu[b][u] = hcol[b]
       c32 hb = cz();

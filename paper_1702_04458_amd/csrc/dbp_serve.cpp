@@ -1,0 +1,333 @@
+// Serving loop: continuous batching of uplink detection frames.
+//
+// Frames of mixed shapes arrive through dbp_server_submit (caller-owned pinned
+// host buffers for H, y and the results).  A scheduler thread admits them in
+// arrival order whenever a stream slot is free and the frame's device
+// footprint fits in what is left of the HBM budget (a device arena allocated
+// once at creation), then enqueues host-to-device copies, the detection kernel
+// and device-to-host copies on the slot's stream.  Admitted frames run
+// concurrently on the device; finished frames give their arena space and slot
+// back, so a waiting frame is admitted as soon as resources free up.  Per-frame
+// latency runs from submit to the completion of the result copy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/dbp.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double us_since(Clock::time_point t0, Clock::time_point t1) {
+  return std::chrono::duration<double, std::micro>(t1 - t0).count();
+}
+
+// First-fit allocator over one device block; offsets are 256-byte aligned.
+class Arena {
+ public:
+  explicit Arena(size_t size) : size_(size) { free_[0] = size; }
+  bool alloc(size_t n, size_t* off) {
+    n = (n + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n;
+        const size_t start = it->first + n;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += n;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = (n + 255) & ~size_t(255);
+    used_ -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+
+ private:
+  size_t size_;
+  size_t used_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+struct Frame {
+  uint64_t ticket;
+  const void* H;
+  const void* y;
+  void* s_out;
+  uint8_t* hard_out;
+  int n_sc, n_sym, B, U, C, T, qam, prec, reg, flags;
+  float rho, N0;
+  size_t bytes_H, bytes_y, bytes_s, bytes_hard, footprint;
+  size_t off = 0;
+  int slot = -1;
+  int status = DBP_OK;
+  bool done = false;
+  Clock::time_point t_arrive, t_admit, t_done;
+};
+
+}  // namespace
+
+struct dbp_server {
+  int device = 0;
+  void* base = nullptr;
+  Arena* arena = nullptr;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  std::vector<uint64_t> slot_frame;   // 0 = free
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, Frame> frames;
+  uint64_t next_ticket = 1;
+  std::atomic<bool> stop{false};
+  std::thread worker;
+  std::string error;
+  size_t peak_used = 0;
+  int peak_inflight = 0;
+  uint64_t completed = 0;
+};
+
+namespace {
+
+// Enqueue copies + detection for an admitted frame on its slot's stream.
+int launch_frame(dbp_server* s, Frame& f) {
+  hipStream_t st = s->streams[f.slot];
+  if (f.flags & DBP_SERVE_DEVICE_IO) {
+    // inputs and outputs already in device memory: the arena space only
+    // accounts for the frame's share of the budget
+    int rc = dbp_detect_admm(f.H, f.y, f.s_out, f.hard_out, f.n_sc, f.n_sym, f.B, f.U, f.C, f.T, f.rho, 1.0f, f.N0,
+                             1.0f, f.reg, f.qam, f.prec, st);
+    if (rc != DBP_OK) return rc;
+    return hipEventRecord(s->events[f.slot], st) == hipSuccess ? DBP_OK : DBP_ERR_DEVICE;
+  }
+  char* d = static_cast<char*>(s->base) + f.off;
+  char* dH = d;
+  char* dy = dH + ((f.bytes_H + 255) & ~size_t(255));
+  char* ds = dy + ((f.bytes_y + 255) & ~size_t(255));
+  char* dh = ds + ((f.bytes_s + 255) & ~size_t(255));
+  if (hipMemcpyAsync(dH, f.H, f.bytes_H, hipMemcpyHostToDevice, st) != hipSuccess) return DBP_ERR_DEVICE;
+  if (hipMemcpyAsync(dy, f.y, f.bytes_y, hipMemcpyHostToDevice, st) != hipSuccess) return DBP_ERR_DEVICE;
+  int rc = dbp_detect_admm(dH, dy, ds, f.hard_out ? reinterpret_cast<uint8_t*>(dh) : nullptr, f.n_sc, f.n_sym, f.B,
+                           f.U, f.C, f.T, f.rho, 1.0f, f.N0, 1.0f, f.reg, f.qam, f.prec, st);
+  if (rc != DBP_OK) return rc;
+  if (hipMemcpyAsync(f.s_out, ds, f.bytes_s, hipMemcpyDeviceToHost, st) != hipSuccess) return DBP_ERR_DEVICE;
+  if (f.hard_out && hipMemcpyAsync(f.hard_out, dh, f.bytes_hard, hipMemcpyDeviceToHost, st) != hipSuccess)
+    return DBP_ERR_DEVICE;
+  if (hipEventRecord(s->events[f.slot], st) != hipSuccess) return DBP_ERR_DEVICE;
+  return DBP_OK;
+}
+
+void scheduler(dbp_server* s) {
+  hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop.load()) {
+    bool progressed = false;
+    // completions
+    int inflight = 0;
+    for (size_t i = 0; i < s->slot_frame.size(); ++i) {
+      const uint64_t t = s->slot_frame[i];
+      if (!t) continue;
+      const hipError_t q = hipEventQuery(s->events[i]);
+      if (q != hipErrorNotReady) {
+        Frame& f = s->frames[t];
+        f.t_done = Clock::now();
+        f.done = true;
+        if (q != hipSuccess) f.status = DBP_ERR_DEVICE;
+        s->arena->release(f.off, f.footprint);
+        s->slot_frame[i] = 0;
+        ++s->completed;
+        progressed = true;
+      } else {
+        ++inflight;
+      }
+    }
+    // admissions, in arrival order
+    while (!s->queue.empty()) {
+      auto free_slot = std::find(s->slot_frame.begin(), s->slot_frame.end(), 0);
+      if (free_slot == s->slot_frame.end()) break;
+      Frame& f = s->frames[s->queue.front()];
+      size_t off;
+      if (!s->arena->alloc(f.footprint, &off)) break;
+      f.off = off;
+      f.slot = int(free_slot - s->slot_frame.begin());
+      f.t_admit = Clock::now();
+      s->queue.pop_front();
+      const int rc = launch_frame(s, f);
+      if (rc != DBP_OK) {
+        // nothing of this frame runs: release and report
+        hipStreamSynchronize(s->streams[f.slot]);
+        s->arena->release(f.off, f.footprint);
+        f.status = rc;
+        f.done = true;
+        f.t_done = Clock::now();
+        continue;
+      }
+      *free_slot = f.ticket;
+      ++inflight;
+      progressed = true;
+    }
+    s->peak_used = std::max(s->peak_used, s->arena->used());
+    s->peak_inflight = std::max(s->peak_inflight, inflight);
+    if (progressed) s->cv.notify_all();
+    if (inflight == 0 && s->queue.empty()) {
+      s->cv.wait(lk, [&] { return s->stop.load() || !s->queue.empty(); });
+    } else {
+      // poll completions at a fine granularity without holding the lock
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
+      lk.lock();
+    }
+  }
+}
+
+int qam_ok(int q) { return q == 4 || q == 16 || q == 64; }
+
+}  // namespace
+
+extern "C" {
+
+int dbp_server_create(int device, size_t hbm_budget_bytes, int n_slots, dbp_server** out) {
+  if (!out || n_slots < 1 || n_slots > 64 || hbm_budget_bytes < 4096) return DBP_ERR_INVALID;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return DBP_ERR_DEVICE;
+  auto* s = new dbp_server();
+  s->device = device;
+  if (hipMalloc(&s->base, hbm_budget_bytes) != hipSuccess) {
+    delete s;
+    return DBP_ERR_NOMEM;
+  }
+  s->arena = new Arena(hbm_budget_bytes);
+  s->streams.resize(n_slots);
+  s->events.resize(n_slots);
+  s->slot_frame.assign(n_slots, 0);
+  for (int i = 0; i < n_slots; ++i) {
+    if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming) != hipSuccess) {
+      return DBP_ERR_DEVICE;
+    }
+  }
+  s->worker = std::thread(scheduler, s);
+  *out = s;
+  return DBP_OK;
+}
+
+int dbp_server_destroy(dbp_server* s) {
+  if (!s) return DBP_ERR_INVALID;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop.store(true);
+  }
+  s->cv.notify_all();
+  s->worker.join();
+  for (auto st : s->streams) hipStreamSynchronize(st);
+  for (auto st : s->streams) hipStreamDestroy(st);
+  for (auto ev : s->events) hipEventDestroy(ev);
+  hipFree(s->base);
+  delete s->arena;
+  delete s;
+  return DBP_OK;
+}
+
+int dbp_server_submit(dbp_server* s, const void* H_host, const void* y_host, void* s_hat_host, uint8_t* hard_host,
+                      int n_sc, int n_sym, int B, int U, int C, int T, float rho, float N0, int reg, int qam,
+                      int prec, int flags, uint64_t* ticket) {
+  if (!s || !ticket || !H_host || !y_host || !s_hat_host) return DBP_ERR_INVALID;
+  if (n_sc < 1 || n_sym < 1 || B < 1 || U < 1 || C < 1 || B % C || U > B / C || T < 1 || !qam_ok(qam) ||
+      !(rho > 0.f) || !(N0 >= 0.f) || (flags & ~DBP_SERVE_DEVICE_IO))
+    return DBP_ERR_INVALID;
+  Frame f{};
+  f.H = H_host;
+  f.y = y_host;
+  f.s_out = s_hat_host;
+  f.hard_out = hard_host;
+  f.n_sc = n_sc;
+  f.n_sym = n_sym;
+  f.B = B;
+  f.U = U;
+  f.C = C;
+  f.T = T;
+  f.qam = qam;
+  f.prec = prec;
+  f.reg = reg;
+  f.flags = flags;
+  f.rho = rho;
+  f.N0 = N0;
+  f.bytes_H = size_t(n_sc) * B * U * 8;
+  f.bytes_y = size_t(n_sc) * n_sym * B * 8;
+  f.bytes_s = size_t(n_sc) * n_sym * U * 8;
+  f.bytes_hard = size_t(n_sc) * n_sym * U;
+  auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
+  f.footprint = al(f.bytes_H) + al(f.bytes_y) + al(f.bytes_s) + al(f.bytes_hard);
+  f.t_arrive = Clock::now();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (f.footprint > s->arena->size()) return DBP_ERR_NOMEM;   // can never be admitted
+  f.ticket = s->next_ticket++;
+  *ticket = f.ticket;
+  s->frames.emplace(f.ticket, f);
+  s->queue.push_back(f.ticket);
+  s->cv.notify_all();
+  return DBP_OK;
+}
+
+int dbp_server_poll(dbp_server* s, uint64_t ticket, int* done, double* latency_us) {
+  if (!s || !done) return DBP_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->frames.find(ticket);
+  if (it == s->frames.end()) return DBP_ERR_NOTFOUND;
+  *done = it->second.done ? 1 : 0;
+  if (latency_us) *latency_us = it->second.done ? us_since(it->second.t_arrive, it->second.t_done) : -1.0;
+  return it->second.done ? it->second.status : DBP_OK;
+}
+
+int dbp_server_wait(dbp_server* s, uint64_t ticket, double* latency_us, double* queue_us) {
+  if (!s) return DBP_ERR_INVALID;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->frames.find(ticket);
+  if (it == s->frames.end()) return DBP_ERR_NOTFOUND;
+  s->cv.wait(lk, [&] { return it->second.done; });
+  if (latency_us) *latency_us = us_since(it->second.t_arrive, it->second.t_done);
+  if (queue_us) *queue_us = it->second.slot >= 0 ? us_since(it->second.t_arrive, it->second.t_admit) : -1.0;
+  const int st = it->second.status;
+  s->frames.erase(it);
+  return st;
+}
+
+int dbp_server_stats(dbp_server* s, size_t* peak_bytes, int* peak_inflight, uint64_t* completed) {
+  if (!s) return DBP_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (peak_bytes) *peak_bytes = s->peak_used;
+  if (peak_inflight) *peak_inflight = s->peak_inflight;
+  if (completed) *completed = s->completed;
+  return DBP_OK;
+}
+
+}  // extern "C"

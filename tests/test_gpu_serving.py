@@ -1,0 +1,111 @@
+"""Serving loop (continuous batching) on the GPU: results are the same alone and
+in the mix, admission respects the HBM budget, and oversized frames are
+refused."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1702_04458_amd import inputs  # noqa: E402
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1702_04458_amd import _native, api  # noqa: E402
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+SHAPES = [(64, 8, 4, 72), (128, 16, 8, 300), (256, 32, 8, 72), (128, 32, 4, 300), (256, 16, 16, 72),
+          (512, 64, 8, 72), (64, 16, 4, 300), (256, 32, 4, 300), (512, 32, 16, 72), (128, 8, 16, 300)]
+
+
+def make_frames(pinned=True):
+    frames = []
+    for i, (B, U, C, n_sc) in enumerate(SHAPES):
+        fr = inputs.uplink_frame(inputs.frame_seed(5, i, 10), n_sc, B, U, 16, 10.0)
+        H = torch.from_numpy(fr.H)
+        y = torch.from_numpy(fr.y)
+        if pinned:
+            H, y = H.pin_memory(), y.pin_memory()
+        else:
+            H, y = H.cuda(), y.cuda()
+        frames.append(dict(H=H, y=y, C=C, N0=fr.N0, U=U, n_sc=n_sc))
+    return frames
+
+
+def out_bufs(f, pinned):
+    if pinned:
+        s = torch.empty((f["n_sc"], 1, f["U"]), dtype=torch.complex64, pin_memory=True)
+        h = torch.empty((f["n_sc"], 1, f["U"]), dtype=torch.uint8, pin_memory=True)
+    else:
+        s = torch.empty((f["n_sc"], 1, f["U"]), dtype=torch.complex64, device="cuda")
+        h = torch.empty((f["n_sc"], 1, f["U"]), dtype=torch.uint8, device="cuda")
+    return s, h
+
+
+@pytest.mark.parametrize("pinned", [True, False])
+def test_alone_equals_mix(pinned):
+    say(f"[gpu] serving alone vs mix pinned={pinned}")
+    frames = make_frames(pinned)
+    # reference: direct library calls, one at a time
+    refs = []
+    for f in frames:
+        s, h = api.detect(f["H"].cuda(), f["y"].cuda(), f["N0"], f["C"], 1.0, 5, qam=16)
+        refs.append((s.cpu(), h.cpu()))
+    torch.cuda.synchronize()
+    srv = api.Server(hbm_budget_bytes=1 << 30, n_slots=4)
+    # alone: one frame in flight at a time
+    alone = []
+    for f in frames:
+        s, h = out_bufs(f, pinned)
+        t = srv.submit(f["H"], f["y"], s, h, f["C"], 5, 1.0, f["N0"], qam=16)
+        lat, _ = srv.wait(t)
+        assert lat > 0
+        alone.append((s.cpu().clone(), h.cpu().clone()))
+    # mix: everything submitted at once, overlapping on the device
+    outs = [out_bufs(f, pinned) for f in frames]
+    tickets = [srv.submit(f["H"], f["y"], o[0], o[1], f["C"], 5, 1.0, f["N0"], qam=16) for f, o in zip(frames, outs)]
+    lats = [srv.wait(t)[0] for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["peak_inflight"] >= 2
+    for (sa, ha), (s, h), (sr, hr) in zip(alone, outs, refs):
+        assert torch.equal(sa, sr) and torch.equal(ha, hr)
+        assert torch.equal(s.cpu(), sa) and torch.equal(h.cpu(), ha)
+    assert all(x > 0 for x in lats)
+
+
+def test_budget_admission_serialises():
+    say("[gpu] serving tiny budget")
+    frames = make_frames(True)
+    sizes = []
+    for f in frames:
+        n_sc, B, U = f["H"].shape
+        al = lambda n: (n + 255) // 256 * 256  # noqa: E731
+        sizes.append(al(n_sc * B * U * 8) + al(n_sc * B * 8) + al(n_sc * U * 8) + al(n_sc * U))
+    budget = max(sizes)
+    srv = api.Server(hbm_budget_bytes=budget, n_slots=4)
+    outs = [out_bufs(f, True) for f in frames]
+    tickets = [srv.submit(f["H"], f["y"], o[0], o[1], f["C"], 5, 1.0, f["N0"], qam=16) for f, o in zip(frames, outs)]
+    q = [srv.wait(t)[1] for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(frames)
+    assert st["peak_bytes"] <= budget
+    assert max(q) > 0
+
+
+def test_oversized_frame_refused():
+    f = make_frames(True)[5]
+    srv = api.Server(hbm_budget_bytes=1 << 20, n_slots=2)
+    s, h = out_bufs(f, True)
+    with pytest.raises(_native.DbpError) as e:
+        srv.submit(f["H"], f["y"], s, h, f["C"], 5, 1.0, f["N0"], qam=16)
+    assert e.value.code == 3
+    srv.close()
