@@ -2,7 +2,10 @@
 
 A step is one pass of the whole detection path -- load H and y, per-cluster Gram
 and regularised inverse, T decentralized ADMM iterations with their consensus
-sums, slicing -- over one frame of 1200 subcarriers.  The default workload is
+sums, slicing -- over one launch of 8 frames x 1200 subcarriers (9600
+independent subcarrier-vectors, each with its own channel; the paper's GPU
+batches 1200 x 7 vectors).  Single-frame (1200-subcarrier) launch latency is
+reported beside it, and the serving run reports latency under load.  The default workload is
 decentralized ADMM uplink detection (Algorithm 1) at B=256 antennas, U=32
 users, C=8 clusters (S=32), 64-QAM, 25 dB, rho=1, T=5, N_sym=1.  Frames are
 synthetic i.i.d. Rayleigh (generated on the device from a fixed seed) and stay
@@ -287,26 +290,37 @@ def profiled_traffic(workload: str):
     return traffic
 
 
-def time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, steps, warmup):
+def time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, steps, warmup, n_streams=1):
     """Runs warmup + steps launches rotating over the resident frames; returns
-    (ms per step from the events bracketing all steps, sorted per-launch ms)."""
+    (ms per step from the events bracketing all steps, sorted per-launch ms).
+    With n_streams > 1 consecutive frames go to different streams (each with
+    its own output buffers), so one frame's tail overlaps the next frame's start,
+    as in a pipelined frame-by-frame receiver."""
     import torch
 
     n_frames = len(frames)
+    main = torch.cuda.current_stream()
+    streams = [main] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
+    outs = [out] + [tuple(torch.empty_like(t) for t in out) for _ in range(n_streams - 1)]
     for i in range(warmup):
         run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out, prec, factor)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     start_all = torch.cuda.Event(enable_timing=True)
     end_all = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    start_all.record(stream)
+    start_all.record(main)
+    for st in streams[1:]:
+        st.wait_event(start_all)
     for i in range(steps):
-        ev[i][0].record(stream)
-        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out, prec, factor)
-        ev[i][1].record(stream)
-    end_all.record(stream)
+        j = i % n_streams
+        with torch.cuda.stream(streams[j]):
+            ev[i][0].record(streams[j])
+            run_step(api, frames[i % n_frames], algo, C, T, N0, qam, outs[j], prec, factor)
+            ev[i][1].record(streams[j])
+    for st in streams[1:]:
+        main.wait_stream(st)
+    end_all.record(main)
     torch.cuda.synchronize()
     per = sorted(e[0].elapsed_time(e[1]) for e in ev)
     return start_all.elapsed_time(end_all) / steps, per
@@ -323,9 +337,12 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (p50/p99) run")
     ap.add_argument("--no-compare", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--n-sc", type=int, default=0, help="subcarriers per step (default: one 1200-subcarrier frame)")
+    ap.add_argument("--frames-per-step", type=int, default=8,
+                    help="1200-subcarrier frames processed by one launch (one step)")
+    ap.add_argument("--n-sc", type=int, default=0, help="subcarriers per step (overrides --frames-per-step)")
     ap.add_argument("--T", type=int, default=0, help="override the iteration count of the workload")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--streams", type=int, default=1, help="streams that consecutive frames alternate over")
     ap.add_argument("--factor", default=None, choices=["auto", "fp32", "fp64"])
     ap.add_argument("--serve-only", action="store_true", help="run only the serving benchmark")
     ap.add_argument("--serve-frames", type=int, default=300, help="frames per offered load in the serving run")
@@ -355,9 +372,8 @@ def main():
         print(json.dumps(serve_bench(frames_per_load=args.serve_frames)), flush=True)
         return
 
-    algo, B, U, C, qam, snr, T, n_sc = WORKLOADS[args.workload]
-    if args.n_sc:
-        n_sc = args.n_sc
+    algo, B, U, C, qam, snr, T, frame_sc = WORKLOADS[args.workload]
+    n_sc = args.n_sc or frame_sc * args.frames_per_step
     if args.T:
         T = args.T
     bytes_vec = algorithmic_bytes(algo, B, U, C)
@@ -377,7 +393,7 @@ def main():
 
     t0 = time.perf_counter()
     ms_per_step, per = time_steps(api, frames, algo, C, T, N0, qam, out, args.prec, args.factor,
-                                  args.steps, args.warmup)
+                                  args.steps, args.warmup, args.streams)
     wall = time.perf_counter() - t0
     avg_kernel_ms = sum(per) / len(per)
     vectors_per_s = n_sc / (ms_per_step * 1e-3)
@@ -386,11 +402,19 @@ def main():
     print(f"[bench] timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step (wall {wall:.3f} s)",
           file=sys.stderr, flush=True)
 
+    # single-frame launches (1200 subcarriers): per-frame latency of the batch form
+    one = [(f[0][:frame_sc], f[1][:frame_sc]) for f in frames]
+    one_out = tuple(t[:frame_sc] for t in out)
+    one_ms, one_per = time_steps(api, one, algo, C, T, N0, qam, one_out, args.prec, args.factor, 50, 5)
+    one_p50 = one_per[len(one_per) // 2]
+    one_p99 = one_per[min(len(one_per) - 1, int(math.ceil(0.99 * len(one_per))) - 1)]
+
     achieved_gbs = bytes_vec * n_sc / (avg_kernel_ms * 1e-3) / 1e9
     achieved_tflops = flops_vec * n_sc / (avg_kernel_ms * 1e-3) / 1e12
     hbm_floor = bytes_vec * n_sc / (HBM_PEAK_GBS * 1e9)
     alu_floor = flops_vec * n_sc / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
-    traffic = profiled_traffic(args.workload) if (args.prec == "fp32" and not args.n_sc and not args.T) else None
+    traffic = (profiled_traffic(args.workload)
+               if (args.prec == "fp32" and not args.n_sc and not args.T and args.frames_per_step == 8) else None)
     if alu_floor > hbm_floor:
         roof = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic}
@@ -407,7 +431,8 @@ def main():
     if algo == "admm" and U == 32 and not args.no_compare:
         compare = {}
         for prec, factor in (("fp16", "auto"), ("fp16", "fp32"), ("bf16", "auto"), ("bf16", "fp32")):
-            ms, _ = time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, max(10, args.steps // 2), 3)
+            ms, _ = time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, max(10, args.steps // 2), 3,
+                               args.streams)
             compare[f"{prec}_factor_{factor}"] = {"vectors_per_s": round(n_sc / (ms * 1e-3), 1),
                                                   "us_per_step": round(ms * 1e3, 2)}
             print(f"[bench] mixed {prec} factor={factor}: {ms * 1e3:.1f} us/step", file=sys.stderr, flush=True)
@@ -445,8 +470,13 @@ def main():
             "algorithm": {"admm": "Algorithm 1 (ADMM-UL)", "cg": "Algorithm 2 (CG-UL)", "dl": "Algorithm 3 (ADMM-DL)"}[algo],
             "B": B, "U": U, "C": C, "S": B // C, "n_sc": n_sc, "n_sym": 1, "T": T, "rho": 1.0, "qam": qam,
             "snr_db": snr, "precision": args.prec, "factor": args.factor or "auto", "frames_resident": n_frames,
-            "step": "one frame of n_sc subcarrier-vectors, inputs resident in HBM",
-            "p50_frame_latency_us": round(p50 * 1e3, 2), "p99_frame_latency_us": round(p99 * 1e3, 2),
+            "step": f"one launch over {n_sc // frame_sc if n_sc % frame_sc == 0 else n_sc / frame_sc} frames "
+                    f"of {frame_sc} subcarriers ({n_sc} subcarrier-vectors), inputs resident in HBM",
+            "streams": args.streams,
+            "p50_step_latency_us": round(p50 * 1e3, 2), "p99_step_latency_us": round(p99 * 1e3, 2),
+            "single_frame": {"n_sc": frame_sc, "vectors_per_s": round(frame_sc / (one_ms * 1e-3), 1),
+                             "p50_frame_latency_us": round(one_p50 * 1e3, 2),
+                             "p99_frame_latency_us": round(one_p99 * 1e3, 2)},
             "mixed_precision": compare,
             "serving": serving,
         },

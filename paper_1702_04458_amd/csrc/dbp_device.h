@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace dbp {
 
 struct c32 {
@@ -68,10 +70,26 @@ __device__ __forceinline__ void lds_read_vec(const c32* p, c32* r) {
 // Sum over the G lanes of a group (G a power of two, groups aligned); every
 // lane of the group receives the identical value (the butterfly adds the same
 // pair of operands on both partners at every level).
+// Within a row of 16 lanes the butterfly uses DPP: quad_perm [1,0,3,2]
+// (xor 1), quad_perm [2,3,0,1] (xor 2), row_half_mirror and row_mirror (which
+// pair the already uniform quads / half-rows); wider groups add a swizzle
+// across rows and a swap of wave halves.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 template <int G>
 __device__ __forceinline__ float group_sum(float v) {
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if constexpr (G >= 2) v += dpp<0xB1>(v);
+  if constexpr (G >= 4) v += dpp<0x4E>(v);
+  if constexpr (G >= 8) v += dpp<0x141>(v);
+  if constexpr (G >= 16) v += dpp<0x140>(v);
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 64) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
   return v;
 }
 template <int G>
@@ -128,9 +146,28 @@ __device__ __forceinline__ void gj_invert(c32 (&A)[G], int u, c32* line, int gba
 }
 
 // out = M q for the group matrix M (row u in A), q distributed one entry per
-// lane; the first n entries of q are used.
+// lane.  A group of 16 lanes is one DPP row: entry v of q is broadcast from
+// lane v with row_newbcast; wider groups go through the wave's LDS line.
+template <int V>
+__device__ __forceinline__ void matvec16_step(const c32 (&A)[16], c32 q, c32& acc) {
+  const c32 qv = c32{dpp<0x150 + V>(q.re), dpp<0x150 + V>(q.im)};
+  cmac(acc, A[V], qv);
+}
+template <int... V>
+__device__ __forceinline__ c32 matvec16(const c32 (&A)[16], c32 q, std::integer_sequence<int, V...>) {
+  c32 acc0 = cz(), acc1 = cz();
+  ((V % 2 == 0 ? matvec16_step<V>(A, q, acc0) : matvec16_step<V>(A, q, acc1)), ...);
+  return cadd(acc0, acc1);
+}
+
 template <int G>
 __device__ __forceinline__ c32 group_matvec(const c32 (&A)[G], c32 q, int u, c32* line, int gbase) {
+  if constexpr (G == 16) {
+    (void)u;
+    (void)line;
+    (void)gbase;
+    return matvec16(A, q, std::make_integer_sequence<int, 16>{});
+  }
   line[gbase + u] = q;
   wave_lds_sync();
   c32 acc0 = cz(), acc1 = cz();

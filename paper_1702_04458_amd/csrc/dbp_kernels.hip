@@ -19,6 +19,16 @@ namespace dbp {
 
 constexpr int kStageRows = 8;   // rows of H_c staged per pass through LDS
 
+// Prefetch depth of the matrix-core Gram prologues (row pairs for U = 32, row
+// quadruples for U = 16): the loads of the next chunk are in flight while the
+// current chunk's MFMAs run.  Build-time tuning knobs.
+#ifndef DBP_PREFETCH_U32
+#define DBP_PREFETCH_U32 2
+#endif
+#ifndef DBP_PREFETCH_U16
+#define DBP_PREFETCH_U16 1
+#endif
+
 // LDS carve-up shared by the kernels (all offsets in c32 units):
 //   stage[nw][kStageRows][64]   staged H rows (one slot per lane)
 //   ystage[nw][kStageRows][8]   staged y entries (one per problem of the wave)
@@ -194,7 +204,7 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
   }
   // Software pipeline: the loads of the next CH row pairs are in flight while
   // the MFMAs of the current ones run.
-  constexpr int CH = 2;
+  constexpr int CH = DBP_PREFETCH_U32;
   c32 hv[2][CH], yv[2][CH], hn[2][CH], yn[2][CH];
   auto fetch = [&](int s0, c32 (&hd)[2][CH], c32 (&yd)[2][CH]) {
 #pragma unroll
@@ -498,7 +508,7 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
     im[p] = f32x4{};
     hyp[p] = cz();
   }
-  constexpr int CH = 1;   // row quadruples per prefetch chunk
+  constexpr int CH = DBP_PREFETCH_U16;   // row quadruples per prefetch chunk
   c32 hv[4][CH], yv[4][CH], hn[4][CH], yn[4][CH];
   auto fetch = [&](int s0, c32 (&hd)[4][CH], c32 (&yd)[4][CH]) {
 #pragma unroll
