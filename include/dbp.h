@@ -53,8 +53,9 @@ extern "C" {
 #define DBP_PREC_MIXED_BF16 2  /* Gram on BF16 MFMA (FP32 accumulate) + FP32 refinement */
 /* Precision of the regularised inverse in the mixed modes, OR-ed into prec.
  * By default (neither flag) the inverse is FP64 when U/S > 0.8 (poorly
- * conditioned regularised Grams) and FP32 otherwise.  The FP32 mode always
- * inverts in FP32. */
+ * conditioned regularised Grams) and FP32 otherwise; the FP64 inverse is
+ * built for U = 32 only, so at U = 64 the default is FP32 and DBP_FACTOR_FP64
+ * returns DBP_ERR_UNSUPPORTED.  The FP32 mode always inverts in FP32. */
 #define DBP_FACTOR_FP32 0x10
 #define DBP_FACTOR_FP64 0x20
 
@@ -81,8 +82,8 @@ const char* dbp_last_error(void);
  *   prec   DBP_PREC_*, optionally OR DBP_FACTOR_*.  In the mixed modes each
  *          cluster's H_c is scaled by a power of two, split as H_hi + H_lo in
  *          the half format, and the Gram accumulates H_hi^H H_hi + H_hi^H H_lo
- *          + H_lo^H H_hi in FP32 on the matrix cores (mixed modes: U = 32 only;
- *          other U return DBP_ERR_UNSUPPORTED).
+ *          + H_lo^H H_hi in FP32 on the matrix cores (mixed modes: U = 32 and
+ *          U = 64; other U return DBP_ERR_UNSUPPORTED).
  * Requires B % C == 0, S = B / C >= U (the U x U branch, S > U in the paper;
  * at S = U the S x S and U x U branches coincide), U in {8, 16, 32, 64},
  * C <= 16, n_sc >= 0 (0 is a no-op), n_sym >= 1.

@@ -125,8 +125,11 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
   if (n_sc > 0 && (!H || !y || !s_hat)) return fail(DBP_ERR_INVALID, "%s: null H, y or s_hat", who);
   const int S = B / C;
   if (S < U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d < U=%d (S x S branch) not built", who, S, U);
-  if (gram_prec != DBP_PREC_FP32 && U != 32)
-    return fail(DBP_ERR_UNSUPPORTED, "%s: mixed precision is built for U=32 only", who);
+  if (gram_prec != DBP_PREC_FP32 && U != 32 && U != 64)
+    return fail(DBP_ERR_UNSUPPORTED, "%s: mixed precision is built for U=32 and U=64 only", who);
+  if (gram_prec != DBP_PREC_FP32 && U == 64 && factor == DBP_FACTOR_FP64)
+    return fail(DBP_ERR_UNSUPPORTED, "%s: the FP64 inverse is built for U=32 only (a 64x64 FP64 row set exceeds a "
+                "wave's registers)", who);
   if (gram_prec == DBP_PREC_FP32 && factor == DBP_FACTOR_FP64)
     return fail(DBP_ERR_UNSUPPORTED, "%s: FP64 inverse is built for the mixed modes only", who);
   if (n_sc == 0) return ok();
@@ -157,7 +160,8 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
   hipStream_t st_ = static_cast<hipStream_t>(stream);
   if (gram_prec == DBP_PREC_FP32) return device_status(who, dbp::launch_admm_ul_f32(a, U, pl.nw, st_));
   // FP64 inverse for poorly conditioned regularised Grams (aspect ratio U/S > 0.8)
-  const bool f64 = (factor == DBP_FACTOR_FP64) || (factor == 0 && 5 * U > 4 * S);
+  // (U = 64 has no FP64 inverse; the rule then falls back to the FP32 one)
+  const bool f64 = (factor == DBP_FACTOR_FP64) || (factor == 0 && 5 * U > 4 * S && U == 32);
   return device_status(who, dbp::launch_admm_ul_mixed(a, U, gram_prec, f64, pl.nw, st_));
 }
 

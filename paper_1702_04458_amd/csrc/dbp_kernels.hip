@@ -634,6 +634,106 @@ __device__ __forceinline__ void gram_dl_mfma_s16_u32(const DlArgs& a, c32 (&A)[1
 // as B.  Gauss-Jordan as in gj_invert_mfma_u32, with the rank-1 update of every
 // pivot issued on all four tiles and one column scale per tile column.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&im)[2][2], int lane, float rho) {
+  const int h = lane >> 5, col = lane & 31;
+  // B = G + rho I
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r / 4) + 4 * h + (r % 4);
+    const float add = (i == col) ? rho : 0.f;
+    re[0][0][r] += add;
+    re[1][1][r] += add;
+  }
+  const float hs = h ? 1.f : -1.f;
+  float sig[2] = {1.f, 1.f};
+#pragma unroll
+  for (int kk = 0; kk < 64; ++kk) {
+    const int Ik = kk / 32, kr = kk % 32;
+    const int rr = 4 * (kr / 8) + (kr % 4);
+    const int hk = (kr / 4) & 1;
+    const bool rowk_here = (h == hk);
+    float first[2], second[2], Sr0[2], Si0[2];
+#pragma unroll
+    for (int J = 0; J < 2; ++J) {
+      const float sr = re[Ik][J][rr], si = im[Ik][J][rr];
+      Sr0[J] = sr;
+      Si0[J] = si;
+      const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(sr), __float_as_uint(si), false, false);
+      const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(si), __float_as_uint(sr), false, false);
+      first[J] = __uint_as_float(fs[hk]);
+      second[J] = __uint_as_float(sf[hk]);
+    }
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Sr0[Ik]), kr + 32 * hk));
+    const float pv = __builtin_amdgcn_rcpf(d);
+    float Are[2], Aim[2], Bre[2], Bim[2], mk[2];
+#pragma unroll
+    for (int J = 0; J < 2; ++J) {
+      const int cidx = 32 * J + col;   // global index of this lane in tile column / row J
+      const float f = (cidx < kk) ? -1.f : (cidx == kk ? 0.f : 1.f);
+      mk[J] = (cidx == kk) ? 0.f : 1.f;
+      const float cc = f * pv * sig[J];
+      Are[J] = -cc * first[J];
+      Aim[J] = (hs * cc) * first[J];
+      Bre[J] = mk[J] * first[J];
+      Bim[J] = mk[J] * second[J];
+    }
+#pragma unroll
+    for (int J = 0; J < 2; ++J) {
+      const bool isk = (32 * J + col == kk);
+      const float fr = rowk_here ? pv * mk[J] : 1.f;
+      const float g = (rowk_here && isk) ? -1.f : 0.f;
+      re[Ik][J][rr] = fmaf(Sr0[J], fr, g);
+      im[Ik][J][rr] = Si0[J] * fr;
+    }
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+      for (int J = 0; J < 2; ++J) {
+        re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are[I], Bre[J], re[I][J], 0, 0, 0);
+        im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim[I], Bim[J], im[I][J], 0, 0, 0);
+      }
+#pragma unroll
+    for (int J = 0; J < 2; ++J) sig[J] = (32 * J + col == kk) ? -pv : sig[J];
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+      for (int J = 0; J < 2; ++J) {
+        re[I][J][r] *= sig[J];
+        im[I][J][r] *= sig[J];
+      }
+}
+
+// accumulator tiles -> lane-row layout: lane u < 32 takes column u of tile
+// column 0, lane 32 + u column u of tile column 1 (conjugated into rows)
+__device__ __forceinline__ void acc_to_rows_u64(const f32x16 (&re)[2][2], const f32x16 (&im)[2][2], c32 (&A)[64],
+                                                int h) {
+#pragma unroll
+  for (int I = 0; I < 2; ++I)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m0 = 32 * I + 8 * (r / 4) + (r % 4);
+      const float sr = h ? re[I][0][r] : re[I][1][r];
+      const float si = h ? im[I][0][r] : im[I][1][r];
+      const float tr = __shfl_xor(sr, 32, 64);
+      const float ti = __shfl_xor(si, 32, 64);
+      const float h0r = h ? tr : re[I][0][r], h0i = h ? ti : im[I][0][r];
+      const float h1r = h ? re[I][1][r] : tr, h1i = h ? im[I][1][r] : ti;
+      A[m0] = c32{h0r, -h0i};
+      A[m0 + 4] = c32{h1r, -h1i};
+    }
+}
+
+// lane u < 32 owns entry u of H_c^H y_c, lane 32 + u entry 32 + u; e0 / e1 are
+// this lane's partial sums of entries col / 32 + col over its half of the rows
+__device__ __forceinline__ c32 combine_hy_u64(c32 e0, c32 e1, int h) {
+  const c32 send = h ? e0 : e1;
+  const c32 got = c32{__shfl_xor(send.re, 32, 64), __shfl_xor(send.im, 32, 64)};
+  return h ? cadd(got, e1) : cadd(e0, got);
+}
+
 template <bool INVERT>
 __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave) {
   const int h = lane >> 5, col = lane & 31;
@@ -680,97 +780,102 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
     x1 = n1;
     yv = ny;
   }
-  if (INVERT) {
-    // B = G + rho I
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = 8 * (r / 4) + 4 * h + (r % 4);
-      const float add = (i == col) ? a.rho : 0.f;
-      re[0][0][r] += add;
-      re[1][1][r] += add;
-    }
-    const float hs = h ? 1.f : -1.f;
-    float sig[2] = {1.f, 1.f};
-#pragma unroll
-    for (int kk = 0; kk < 64; ++kk) {
-      const int Ik = kk / 32, kr = kk % 32;
-      const int rr = 4 * (kr / 8) + (kr % 4);
-      const int hk = (kr / 4) & 1;
-      const bool rowk_here = (h == hk);
-      float first[2], second[2], Sr0[2], Si0[2];
-#pragma unroll
-      for (int J = 0; J < 2; ++J) {
-        const float sr = re[Ik][J][rr], si = im[Ik][J][rr];
-        Sr0[J] = sr;
-        Si0[J] = si;
-        const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(sr), __float_as_uint(si), false, false);
-        const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(si), __float_as_uint(sr), false, false);
-        first[J] = __uint_as_float(fs[hk]);
-        second[J] = __uint_as_float(sf[hk]);
-      }
-      const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Sr0[Ik]), kr + 32 * hk));
-      const float pv = __builtin_amdgcn_rcpf(d);
-      float Are[2], Aim[2], Bre[2], Bim[2], mk[2];
-#pragma unroll
-      for (int J = 0; J < 2; ++J) {
-        const int cidx = 32 * J + col;   // global column / row index of this lane in tile column / row J
-        const float f = (cidx < kk) ? -1.f : (cidx == kk ? 0.f : 1.f);
-        mk[J] = (cidx == kk) ? 0.f : 1.f;
-        const float cc = f * pv * sig[J];
-        Are[J] = -cc * first[J];
-        Aim[J] = (hs * cc) * first[J];
-        Bre[J] = mk[J] * first[J];
-        Bim[J] = mk[J] * second[J];
-      }
-#pragma unroll
-      for (int J = 0; J < 2; ++J) {
-        const bool isk = (32 * J + col == kk);
-        const float fr = rowk_here ? pv * mk[J] : 1.f;
-        const float g = (rowk_here && isk) ? -1.f : 0.f;
-        re[Ik][J][rr] = fmaf(Sr0[J], fr, g);
-        im[Ik][J][rr] = Si0[J] * fr;
-      }
-#pragma unroll
-      for (int I = 0; I < 2; ++I)
-#pragma unroll
-        for (int J = 0; J < 2; ++J) {
-          re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are[I], Bre[J], re[I][J], 0, 0, 0);
-          im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim[I], Bim[J], im[I][J], 0, 0, 0);
-        }
-#pragma unroll
-      for (int J = 0; J < 2; ++J) sig[J] = (32 * J + col == kk) ? -pv : sig[J];
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-#pragma unroll
-      for (int I = 0; I < 2; ++I)
-#pragma unroll
-        for (int J = 0; J < 2; ++J) {
-          re[I][J][r] *= sig[J];
-          im[I][J][r] *= sig[J];
-        }
-  }
-  // accumulator tiles -> lane-row layout: lane u < 32 takes column u of tile
-  // column 0, lane 32 + u column u of tile column 1 (conjugated into rows)
+  if (INVERT) gj_invert_mfma_u64(re, im, lane, a.rho);
+  acc_to_rows_u64(re, im, A, h);
+  return combine_hy_u64(hy0, hy1, h);
+}
+
+// Mixed-precision Gram for U = 64 (one problem per wave): split half-precision
+// H = H_hi + H_lo after a power-of-two scaling, four 32x32 tiles on
+// v_mfma_f32_32x32x16_{f16,bf16}; lane l supplies rows 8(l/32) .. 8(l/32)+7 of
+// each 16-row chunk at column 32I + l%32 (A) and 32J + l%32 (B).  Then the FP32
+// Gauss-Jordan inverse on the matrix cores.
+template <typename HT>
+__device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave) {
+  typedef typename HalfMma<HT>::V V;
+  const int h = lane >> 5, col = lane & 31;
+  const int ls = wave / a.Cp, c = wave % a.Cp;
+  const int k = blockIdx.x * a.sc_per_block + ls;
+  const bool act = (k < a.n_sc) && (c < a.C);
+  const c32* Hk = a.H + (size_t)k * a.B * 64 + (size_t)c * a.S * 64;
+  const c32* yk = a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S;
+  f32x16 re[2][2], im[2][2];
 #pragma unroll
   for (int I = 0; I < 2; ++I)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m0 = 32 * I + 8 * (r / 4) + (r % 4);
-      const float sr = h ? re[I][0][r] : re[I][1][r];
-      const float si = h ? im[I][0][r] : im[I][1][r];
-      const float tr = __shfl_xor(sr, 32, 64);
-      const float ti = __shfl_xor(si, 32, 64);
-      const float h0r = h ? tr : re[I][0][r], h0i = h ? ti : im[I][0][r];
-      const float h1r = h ? re[I][1][r] : tr, h1i = h ? im[I][1][r] : ti;
-      A[m0] = c32{h0r, -h0i};
-      A[m0 + 4] = c32{h1r, -h1i};
+    for (int J = 0; J < 2; ++J) {
+      re[I][J] = f32x16{};
+      im[I][J] = f32x16{};
     }
-  // lane u < 32 owns entry u, lane 32 + u entry 32 + u: add the partner's
-  // parity (rows of parity 0 first)
-  const c32 send = h ? hy0 : hy1;
-  const c32 got = c32{__shfl_xor(send.re, 32, 64), __shfl_xor(send.im, 32, 64)};
-  return h ? cadd(got, hy1) : cadd(hy0, got);
+  // pass 1: scale exponent from the largest |Re|, |Im|
+  float mx = 0.f;
+  for (int s0 = 0; s0 < a.S; s0 += 16) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int s = s0 + 8 * h + t;
+      const bool ok = act && s < a.S;
+      const c32 v0 = ok ? Hk[(size_t)s * 64 + col] : cz();
+      const c32 v1 = ok ? Hk[(size_t)s * 64 + 32 + col] : cz();
+      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v0.re), fabsf(v0.im)), fmaxf(fabsf(v1.re), fabsf(v1.im))));
+    }
+  }
+  mx = wave_max(mx);
+  int x = 0;
+  if (mx > 0.f) frexpf(mx, &x);
+  const int ex = 14 - x;
+  c32 hy0 = cz(), hy1 = cz();
+  // pass 2: split and accumulate
+  for (int s0 = 0; s0 < a.S; s0 += 16) {
+    V rh[2], rl[2], ih[2], il[2], nih[2], nil[2];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int s = s0 + 8 * h + t;
+      const bool ok = act && s < a.S;
+      const c32 yv = ok ? yk[s] : cz();
+#pragma unroll
+      for (int I = 0; I < 2; ++I) {
+        const c32 v = ok ? Hk[(size_t)s * 64 + 32 * I + col] : cz();
+        cmacc(I ? hy1 : hy0, v, yv);
+        const float xr = ldexpf(v.re, ex), xi = ldexpf(v.im, ex);
+        const HT hr = (HT)xr, hi = (HT)xi;
+        rh[I][t] = hr;
+        rl[I][t] = (HT)(xr - (float)hr);
+        ih[I][t] = hi;
+        il[I][t] = (HT)(xi - (float)hi);
+        nih[I][t] = -ih[I][t];
+        nil[I][t] = -il[I][t];
+      }
+    }
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+      for (int J = 0; J < 2; ++J) {
+        re[I][J] = HalfMma<HT>::mma(rh[I], rh[J], re[I][J]);
+        re[I][J] = HalfMma<HT>::mma(rh[I], rl[J], re[I][J]);
+        re[I][J] = HalfMma<HT>::mma(rl[I], rh[J], re[I][J]);
+        re[I][J] = HalfMma<HT>::mma(ih[I], ih[J], re[I][J]);
+        re[I][J] = HalfMma<HT>::mma(ih[I], il[J], re[I][J]);
+        re[I][J] = HalfMma<HT>::mma(il[I], ih[J], re[I][J]);
+        im[I][J] = HalfMma<HT>::mma(rh[I], ih[J], im[I][J]);
+        im[I][J] = HalfMma<HT>::mma(rh[I], il[J], im[I][J]);
+        im[I][J] = HalfMma<HT>::mma(rl[I], ih[J], im[I][J]);
+        im[I][J] = HalfMma<HT>::mma(nih[I], rh[J], im[I][J]);
+        im[I][J] = HalfMma<HT>::mma(nih[I], rl[J], im[I][J]);
+        im[I][J] = HalfMma<HT>::mma(nil[I], rh[J], im[I][J]);
+      }
+  }
+#pragma unroll
+  for (int I = 0; I < 2; ++I)
+#pragma unroll
+    for (int J = 0; J < 2; ++J)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        re[I][J][r] = ldexpf(re[I][J][r], -2 * ex);
+        im[I][J][r] = ldexpf(im[I][J][r], -2 * ex);
+      }
+  gj_invert_mfma_u64(re, im, lane, a.rho);
+  acc_to_rows_u64(re, im, A, h);
+  return combine_hy_u64(hy0, hy1, h);
 }
 
 // Consensus: every lane of cluster c writes its entry of w_c into its slot;
@@ -828,6 +933,10 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
     gj_invert<G>(A, u, line, gbase);
   } else if constexpr (G == 64 && MODE == 0) {
     hy0 = gram_mfma_u64<true>(a, A, lane, wave);
+  } else if constexpr (G == 64 && MODE == 1) {
+    hy0 = gram_inv_mixed_u64<_Float16>(a, A, lane, wave);
+  } else if constexpr (G == 64 && MODE == 2) {
+    hy0 = gram_inv_mixed_u64<__bf16>(a, A, lane, wave);
   } else {
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 #pragma unroll
@@ -1102,6 +1211,7 @@ hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st) {
 }
 
 hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, bool f64, int nw, hipStream_t st) {
+  if (U == 64 && !f64) return half == 1 ? launch(admm_ul_f32<64, 1>, a, nw, st) : launch(admm_ul_f32<64, 2>, a, nw, st);
   if (U != 32) return hipErrorInvalidValue;
   if (half == 1) return f64 ? launch(admm_ul_f32<32, 3>, a, nw, st) : launch(admm_ul_f32<32, 1>, a, nw, st);
   return f64 ? launch(admm_ul_f32<32, 4>, a, nw, st) : launch(admm_ul_f32<32, 2>, a, nw, st);

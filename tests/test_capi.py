@@ -54,7 +54,7 @@ def _admm(**kw):
     (dict(prec=9), 1), (dict(H=None), 1), (dict(y=None), 1), (dict(s=None), 1), (dict(n_sc=-1), 1),
     (dict(n_sym=0), 1), (dict(U=12, B=96, C=4), 2), (dict(B=64, C=8, U=16), 2), (dict(C=32, B=512), 2),
     (dict(rho=float("nan")), 1), (dict(prec=1, U=16, B=128, C=8), 2), (dict(prec=0x40), 1),
-    (dict(prec=0x20), 2), (dict(prec=0x13), 1),
+    (dict(prec=0x20), 2), (dict(prec=0x13), 1), (dict(prec=0x21, U=64, B=512, C=8), 2),
 ])
 def test_detect_admm_rejects(kw, code):
     assert _admm(**kw) == code

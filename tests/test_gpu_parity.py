@@ -296,3 +296,21 @@ def test_power_of_two_scaling_bit_exact(prec, factor):
     torch.cuda.synchronize()
     assert torch.equal(s0, s1)
     assert torch.equal(h0, h1)
+
+
+# -- configuration 4: B=512, C=8 (S=64), U=64, 64-QAM, 25 dB, mixed FP16 / BF16
+# Gram with FP32 accumulation and the FP32 inverse (the FP64 inverse is built
+# for U=32 only), i.i.d. and correlated 0.7 channels.
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("corr", [0.0, 0.7])
+def test_cfg4_mixed(prec, corr):
+    say(f"[gpu] cfg4 mixed prec={prec} corr={corr}")
+    fr = inputs.uplink_frame(inputs.frame_seed(4, 2, 25), 9, 512, 64, 64, 25.0, corr=corr)
+    s, h = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, 8, 1.0, 5, qam=64, prec=prec)
+    torch.cuda.synchronize()
+    s, h = s.cpu().numpy(), h.cpu().numpy()
+    ref = O.admm_ul_frame(fr.H, fr.y, 8, 1.0, 5, fr.N0)
+    err = rel_err(s, ref)
+    say(f"    rel_err={err:.2e}")
+    assert err <= (1e-5 if prec == "fp16" else 1e-3)
+    check_hard(s, h, ref, 64)
