@@ -344,7 +344,7 @@ def main():
     ap.add_argument("--T", type=int, default=0, help="override the iteration count of the workload")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--streams", type=int, default=1, help="streams that consecutive frames alternate over")
-    ap.add_argument("--factor", default=None, choices=["auto", "fp32", "fp64"])
+    ap.add_argument("--factor", default=None, choices=["auto", "fp32", "fp64", "f16x2"])
     ap.add_argument("--serve-only", action="store_true", help="run only the serving benchmark")
     ap.add_argument("--serve-frames", type=int, default=300, help="frames per offered load in the serving run")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -435,7 +435,8 @@ def main():
     compare = None
     if algo == "admm" and U == 32 and not args.no_compare:
         compare = {}
-        for prec, factor in (("fp16", "auto"), ("fp16", "fp32"), ("bf16", "auto"), ("bf16", "fp32")):
+        for prec, factor in (("fp16", "auto"), ("fp16", "fp32"), ("fp16", "f16x2"), ("bf16", "auto"), ("bf16", "fp32"),
+                             ("bf16", "f16x2")):
             ms, _ = time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, max(10, args.steps // 2), 3,
                                args.streams)
             compare[f"{prec}_factor_{factor}"] = {"vectors_per_s": round(n_sc / (ms * 1e-3), 1),

@@ -51,13 +51,24 @@ extern "C" {
 #define DBP_PREC_FP32 0        /* everything in FP32                                     */
 #define DBP_PREC_MIXED_FP16 1  /* Gram on FP16 MFMA (FP32 accumulate) + FP32 refinement */
 #define DBP_PREC_MIXED_BF16 2  /* Gram on BF16 MFMA (FP32 accumulate) + FP32 refinement */
-/* Precision of the regularised inverse in the mixed modes, OR-ed into prec.
- * By default (neither flag) the inverse is FP64 when U/S > 0.8 (poorly
- * conditioned regularised Grams) and FP32 otherwise; the FP64 inverse is
- * built for U = 32 only, so at U = 64 the default is FP32 and DBP_FACTOR_FP64
- * returns DBP_ERR_UNSUPPORTED.  The FP32 mode always inverts in FP32. */
+/* Precision of the regularised inverse in the mixed modes, OR-ed into prec:
+ *   DBP_FACTOR_FP32   Gauss-Jordan on the FP32 matrix cores;
+ *   DBP_FACTOR_FP64   Gauss-Jordan in FP64 on the vector units (U = 32 only;
+ *                     at U = 64 it returns DBP_ERR_UNSUPPORTED);
+ *   DBP_FACTOR_F16X2  Gauss-Jordan on the FP16 matrix cores with every
+ *                     operand split into an FP16 hi + lo pair (about 22
+ *                     significant bits) and FP32 accumulation; the FP16
+ *                     matrix cores run beside the vector units, but their
+ *                     accumulation is not correctly rounded under
+ *                     cancellation, so the inverse is about 30x less
+ *                     accurate than DBP_FACTOR_FP32 (frame error ~5e-5).
+ * By default (no flag) the inverse is FP64 when U/S > 0.8 (poorly
+ * conditioned regularised Grams) and FP32 otherwise; U = 64 defaults to
+ * FP32.  The FP32 mode (DBP_PREC_FP32) always inverts on the FP32 matrix
+ * cores and accepts no other factor flag. */
 #define DBP_FACTOR_FP32 0x10
 #define DBP_FACTOR_FP64 0x20
+#define DBP_FACTOR_F16X2 0x30
 
 const char* dbp_version(void);
 const char* dbp_strerror(int status);

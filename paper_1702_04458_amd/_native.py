@@ -9,7 +9,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdbp.so")
+# DBP_LIBRARY may name another build of the same library (e.g. to compare two
+# builds on one device); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("DBP_LIBRARY") or os.path.join(_HERE, "libdbp.so")
 
 # Entry points declared in include/dbp.h: (name, restype, argtypes)
 _vp, _i, _f, _u8p, _fp = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p

@@ -12,7 +12,7 @@ from . import _native
 
 REG = {"mmse": 0, "zf": 1, "box": 2}
 PREC = {"fp32": 0, "fp16": 1, "bf16": 2, "mixed_fp16": 1, "mixed_bf16": 2}
-FACTOR = {None: 0, "auto": 0, "fp32": 0x10, "fp64": 0x20}
+FACTOR = {None: 0, "auto": 0, "fp32": 0x10, "fp64": 0x20, "f16x2": 0x30}
 
 
 def _dev(t: torch.Tensor, name: str, dtype=torch.complex64) -> torch.Tensor:
@@ -52,7 +52,7 @@ def detect(H, y, N0, C, rho=1.0, T=5, *, algo="admm", reg="mmse", qam=16, Es=1.0
     ``algo="admm"`` runs Algorithm 1 (``rho`` is the ADMM penalty),
     ``algo="cg"`` runs Algorithm 2 (regulariser N0/Es, ``rho`` unused).
     ``prec`` selects the Gram arithmetic ("fp32", "fp16", "bf16"); in the mixed
-    modes ``factor`` ("auto", "fp32", "fp64") selects the inverse's precision.
+    modes ``factor`` ("auto", "fp32", "fp64", "f16x2") selects the inverse's precision.
     Returns ``(s_hat [n_sc, n_sym, U] complex64, hard [n_sc, n_sym, U] uint8 or None)``.
     """
     _dev(H, "H")

@@ -120,7 +120,7 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
   if (!L) return fail(DBP_ERR_INVALID, "%s: qam=%d not in {4,16,64}", who, qam);
   const int gram_prec = prec & 0xF, factor = prec & ~0xF;
   if (gram_prec < DBP_PREC_FP32 || gram_prec > DBP_PREC_MIXED_BF16 ||
-      (factor != 0 && factor != DBP_FACTOR_FP32 && factor != DBP_FACTOR_FP64))
+      (factor != 0 && factor != DBP_FACTOR_FP32 && factor != DBP_FACTOR_FP64 && factor != DBP_FACTOR_F16X2))
     return fail(DBP_ERR_INVALID, "%s: prec=%d", who, prec);
   if (n_sc > 0 && (!H || !y || !s_hat)) return fail(DBP_ERR_INVALID, "%s: null H, y or s_hat", who);
   const int S = B / C;
@@ -130,8 +130,8 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
   if (gram_prec != DBP_PREC_FP32 && U == 64 && factor == DBP_FACTOR_FP64)
     return fail(DBP_ERR_UNSUPPORTED, "%s: the FP64 inverse is built for U=32 only (a 64x64 FP64 row set exceeds a "
                 "wave's registers)", who);
-  if (gram_prec == DBP_PREC_FP32 && factor == DBP_FACTOR_FP64)
-    return fail(DBP_ERR_UNSUPPORTED, "%s: FP64 inverse is built for the mixed modes only", who);
+  if (gram_prec == DBP_PREC_FP32 && (factor == DBP_FACTOR_FP64 || factor == DBP_FACTOR_F16X2))
+    return fail(DBP_ERR_UNSUPPORTED, "%s: the FP64 and split-FP16 inverses are built for the mixed modes only", who);
   if (n_sc == 0) return ok();
 
   const Plan pl = make_plan(U, C);
@@ -159,10 +159,13 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
   a.kappa = (float)std::sqrt(2.0 * (qam - 1) / 3.0);
   hipStream_t st_ = static_cast<hipStream_t>(stream);
   if (gram_prec == DBP_PREC_FP32) return device_status(who, dbp::launch_admm_ul_f32(a, U, pl.nw, st_));
-  // FP64 inverse for poorly conditioned regularised Grams (aspect ratio U/S > 0.8)
-  // (U = 64 has no FP64 inverse; the rule then falls back to the FP32 one)
-  const bool f64 = (factor == DBP_FACTOR_FP64) || (factor == 0 && 5 * U > 4 * S && U == 32);
-  return device_status(who, dbp::launch_admm_ul_mixed(a, U, gram_prec, f64, pl.nw, st_));
+  // Default rule: FP64 inverse for poorly conditioned regularised Grams
+  // (aspect ratio U/S > 0.8), the FP32 matrix-core inverse otherwise (U = 64
+  // has no FP64 inverse and takes the FP32 one).
+  int inv = 0;
+  if (factor == DBP_FACTOR_F16X2) inv = 2;
+  else if (factor == DBP_FACTOR_FP64 || (factor == 0 && 5 * U > 4 * S && U == 32)) inv = 1;
+  return device_status(who, dbp::launch_admm_ul_mixed(a, U, gram_prec, inv, pl.nw, st_));
 }
 
 int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int n_sc, int n_sym, int B, int U,

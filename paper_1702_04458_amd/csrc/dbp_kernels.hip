@@ -19,6 +19,15 @@ namespace dbp {
 
 constexpr int kStageRows = 8;   // rows of H_c staged per pass through LDS
 
+// Loads in the Gram prologues never branch: a request outside the problem
+// (padding cluster, subcarrier past the end, ragged row past S) reads a valid
+// address of the same array instead (row min(s, S-1) of a base clamped to the
+// array start) and is zeroed by a select.
+__device__ __forceinline__ c32 ld_or_zero(const c32* p, bool ok) {
+  const c32 v = *p;
+  return ok ? v : c32{0.f, 0.f};
+}
+
 // Prefetch depth of the matrix-core Gram prologues (row pairs for U = 32, row
 // quadruples for U = 16): the loads of the next chunk are in flight while the
 // current chunk's MFMAs run.  Build-time tuning knobs.
@@ -101,73 +110,88 @@ __device__ __forceinline__ c32 cluster_pass(const c32* __restrict__ H, const c32
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Regularised inverse on the matrix cores, for the two Gram matrices of a wave
-// held in the 32x32 accumulator layout (lane l: column l%32, rows
-// 8(r/4) + 4(l/32) + r%4).  Gauss-Jordan elimination of the HPD matrix
-// B = G + rho I, where every pivot step k is a complex rank-1 update
-// S -= m (x) row_k, issued as two v_mfma_f32_32x32x2f32 (real part with
-// operands [-Re m, Im m] x [Re row; Im row], imaginary part with
-// [-Re m, -Im m] x [Im row; Re row]).  The multipliers m_i = B[i][k] / B[k][k]
-// come from row k through the signed Hermitian symmetry of the partially swept
-// matrix (entry (i, k) is the conjugate of entry (k, i), negated when exactly
-// one of i, k has been swept).  The swept pivot column is not rewritten: each
-// column carries a scale factor sigma_j (true = stored * sigma_j), and the new
-// column k is the old one times -1/B[k][k], so only sigma_k changes.  Row k is
-// rescaled in place.  The result is multiplied out by sigma at the end.
-__device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)[2], int lane, float rho) {
+// Gauss-Jordan inversion of the HPD matrix B = G + rho I in the 32x32
+// accumulator layout (lane l: column l%32, rows 8(r/4) + 4(l/32) + r%4), for
+// the two Gram matrices of a wave, with lazy row and column scales: the stored
+// matrix S relates to the partially swept one by true_ij = S_ij tau_i sigma_j,
+// where a row / column not yet swept has scale 1 and sweeping pivot k (value
+// d = B[k][k] of the current Schur complement) sets tau_k = 1/d and
+// sigma_k = -1/d.  With these scales the sweep leaves row k and column k of S
+// unchanged except for the diagonal, which becomes -d, and every other entry
+// takes the plain Hermitian rank-1 update
+//   S_ij -= conj(S_ki) S_kj / d,
+// so S stays Hermitian throughout (the signed symmetry of the swept matrix is
+// absorbed by the opposite signs of tau and sigma) and the multipliers of the
+// update come from row k alone.  At the end every index is swept and
+// B^{-1}_ij = -S_ij / (d_i d_j).
+//
+// Row k lives in register 4(k/8) + k%4 of lane half (k/4)&1.  On the FP32
+// matrix cores the complex rank-1 update is two v_mfma_f32_32x32x2f32 whose
+// K = 2 slots are the two lane halves, so row k is first copied into the
+// other half (lanes < 32 get (Re, Im), lanes >= 32 (Im, Re)).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Undo the lazy scales of one swept 32x32 accumulator: entry (i, j) becomes
+// -S_ij * pv_i * pv_j * extra, pv the reciprocal pivots.  pvv holds pv of this
+// lane's column; the row factors come through 32 floats of wave-private LDS.
+__device__ __forceinline__ void gj_unscale_u32(f32x16& re, f32x16& im, float pvv, float extra, int lane, float* line) {
+  const int h = lane >> 5, col = lane & 31;
+  if (h == 0) line[col] = pvv;
+  wave_lds_sync();
+  float4 q[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) q[g] = *reinterpret_cast<const float4*>(line + 8 * g + 4 * h);
+  wave_lds_sync();
+  const float cs = -pvv * extra;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const float4 v = q[r / 4];
+    const float pr = (r % 4 == 0) ? v.x : (r % 4 == 1) ? v.y : (r % 4 == 2) ? v.z : v.w;
+    const float sc = cs * pr;
+    re[r] *= sc;
+    im[r] *= sc;
+  }
+}
+
+__device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)[2], int lane, float rho, float* line) {
   const int h = lane >> 5, col = lane & 31;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int i = 8 * (r / 4) + 4 * h + (r % 4);
-    const float add = (i == col) ? rho : 0.f;
-    re[0][r] += add;
-    re[1][r] += add;
+    const bool dg = (8 * (r / 4) + 4 * h + (r % 4) == col);
+    re[0][r] += dg ? rho : 0.f;
+    re[1][r] += dg ? rho : 0.f;
   }
   const float hs = h ? 1.f : -1.f;
-  float sig[2] = {1.f, 1.f};
+  float pvv[2] = {0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     const int rr = 4 * (k / 8) + (k % 4);   // register holding row k
     const int hk = (k / 4) & 1;             // lane half holding row k
     const bool isk = (col == k);
-    const bool rowk_here = (h == hk);
-    // multiplier sign: -1 for swept rows (col < k), 0 for the pivot row itself
-    const float f = (col < k) ? -1.f : (isk ? 0.f : 1.f);
-    const float mk = isk ? 0.f : 1.f;
-    const float g = (rowk_here && isk) ? -1.f : 0.f;
+    const float mk = isk ? 0.f : 1.f;       // row and column k are left alone
+    const float dn = (isk && h == hk) ? -1.f : 1.f;
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const float sr = re[p][rr], si = im[p][rr];
-      // row k at column col, arranged for the operands: lanes < 32 get
-      // (first, second) = (Re, Im), lanes >= 32 get (Im, Re)
+      // row k at column col: lanes < 32 get (first, second) = (Re, Im), lanes >= 32 (Im, Re)
       const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(sr), __float_as_uint(si), false, false);
       const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(si), __float_as_uint(sr), false, false);
       const float first = __uint_as_float(fs[hk]);
       const float second = __uint_as_float(sf[hk]);
       const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sr), k + 32 * hk));
       const float pv = __builtin_amdgcn_rcpf(d);
-      const float c = f * pv * sig[p];          // m_col = c * conj(stored row k entry)
-      const float Are = -c * first;             // lanes < 32: -Re m, lanes >= 32: Im m
-      const float Aim = (hs * c) * first;       // lanes < 32: -Re m, lanes >= 32: -Im m
-      const float Bre = mk * first, Bim = mk * second;
-      // row k <- row k / B[k][k]; the diagonal becomes 1/B[k][k], stored as -1
-      // under sigma_k = -1/B[k][k]
-      const float fr = rowk_here ? pv * mk : 1.f;
-      re[p][rr] = fmaf(sr, fr, g);
-      im[p][rr] = si * fr;
-      re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are, Bre, re[p], 0, 0, 0);
-      im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim, Bim, im[p], 0, 0, 0);
-      sig[p] = isk ? -pv : sig[p];
+      const float t = pv * mk;
+      // Re: -t (Re_i Re_j + Im_i Im_j), Im: -t (Re_i Im_j - Im_i Re_j)
+      const float Are = -t * first;
+      const float Aim = (hs * t) * first;
+      re[p][rr] = sr * dn;
+      re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are, mk * first, re[p], 0, 0, 0);
+      im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim, mk * second, im[p], 0, 0, 0);
+      pvv[p] = isk ? pv : pvv[p];
     }
   }
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      re[p][r] *= sig[p];
-      im[p][r] *= sig[p];
-    }
-  }
+  for (int p = 0; p < 2; ++p) gj_unscale_u32(re[p], im[p], pvv[p], 1.f, lane, line);
 }
 
 // Gram matrices of the two problems of a wave (U = 32, P = 2) on the matrix
@@ -183,7 +207,7 @@ __device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)
 // its own problem (lane-row layout, problem = l/32).  Returns row u of
 // H_c^H y_c for symbol 0.
 template <bool INVERT>
-__device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave) {
+__device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave, float* line) {
   const int h = lane >> 5, col = lane & 31;
   f32x16 re[2], im[2];
   c32 hyp[2];
@@ -196,8 +220,8 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
     const int ls = lp / a.Cp, c = lp % a.Cp;
     const int k = blockIdx.x * a.sc_per_block + ls;
     act[p] = (k < a.n_sc) && (c < a.C);
-    Hp[p] = a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32;
-    yp[p] = a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S;
+    Hp[p] = act[p] ? a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32 : a.H;
+    yp[p] = act[p] ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
     re[p] = f32x16{};
     im[p] = f32x16{};
     hyp[p] = cz();
@@ -213,8 +237,9 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         const bool ok = act[p] && s < a.S;
-        hd[p][q] = ok ? Hp[p][(size_t)s * 32 + col] : cz();
-        yd[p][q] = ok ? yp[p][s] : cz();
+        const int sc = min(s, a.S - 1);
+        hd[p][q] = ld_or_zero(Hp[p] + (size_t)sc * 32 + col, ok);
+        yd[p][q] = ld_or_zero(yp[p] + sc, ok);
       }
     }
   };
@@ -241,7 +266,7 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
         yv[p][q] = yn[p][q];
       }
   }
-  if (INVERT) gj_invert_mfma_u32(re, im, lane, a.rho);
+  if (INVERT) gj_invert_mfma_u32(re, im, lane, a.rho, line);
   // exchange halves: lanes < 32 keep problem 0, lanes >= 32 keep problem 1
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -301,9 +326,24 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
-template <typename HT>
+// Normalisation of the mixed-mode Gram before the FP16 inverse.  H_c is scaled
+// by 2^ex so that its largest entry lies in [2^13, 2^14); the Gram of i.i.d.
+// entries then has diagonal about S * 2^24, and a shift of 9 + ceil(log2 S)
+// brings it to about 2^15.  The FP16 inverse works on the operands r 2^-7 and
+// 2^7 r / d of a pivot row r (both about 2^8 for entries of the diagonal's
+// size, far below the FP16 limit of 2^16), so that values the matrix cores
+// would flush (below 2^-14) only occur for contributions 2^-21 or more below
+// the entries they update.  The shift
+// depends on S only, so scaling H by 2^k changes ex alone and the result stays
+// bit-exact.
+__device__ __forceinline__ int norm_shift(int S) { return 9 + (32 - __builtin_clz((unsigned)(S > 1 ? S - 1 : 1))); }
+
+// With NORM the Gram leaves scaled by 2^-norm_shift(S) instead of being
+// returned to the units of H (see gj_invert_split16_u32); ex receives each
+// problem's scaling exponent either way.
+template <typename HT, bool NORM>
 __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2], f32x16 (&im)[2], c32 (&hyp)[2],
-                                               int lane, int wave) {
+                                               int lane, int wave, int (&ex)[2]) {
   typedef typename HalfMma<HT>::V V;
   const int h = lane >> 5, col = lane & 31;
   const c32* Hp[2];
@@ -315,14 +355,13 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
     const int ls = lp / a.Cp, c = lp % a.Cp;
     const int k = blockIdx.x * a.sc_per_block + ls;
     act[p] = (k < a.n_sc) && (c < a.C);
-    Hp[p] = a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32;
-    yp[p] = a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S;
+    Hp[p] = act[p] ? a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32 : a.H;
+    yp[p] = act[p] ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
     re[p] = f32x16{};
     im[p] = f32x16{};
     hyp[p] = cz();
   }
   // pass 1: largest |Re|, |Im| of each problem -> scale exponent
-  int ex[2];
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     float m = 0.f;
@@ -330,7 +369,7 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int s = s0 + 8 * h + t;
-        const c32 v = (act[p] && s < a.S) ? Hp[p][(size_t)s * 32 + col] : cz();
+        const c32 v = ld_or_zero(Hp[p] + (size_t)min(s, a.S - 1) * 32 + col, act[p] && s < a.S);
         m = fmaxf(m, fmaxf(fabsf(v.re), fabsf(v.im)));
       }
     }
@@ -348,8 +387,9 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
       for (int t = 0; t < 8; ++t) {
         const int s = s0 + 8 * h + t;
         const bool ok = act[p] && s < a.S;
-        v[t] = ok ? Hp[p][(size_t)s * 32 + col] : cz();
-        const c32 yv = ok ? yp[p][s] : cz();
+        const int sc = min(s, a.S - 1);
+        v[t] = ld_or_zero(Hp[p] + (size_t)sc * 32 + col, ok);
+        const c32 yv = ld_or_zero(yp[p] + sc, ok);
         cmacc(hyp[p], v[t], yv);
       }
       V rh, rl, ih, il, nih, nil;
@@ -382,10 +422,11 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
   }
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
+    const int sh = NORM ? norm_shift(a.S) : 2 * ex[p];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      re[p][r] = ldexpf(re[p][r], -2 * ex[p]);
-      im[p][r] = ldexpf(im[p][r], -2 * ex[p]);
+      re[p][r] = ldexpf(re[p][r], -sh);
+      im[p][r] = ldexpf(im[p][r], -sh);
     }
   }
 }
@@ -455,16 +496,109 @@ __device__ __forceinline__ void gj_invert64(c64 (&A)[G], int u, c64* line) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Regularised inverse on the FP16 matrix cores (mixed modes): the sweep of
+// gj_invert_mfma_u32 (lazy row / column scales, Hermitian update
+// S_ij -= conj(S_ki) S_kj / d), with the rank-1 update issued as one
+// v_mfma_f32_32x32x16_f16 per real / imaginary part.  The update is a_i b_j
+// with a = -conj(r) 2^7 / d and b = r 2^-7 (r = row k): the same FP32
+// coefficient 1/d as the FP32 sweep and its final unscaling, and two operands
+// of comparable size (the power of two is exact).  Each operand is split into
+// an FP16 hi + lo pair (round to nearest, about 22 significant bits together)
+// and the K-terms hi.hi, hi.lo, lo.hi of the two real products take six of
+// the eight K-slots of the lane half that holds row k: every operand a lane
+// supplies comes from its own registers, and the other half supplies zeros,
+// so nothing crosses lane halves.  Accumulation is FP32; the dropped lo.lo
+// terms are 2^-22 relative.  FP16 MFMA runs beside the VALU, unlike FP32
+// MFMA.  The matrix arrives normalised (norm_shift): rho is the normalised
+// regulariser and post the power of two that undoes it.
+// ---------------------------------------------------------------------------
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// (x, y) -> packed FP16 pairs hi = (x_hi, y_hi) and lo = (x - x_hi, y - y_hi)
+__device__ __forceinline__ void split_f16(float x, float y, unsigned& hi, unsigned& lo) {
+  const f16x2 hv = f16x2{(_Float16)x, (_Float16)y};
+  const f16x2 lv = f16x2{(_Float16)(x - (float)hv[0]), (_Float16)(y - (float)hv[1])};
+  hi = __builtin_bit_cast(unsigned, hv);
+  lo = __builtin_bit_cast(unsigned, lv);
+}
+
+__device__ __forceinline__ f16x8 as_f16x8(u32x4 v) { return __builtin_bit_cast(f16x8, v); }
+
+// S += a (x) b from the split pairs ah / al = (Re a, Im a), bh / bl = (Re b, Im b).
+// K-slot pairs (dwords): real part (Re a, -Im a).(Re b, Im b), imaginary part
+// (Re a, Im a).(Im b, Re b).
+__device__ __forceinline__ void rank1_split16(f32x16& re, f32x16& im, unsigned ah, unsigned al, unsigned bh,
+                                              unsigned bl) {
+  const unsigned ahc = ah ^ 0x80000000u, alc = al ^ 0x80000000u;
+  const unsigned bhs = __builtin_amdgcn_alignbit(bh, bh, 16), bls = __builtin_amdgcn_alignbit(bl, bl, 16);
+  re = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(u32x4{ahc, ahc, alc, 0u}), as_f16x8(u32x4{bh, bl, bh, 0u}), re,
+                                              0, 0, 0);
+  im = __builtin_amdgcn_mfma_f32_32x32x16_f16(as_f16x8(u32x4{ah, ah, al, 0u}), as_f16x8(u32x4{bhs, bls, bhs, 0u}), im,
+                                              0, 0, 0);
+}
+
+__device__ __forceinline__ void gj_invert_split16_u32(f32x16 (&re)[2], f32x16 (&im)[2], int lane, const float (&rho)[2],
+                                                      const float (&post)[2], float* line) {
+  const int h = lane >> 5, col = lane & 31;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const bool dg = (8 * (r / 4) + 4 * h + (r % 4) == col);
+    re[0][r] += dg ? rho[0] : 0.f;
+    re[1][r] += dg ? rho[1] : 0.f;
+  }
+  float pvv[2] = {0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const int rr = 4 * (k / 8) + (k % 4);   // register holding row k
+    const int hk = (k / 4) & 1;             // lane half holding row k
+    const bool isk = (col == k);
+    const bool here = (h == hk);
+    // operand masks (row k's half, column k excluded) with the 2^7 / 2^-7 balance
+    const float ma = (here && !isk) ? 128.f : 0.f;
+    const float mb = (here && !isk) ? 0.0078125f : 0.f;
+    const float dn = (here && isk) ? -1.f : 1.f;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const float sr = re[p][rr], si = im[p][rr];
+      const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sr), k + 32 * hk));
+      const float pv = __builtin_amdgcn_rcpf(d);
+      const float t = pv * ma;
+      unsigned ah, al, bh, bl;
+      split_f16(-sr * t, si * t, ah, al);
+      split_f16(sr * mb, si * mb, bh, bl);
+      re[p][rr] = sr * dn;
+      rank1_split16(re[p], im[p], ah, al, bh, bl);
+      pvv[p] = isk ? pv : pvv[p];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p) gj_unscale_u32(re[p], im[p], pvv[p], post[p], lane, line);
+}
+
 // Mixed-precision Gram + regularised inverse for U = 32; returns row u of
-// H_c^H y_c and leaves row u of (G + rho I)^{-1} in A.
-template <typename HT, bool F64>
+// H_c^H y_c and leaves row u of (G + rho I)^{-1} in A.  INV selects the
+// inverse: 0 FP32 matrix cores, 1 FP64 VALU, 2 split FP16 matrix cores.
+template <typename HT, int INV>
 __device__ __forceinline__ c32 gram_inv_mixed_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave, c64* line64) {
   const int h = lane >> 5;
   f32x16 re[2], im[2];
   c32 hyp[2];
-  gram_split_u32<HT>(a, re, im, hyp, lane, wave);
-  if (!F64) {
-    gj_invert_mfma_u32(re, im, lane, a.rho);
+  int ex[2];
+  gram_split_u32<HT, INV == 2>(a, re, im, hyp, lane, wave, ex);
+  if (INV == 0) {
+    gj_invert_mfma_u32(re, im, lane, a.rho, reinterpret_cast<float*>(line64));
+    acc_to_rows_u32(re, im, A, h);
+  } else if (INV == 2) {
+    float rho_n[2], post[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int e = 2 * ex[p] - norm_shift(a.S);
+      rho_n[p] = ldexpf(a.rho, e);
+      post[p] = ldexpf(1.f, e);
+    }
+    gj_invert_split16_u32(re, im, lane, rho_n, post, reinterpret_cast<float*>(line64));
     acc_to_rows_u32(re, im, A, h);
   } else {
     acc_to_rows_u32(re, im, A, h);
@@ -502,8 +636,8 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
     const int ls = lp / a.Cp, c = lp % a.Cp;
     const int k = blockIdx.x * a.sc_per_block + ls;
     act[p] = (k < a.n_sc) && (c < a.C);
-    Hp[p] = a.H + (size_t)k * a.B * 16 + (size_t)c * a.S * 16;
-    yp[p] = a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S;
+    Hp[p] = act[p] ? a.H + (size_t)k * a.B * 16 + (size_t)c * a.S * 16 : a.H;
+    yp[p] = act[p] ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
     re[p] = f32x4{};
     im[p] = f32x4{};
     hyp[p] = cz();
@@ -517,8 +651,9 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         const bool ok = act[p] && s < a.S;
-        hd[p][j] = ok ? Hp[p][(size_t)s * 16 + col] : cz();
-        yd[p][j] = ok ? yp[p][s] : cz();
+        const int sc = min(s, a.S - 1);
+        hd[p][j] = ld_or_zero(Hp[p] + (size_t)sc * 16 + col, ok);
+        yd[p][j] = ld_or_zero(yp[p] + sc, ok);
       }
     }
   };
@@ -594,10 +729,10 @@ __device__ __forceinline__ void gram_dl_mfma_s16_u32(const DlArgs& a, c32 (&A)[1
     const int ls = lp / a.Cp, c = lp % a.Cp;
     const int k = blockIdx.x * a.sc_per_block + ls;
     const bool act = (k < a.n_sc) && (c < a.C) && (r16 < a.S);
-    const c32* Hk = a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32 + (size_t)r16 * 32 + q;
+    const c32* Hk = act ? a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32 + (size_t)r16 * 32 + q : a.H + q;
     c32 x[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = act ? Hk[4 * j] : cz();
+    for (int j = 0; j < 8; ++j) x[j] = ld_or_zero(Hk + 4 * j, act);
     re[p] = f32x4{};
     im[p] = f32x4{};
 #pragma unroll
@@ -632,58 +767,75 @@ __device__ __forceinline__ void gram_dl_mfma_s16_u32(const DlArgs& a, c32 (&A)[1
 // column 32J + l%32 of tile (I, J) for rows 32I + 8(r/4) + 4(l/32) + r%4).
 // Gram: lane l supplies H[s0 + l/32][32I + l%32] as A and H[s0 + l/32][32J + l%32]
 // as B.  Gauss-Jordan as in gj_invert_mfma_u32, with the rank-1 update of every
-// pivot issued on all four tiles and one column scale per tile column.
+// pivot issued on all four tiles.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&im)[2][2], int lane, float rho) {
+// Undo the lazy scales of the four swept tiles (as gj_unscale_u32): pvv[J]
+// holds pv of column 32J + l%32; the 64 row factors go through LDS.
+__device__ __forceinline__ void gj_unscale_u64(f32x16 (&re)[2][2], f32x16 (&im)[2][2], const float (&pvv)[2],
+                                               float extra, int lane, float* line) {
+  const int h = lane >> 5, col = lane & 31;
+  line[32 * h + col] = pvv[h];
+  wave_lds_sync();
+  const float cs[2] = {-pvv[0] * extra, -pvv[1] * extra};
+#pragma unroll
+  for (int I = 0; I < 2; ++I) {
+    float4 q[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) q[g] = *reinterpret_cast<const float4*>(line + 32 * I + 8 * g + 4 * h);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float4 v = q[r / 4];
+      const float pr = (r % 4 == 0) ? v.x : (r % 4 == 1) ? v.y : (r % 4 == 2) ? v.z : v.w;
+#pragma unroll
+      for (int J = 0; J < 2; ++J) {
+        const float sc = cs[J] * pr;
+        re[I][J][r] *= sc;
+        im[I][J][r] *= sc;
+      }
+    }
+  }
+  wave_lds_sync();
+}
+
+__device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&im)[2][2], int lane, float rho,
+                                                   float* line) {
   const int h = lane >> 5, col = lane & 31;
   // B = G + rho I
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int i = 8 * (r / 4) + 4 * h + (r % 4);
-    const float add = (i == col) ? rho : 0.f;
-    re[0][0][r] += add;
-    re[1][1][r] += add;
+    const bool dg = (8 * (r / 4) + 4 * h + (r % 4) == col);
+    re[0][0][r] += dg ? rho : 0.f;
+    re[1][1][r] += dg ? rho : 0.f;
   }
   const float hs = h ? 1.f : -1.f;
-  float sig[2] = {1.f, 1.f};
+  float pvv[2] = {0.f, 0.f};
 #pragma unroll
   for (int kk = 0; kk < 64; ++kk) {
     const int Ik = kk / 32, kr = kk % 32;
     const int rr = 4 * (kr / 8) + (kr % 4);
     const int hk = (kr / 4) & 1;
-    const bool rowk_here = (h == hk);
-    float first[2], second[2], Sr0[2], Si0[2];
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(re[Ik][Ik][rr]), kr + 32 * hk));
+    const float pv = __builtin_amdgcn_rcpf(d);
+    float first[2], second[2], mk[2];
 #pragma unroll
     for (int J = 0; J < 2; ++J) {
       const float sr = re[Ik][J][rr], si = im[Ik][J][rr];
-      Sr0[J] = sr;
-      Si0[J] = si;
       const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(sr), __float_as_uint(si), false, false);
       const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(si), __float_as_uint(sr), false, false);
       first[J] = __uint_as_float(fs[hk]);
       second[J] = __uint_as_float(sf[hk]);
+      const bool isk = (32 * J + col == kk);
+      mk[J] = isk ? 0.f : 1.f;
+      re[Ik][J][rr] = (isk && h == hk) ? -sr : sr;
     }
-    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Sr0[Ik]), kr + 32 * hk));
-    const float pv = __builtin_amdgcn_rcpf(d);
-    float Are[2], Aim[2], Bre[2], Bim[2], mk[2];
+    float Are[2], Aim[2], Bre[2], Bim[2];
 #pragma unroll
     for (int J = 0; J < 2; ++J) {
-      const int cidx = 32 * J + col;   // global index of this lane in tile column / row J
-      const float f = (cidx < kk) ? -1.f : (cidx == kk ? 0.f : 1.f);
-      mk[J] = (cidx == kk) ? 0.f : 1.f;
-      const float cc = f * pv * sig[J];
-      Are[J] = -cc * first[J];
-      Aim[J] = (hs * cc) * first[J];
+      const float t = pv * mk[J];
+      Are[J] = -t * first[J];
+      Aim[J] = (hs * t) * first[J];
       Bre[J] = mk[J] * first[J];
       Bim[J] = mk[J] * second[J];
-    }
-#pragma unroll
-    for (int J = 0; J < 2; ++J) {
-      const bool isk = (32 * J + col == kk);
-      const float fr = rowk_here ? pv * mk[J] : 1.f;
-      const float g = (rowk_here && isk) ? -1.f : 0.f;
-      re[Ik][J][rr] = fmaf(Sr0[J], fr, g);
-      im[Ik][J][rr] = Si0[J] * fr;
     }
 #pragma unroll
     for (int I = 0; I < 2; ++I)
@@ -693,17 +845,9 @@ __device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&
         im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim[I], Bim[J], im[I][J], 0, 0, 0);
       }
 #pragma unroll
-    for (int J = 0; J < 2; ++J) sig[J] = (32 * J + col == kk) ? -pv : sig[J];
+    for (int J = 0; J < 2; ++J) pvv[J] = (32 * J + col == kk) ? pv : pvv[J];
   }
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-#pragma unroll
-    for (int I = 0; I < 2; ++I)
-#pragma unroll
-      for (int J = 0; J < 2; ++J) {
-        re[I][J][r] *= sig[J];
-        im[I][J][r] *= sig[J];
-      }
+  gj_unscale_u64(re, im, pvv, 1.f, lane, line);
 }
 
 // accumulator tiles -> lane-row layout: lane u < 32 takes column u of tile
@@ -735,15 +879,15 @@ __device__ __forceinline__ c32 combine_hy_u64(c32 e0, c32 e1, int h) {
 }
 
 template <bool INVERT>
-__device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave) {
+__device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave, float* line) {
   const int h = lane >> 5, col = lane & 31;
   f32x16 re[2][2], im[2][2];
   c32 hy0 = cz(), hy1 = cz();
   const int ls = wave / a.Cp, c = wave % a.Cp;
   const int k = blockIdx.x * a.sc_per_block + ls;
   const bool act = (k < a.n_sc) && (c < a.C);
-  const c32* Hk = a.H + (size_t)k * a.B * 64 + (size_t)c * a.S * 64;
-  const c32* yk = a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S;
+  const c32* Hk = act ? a.H + (size_t)k * a.B * 64 + (size_t)c * a.S * 64 : a.H;
+  const c32* yk = act ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
 #pragma unroll
   for (int I = 0; I < 2; ++I)
 #pragma unroll
@@ -755,9 +899,10 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
   auto fetch = [&](int s0, c32& o0, c32& o1, c32& oy) {
     const int s = s0 + h;
     const bool ok = act && s < a.S;
-    o0 = ok ? Hk[(size_t)s * 64 + col] : cz();
-    o1 = ok ? Hk[(size_t)s * 64 + 32 + col] : cz();
-    oy = ok ? yk[s] : cz();
+    const int sc = min(s, a.S - 1);
+    o0 = ld_or_zero(Hk + (size_t)sc * 64 + col, ok);
+    o1 = ld_or_zero(Hk + (size_t)sc * 64 + 32 + col, ok);
+    oy = ld_or_zero(yk + sc, ok);
   };
   fetch(0, x0, x1, yv);
   for (int s0 = 0; s0 < a.S; s0 += 2) {
@@ -780,25 +925,72 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
     x1 = n1;
     yv = ny;
   }
-  if (INVERT) gj_invert_mfma_u64(re, im, lane, a.rho);
+  if (INVERT) gj_invert_mfma_u64(re, im, lane, a.rho, line);
   acc_to_rows_u64(re, im, A, h);
   return combine_hy_u64(hy0, hy1, h);
+}
+
+// Split-FP16 Gauss-Jordan inverse for U = 64 (four 32x32 tiles, one problem
+// per wave), as gj_invert_split16_u32: the pivot row kk lives in tile row Ik,
+// half hk of tiles (Ik, 0) and (Ik, 1); with the Hermitian stored matrix the
+// operand a of tile row I comes from tile (Ik, I) and b of tile column J from
+// tile (Ik, J), all in half hk, so each of the four tile updates is two FP16
+// MFMAs built from lane-local registers.
+__device__ __forceinline__ void gj_invert_split16_u64(f32x16 (&re)[2][2], f32x16 (&im)[2][2], int lane, float rho,
+                                                      float post, float* line) {
+  const int h = lane >> 5, col = lane & 31;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const bool dg = (8 * (r / 4) + 4 * h + (r % 4) == col);
+    re[0][0][r] += dg ? rho : 0.f;
+    re[1][1][r] += dg ? rho : 0.f;
+  }
+  float pvv[2] = {0.f, 0.f};
+#pragma unroll
+  for (int kk = 0; kk < 64; ++kk) {
+    const int Ik = kk / 32, kr = kk % 32;
+    const int rr = 4 * (kr / 8) + (kr % 4);
+    const int hk = (kr / 4) & 1;
+    const bool here = (h == hk);
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(re[Ik][Ik][rr]), kr + 32 * hk));
+    const float pv = __builtin_amdgcn_rcpf(d);
+    unsigned ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int J = 0; J < 2; ++J) {
+      const bool isk = (32 * J + col == kk);
+      const float t = (here && !isk) ? pv * 128.f : 0.f;
+      const float mb = (here && !isk) ? 0.0078125f : 0.f;
+      const float sr = re[Ik][J][rr], si = im[Ik][J][rr];
+      split_f16(-sr * t, si * t, ah[J], al[J]);
+      split_f16(sr * mb, si * mb, bh[J], bl[J]);
+      re[Ik][J][rr] = (here && isk) ? -sr : sr;
+    }
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+      for (int J = 0; J < 2; ++J) rank1_split16(re[I][J], im[I][J], ah[I], al[I], bh[J], bl[J]);
+#pragma unroll
+    for (int J = 0; J < 2; ++J) pvv[J] = (32 * J + col == kk) ? pv : pvv[J];
+  }
+  gj_unscale_u64(re, im, pvv, post, lane, line);
 }
 
 // Mixed-precision Gram for U = 64 (one problem per wave): split half-precision
 // H = H_hi + H_lo after a power-of-two scaling, four 32x32 tiles on
 // v_mfma_f32_32x32x16_{f16,bf16}; lane l supplies rows 8(l/32) .. 8(l/32)+7 of
-// each 16-row chunk at column 32I + l%32 (A) and 32J + l%32 (B).  Then the FP32
-// Gauss-Jordan inverse on the matrix cores.
-template <typename HT>
-__device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave) {
+// each 16-row chunk at column 32I + l%32 (A) and 32J + l%32 (B).  Then the
+// Gauss-Jordan inverse on the matrix cores: FP32 (INV = 0) or split FP16 on
+// the normalised Gram (INV = 2).
+template <typename HT, int INV>
+__device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave,
+                                                  float* line) {
   typedef typename HalfMma<HT>::V V;
   const int h = lane >> 5, col = lane & 31;
   const int ls = wave / a.Cp, c = wave % a.Cp;
   const int k = blockIdx.x * a.sc_per_block + ls;
   const bool act = (k < a.n_sc) && (c < a.C);
-  const c32* Hk = a.H + (size_t)k * a.B * 64 + (size_t)c * a.S * 64;
-  const c32* yk = a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S;
+  const c32* Hk = act ? a.H + (size_t)k * a.B * 64 + (size_t)c * a.S * 64 : a.H;
+  const c32* yk = act ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
   f32x16 re[2][2], im[2][2];
 #pragma unroll
   for (int I = 0; I < 2; ++I)
@@ -814,8 +1006,9 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
     for (int t = 0; t < 8; ++t) {
       const int s = s0 + 8 * h + t;
       const bool ok = act && s < a.S;
-      const c32 v0 = ok ? Hk[(size_t)s * 64 + col] : cz();
-      const c32 v1 = ok ? Hk[(size_t)s * 64 + 32 + col] : cz();
+      const int sc = min(s, a.S - 1);
+      const c32 v0 = ld_or_zero(Hk + (size_t)sc * 64 + col, ok);
+      const c32 v1 = ld_or_zero(Hk + (size_t)sc * 64 + 32 + col, ok);
       mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v0.re), fabsf(v0.im)), fmaxf(fabsf(v1.re), fabsf(v1.im))));
     }
   }
@@ -831,10 +1024,11 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
     for (int t = 0; t < 8; ++t) {
       const int s = s0 + 8 * h + t;
       const bool ok = act && s < a.S;
-      const c32 yv = ok ? yk[s] : cz();
+      const int sc = min(s, a.S - 1);
+      const c32 yv = ld_or_zero(yk + sc, ok);
 #pragma unroll
       for (int I = 0; I < 2; ++I) {
-        const c32 v = ok ? Hk[(size_t)s * 64 + 32 * I + col] : cz();
+        const c32 v = ld_or_zero(Hk + (size_t)sc * 64 + 32 * I + col, ok);
         cmacc(I ? hy1 : hy0, v, yv);
         const float xr = ldexpf(v.re, ex), xi = ldexpf(v.im, ex);
         const HT hr = (HT)xr, hi = (HT)xi;
@@ -864,16 +1058,20 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
         im[I][J] = HalfMma<HT>::mma(nil[I], rh[J], im[I][J]);
       }
   }
+  const int sh = (INV == 2) ? norm_shift(a.S) : 2 * ex;
 #pragma unroll
   for (int I = 0; I < 2; ++I)
 #pragma unroll
     for (int J = 0; J < 2; ++J)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        re[I][J][r] = ldexpf(re[I][J][r], -2 * ex);
-        im[I][J][r] = ldexpf(im[I][J][r], -2 * ex);
+        re[I][J][r] = ldexpf(re[I][J][r], -sh);
+        im[I][J][r] = ldexpf(im[I][J][r], -sh);
       }
-  gj_invert_mfma_u64(re, im, lane, a.rho);
+  if (INV == 2)
+    gj_invert_split16_u64(re, im, lane, ldexpf(a.rho, 2 * ex - sh), ldexpf(1.f, 2 * ex - sh), line);
+  else
+    gj_invert_mfma_u64(re, im, lane, a.rho, line);
   acc_to_rows_u64(re, im, A, h);
   return combine_hy_u64(hy0, hy1, h);
 }
@@ -896,9 +1094,10 @@ __device__ __forceinline__ c32 consensus(c32 wc, int buf, int ls, int G, int u, 
 // ---------------------------------------------------------------------------
 // Algorithm 1, U x U branch (S >= U), FP32.  Group size G = U.
 // ---------------------------------------------------------------------------
-// MODE: 0 FP32; 1 / 2 mixed FP16 / BF16 Gram with an FP32 (MFMA) inverse;
-// 3 / 4 the same with an FP64 inverse.  Mixed modes exist for U = 32 only.
-template <int G, int MODE>
+// HALF: 0 FP32 Gram, 1 / 2 split FP16 / BF16 Gram (mixed modes, U = 32, 64).
+// INV (mixed modes): 0 FP32 matrix-core inverse, 1 FP64 VALU inverse (U = 32),
+// 2 split-FP16 matrix-core inverse.
+template <int G, int HALF, int INV>
 __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   constexpr int P = 64 / G;
   extern __shared__ float4 smem_raw[];
@@ -919,24 +1118,24 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
 #pragma unroll
   for (int v = 0; v < G; ++v) A[v] = cz();
   c32 hy0;
-  if constexpr (G == 32 && MODE == 0) {
-    hy0 = gram_mfma_u32<true>(a, A, lane, wave);
-  } else if constexpr (G == 32 && (MODE == 1 || MODE == 3)) {
-    hy0 = gram_inv_mixed_u32<_Float16, MODE == 3>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
-  } else if constexpr (G == 32 && (MODE == 2 || MODE == 4)) {
-    hy0 = gram_inv_mixed_u32<__bf16, MODE == 4>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
+  if constexpr (G == 32 && HALF == 0) {
+    hy0 = gram_mfma_u32<true>(a, A, lane, wave, reinterpret_cast<float*>(line));
+  } else if constexpr (G == 32 && HALF == 1) {
+    hy0 = gram_inv_mixed_u32<_Float16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
+  } else if constexpr (G == 32 && HALF == 2) {
+    hy0 = gram_inv_mixed_u32<__bf16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
   } else if constexpr (G == 16) {
     hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
 #pragma unroll
     for (int v = 0; v < G; ++v)
       if (v == u) A[v].re += a.rho;
     gj_invert<G>(A, u, line, gbase);
-  } else if constexpr (G == 64 && MODE == 0) {
-    hy0 = gram_mfma_u64<true>(a, A, lane, wave);
-  } else if constexpr (G == 64 && MODE == 1) {
-    hy0 = gram_inv_mixed_u64<_Float16>(a, A, lane, wave);
-  } else if constexpr (G == 64 && MODE == 2) {
-    hy0 = gram_inv_mixed_u64<__bf16>(a, A, lane, wave);
+  } else if constexpr (G == 64 && HALF == 0) {
+    hy0 = gram_mfma_u64<true>(a, A, lane, wave, reinterpret_cast<float*>(line));
+  } else if constexpr (G == 64 && HALF == 1) {
+    hy0 = gram_inv_mixed_u64<_Float16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line));
+  } else if constexpr (G == 64 && HALF == 2) {
+    hy0 = gram_inv_mixed_u64<__bf16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line));
   } else {
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 #pragma unroll
@@ -1013,11 +1212,11 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   for (int v = 0; v < G; ++v) A[v] = cz();
   c32 hy0;
   if constexpr (G == 32)
-    hy0 = gram_mfma_u32<false>(a, A, lane, wave);
+    hy0 = gram_mfma_u32<false>(a, A, lane, wave, reinterpret_cast<float*>(line));
   else if constexpr (G == 16)
     hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
   else if constexpr (G == 64)
-    hy0 = gram_mfma_u64<false>(a, A, lane, wave);
+    hy0 = gram_mfma_u64<false>(a, A, lane, wave, reinterpret_cast<float*>(line));
   else
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 
@@ -1202,19 +1401,30 @@ static hipError_t launch(K kernel, const Args& a, int nw, hipStream_t st) {
 
 hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st) {
   switch (U) {
-    case 8: return launch(admm_ul_f32<8, 0>, a, nw, st);
-    case 16: return launch(admm_ul_f32<16, 0>, a, nw, st);
-    case 32: return launch(admm_ul_f32<32, 0>, a, nw, st);
-    case 64: return launch(admm_ul_f32<64, 0>, a, nw, st);
+    case 8: return launch(admm_ul_f32<8, 0, 0>, a, nw, st);
+    case 16: return launch(admm_ul_f32<16, 0, 0>, a, nw, st);
+    case 32: return launch(admm_ul_f32<32, 0, 0>, a, nw, st);
+    case 64: return launch(admm_ul_f32<64, 0, 0>, a, nw, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, bool f64, int nw, hipStream_t st) {
-  if (U == 64 && !f64) return half == 1 ? launch(admm_ul_f32<64, 1>, a, nw, st) : launch(admm_ul_f32<64, 2>, a, nw, st);
-  if (U != 32) return hipErrorInvalidValue;
-  if (half == 1) return f64 ? launch(admm_ul_f32<32, 3>, a, nw, st) : launch(admm_ul_f32<32, 1>, a, nw, st);
-  return f64 ? launch(admm_ul_f32<32, 4>, a, nw, st) : launch(admm_ul_f32<32, 2>, a, nw, st);
+template <int G, int HALF>
+static hipError_t launch_mixed_inv(const UlArgs& a, int inv, int nw, hipStream_t st) {
+  switch (inv) {
+    case 0: return launch(admm_ul_f32<G, HALF, 0>, a, nw, st);
+    case 2: return launch(admm_ul_f32<G, HALF, 2>, a, nw, st);
+  }
+  if constexpr (G == 32) {
+    if (inv == 1) return launch(admm_ul_f32<G, HALF, 1>, a, nw, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, int inv, int nw, hipStream_t st) {
+  if (U == 32) return half == 1 ? launch_mixed_inv<32, 1>(a, inv, nw, st) : launch_mixed_inv<32, 2>(a, inv, nw, st);
+  if (U == 64) return half == 1 ? launch_mixed_inv<64, 1>(a, inv, nw, st) : launch_mixed_inv<64, 2>(a, inv, nw, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st) {

@@ -38,7 +38,8 @@ struct DlArgs {
 
 size_t smem_bytes(int nw);
 hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
-hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, bool f64, int nw, hipStream_t st);
+// inv: 0 FP32 matrix-core inverse, 1 FP64 VALU inverse (U = 32), 2 split-FP16 matrix-core inverse
+hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, int inv, int nw, hipStream_t st);
 hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
 hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st);
 

@@ -255,9 +255,11 @@ def test_precode_shapes(B, U, C):
 
 # -- mixed precision (split FP16 / BF16 Gram on the matrix cores), U = 32.
 # Bar: frame-level relative error <= 1e-3 and hard decisions as above; the FP16
-# split is expected to be close to the FP32 path, BF16 looser.
+# split is expected to be close to the FP32 path, BF16 looser.  Inverses: FP32
+# and split-FP16 matrix cores, FP64 vector units ("auto" is FP64 at C = 8,
+# where U/S = 1 > 0.8, and FP32 at C = 4).
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-@pytest.mark.parametrize("C,factor", [(8, "auto"), (8, "fp32"), (4, "auto"), (4, "fp64")])
+@pytest.mark.parametrize("C,factor", [(8, "auto"), (8, "fp32"), (8, "f16x2"), (4, "auto"), (4, "fp64"), (4, "f16x2")])
 def test_mixed_headline_shape(prec, C, factor):
     say(f"[gpu] mixed prec={prec} C={C} factor={factor}")
     fr = inputs.uplink_frame(inputs.frame_seed(6, 10 + C, 25), 41, 256, 32, 64, 25.0)
@@ -268,8 +270,19 @@ def test_mixed_headline_shape(prec, C, factor):
     ref = O.admm_ul_frame(fr.H, fr.y, C, 1.0, 5, fr.N0)
     err = rel_err(s, ref)
     say(f"    rel_err={err:.2e}")
-    assert err <= (1e-5 if prec == "fp16" else 1e-3)
+    assert err <= mixed_bar(prec, factor)
     check_hard(s, h, ref, 64)
+
+
+def mixed_bar(prec, factor):
+    """Frame-level bar of the mixed modes: the FP16 split Gram with an FP32 or
+    FP64 inverse stays at the FP32 path's level (1e-5); the split-FP16 inverse
+    (FP16 matrix-core accumulation is not correctly rounded under
+    cancellation; measured 4e-6 .. 2e-4) and the BF16 Gram are held to the
+    low-precision bar of 1e-3."""
+    if prec == "bf16" or factor == "f16x2":
+        return 1e-3
+    return 1e-5
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
@@ -283,7 +296,8 @@ def test_mixed_correlated_channel(prec):
     check_hard(s.cpu().numpy(), h.cpu().numpy(), ref, 64)
 
 
-@pytest.mark.parametrize("prec,factor", [("fp32", None), ("fp16", "auto"), ("bf16", "fp32")])
+@pytest.mark.parametrize("prec,factor", [("fp32", None), ("fp16", "auto"), ("bf16", "fp32"), ("fp16", "f16x2"),
+                                         ("bf16", "f16x2")])
 def test_power_of_two_scaling_bit_exact(prec, factor):
     """(H, y, N0, rho) -> (2^k H, 2^k y, 4^k N0, 4^k rho) leaves the output bits
     unchanged: every step scales exactly, including the mixed path's
@@ -299,18 +313,19 @@ def test_power_of_two_scaling_bit_exact(prec, factor):
 
 
 # -- configuration 4: B=512, C=8 (S=64), U=64, 64-QAM, 25 dB, mixed FP16 / BF16
-# Gram with FP32 accumulation and the FP32 inverse (the FP64 inverse is built
-# for U=32 only), i.i.d. and correlated 0.7 channels.
+# Gram with FP32 accumulation; the inverse on the FP32 (default) or split-FP16
+# matrix cores (the FP64 inverse is built for U=32 only); i.i.d. and correlated
+# 0.7 channels.
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-@pytest.mark.parametrize("corr", [0.0, 0.7])
-def test_cfg4_mixed(prec, corr):
-    say(f"[gpu] cfg4 mixed prec={prec} corr={corr}")
+@pytest.mark.parametrize("corr,factor", [(0.0, "auto"), (0.7, "auto"), (0.0, "f16x2"), (0.7, "f16x2")])
+def test_cfg4_mixed(prec, corr, factor):
+    say(f"[gpu] cfg4 mixed prec={prec} corr={corr} factor={factor}")
     fr = inputs.uplink_frame(inputs.frame_seed(4, 2, 25), 9, 512, 64, 64, 25.0, corr=corr)
-    s, h = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, 8, 1.0, 5, qam=64, prec=prec)
+    s, h = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, 8, 1.0, 5, qam=64, prec=prec, factor=factor)
     torch.cuda.synchronize()
     s, h = s.cpu().numpy(), h.cpu().numpy()
     ref = O.admm_ul_frame(fr.H, fr.y, 8, 1.0, 5, fr.N0)
     err = rel_err(s, ref)
     say(f"    rel_err={err:.2e}")
-    assert err <= (1e-5 if prec == "fp16" else 1e-3)
+    assert err <= mixed_bar(prec, factor)
     check_hard(s, h, ref, 64)
