@@ -74,9 +74,12 @@ __device__ __forceinline__ void lds_read_vec(const c32* p, c32* r) {
 // (xor 1), quad_perm [2,3,0,1] (xor 2), row_half_mirror and row_mirror (which
 // pair the already uniform quads / half-rows); wider groups add a swizzle
 // across rows and a swap of wave halves.
+// Every control used here (quad_perm, row mirrors, row_newbcast) reads a valid
+// lane of the same row for every lane, so no "old" value is needed and the
+// move carries no initialisation of its destination.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 template <int G>

@@ -1080,15 +1080,31 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
 // after the barrier each lane sums the C clusters of its subcarrier in cluster
 // order 1..C (identical sum on every cluster, as if broadcast by the fusion
 // node).
+// The padding clusters C..Cp-1 of a subcarrier write zeros, so the sum runs
+// over all Cp slots (a power of two) with a fully unrolled loop; adding the
+// trailing zeros leaves the value unchanged.
+template <int N>
+__device__ __forceinline__ c32 sum_slots(const c32* src, int G) {
+  c32 w = cz();
+#pragma unroll
+  for (int cc = 0; cc < N; ++cc) w = cadd(w, src[cc * G]);
+  return w;
+}
+
 __device__ __forceinline__ c32 consensus(c32 wc, int buf, int ls, int G, int u, int C, int Cp, const Smem& sm,
                                          int slot, int nw) {
+  (void)C;
   c32* cb = sm.cons + buf * nw * 64;
   cb[slot] = wc;
   __syncthreads();
-  c32 w = cz();
   const c32* src = cb + (size_t)ls * Cp * G + u;
-  for (int cc = 0; cc < C; ++cc) w = cadd(w, src[cc * G]);
-  return w;
+  switch (Cp) {
+    case 1: return src[0];
+    case 2: return sum_slots<2>(src, G);
+    case 4: return sum_slots<4>(src, G);
+    case 8: return sum_slots<8>(src, G);
+    default: return sum_slots<16>(src, G);
+  }
 }
 
 // ---------------------------------------------------------------------------
