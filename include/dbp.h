@@ -104,6 +104,30 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard,
                     float rho, float gamma, float N0, float Es,
                     int reg, int qam, int prec, void* stream);
 
+/* Resident factorisation for a static channel.  Algorithm 1's preprocessing
+ * (Section III-B, the U x U form of step E1: B_c = H_c^H H_c + rho I_U and its
+ * inverse) depends on H and rho only; the paper precomputes B_c^{-1} once per
+ * channel.  dbp_factor_admm runs that preprocessing for every (subcarrier,
+ * cluster) and writes B_c^{-1} to `factors` (device, caller-owned,
+ * dbp_factor_bytes(n_sc, U, C) bytes, an internal layout of n_sc * C blocks
+ * of U x U complex64).  dbp_detect_admm_factored then runs Algorithm 1's
+ * iterations for any received frame y against that channel: it reads H (for
+ * H_c^H y_c) and the factors, and forms no Gram and no inverse.
+ *   prec (factor only)  as for dbp_detect_admm: the Gram and inverse
+ *          precision of the stored B_c^{-1};
+ *   rho    must be the value the factors were made with (not checked).
+ * Other arguments, requirements and errors are those of dbp_detect_admm.
+ * The result equals dbp_detect_admm up to the rounding of H_c^H y_c, which
+ * the factored path forms on the vector units. */
+size_t dbp_factor_bytes(int n_sc, int U, int C);
+int dbp_factor_admm(const void* H, void* factors, int n_sc, int B, int U, int C,
+                    float rho, int prec, void* stream);
+int dbp_detect_admm_factored(const void* H, const void* factors, const void* y,
+                             void* s_hat, uint8_t* hard,
+                             int n_sc, int n_sym, int B, int U, int C, int T,
+                             float rho, float gamma, float N0, float Es,
+                             int reg, int qam, void* stream);
+
 /* Decentralized conjugate-gradient data detection: Algorithm 2 (Section
  * III-D) with the broadcast-w variant (every cluster keeps its own x, r, p).
  * The CG regulariser is N0/Es for DBP_REG_MMSE and 0 for DBP_REG_ZF; T >= 1

@@ -79,6 +79,43 @@ def detect(H, y, N0, C, rho=1.0, T=5, *, algo="admm", reg="mmse", qam=16, Es=1.0
     return s_hat, hd
 
 
+def factor(H, C, rho=1.0, *, prec="fp32", factor=None, out=None, stream=None):
+    """Algorithm 1's preprocessing for a static channel: B_c^{-1} for every
+    (subcarrier, cluster), kept resident for :func:`detect_factored`.  Returns a
+    complex64 device tensor [n_sc, C, U, U] in the library's internal layout."""
+    _dev(H, "H")
+    n_sc, B, U = H.shape
+    f = out if out is not None else torch.empty((n_sc, C, U, U), dtype=torch.complex64, device=H.device)
+    _dev(f, "factors")
+    if f.numel() * 8 != _native.lib().dbp_factor_bytes(n_sc, U, C):
+        raise ValueError("factors must hold n_sc * C * U * U complex64")
+    _native.check(_native.lib().dbp_factor_admm(H.data_ptr(), f.data_ptr(), n_sc, B, U, C, float(rho),
+                                                PREC[prec] | FACTOR[factor], _stream(stream)))
+    return f
+
+
+def detect_factored(H, factors, y, N0, C, rho=1.0, T=5, *, reg="mmse", qam=16, Es=1.0, gamma=1.0, hard=True,
+                    out=None, stream=None):
+    """Algorithm 1's iterations against resident factors from :func:`factor`
+    (same ``rho``); forms no Gram and no inverse."""
+    _dev(H, "H")
+    _dev(y, "y")
+    _dev(factors, "factors")
+    n_sc, n_sym, B, U, y = _shapes(H, y)
+    if factors.numel() * 8 != _native.lib().dbp_factor_bytes(n_sc, U, C):
+        raise ValueError("factors do not match (n_sc, U, C)")
+    if out is None:
+        s_hat = torch.empty((n_sc, n_sym, U), dtype=torch.complex64, device=H.device)
+        hd = torch.empty((n_sc, n_sym, U), dtype=torch.uint8, device=H.device) if hard else None
+    else:
+        s_hat, hd = out
+    code = _native.lib().dbp_detect_admm_factored(
+        H.data_ptr(), factors.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hd.data_ptr() if hd is not None else None,
+        n_sc, n_sym, B, U, C, T, float(rho), float(gamma), float(N0), float(Es), REG[reg], qam, _stream(stream))
+    _native.check(code)
+    return s_hat, hd
+
+
 def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, P_cluster=None, out=None, stream=None):
     """Decentralized ADMM beamforming (Algorithm 3, epsilon = 0).
 

@@ -105,10 +105,14 @@ const char* dbp_strerror(int status) {
 
 const char* dbp_last_error(void) { return g_last_error.c_str(); }
 
-int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, int n_sc, int n_sym, int B, int U,
-                    int C, int T, float rho, float gamma, float N0, float Es, int reg, int qam, int prec,
-                    void* stream) {
-  const char* who = "dbp_detect_admm";
+}  // extern "C"
+
+namespace {
+
+// Validation and argument block shared by the ADMM uplink entry points
+// (everything except the pointers and the precision flags).
+int admm_args(const char* who, int n_sc, int n_sym, int B, int U, int C, int T, float rho, float gamma, float N0,
+              float Es, int reg, int qam, dbp::UlArgs* a, int* Sout) {
   int st = common_shape(who, n_sc, n_sym, B, U, C, T);
   if (st) return st;
   if (!(rho > 0.f) || !std::isfinite(rho)) return fail(DBP_ERR_INVALID, "%s: rho must be > 0", who);
@@ -118,54 +122,130 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
   if (reg < DBP_REG_MMSE || reg > DBP_REG_BOX) return fail(DBP_ERR_INVALID, "%s: reg=%d", who, reg);
   const int L = qam_side(qam);
   if (!L) return fail(DBP_ERR_INVALID, "%s: qam=%d not in {4,16,64}", who, qam);
-  const int gram_prec = prec & 0xF, factor = prec & ~0xF;
-  if (gram_prec < DBP_PREC_FP32 || gram_prec > DBP_PREC_MIXED_BF16 ||
+  const int S = B / C;
+  *Sout = S;
+  const Plan pl = make_plan(U, C);
+  *a = dbp::UlArgs{};
+  a->n_sc = n_sc;
+  a->n_sym = n_sym;
+  a->B = B;
+  a->C = C;
+  a->Cp = pl.Cp;
+  a->S = S;
+  a->T = T;
+  a->sc_per_block = pl.scpb;
+  a->reg = reg;
+  a->L = L;
+  a->rho = rho;
+  a->gamma = gamma;
+  const double nu = (reg == DBP_REG_MMSE) ? (double)N0 / ((double)rho * (double)Es) : 0.0;
+  a->inv_den = (float)(1.0 / (nu + C));
+  a->invC = (float)(1.0 / C);
+  a->box_r = (float)((L - 1) / std::sqrt(2.0 * (qam - 1) / 3.0));
+  a->kappa = (float)std::sqrt(2.0 * (qam - 1) / 3.0);
+  return DBP_OK;
+}
+
+// Precision flags of the ADMM preprocessing -> (gram_prec, inverse kind).
+int admm_prec(const char* who, int prec, int U, int S, int* gram_prec, int* inv) {
+  *gram_prec = prec & 0xF;
+  const int factor = prec & ~0xF;
+  if (*gram_prec < DBP_PREC_FP32 || *gram_prec > DBP_PREC_MIXED_BF16 ||
       (factor != 0 && factor != DBP_FACTOR_FP32 && factor != DBP_FACTOR_FP64 && factor != DBP_FACTOR_F16X2))
     return fail(DBP_ERR_INVALID, "%s: prec=%d", who, prec);
-  if (n_sc > 0 && (!H || !y || !s_hat)) return fail(DBP_ERR_INVALID, "%s: null H, y or s_hat", who);
-  const int S = B / C;
   if (S < U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d < U=%d (S x S branch) not built", who, S, U);
-  if (gram_prec != DBP_PREC_FP32 && U != 32 && U != 64)
+  if (*gram_prec != DBP_PREC_FP32 && U != 32 && U != 64)
     return fail(DBP_ERR_UNSUPPORTED, "%s: mixed precision is built for U=32 and U=64 only", who);
-  if (gram_prec != DBP_PREC_FP32 && U == 64 && factor == DBP_FACTOR_FP64)
+  if (*gram_prec != DBP_PREC_FP32 && U == 64 && factor == DBP_FACTOR_FP64)
     return fail(DBP_ERR_UNSUPPORTED, "%s: the FP64 inverse is built for U=32 only (a 64x64 FP64 row set exceeds a "
                 "wave's registers)", who);
-  if (gram_prec == DBP_PREC_FP32 && (factor == DBP_FACTOR_FP64 || factor == DBP_FACTOR_F16X2))
+  if (*gram_prec == DBP_PREC_FP32 && (factor == DBP_FACTOR_FP64 || factor == DBP_FACTOR_F16X2))
     return fail(DBP_ERR_UNSUPPORTED, "%s: the FP64 and split-FP16 inverses are built for the mixed modes only", who);
-  if (n_sc == 0) return ok();
+  // Default rule: FP64 inverse for poorly conditioned regularised Grams
+  // (aspect ratio U/S > 0.8), the FP32 matrix-core inverse otherwise (U = 64
+  // has no FP64 inverse and takes the FP32 one).
+  *inv = 0;
+  if (factor == DBP_FACTOR_F16X2) *inv = 2;
+  else if (factor == DBP_FACTOR_FP64 || (factor == 0 && 5 * U > 4 * S && U == 32)) *inv = 1;
+  return DBP_OK;
+}
 
+int launch_preprocessing(const dbp::UlArgs& a, int U, int C, int gram_prec, int inv, hipStream_t st, int stage) {
   const Plan pl = make_plan(U, C);
-  dbp::UlArgs a{};
+  if (gram_prec == DBP_PREC_FP32) return dbp::launch_admm_ul_f32(a, U, pl.nw, st, stage) == hipSuccess ? 0 : -1;
+  return dbp::launch_admm_ul_mixed(a, U, gram_prec, inv, pl.nw, st, stage) == hipSuccess ? 0 : -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, int n_sc, int n_sym, int B, int U,
+                    int C, int T, float rho, float gamma, float N0, float Es, int reg, int qam, int prec,
+                    void* stream) {
+  const char* who = "dbp_detect_admm";
+  dbp::UlArgs a;
+  int S = 0;
+  int st = admm_args(who, n_sc, n_sym, B, U, C, T, rho, gamma, N0, Es, reg, qam, &a, &S);
+  if (st) return st;
+  int gram_prec = 0, inv = 0;
+  st = admm_prec(who, prec, U, S, &gram_prec, &inv);
+  if (st) return st;
+  if (n_sc > 0 && (!H || !y || !s_hat)) return fail(DBP_ERR_INVALID, "%s: null H, y or s_hat", who);
+  if (n_sc == 0) return ok();
   a.H = static_cast<const dbp::c32*>(H);
   a.y = static_cast<const dbp::c32*>(y);
   a.shat = static_cast<dbp::c32*>(s_hat);
   a.hard = hard;
-  a.n_sc = n_sc;
-  a.n_sym = n_sym;
-  a.B = B;
-  a.C = C;
-  a.Cp = pl.Cp;
-  a.S = S;
-  a.T = T;
-  a.sc_per_block = pl.scpb;
-  a.reg = reg;
-  a.L = L;
-  a.rho = rho;
-  a.gamma = gamma;
-  const double nu = (reg == DBP_REG_MMSE) ? (double)N0 / ((double)rho * (double)Es) : 0.0;
-  a.inv_den = (float)(1.0 / (nu + C));
-  a.invC = (float)(1.0 / C);
-  a.box_r = (float)((L - 1) / std::sqrt(2.0 * (qam - 1) / 3.0));
-  a.kappa = (float)std::sqrt(2.0 * (qam - 1) / 3.0);
-  hipStream_t st_ = static_cast<hipStream_t>(stream);
-  if (gram_prec == DBP_PREC_FP32) return device_status(who, dbp::launch_admm_ul_f32(a, U, pl.nw, st_));
-  // Default rule: FP64 inverse for poorly conditioned regularised Grams
-  // (aspect ratio U/S > 0.8), the FP32 matrix-core inverse otherwise (U = 64
-  // has no FP64 inverse and takes the FP32 one).
-  int inv = 0;
-  if (factor == DBP_FACTOR_F16X2) inv = 2;
-  else if (factor == DBP_FACTOR_FP64 || (factor == 0 && 5 * U > 4 * S && U == 32)) inv = 1;
-  return device_status(who, dbp::launch_admm_ul_mixed(a, U, gram_prec, inv, pl.nw, st_));
+  if (launch_preprocessing(a, U, C, gram_prec, inv, static_cast<hipStream_t>(stream), 0))
+    return device_status(who, hipGetLastError());
+  return ok();
+}
+
+size_t dbp_factor_bytes(int n_sc, int U, int C) {
+  if (n_sc < 0 || U < 1 || C < 1) return 0;
+  return (size_t)n_sc * C * U * U * 8;
+}
+
+int dbp_factor_admm(const void* H, void* factors, int n_sc, int B, int U, int C, float rho, int prec, void* stream) {
+  const char* who = "dbp_factor_admm";
+  dbp::UlArgs a;
+  int S = 0;
+  int st = admm_args(who, n_sc, 1, B, U, C, 1, rho, 1.0f, 0.0f, 1.0f, DBP_REG_ZF, 4, &a, &S);
+  if (st) return st;
+  int gram_prec = 0, inv = 0;
+  st = admm_prec(who, prec, U, S, &gram_prec, &inv);
+  if (st) return st;
+  if (n_sc > 0 && (!H || !factors)) return fail(DBP_ERR_INVALID, "%s: null H or factors", who);
+  if (n_sc == 0) return ok();
+  a.H = static_cast<const dbp::c32*>(H);
+  // the preprocessing also forms H_c^H y_c, which is discarded here: H itself
+  // serves as a readable stand-in for y (n_sym = 1 keeps every read inside it)
+  a.y = a.H;
+  a.fac = static_cast<dbp::c32*>(factors);
+  if (launch_preprocessing(a, U, C, gram_prec, inv, static_cast<hipStream_t>(stream), 1))
+    return device_status(who, hipGetLastError());
+  return ok();
+}
+
+int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, void* s_hat, uint8_t* hard, int n_sc,
+                             int n_sym, int B, int U, int C, int T, float rho, float gamma, float N0, float Es,
+                             int reg, int qam, void* stream) {
+  const char* who = "dbp_detect_admm_factored";
+  dbp::UlArgs a;
+  int S = 0;
+  int st = admm_args(who, n_sc, n_sym, B, U, C, T, rho, gamma, N0, Es, reg, qam, &a, &S);
+  if (st) return st;
+  if (S < U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d < U=%d (S x S branch) not built", who, S, U);
+  if (n_sc > 0 && (!H || !factors || !y || !s_hat)) return fail(DBP_ERR_INVALID, "%s: null pointer", who);
+  if (n_sc == 0) return ok();
+  a.H = static_cast<const dbp::c32*>(H);
+  a.y = static_cast<const dbp::c32*>(y);
+  a.shat = static_cast<dbp::c32*>(s_hat);
+  a.hard = hard;
+  a.fac = const_cast<dbp::c32*>(static_cast<const dbp::c32*>(factors));
+  const Plan pl = make_plan(U, C);
+  return device_status(who, dbp::launch_admm_ul_factored(a, U, pl.nw, static_cast<hipStream_t>(stream)));
 }
 
 int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int n_sc, int n_sym, int B, int U,

@@ -1113,7 +1113,10 @@ __device__ __forceinline__ c32 consensus(c32 wc, int buf, int ls, int G, int u, 
 // HALF: 0 FP32 Gram, 1 / 2 split FP16 / BF16 Gram (mixed modes, U = 32, 64).
 // INV (mixed modes): 0 FP32 matrix-core inverse, 1 FP64 VALU inverse (U = 32),
 // 2 split-FP16 matrix-core inverse.
-template <int G, int HALF, int INV>
+// STAGE: 0 preprocessing and iterations; 1 preprocessing only, B_c^{-1} is
+// written to a.fac (a static channel factored once); 2 iterations only, B_c^{-1}
+// read from a.fac (every symbol's H_c^H y_c by the VALU pass).
+template <int G, int HALF, int INV, int STAGE>
 __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   constexpr int P = 64 / G;
   extern __shared__ float4 smem_raw[];
@@ -1133,8 +1136,15 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   c32 A[G];
 #pragma unroll
   for (int v = 0; v < G; ++v) A[v] = cz();
-  c32 hy0;
-  if constexpr (G == 32 && HALF == 0) {
+  c32 hy0 = cz();
+  // resident factors of this problem: entry v of lane u's row at v * G + u
+  const size_t fo = ((size_t)k * a.C + c) * G * G + u;
+  if constexpr (STAGE == 2) {
+    if (active) {
+#pragma unroll
+      for (int v = 0; v < G; ++v) A[v] = a.fac[fo + (size_t)v * G];
+    }
+  } else if constexpr (G == 32 && HALF == 0) {
     hy0 = gram_mfma_u32<true>(a, A, lane, wave, reinterpret_cast<float*>(line));
   } else if constexpr (G == 32 && HALF == 1) {
     hy0 = gram_inv_mixed_u32<_Float16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
@@ -1159,11 +1169,19 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
       if (v == u) A[v].re += a.rho;
     gj_invert<G>(A, u, line, gbase);
   }
+  if constexpr (STAGE == 1) {
+    if (active) {
+#pragma unroll
+      for (int v = 0; v < G; ++v) a.fac[fo + (size_t)v * G] = A[v];
+    }
+    return;
+  }
 
   int buf = 0;
   for (int n = 0; n < a.n_sym; ++n) {
     c32 hy = hy0;
-    if (n > 0) hy = cluster_pass<G, false>(a.H, a.y, A, k, c, n, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
+    if (n > 0 || STAGE == 2)
+      hy = cluster_pass<G, false>(a.H, a.y, A, k, c, n, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
     // y_c^reg = B_c^{-1} H_c^H y_c; z = y^reg; lambda = 0
     const c32 yreg = group_matvec<G>(A, hy, u, line, gbase);
     c32 z = yreg, lam = cz();
@@ -1415,31 +1433,48 @@ static hipError_t launch(K kernel, const Args& a, int nw, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st) {
+template <int G, int HALF, int INV>
+static hipError_t launch_stage(const UlArgs& a, int nw, hipStream_t st, int stage) {
+  return stage == 1 ? launch(admm_ul_f32<G, HALF, INV, 1>, a, nw, st) : launch(admm_ul_f32<G, HALF, INV, 0>, a, nw, st);
+}
+
+hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st, int stage) {
   switch (U) {
-    case 8: return launch(admm_ul_f32<8, 0, 0>, a, nw, st);
-    case 16: return launch(admm_ul_f32<16, 0, 0>, a, nw, st);
-    case 32: return launch(admm_ul_f32<32, 0, 0>, a, nw, st);
-    case 64: return launch(admm_ul_f32<64, 0, 0>, a, nw, st);
+    case 8: return launch_stage<8, 0, 0>(a, nw, st, stage);
+    case 16: return launch_stage<16, 0, 0>(a, nw, st, stage);
+    case 32: return launch_stage<32, 0, 0>(a, nw, st, stage);
+    case 64: return launch_stage<64, 0, 0>(a, nw, st, stage);
   }
   return hipErrorInvalidValue;
 }
 
 template <int G, int HALF>
-static hipError_t launch_mixed_inv(const UlArgs& a, int inv, int nw, hipStream_t st) {
+static hipError_t launch_mixed_inv(const UlArgs& a, int inv, int nw, hipStream_t st, int stage) {
   switch (inv) {
-    case 0: return launch(admm_ul_f32<G, HALF, 0>, a, nw, st);
-    case 2: return launch(admm_ul_f32<G, HALF, 2>, a, nw, st);
+    case 0: return launch_stage<G, HALF, 0>(a, nw, st, stage);
+    case 2: return launch_stage<G, HALF, 2>(a, nw, st, stage);
   }
   if constexpr (G == 32) {
-    if (inv == 1) return launch(admm_ul_f32<G, HALF, 1>, a, nw, st);
+    if (inv == 1) return launch_stage<G, HALF, 1>(a, nw, st, stage);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, int inv, int nw, hipStream_t st) {
-  if (U == 32) return half == 1 ? launch_mixed_inv<32, 1>(a, inv, nw, st) : launch_mixed_inv<32, 2>(a, inv, nw, st);
-  if (U == 64) return half == 1 ? launch_mixed_inv<64, 1>(a, inv, nw, st) : launch_mixed_inv<64, 2>(a, inv, nw, st);
+hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, int inv, int nw, hipStream_t st, int stage) {
+  if (U == 32)
+    return half == 1 ? launch_mixed_inv<32, 1>(a, inv, nw, st, stage) : launch_mixed_inv<32, 2>(a, inv, nw, st, stage);
+  if (U == 64)
+    return half == 1 ? launch_mixed_inv<64, 1>(a, inv, nw, st, stage) : launch_mixed_inv<64, 2>(a, inv, nw, st, stage);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_admm_ul_factored(const UlArgs& a, int U, int nw, hipStream_t st) {
+  switch (U) {
+    case 8: return launch(admm_ul_f32<8, 0, 0, 2>, a, nw, st);
+    case 16: return launch(admm_ul_f32<16, 0, 0, 2>, a, nw, st);
+    case 32: return launch(admm_ul_f32<32, 0, 0, 2>, a, nw, st);
+    case 64: return launch(admm_ul_f32<64, 0, 0, 2>, a, nw, st);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -23,6 +23,7 @@ struct UlArgs {
   float invC;
   float box_r;
   float kappa;
+  c32* fac;           // [n_sc][C][U][U] resident factors B_c^{-1} (column v of lane u at v*U + u), or null
 };
 
 struct DlArgs {
@@ -37,9 +38,12 @@ struct DlArgs {
 };
 
 size_t smem_bytes(int nw);
-hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
+// stage: 0 detect, 1 only factor (write B_c^{-1} to a.fac)
+hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st, int stage = 0);
 // inv: 0 FP32 matrix-core inverse, 1 FP64 VALU inverse (U = 32), 2 split-FP16 matrix-core inverse
-hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, int inv, int nw, hipStream_t st);
+hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, int inv, int nw, hipStream_t st, int stage = 0);
+// detection against resident factors a.fac (no Gram, no inverse)
+hipError_t launch_admm_ul_factored(const UlArgs& a, int U, int nw, hipStream_t st);
 hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
 hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st);
 

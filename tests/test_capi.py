@@ -85,3 +85,28 @@ def test_precode_rejects():
     bad_ptr = list(ok)
     bad_ptr[2] = None
     assert L.dbp_precode_admm(*bad_ptr) == 1
+
+
+def test_factor_entry_points_reject():
+    L = _native.lib()
+    assert L.dbp_factor_bytes(1200, 32, 8) == 1200 * 8 * 32 * 32 * 8
+    # dbp_factor_admm(H, factors, n_sc, B, U, C, rho, prec, stream)
+    assert L.dbp_factor_admm(1, 1, 4, 256, 32, 8, 0.0, 0, None) == 1          # rho <= 0
+    assert L.dbp_factor_admm(1, None, 4, 256, 32, 8, 1.0, 0, None) == 1       # null factors
+    assert L.dbp_factor_admm(1, 1, 4, 256, 32, 16, 1.0, 0, None) == 2         # S = 16 < U
+    assert L.dbp_factor_admm(1, 1, 4, 256, 32, 8, 1.0, 0x20, None) == 2       # FP64 inverse needs a mixed Gram
+    assert L.dbp_factor_admm(None, None, 0, 256, 32, 8, 1.0, 0, None) == 0    # empty is a no-op
+    # dbp_detect_admm_factored(H, F, y, s, hard, n_sc, n_sym, B, U, C, T, rho, gamma, N0, Es, reg, qam, stream)
+    ok = [1, 1, 1, 1, None, 4, 1, 256, 32, 8, 5, 1.0, 1.0, 0.1, 1.0, 0, 64, None]
+    bad = list(ok)
+    bad[1] = None
+    assert L.dbp_detect_admm_factored(*bad) == 1
+    bad = list(ok)
+    bad[10] = 0
+    assert L.dbp_detect_admm_factored(*bad) == 1                               # T < 1
+    bad = list(ok)
+    bad[16] = 8
+    assert L.dbp_detect_admm_factored(*bad) == 1                               # qam
+    bad = list(ok)
+    bad[8] = 12
+    assert L.dbp_detect_admm_factored(*bad) == 2                               # U not built
