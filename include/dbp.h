@@ -39,8 +39,8 @@ extern "C" {
 #define DBP_ERR_UNSUPPORTED 2  /* valid for the method, not built for the GPU     */
 #define DBP_ERR_NOMEM 3        /* device memory or serving budget exhausted       */
 #define DBP_ERR_DEVICE 4       /* HIP runtime or launch failure                   */
-#define DBP_ERR_BUSY 5         /* serving queue full                              */
-#define DBP_ERR_NOTFOUND 6     /* unknown serving ticket                          */
+#define DBP_ERR_BUSY 5         /* resource still in use (resident channel)        */
+#define DBP_ERR_NOTFOUND 6     /* unknown serving ticket or channel handle        */
 
 /* Regularizer g(s) of the equalization problem (E0), Section III-A. */
 #define DBP_REG_MMSE 0   /* g = N0/(2 Es) ||s||^2, proximal step (E2-MMSE)     */
@@ -195,6 +195,30 @@ int dbp_server_poll(dbp_server* srv, uint64_t ticket, int* done, double* latency
  * admission), and forgets the ticket.  Returns the frame's status. */
 int dbp_server_wait(dbp_server* srv, uint64_t ticket, double* latency_us, double* queue_us);
 int dbp_server_stats(dbp_server* srv, size_t* peak_bytes, int* peak_inflight, uint64_t* completed);
+
+/* Static channels (resident state of the serving loop).  The channel of a
+ * coherence interval is loaded once: dbp_channel_load copies H (pinned host
+ * buffer, or device buffer with DBP_SERVE_DEVICE_IO) into the arena and runs
+ * dbp_factor_admm on it (Algorithm 1's preprocessing, B_c^{-1} kept
+ * resident); it returns once H is copied (H may then be released) while the
+ * factorisation runs on asynchronously.  Frames of received vectors are then
+ * submitted
+ * with dbp_server_submit_factored, which carries only y and runs Algorithm
+ * 1's iterations (dbp_detect_admm_factored) against the resident factors,
+ * ordered after the factorisation.  The channel holds
+ * n_sc*B*U*8 + dbp_factor_bytes(n_sc, U, C) bytes of the budget until
+ * dbp_channel_free, which returns DBP_ERR_BUSY while frames against it are
+ * queued or running and DBP_ERR_NOTFOUND for an unknown handle.  Load returns
+ * DBP_ERR_NOMEM if the channel does not fit in what is free of the budget now;
+ * a frame that cannot fit beside the resident channels is refused with
+ * DBP_ERR_NOMEM at submission.  y / s_hat / hard follow the rules of
+ * dbp_server_submit. */
+int dbp_channel_load(dbp_server* srv, const void* H, int n_sc, int B, int U, int C,
+                     float rho, int prec, int flags, uint64_t* channel);
+int dbp_channel_free(dbp_server* srv, uint64_t channel);
+int dbp_server_submit_factored(dbp_server* srv, uint64_t channel, const void* y,
+                               void* s_hat, uint8_t* hard, int n_sym, int T, float N0,
+                               int reg, int qam, int flags, uint64_t* ticket);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,10 @@ SIGNATURES = {
     "dbp_server_destroy": (_i, [_vp]),
     "dbp_server_submit": (_i, [_vp, _vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i, _i, _i,
                                ctypes.POINTER(ctypes.c_uint64)]),
+    "dbp_channel_load": (_i, [_vp, _vp, _i, _i, _i, _i, _f, _i, _i, ctypes.POINTER(ctypes.c_uint64)]),
+    "dbp_channel_free": (_i, [_vp, ctypes.c_uint64]),
+    "dbp_server_submit_factored": (_i, [_vp, ctypes.c_uint64, _vp, _vp, _u8p, _i, _i, _f, _i, _i, _i,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
     "dbp_server_poll": (_i, [_vp, ctypes.c_uint64, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double)]),
     "dbp_server_wait": (_i, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "dbp_server_stats": (_i, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_uint64)]),

@@ -185,6 +185,41 @@ class Server:
         _native.check(code)
         return tk.value
 
+    def load_channel(self, H, C, rho=1.0, *, prec="fp32", factor=None) -> int:
+        """Copy a static channel H (pinned host or device tensor) into the arena
+        and factor it once; returns a channel handle for :meth:`submit_factored`."""
+        ct = self._ct
+        if not H.is_contiguous():
+            raise ValueError("H must be contiguous")
+        if not H.is_cuda and not H.is_pinned():
+            raise ValueError("H must be a pinned host tensor or a device tensor")
+        n_sc, B, U = H.shape
+        ch = ct.c_uint64()
+        _native.check(_native.lib().dbp_channel_load(self._h, H.data_ptr(), n_sc, B, U, C, float(rho),
+                                                     PREC[prec] | FACTOR[factor], 1 if H.is_cuda else 0,
+                                                     ct.byref(ch)))
+        return ch.value
+
+    def free_channel(self, channel: int):
+        _native.check(_native.lib().dbp_channel_free(self._h, self._ct.c_uint64(channel)))
+
+    def submit_factored(self, channel: int, y, s_out, hard_out, T=5, N0=0.0, *, reg="mmse", qam=16) -> int:
+        """Queue a frame of received vectors y [n_sc, n_sym, B] against a loaded channel."""
+        ct = self._ct
+        dev = y.is_cuda
+        for t, n in ((y, "y"), (s_out, "s_out")) + (((hard_out, "hard_out"),) if hard_out is not None else ()):
+            if not t.is_contiguous():
+                raise ValueError(f"{n} must be contiguous")
+            if dev != t.is_cuda or (not dev and not t.is_pinned()):
+                raise ValueError(f"{n} must be a pinned host tensor, or a device tensor like y")
+        tk = ct.c_uint64()
+        code = _native.lib().dbp_server_submit_factored(
+            self._h, ct.c_uint64(channel), y.data_ptr(), s_out.data_ptr(),
+            hard_out.data_ptr() if hard_out is not None else None, y.shape[1], T, float(N0), REG[reg], qam,
+            1 if dev else 0, ct.byref(tk))
+        _native.check(code)
+        return tk.value
+
     def poll(self, ticket: int):
         ct = self._ct
         done, lat = ct.c_int(), ct.c_double()

@@ -9,6 +9,11 @@
 // concurrently on the device; finished frames give their arena space and slot
 // back, so a waiting frame is admitted as soon as resources free up.  Per-frame
 // latency runs from submit to the completion of the result copy.
+//
+// Static channels: dbp_channel_load copies H into the arena and factors it
+// once (B_c^{-1} per subcarrier and cluster, resident until dbp_channel_free);
+// frames submitted with dbp_server_submit_factored carry only y and run the
+// iterations against those resident factors.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,8 +83,18 @@ class Arena {
   std::map<size_t, size_t> free_;
 };
 
+struct Channel {
+  size_t off = 0, footprint = 0;     // arena block: H copy, then the factors
+  size_t bytes_H = 0;
+  int n_sc = 0, B = 0, U = 0, C = 0;
+  float rho = 0.f;
+  hipEvent_t ready = nullptr;        // recorded after the factorisation
+  int refs = 0;                      // frames queued or in flight against it
+};
+
 struct Frame {
   uint64_t ticket;
+  uint64_t channel = 0;              // nonzero: detect against a resident channel
   const void* H;
   const void* y;
   void* s_out;
@@ -108,6 +123,10 @@ struct dbp_server {
   std::deque<uint64_t> queue;
   std::map<uint64_t, Frame> frames;
   uint64_t next_ticket = 1;
+  std::map<uint64_t, Channel> channels;
+  uint64_t next_channel = 1;
+  size_t channel_bytes = 0;          // arena space held by resident channels
+  hipStream_t load_stream = nullptr;
   std::atomic<bool> stop{false};
   std::thread worker;
   std::string error;
@@ -118,9 +137,42 @@ struct dbp_server {
 
 namespace {
 
+// Frames against a resident channel: wait for its factorisation, then copy y,
+// run the factored iterations and copy the results back.
+int launch_factored(dbp_server* s, Frame& f, hipStream_t st) {
+  const Channel& ch = s->channels.at(f.channel);
+  const char* cbase = static_cast<const char*>(s->base) + ch.off;
+  const void* dH = cbase;
+  const void* dF = cbase + ((ch.bytes_H + 255) & ~size_t(255));
+  if (hipStreamWaitEvent(st, ch.ready, 0) != hipSuccess) return DBP_ERR_DEVICE;
+  const void* y = f.y;
+  void* so = f.s_out;
+  uint8_t* ho = f.hard_out;
+  char* d = static_cast<char*>(s->base) + f.off;
+  if (!(f.flags & DBP_SERVE_DEVICE_IO)) {
+    char* dy = d;
+    char* ds = dy + ((f.bytes_y + 255) & ~size_t(255));
+    char* dh = ds + ((f.bytes_s + 255) & ~size_t(255));
+    if (hipMemcpyAsync(dy, f.y, f.bytes_y, hipMemcpyHostToDevice, st) != hipSuccess) return DBP_ERR_DEVICE;
+    y = dy;
+    so = ds;
+    ho = f.hard_out ? reinterpret_cast<uint8_t*>(dh) : nullptr;
+  }
+  int rc = dbp_detect_admm_factored(dH, dF, y, so, ho, f.n_sc, f.n_sym, f.B, f.U, f.C, f.T, f.rho, 1.0f, f.N0, 1.0f,
+                                    f.reg, f.qam, st);
+  if (rc != DBP_OK) return rc;
+  if (!(f.flags & DBP_SERVE_DEVICE_IO)) {
+    if (hipMemcpyAsync(f.s_out, so, f.bytes_s, hipMemcpyDeviceToHost, st) != hipSuccess) return DBP_ERR_DEVICE;
+    if (f.hard_out && hipMemcpyAsync(f.hard_out, ho, f.bytes_hard, hipMemcpyDeviceToHost, st) != hipSuccess)
+      return DBP_ERR_DEVICE;
+  }
+  return hipEventRecord(s->events[f.slot], st) == hipSuccess ? DBP_OK : DBP_ERR_DEVICE;
+}
+
 // Enqueue copies + detection for an admitted frame on its slot's stream.
 int launch_frame(dbp_server* s, Frame& f) {
   hipStream_t st = s->streams[f.slot];
+  if (f.channel) return launch_factored(s, f, st);
   if (f.flags & DBP_SERVE_DEVICE_IO) {
     // inputs and outputs already in device memory: the arena space only
     // accounts for the frame's share of the budget
@@ -163,6 +215,7 @@ void scheduler(dbp_server* s) {
         f.done = true;
         if (q != hipSuccess) f.status = DBP_ERR_DEVICE;
         s->arena->release(f.off, f.footprint);
+        if (f.channel) --s->channels[f.channel].refs;
         s->slot_frame[i] = 0;
         ++s->completed;
         progressed = true;
@@ -186,6 +239,7 @@ void scheduler(dbp_server* s) {
         // nothing of this frame runs: release and report
         hipStreamSynchronize(s->streams[f.slot]);
         s->arena->release(f.off, f.footprint);
+        if (f.channel) --s->channels[f.channel].refs;
         f.status = rc;
         f.done = true;
         f.t_done = Clock::now();
@@ -235,6 +289,7 @@ int dbp_server_create(int device, size_t hbm_budget_bytes, int n_slots, dbp_serv
       return DBP_ERR_DEVICE;
     }
   }
+  if (hipStreamCreateWithFlags(&s->load_stream, hipStreamNonBlocking) != hipSuccess) return DBP_ERR_DEVICE;
   s->worker = std::thread(scheduler, s);
   *out = s;
   return DBP_OK;
@@ -249,8 +304,11 @@ int dbp_server_destroy(dbp_server* s) {
   s->cv.notify_all();
   s->worker.join();
   for (auto st : s->streams) hipStreamSynchronize(st);
+  hipStreamSynchronize(s->load_stream);
   for (auto st : s->streams) hipStreamDestroy(st);
   for (auto ev : s->events) hipEventDestroy(ev);
+  for (auto& kv : s->channels) hipEventDestroy(kv.second.ready);
+  hipStreamDestroy(s->load_stream);
   hipFree(s->base);
   delete s->arena;
   delete s;
@@ -289,7 +347,110 @@ int dbp_server_submit(dbp_server* s, const void* H_host, const void* y_host, voi
   f.footprint = al(f.bytes_H) + al(f.bytes_y) + al(f.bytes_s) + al(f.bytes_hard);
   f.t_arrive = Clock::now();
   std::lock_guard<std::mutex> lk(s->mu);
-  if (f.footprint > s->arena->size()) return DBP_ERR_NOMEM;   // can never be admitted
+  if (f.footprint > s->arena->size() - s->channel_bytes) return DBP_ERR_NOMEM;   // can never be admitted
+  f.ticket = s->next_ticket++;
+  *ticket = f.ticket;
+  s->frames.emplace(f.ticket, f);
+  s->queue.push_back(f.ticket);
+  s->cv.notify_all();
+  return DBP_OK;
+}
+
+int dbp_channel_load(dbp_server* s, const void* H, int n_sc, int B, int U, int C, float rho, int prec, int flags,
+                     uint64_t* channel) {
+  if (!s || !H || !channel) return DBP_ERR_INVALID;
+  if (n_sc < 1 || B < 1 || U < 1 || C < 1 || B % C || U > B / C || !(rho > 0.f) || (flags & ~DBP_SERVE_DEVICE_IO))
+    return DBP_ERR_INVALID;
+  Channel ch;
+  ch.n_sc = n_sc;
+  ch.B = B;
+  ch.U = U;
+  ch.C = C;
+  ch.rho = rho;
+  ch.bytes_H = size_t(n_sc) * B * U * 8;
+  ch.footprint = ((ch.bytes_H + 255) & ~size_t(255)) + dbp_factor_bytes(n_sc, U, C);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->arena->alloc(ch.footprint, &ch.off)) return DBP_ERR_NOMEM;
+    s->peak_used = std::max(s->peak_used, s->arena->used());
+  }
+  // The block is reserved and known to no one else yet: copy H outside the
+  // lock (synchronously, so the caller may release H on return), then queue
+  // the factorisation and mark its completion.
+  char* d = static_cast<char*>(s->base) + ch.off;
+  void* dF = d + ((ch.bytes_H + 255) & ~size_t(255));
+  const hipMemcpyKind kind = (flags & DBP_SERVE_DEVICE_IO) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  int rc = DBP_OK;
+  if (hipEventCreateWithFlags(&ch.ready, hipEventDisableTiming) != hipSuccess ||
+      hipMemcpyAsync(d, H, ch.bytes_H, kind, s->load_stream) != hipSuccess ||
+      hipStreamSynchronize(s->load_stream) != hipSuccess)
+    rc = DBP_ERR_DEVICE;
+  if (rc == DBP_OK) rc = dbp_factor_admm(d, dF, n_sc, B, U, C, rho, prec, s->load_stream);
+  if (rc == DBP_OK && hipEventRecord(ch.ready, s->load_stream) != hipSuccess) rc = DBP_ERR_DEVICE;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (rc != DBP_OK) {
+    hipStreamSynchronize(s->load_stream);
+    if (ch.ready) hipEventDestroy(ch.ready);
+    s->arena->release(ch.off, ch.footprint);
+    return rc;
+  }
+  s->channel_bytes += (ch.footprint + 255) & ~size_t(255);
+  *channel = s->next_channel++;
+  s->channels.emplace(*channel, ch);
+  return DBP_OK;
+}
+
+int dbp_channel_free(dbp_server* s, uint64_t channel) {
+  if (!s) return DBP_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->channels.find(channel);
+  if (it == s->channels.end()) return DBP_ERR_NOTFOUND;
+  if (it->second.refs > 0) return DBP_ERR_BUSY;
+  // the factorisation must be finished before its memory can be handed out again
+  hipEventSynchronize(it->second.ready);
+  hipEventDestroy(it->second.ready);
+  s->arena->release(it->second.off, it->second.footprint);
+  s->channel_bytes -= (it->second.footprint + 255) & ~size_t(255);
+  s->channels.erase(it);
+  return DBP_OK;
+}
+
+int dbp_server_submit_factored(dbp_server* s, uint64_t channel, const void* y, void* s_hat, uint8_t* hard, int n_sym,
+                               int T, float N0, int reg, int qam, int flags, uint64_t* ticket) {
+  if (!s || !ticket || !y || !s_hat) return DBP_ERR_INVALID;
+  if (n_sym < 1 || T < 1 || !qam_ok(qam) || !(N0 >= 0.f) || (flags & ~DBP_SERVE_DEVICE_IO)) return DBP_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->channels.find(channel);
+  if (it == s->channels.end()) return DBP_ERR_NOTFOUND;
+  Channel& ch = it->second;
+  Frame f{};
+  f.channel = channel;
+  f.H = nullptr;
+  f.y = y;
+  f.s_out = s_hat;
+  f.hard_out = hard;
+  f.n_sc = ch.n_sc;
+  f.n_sym = n_sym;
+  f.B = ch.B;
+  f.U = ch.U;
+  f.C = ch.C;
+  f.T = T;
+  f.qam = qam;
+  f.prec = 0;
+  f.reg = reg;
+  f.flags = flags;
+  f.rho = ch.rho;
+  f.N0 = N0;
+  f.bytes_H = 0;
+  f.bytes_y = size_t(f.n_sc) * n_sym * f.B * 8;
+  f.bytes_s = size_t(f.n_sc) * n_sym * f.U * 8;
+  f.bytes_hard = size_t(f.n_sc) * n_sym * f.U;
+  auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
+  f.footprint = al(f.bytes_y) + al(f.bytes_s) + al(f.bytes_hard);
+  f.t_arrive = Clock::now();
+  // a frame that does not fit beside the resident channels could never be admitted
+  if (f.footprint > s->arena->size() - s->channel_bytes) return DBP_ERR_NOMEM;
+  ++ch.refs;
   f.ticket = s->next_ticket++;
   *ticket = f.ticket;
   s->frames.emplace(f.ticket, f);

@@ -109,3 +109,57 @@ def test_oversized_frame_refused():
         srv.submit(f["H"], f["y"], s, h, f["C"], 5, 1.0, f["N0"], qam=16)
     assert e.value.code == 3
     srv.close()
+
+
+@pytest.mark.parametrize("pinned", [True, False])
+def test_resident_channel_frames(pinned):
+    """A static channel loaded once; four received frames against it, mixed
+    with ordinary frames, each bit-identical to the library's factored call."""
+    say(f"[gpu] serving resident channel pinned={pinned}")
+    B, U, C, n_sc = 256, 32, 8, 120
+    fr = inputs.uplink_frame(inputs.frame_seed(5, 99, 25), n_sc, B, U, 64, 25.0, n_sym=4)
+    Hd = torch.from_numpy(fr.H).cuda()
+    fac = api.factor(Hd, C, 1.0)
+    srv = api.Server(hbm_budget_bytes=1 << 30, n_slots=4)
+    H = torch.from_numpy(fr.H).pin_memory() if pinned else Hd
+    ch = srv.load_channel(H, C, 1.0)
+    others = make_frames(pinned)[:3]
+    tickets, outs, refs = [], [], []
+    for n in range(4):
+        yn = torch.from_numpy(np.ascontiguousarray(fr.y[:, n:n + 1]))
+        yd = yn.cuda()
+        r = api.detect_factored(Hd, fac, yd, fr.N0, C, 1.0, 5, qam=64)
+        refs.append((r[0].cpu(), r[1].cpu()))
+        y = yn.pin_memory() if pinned else yd
+        s, h = out_bufs(dict(n_sc=n_sc, U=U), pinned)
+        tickets.append(srv.submit_factored(ch, y, s, h, 5, fr.N0, qam=64))
+        outs.append((s, h, y))
+        f = others[n % 3]
+        so, ho = out_bufs(f, pinned)
+        tickets.append(srv.submit(f["H"], f["y"], so, ho, f["C"], 5, 1.0, f["N0"], qam=16))
+        outs.append((so, ho, None))
+    for t in tickets:
+        lat, _ = srv.wait(t)
+        assert lat > 0
+    for n in range(4):
+        s, h, _ = outs[2 * n]
+        assert torch.equal(s.cpu(), refs[n][0]) and torch.equal(h.cpu(), refs[n][1])
+    with pytest.raises(_native.DbpError) as e:
+        srv.free_channel(ch + 1000)
+    assert e.value.code == 6
+    srv.free_channel(ch)
+    with pytest.raises(_native.DbpError) as e:
+        srv.free_channel(ch)
+    assert e.value.code == 6
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 8
+
+
+def test_channel_too_large_refused():
+    f = make_frames(True)[5]
+    srv = api.Server(hbm_budget_bytes=1 << 20, n_slots=2)
+    with pytest.raises(_native.DbpError) as e:
+        srv.load_channel(f["H"], f["C"], 1.0)
+    assert e.value.code == 3
+    srv.close()
