@@ -1080,9 +1080,10 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
 // after the barrier each lane sums the C clusters of its subcarrier in cluster
 // order 1..C (identical sum on every cluster, as if broadcast by the fusion
 // node).
-// The padding clusters C..Cp-1 of a subcarrier write zeros, so the sum runs
-// over all Cp slots (a power of two) with a fully unrolled loop; adding the
-// trailing zeros leaves the value unchanged.
+// The padding clusters C..Cp-1 of a subcarrier write zeros, so with UNROLL the
+// sum runs over all Cp slots (a power of two) with a fully unrolled loop;
+// adding the trailing zeros leaves the value unchanged.  Without UNROLL (kernels
+// whose register budget the unrolled form would cut into) it is a loop over C.
 template <int N>
 __device__ __forceinline__ c32 sum_slots(const c32* src, int G) {
   c32 w = cz();
@@ -1091,13 +1092,18 @@ __device__ __forceinline__ c32 sum_slots(const c32* src, int G) {
   return w;
 }
 
+template <bool UNROLL = true>
 __device__ __forceinline__ c32 consensus(c32 wc, int buf, int ls, int G, int u, int C, int Cp, const Smem& sm,
                                          int slot, int nw) {
-  (void)C;
   c32* cb = sm.cons + buf * nw * 64;
   cb[slot] = wc;
   __syncthreads();
   const c32* src = cb + (size_t)ls * Cp * G + u;
+  if (!UNROLL) {
+    c32 w = cz();
+    for (int cc = 0; cc < C; ++cc) w = cadd(w, src[cc * G]);
+    return w;
+  }
   switch (Cp) {
     case 1: return src[0];
     case 2: return sum_slots<2>(src, G);
@@ -1185,7 +1191,7 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
     // y_c^reg = B_c^{-1} H_c^H y_c; z = y^reg; lambda = 0
     const c32 yreg = group_matvec<G>(A, hy, u, line, gbase);
     c32 z = yreg, lam = cz();
-    c32 w = consensus(active ? z : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+    c32 w = consensus<HALF == 0>(active ? z : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
     buf ^= 1;
     c32 s;
     if (a.reg == 2) {
@@ -1200,7 +1206,7 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
       const c32 q = csub(s, lam);
       const c32 bq = group_matvec<G>(A, q, u, line, gbase);
       z = c32{fmaf(a.rho, bq.re, yreg.re), fmaf(a.rho, bq.im, yreg.im)};
-      w = consensus(active ? cadd(z, lam) : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+      w = consensus<HALF == 0>(active ? cadd(z, lam) : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
       buf ^= 1;
       if (a.reg == 2) {
         c32 v = cscale(w, a.invC);
