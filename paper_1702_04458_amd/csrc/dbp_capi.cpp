@@ -170,10 +170,11 @@ int admm_prec(const char* who, int prec, int U, int S, int* gram_prec, int* inv)
   return DBP_OK;
 }
 
-int launch_preprocessing(const dbp::UlArgs& a, int U, int C, int gram_prec, int inv, hipStream_t st, int stage) {
+hipError_t launch_preprocessing(const dbp::UlArgs& a, int U, int C, int gram_prec, int inv, hipStream_t st,
+                                int stage) {
   const Plan pl = make_plan(U, C);
-  if (gram_prec == DBP_PREC_FP32) return dbp::launch_admm_ul_f32(a, U, pl.nw, st, stage) == hipSuccess ? 0 : -1;
-  return dbp::launch_admm_ul_mixed(a, U, gram_prec, inv, pl.nw, st, stage) == hipSuccess ? 0 : -1;
+  if (gram_prec == DBP_PREC_FP32) return dbp::launch_admm_ul_f32(a, U, pl.nw, st, stage);
+  return dbp::launch_admm_ul_mixed(a, U, gram_prec, inv, pl.nw, st, stage);
 }
 
 }  // namespace
@@ -197,9 +198,7 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
   a.y = static_cast<const dbp::c32*>(y);
   a.shat = static_cast<dbp::c32*>(s_hat);
   a.hard = hard;
-  if (launch_preprocessing(a, U, C, gram_prec, inv, static_cast<hipStream_t>(stream), 0))
-    return device_status(who, hipGetLastError());
-  return ok();
+  return device_status(who, launch_preprocessing(a, U, C, gram_prec, inv, static_cast<hipStream_t>(stream), 0));
 }
 
 size_t dbp_factor_bytes(int n_sc, int U, int C) {
@@ -223,9 +222,7 @@ int dbp_factor_admm(const void* H, void* factors, int n_sc, int B, int U, int C,
   // serves as a readable stand-in for y (n_sym = 1 keeps every read inside it)
   a.y = a.H;
   a.fac = static_cast<dbp::c32*>(factors);
-  if (launch_preprocessing(a, U, C, gram_prec, inv, static_cast<hipStream_t>(stream), 1))
-    return device_status(who, hipGetLastError());
-  return ok();
+  return device_status(who, launch_preprocessing(a, U, C, gram_prec, inv, static_cast<hipStream_t>(stream), 1));
 }
 
 int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, void* s_hat, uint8_t* hard, int n_sc,

@@ -1323,14 +1323,22 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
   const int S = a.S;
   const c32* Hk = a.H + (size_t)k * a.B * G + (size_t)c * S * G;
 
-  c32 hcol[SG], hrow[G], A[SG];
+  // When SG = G / 2 the row of Hu_c that H_c^H v needs is split over two
+  // lanes: lane u holds entries RS * (u / SG) .. + RS - 1 of row u % SG, and
+  // the two half sums are combined by one exchange.  Otherwise lane u < S
+  // holds the whole row u.
+  constexpr bool SPLIT = (2 * SG == G);
+  constexpr int RS = SPLIT ? SG : G;       // row entries held per lane
+  const int ra = SPLIT ? (u % SG) : u;     // row of Hu_c held by this lane
+  const int r0 = SPLIT ? RS * (u / SG) : 0;
+  c32 hcol[SG], hrow[RS], A[SG];
 #pragma unroll
   for (int i = 0; i < SG; ++i) {
     hcol[i] = (active && i < S) ? Hk[(size_t)i * G + u] : cz();
     A[i] = cz();
   }
 #pragma unroll
-  for (int i = 0; i < G; ++i) hrow[i] = (active && u < S) ? Hk[(size_t)u * G + i] : cz();
+  for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * G + r0 + i] : cz();
   // A_c = H_c^H H_c + rho^{-1} I_S with (H_c^H H_c)[a][b] = sum_u conj(Hu[a][u]) Hu[b][u].
   if constexpr (G == 32 && SG == 16) {
     gram_dl_mfma_s16_u32(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
@@ -1347,13 +1355,14 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
       wave_lds_sync();
       c32 acc = cz();
 #pragma unroll
-      for (int v0 = 0; v0 < G; v0 += 8) {
+      for (int v0 = 0; v0 < RS; v0 += 8) {
         c32 row[8];
-        lds_read_vec<8>(stage + gbase + v0, row);
+        lds_read_vec<8>(stage + gbase + r0 + v0, row);
 #pragma unroll
         for (int v = 0; v < 8; ++v) cmacc(acc, hrow[v0 + v], row[v]);
       }
       wave_lds_sync();
+      if (SPLIT) acc = cadd(acc, c32{__shfl_xor(acc.re, SG, 64), __shfl_xor(acc.im, SG, 64)});
 #pragma unroll
       for (int i = 0; i < SG; ++i)
         if (i == b) A[i] = (u < S) ? acc : cz();
@@ -1376,13 +1385,14 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
       wave_lds_sync();
       c32 acc = cz();
 #pragma unroll
-      for (int v0 = 0; v0 < G; v0 += 8) {
+      for (int v0 = 0; v0 < RS; v0 += 8) {
         c32 vv[8];
-        lds_read_vec<8>(line + gbase + v0, vv);
+        lds_read_vec<8>(line + gbase + r0 + v0, vv);
 #pragma unroll
         for (int i = 0; i < 8; ++i) cmacc(acc, hrow[v0 + i], vv[i]);
       }
       wave_lds_sync();
+      if (SPLIT) acc = cadd(acc, c32{__shfl_xor(acc.re, SG, 64), __shfl_xor(acc.im, SG, 64)});
       return group_matvec<SG>(A, (u < S) ? acc : cz(), u, line, gbase);
     };
     c32 x = apply(z);
