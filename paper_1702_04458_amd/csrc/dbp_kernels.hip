@@ -199,7 +199,8 @@ __device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)
 //   Re G = sum_s Hr[s]^T Hr[s] + Hi[s]^T Hi[s],
 //   Im G = sum_s Hr[s]^T Hi[s] - Hi[s]^T Hr[s].
 // For the Gram of one problem lane l supplies H[s0 + l/32][l%32] as both the A
-// and the B operand.  The 32x32 result leaves lane l holding column l%32 for
+// and the B operand; the imaginary part accumulates only M = Hr^T Hi (one
+// MFMA per row pair instead of two) and is antisymmetrised at the end.  The 32x32 result leaves lane l holding column l%32 for
 // rows 8(r/4) + 4(l/32) + r%4 (r = 0..15); by Hermitian symmetry that is row
 // l%32 conjugated, for half h = l/32 of the columns.  With INVERT the
 // accumulators are replaced by (G + rho I)^{-1} on the matrix cores first.
@@ -207,7 +208,8 @@ __device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)
 // its own problem (lane-row layout, problem = l/32).  Returns row u of
 // H_c^H y_c for symbol 0.
 template <bool INVERT>
-__device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave, float* line) {
+__device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave, float* line,
+                                             float* stage) {
   const int h = lane >> 5, col = lane & 31;
   f32x16 re[2], im[2];
   c32 hyp[2];
@@ -254,7 +256,6 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
         re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, x.re, re[p], 0, 0, 0);
         re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, x.im, re[p], 0, 0, 0);
         im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, x.im, im[p], 0, 0, 0);
-        im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(-x.im, x.re, im[p], 0, 0, 0);
         cmacc(hyp[p], x, yv[p][q]);
       }
     }
@@ -265,6 +266,24 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
         hv[p][q] = hn[p][q];
         yv[p][q] = yn[p][q];
       }
+  }
+  // im holds M = Hr^T Hi; Im G = M - M^T.  M goes through the wave's 4 KB
+  // stage buffer with an XOR-swizzled column (entry (i, j) at 32 i + (j ^ i)),
+  // conflict-free both for the row-wise write and the transposed read.
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      stage[32 * i + (col ^ i)] = im[p][r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      im[p][r] -= stage[32 * col + (i ^ col)];
+    }
+    wave_lds_sync();
   }
   if (INVERT) gj_invert_mfma_u32(re, im, lane, a.rho, line);
   // exchange halves: lanes < 32 keep problem 0, lanes >= 32 keep problem 1
@@ -343,7 +362,7 @@ __device__ __forceinline__ int norm_shift(int S) { return 9 + (32 - __builtin_cl
 // problem's scaling exponent either way.
 template <typename HT, bool NORM>
 __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2], f32x16 (&im)[2], c32 (&hyp)[2],
-                                               int lane, int wave, int (&ex)[2]) {
+                                               int lane, int wave, int (&ex)[2], float* stage) {
   typedef typename HalfMma<HT>::V V;
   const int h = lane >> 5, col = lane & 31;
   const c32* Hp[2];
@@ -392,7 +411,7 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
         const c32 yv = ld_or_zero(yp[p] + sc, ok);
         cmacc(hyp[p], v[t], yv);
       }
-      V rh, rl, ih, il, nih, nil;
+      V rh, rl, ih, il;
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const float xr = ldexpf(v[t].re, ex[p]), xi = ldexpf(v[t].im, ex[p]);
@@ -401,8 +420,6 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
         rl[t] = (HT)(xr - (float)hr);
         ih[t] = hi;
         il[t] = (HT)(xi - (float)hi);
-        nih[t] = -ih[t];
-        nil[t] = -il[t];
       }
       // Re G = Hr^T Hr + Hi^T Hi
       re[p] = HalfMma<HT>::mma(rh, rh, re[p]);
@@ -411,14 +428,27 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
       re[p] = HalfMma<HT>::mma(ih, ih, re[p]);
       re[p] = HalfMma<HT>::mma(ih, il, re[p]);
       re[p] = HalfMma<HT>::mma(il, ih, re[p]);
-      // Im G = Hr^T Hi - Hi^T Hr
+      // M = Hr^T Hi (Im G = M - M^T, below)
       im[p] = HalfMma<HT>::mma(rh, ih, im[p]);
       im[p] = HalfMma<HT>::mma(rh, il, im[p]);
       im[p] = HalfMma<HT>::mma(rl, ih, im[p]);
-      im[p] = HalfMma<HT>::mma(nih, rh, im[p]);
-      im[p] = HalfMma<HT>::mma(nih, rl, im[p]);
-      im[p] = HalfMma<HT>::mma(nil, rh, im[p]);
     }
+  }
+  // antisymmetrise through the stage buffer, as in gram_mfma_u32
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      stage[32 * i + (col ^ i)] = im[p][r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      im[p][r] -= stage[32 * col + (i ^ col)];
+    }
+    wave_lds_sync();
   }
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
@@ -586,7 +616,7 @@ __device__ __forceinline__ c32 gram_inv_mixed_u32(const UlArgs& a, c32 (&A)[32],
   f32x16 re[2], im[2];
   c32 hyp[2];
   int ex[2];
-  gram_split_u32<HT, INV == 2>(a, re, im, hyp, lane, wave, ex);
+  gram_split_u32<HT, INV == 2>(a, re, im, hyp, lane, wave, ex, reinterpret_cast<float*>(line64));
   if (INV == 0) {
     gj_invert_mfma_u32(re, im, lane, a.rho, reinterpret_cast<float*>(line64));
     acc_to_rows_u32(re, im, A, h);
@@ -1151,7 +1181,8 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
       for (int v = 0; v < G; ++v) A[v] = a.fac[fo + (size_t)v * G];
     }
   } else if constexpr (G == 32 && HALF == 0) {
-    hy0 = gram_mfma_u32<true>(a, A, lane, wave, reinterpret_cast<float*>(line));
+    hy0 = gram_mfma_u32<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
+                              reinterpret_cast<float*>(sm.stage + wave * kStageRows * 64));
   } else if constexpr (G == 32 && HALF == 1) {
     hy0 = gram_inv_mixed_u32<_Float16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
   } else if constexpr (G == 32 && HALF == 2) {
@@ -1252,7 +1283,8 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   for (int v = 0; v < G; ++v) A[v] = cz();
   c32 hy0;
   if constexpr (G == 32)
-    hy0 = gram_mfma_u32<false>(a, A, lane, wave, reinterpret_cast<float*>(line));
+    hy0 = gram_mfma_u32<false>(a, A, lane, wave, reinterpret_cast<float*>(line),
+                               reinterpret_cast<float*>(sm.stage + wave * kStageRows * 64));
   else if constexpr (G == 16)
     hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
   else if constexpr (G == 64)
