@@ -645,7 +645,9 @@ __device__ __forceinline__ c32 gram_inv_mixed_u32(const UlArgs& a, c32 (&A)[32],
 
 // Gram matrices of the four problems of a wave for U = 16 (P = 4) on the
 // matrix cores with v_mfma_f32_16x16x4f32, K running over quadruples of
-// antenna rows: lane l supplies H[s0 + l/16][l%16] as both operands.  The
+// antenna rows: lane l supplies H[s0 + l/16][l%16] as both operands; the
+// imaginary part accumulates only M = Hr^T Hi (three MFMAs per row quadruple
+// instead of four) and Im G = M - M^T is formed in the transpose.  The
 // 16x16 result leaves lane l holding column l%16 for rows 4(l/16) + r
 // (r = 0..3) of every problem; by Hermitian symmetry that is row l%16
 // conjugated, columns 4(l/16) .. 4(l/16)+3.  An LDS transpose (two problems
@@ -697,8 +699,7 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
         const c32 x = hv[p][j];
         re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, x.re, re[p], 0, 0, 0);
         re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, x.im, re[p], 0, 0, 0);
-        im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, x.im, im[p], 0, 0, 0);
-        im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(-x.im, x.re, im[p], 0, 0, 0);
+        im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, x.im, im[p], 0, 0, 0);   // M = Hr^T Hi
         cmacc(hyp[p], x, yv[p][j]);
       }
     }
@@ -710,23 +711,29 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
         yv[p][j] = yn[p][j];
       }
   }
-  // transpose through LDS: buf[pp][q'][r][col], two problems per pass
+  // Transpose through LDS, two problems per pass: entry (i, j) of problem pp at
+  // (16 pp + i) 16 + (j ^ i) (XOR swizzle: conflict-free for the column read
+  // and for the transposed read).  im holds M = Hr^T Hi, and
+  // Im G[v][col] = M[v][col] - M[col][v].
+  float* stf = reinterpret_cast<float*>(stage);
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
 #pragma unroll
     for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) stage[((pp * 4 + q) * 4 + r) * 16 + col] = c32{re[2 * half + pp][r], im[2 * half + pp][r]};
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * q + r;
+        stage[(16 * pp + i) * 16 + (col ^ i)] = c32{re[2 * half + pp][r], im[2 * half + pp][r]};
+      }
     wave_lds_sync();
     if ((q >> 1) == half) {
       const int pp = q & 1;
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const c32 v = stage[((pp * 4 + qq) * 4 + r) * 16 + col];
-          A[4 * qq + r] = c32{v.re, -v.im};
-        }
+      for (int v = 0; v < 16; ++v) {
+        const c32 g = stage[(16 * pp + v) * 16 + (col ^ v)];
+        const float mt = stf[2 * ((16 * pp + col) * 16 + (v ^ col)) + 1];
+        A[v] = c32{g.re, mt - g.im};
+      }
     }
     wave_lds_sync();
   }
@@ -1307,13 +1314,14 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
       buf ^= 1;
       const c32 e = c32{fmaf(a.rho, pv.re, w.re), fmaf(a.rho, pv.im, w.im)};
       const float pe = group_sum<G>(pv.re * e.re + pv.im * e.im);
-      const float alpha = (rr > 0.f) ? rr / pe : 0.f;
+      // quotients by the hardware reciprocal (1 ulp) instead of a full division
+      const float alpha = (rr > 0.f) ? rr * __builtin_amdgcn_rcpf(pe) : 0.f;
       x.re = fmaf(alpha, pv.re, x.re);
       x.im = fmaf(alpha, pv.im, x.im);
       r.re = fmaf(-alpha, e.re, r.re);
       r.im = fmaf(-alpha, e.im, r.im);
       const float rr_new = group_sum<G>(r.re * r.re + r.im * r.im);
-      const float beta = (rr > 0.f) ? rr_new / rr : 0.f;
+      const float beta = (rr > 0.f) ? rr_new * __builtin_amdgcn_rcpf(rr) : 0.f;
       pv.re = fmaf(beta, pv.re, r.re);
       pv.im = fmaf(beta, pv.im, r.im);
       rr = rr_new;
