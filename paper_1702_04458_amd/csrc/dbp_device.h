@@ -120,7 +120,7 @@ __device__ __forceinline__ float group_min(float v) {
 // column it stands for, so one broadcast line per step gives row k in slot
 // order.
 template <int G>
-__device__ __forceinline__ void gj_invert(c32 (&A)[G], int u, c32* line, int gbase) {
+__device__ __forceinline__ void gj_invert_rot(c32 (&A)[G], int u, c32* line, int gbase) {
   for (int k = 0; k < G; ++k) {
     const float sg = (u < k) ? -1.f : 1.f;
     // lanes past the matrix (a group wider than G) must not publish
@@ -146,6 +146,77 @@ __device__ __forceinline__ void gj_invert(c32 (&A)[G], int u, c32* line, int gba
     A[G - 1] = pivot_new;
     wave_lds_sync();
   }
+}
+
+// The same inversion with lazy row and column scales, fully unrolled (small
+// G): the stored matrix S stays Hermitian, so lane u's multiplier for pivot k
+// is its own entry conj(S[k][u]) = S[u][k] and only column k is broadcast.
+// Sweeping pivot k (value d) leaves row k and column k unchanged except the
+// diagonal, which becomes -d, and updates every other entry by
+// S[u][j] -= S[u][k] conj(S[j][k]) / d; at the end
+// B^{-1}[u][j] = -S[u][j] / (d_u d_j).  Lanes u >= N (a group wider than the
+// matrix) take no part.
+template <int N>
+__device__ __forceinline__ void gj_invert_sym(c32 (&A)[N], int u, c32* line, int gbase) {
+  float pvv = 0.f;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (u < N) line[gbase + u] = A[k];
+    wave_lds_sync();
+    c32 col[N];
+#pragma unroll
+    for (int j = 0; j < N; j += 2) {
+      const float4 v = *reinterpret_cast<const float4*>(line + gbase + j);
+      col[j] = c32{v.x, v.y};
+      col[j + 1] = c32{v.z, v.w};
+    }
+    wave_lds_sync();
+    const float pv = __builtin_amdgcn_rcpf(col[k].re);
+    const bool me = (u == k);
+    // t = -S[u][k] / d (zero on the pivot row, which the sweep leaves alone)
+    const float tr = me ? 0.f : -A[k].re * pv, ti = me ? 0.f : -A[k].im * pv;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (j == k) continue;
+      // A[j] += t * conj(col[j])
+      A[j].re = fmaf(tr, col[j].re, A[j].re);
+      A[j].re = fmaf(ti, col[j].im, A[j].re);
+      A[j].im = fmaf(ti, col[j].re, A[j].im);
+      A[j].im = fmaf(-tr, col[j].im, A[j].im);
+    }
+    if (me) {
+      A[k].re = -A[k].re;
+      pvv = pv;
+    }
+    // Keep every update of this step in place: without this the compiler
+    // defers updates to the entries a later step reads, keeping the broadcast
+    // columns of many steps live at once.
+#pragma unroll
+    for (int j = 0; j < N; ++j) asm volatile("" : "+v"(A[j].re), "+v"(A[j].im));
+  }
+  if (u < N) line[gbase + u] = c32{pvv, 0.f};
+  wave_lds_sync();
+#pragma unroll
+  for (int j = 0; j < N; j += 2) {
+    const float4 v = *reinterpret_cast<const float4*>(line + gbase + j);
+    const float s0 = -pvv * v.x, s1 = -pvv * v.z;
+    A[j].re *= s0;
+    A[j].im *= s0;
+    A[j + 1].re *= s1;
+    A[j + 1].im *= s1;
+  }
+  wave_lds_sync();
+}
+
+// Regularised-matrix inverse of the lane-row layout: the unrolled Hermitian
+// sweep for matrices up to 16 x 16 (N a multiple of 8), the rolled rotated
+// sweep above for larger ones (code size).
+template <int G>
+__device__ __forceinline__ void gj_invert(c32 (&A)[G], int u, c32* line, int gbase) {
+  if constexpr (G <= 16 && G % 8 == 0)
+    gj_invert_sym<G>(A, u, line, gbase);
+  else
+    gj_invert_rot<G>(A, u, line, gbase);
 }
 
 // out = M q for the group matrix M (row u in A), q distributed one entry per
