@@ -222,17 +222,45 @@ __device__ __forceinline__ void gj_invert(c32 (&A)[G], int u, c32* line, int gba
 // out = M q for the group matrix M (row u in A), q distributed one entry per
 // lane.  A group of 16 lanes is one DPP row: entry v of q is broadcast from
 // lane v with row_newbcast; wider groups go through the wave's LDS line.
-template <int V>
-__device__ __forceinline__ void matvec16_step(const c32 (&A)[16], c32 q, c32& acc) {
-  const c32 qv = c32{dpp<0x150 + V>(q.re), dpp<0x150 + V>(q.im)};
-  cmac(acc, A[V], qv);
+// Four entries v0 .. v0+3 of the 16-lane matrix-vector product: every FMA
+// takes its broadcast operand straight through DPP (row_newbcast), so the
+// broadcast costs no separate move.  The surrounding s_nop 1 covers the two
+// wait states a DPP read needs after a VALU write of its source (q), and the
+// same for any DPP consumer of the results after the block.
+#define DBP_MV16_BLOCK(V0, V1, V2, V3)                                                     \
+  asm volatile(                                                                          \
+      "s_nop 1\n\t"                                                                      \
+      "v_fmac_f32_dpp %0, %4, %6 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %0, -%5, %7 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %1, %5, %6 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %1, %4, %7 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %2, %4, %8 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %2, -%5, %9 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %3, %5, %8 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %3, %4, %9 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %0, %4, %10 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %0, -%5, %11 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"  \
+      "v_fmac_f32_dpp %1, %5, %10 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %1, %4, %11 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %2, %4, %12 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %2, -%5, %13 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"  \
+      "v_fmac_f32_dpp %3, %5, %12 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %3, %4, %13 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "s_nop 1"                                                                          \
+      : "+v"(a0.re), "+v"(a0.im), "+v"(a1.re), "+v"(a1.im)                               \
+      : "v"(q.re), "v"(q.im), "v"(A[V0].re), "v"(A[V0].im), "v"(A[V1].re), "v"(A[V1].im), \
+        "v"(A[V2].re), "v"(A[V2].im), "v"(A[V3].re), "v"(A[V3].im))
+
+// acc = sum_v A[v] * q_v with q_v held by lane v of the 16-lane row
+__device__ __forceinline__ c32 matvec16(const c32 (&A)[16], c32 q) {
+  c32 a0 = cz(), a1 = cz();
+  DBP_MV16_BLOCK(0, 1, 2, 3);
+  DBP_MV16_BLOCK(4, 5, 6, 7);
+  DBP_MV16_BLOCK(8, 9, 10, 11);
+  DBP_MV16_BLOCK(12, 13, 14, 15);
+  return cadd(a0, a1);
 }
-template <int... V>
-__device__ __forceinline__ c32 matvec16(const c32 (&A)[16], c32 q, std::integer_sequence<int, V...>) {
-  c32 acc0 = cz(), acc1 = cz();
-  ((V % 2 == 0 ? matvec16_step<V>(A, q, acc0) : matvec16_step<V>(A, q, acc1)), ...);
-  return cadd(acc0, acc1);
-}
+#undef DBP_MV16_BLOCK
 
 template <int G>
 __device__ __forceinline__ c32 group_matvec(const c32 (&A)[G], c32 q, int u, c32* line, int gbase) {
@@ -240,7 +268,7 @@ __device__ __forceinline__ c32 group_matvec(const c32 (&A)[G], c32 q, int u, c32
     (void)u;
     (void)line;
     (void)gbase;
-    return matvec16(A, q, std::make_integer_sequence<int, 16>{});
+    return matvec16(A, q);
   }
   line[gbase + u] = q;
   wave_lds_sync();
