@@ -1,0 +1,86 @@
+"""Full-size launches as the benchmark times them, checked on sampled outputs
+the FP64 oracle computes one by one, and hard-decision agreement with the
+oracle counted over whole frames."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import dbp_oracle as O  # noqa: E402
+from paper_1702_04458_amd import inputs  # noqa: E402
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1702_04458_amd import api  # noqa: E402
+
+from test_gpu_parity import check_hard, rel_err, threshold_gap, to_dev  # noqa: E402
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def device_frame(n_sc, B, U, qam, snr_db, seed):
+    """Seeded frame generated on the device (same distribution as the input
+    recipe: CN(0,1) channel, unit-energy QAM, N0 = U / SNR)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    L = inputs.qam_side(qam)
+    kappa = inputs.qam_kappa(qam)
+    sd = 0.5 ** 0.5
+    H = torch.complex(torch.randn(n_sc, B, U, device="cuda", generator=g) * sd,
+                      torch.randn(n_sc, B, U, device="cuda", generator=g) * sd)
+    iI = torch.randint(0, L, (n_sc, U), device="cuda", generator=g)
+    iQ = torch.randint(0, L, (n_sc, U), device="cuda", generator=g)
+    s = torch.complex((2 * iI - (L - 1)).float() / kappa, (2 * iQ - (L - 1)).float() / kappa)
+    N0 = U / 10.0 ** (snr_db / 10.0)
+    nsd = (N0 / 2) ** 0.5
+    n = torch.complex(torch.randn(n_sc, B, device="cuda", generator=g) * nsd,
+                      torch.randn(n_sc, B, device="cuda", generator=g) * nsd)
+    y = (torch.matmul(H, s.unsqueeze(-1)).squeeze(-1) + n).unsqueeze(1).contiguous()
+    return H.contiguous(), y, N0
+
+
+@pytest.mark.parametrize("algo,B,U,C,qam,snr", [("admm", 256, 32, 8, 64, 25.0), ("admm", 128, 16, 8, 16, 10.0),
+                                                ("cg", 128, 16, 8, 16, 10.0)])
+def test_bench_launch_sampled(algo, B, U, C, qam, snr):
+    """9600 subcarriers (eight 1200-subcarrier frames) in one launch, as the
+    benchmark step; 48 sampled subcarriers against the oracle."""
+    say(f"[gpu] full-size launch {algo} B={B} U={U} C={C}")
+    H, y, N0 = device_frame(9600, B, U, qam, snr, seed=77 + U)
+    s, h = api.detect(H, y, N0, C, 1.0, 5, algo=algo, qam=qam)
+    torch.cuda.synchronize()
+    sel = np.sort(np.random.default_rng(U).choice(9600, 48, replace=False))
+    Hs = H[sel].cpu().numpy()
+    ys = y[sel].cpu().numpy()
+    if algo == "admm":
+        ref = O.admm_ul_frame(Hs, ys, C, 1.0, 5, N0)
+    else:
+        ref = O.dcg_ul_frame(Hs, ys, C, 5, N0)
+    ss, hs = s[sel].cpu().numpy(), h[sel].cpu().numpy()
+    err = rel_err(ss, ref)
+    say(f"    rel_err={err:.2e}")
+    assert err <= 1e-5
+    check_hard(ss, hs, ref, qam)
+
+
+@pytest.mark.parametrize("B,U,C,qam,snr", [(256, 32, 8, 64, 15.0), (128, 16, 8, 16, 0.0)])
+def test_hard_decisions_agree_on_whole_frames(B, U, C, qam, snr):
+    """Every symbol of a 1200-subcarrier frame against the oracle's FP64
+    decision: the count of differing symbols is printed; all of them must sit
+    within the guard band of a threshold and they may make up at most 1e-4 of
+    the symbols (identical decisions on >= 99.99 %)."""
+    say(f"[gpu] hard-decision agreement B={B} U={U} snr={snr}")
+    fr = inputs.uplink_frame(inputs.frame_seed(31, U, int(snr)), 1200, B, U, qam, snr)
+    s, h = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, C, 1.0, 5, qam=qam)
+    torch.cuda.synchronize()
+    s, h = s.cpu().numpy(), h.cpu().numpy()
+    ref = O.admm_ul_frame(fr.H, fr.y, C, 1.0, 5, fr.N0)
+    diff = h != O.slice_qam(ref, qam)
+    near = threshold_gap(ref, qam) < 1e-3
+    say(f"    {int(diff.sum())} of {diff.size} decisions differ ({int(near.sum())} oracle values near a threshold)")
+    check_hard(s, h, ref, qam)
