@@ -1165,7 +1165,8 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   extern __shared__ float4 smem_raw[];
   const int nw = blockDim.x >> 6;
   Smem sm = carve(reinterpret_cast<c32*>(smem_raw), nw);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: addresses in SALU
   const int g = lane / G, u = lane % G;
   const int lp = wave * P + g;
   const int ls = lp / a.Cp, c = lp % a.Cp;
@@ -1275,7 +1276,8 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   extern __shared__ float4 smem_raw[];
   const int nw = blockDim.x >> 6;
   Smem sm = carve(reinterpret_cast<c32*>(smem_raw), nw);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: addresses in SALU
   const int g = lane / G, u = lane % G;
   const int lp = wave * P + g;
   const int ls = lp / a.Cp, c = lp % a.Cp;
@@ -1351,7 +1353,8 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
   extern __shared__ float4 smem_raw[];
   const int nw = blockDim.x >> 6;
   Smem sm = carve(reinterpret_cast<c32*>(smem_raw), nw);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: addresses in SALU
   const int g = lane / G, u = lane % G;
   const int lp = wave * P + g;
   const int ls = lp / a.Cp, c = lp % a.Cp;
