@@ -370,8 +370,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-single-frame", action="store_true", help="skip the single-frame latency launches")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--frames-per-step", type=int, default=8,
-                    help="1200-subcarrier frames processed by one launch (one step)")
+    ap.add_argument("--frames-per-step", type=int, default=32,
+                    help="1200-subcarrier frames processed by one launch (one step); 32 frames keep the "
+                         "wave-scheduling tail of the launch near 1 %%")
     ap.add_argument("--n-sc", type=int, default=0, help="subcarriers per step (overrides --frames-per-step)")
     ap.add_argument("--T", type=int, default=0, help="override the iteration count of the workload")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
