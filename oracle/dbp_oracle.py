@@ -17,9 +17,11 @@ Baseband Processing for Massive MU-MIMO Systems" (arXiv:1702.04458):
 * ``dcg_ul``       -- Algorithm 2 (decentralized conjugate gradients,
                       Section III-D, eqs. CGiteration / CGdecentralization).
 * ``admm_dl``      -- Algorithm 3 (decentralized ADMM beamforming, Section IV),
-                      A_c (S x S) and B_c (U x U) branches, epsilon = 0.
+                      A_c (S x S) and B_c (U x U) branches; epsilon = 0 as in the
+                      algorithm, or epsilon > 0 with the z-update of Lemma 2.
 * ``admm_dl_literal`` -- the steps (P1), (P2), (P3) of Section IV-B written as
-                      argmin / projection problems; used to pin ``admm_dl``.
+                      argmin / projection problems (P2 for epsilon > 0 solved
+                      through its Lagrange multiplier); used to pin ``admm_dl``.
 * ``mmse_detect``, ``zf_detect``, ``zf_precode`` -- centralized closed forms
                       (Section III-A, problem E0; Section IV-A, problem P0 with
                       epsilon = 0) used as convergence pins.
@@ -46,6 +48,10 @@ Readings of points where the paper is silent or inconsistent:
 * Downlink per-cluster power budget (not part of problem P0): after Algorithm 3,
   a common gain beta = min(1, min_c sqrt(P_c / ||x_c||^2)) is applied to the
   whole vector, so every cluster meets its budget and the users see beta * s.
+* Lemma 2 (epsilon > 0): the statement divides epsilon by ||s - v|| with
+  v = w / C, the proof by ||s - D w_all|| = ||s - w||.  Only the proof's form
+  yields a z with ||s - sum_c z_c|| <= epsilon, so the oracle uses ||s - w||.
+  When s = w the step adds nothing (factor 0).
 """
 from __future__ import annotations
 
@@ -56,7 +62,8 @@ import numpy as np
 __all__ = [
     "partition_rows", "admm_ul", "admm_ul_literal", "admm_ul_frame",
     "dcg_ul", "dcg_ul_frame", "admm_dl", "admm_dl_literal", "admm_dl_frame",
-    "mmse_detect", "zf_detect", "zf_precode", "slice_qam", "slice_qam_f32",
+    "mmse_detect", "zf_detect", "zf_precode", "eps_precode", "lemma2_factor",
+    "project_ball_constraint", "slice_qam", "slice_qam_f32",
     "qam_levels", "box_radius", "power_scale", "prox",
 ]
 
@@ -327,10 +334,18 @@ def dcg_ul_frame(H, y, C, T, N0, Es=1.0, reg="mmse"):
 
 
 # ---------------------------------------------------------------------------
-# Algorithm 3: decentralized ADMM-based beamforming (epsilon = 0)
+# Algorithm 3: decentralized ADMM-based beamforming
 # ---------------------------------------------------------------------------
 
-def admm_dl(Hu, s, C, rho, T, gamma=1.0, mode=None):
+def lemma2_factor(d, eps):
+    """Scale max{0, 1 - eps / ||d||} of Lemma 2 for d = s - w (1 at eps = 0)."""
+    if eps == 0.0:
+        return 1.0
+    nd = float(np.linalg.norm(d))
+    return max(0.0, 1.0 - eps / nd) if nd > 0.0 else 0.0
+
+
+def admm_dl(Hu, s, C, rho, T, gamma=1.0, mode=None, eps=0.0):
     """Algorithm 3 for one target vector s (U,).
 
     ``Hu`` is the uplink channel (B, U); by reciprocity the downlink channel is
@@ -339,8 +354,10 @@ def admm_dl(Hu, s, C, rho, T, gamma=1.0, mode=None):
                     S >  U: B_c = H_c H_c^H + rho^-1 I_U,  x_c = H_c^H B_c^{-1} v
     Init: z_c = max(U/B, 1/C) s, lambda_c = 0, x_c = apply(z_c).
     For t = 2..T:  m_c = H_c x_c;  w_c = m_c - lambda_c;  w = sum_c w_c;
-                   z_c = w_c + (s - w)/C;  lambda_c -= gamma (m_c - z_c);
+                   z_c = w_c + f (s - w)/C;  lambda_c -= gamma (m_c - z_c);
                    x_c = apply(z_c + lambda_c).
+    f = 1 for eps = 0 (Algorithm 3); f = max{0, 1 - eps/||s - w||} for
+    eps > 0 (Lemma 2, the z-update of problem P0 with ||s - H x|| <= eps).
     Returns x = [x_1; ...; x_C] (B,).
     """
     Hu = np.asarray(Hu, dtype=np.complex128)
@@ -371,23 +388,54 @@ def admm_dl(Hu, s, C, rho, T, gamma=1.0, mode=None):
         w = np.zeros(U, np.complex128)
         for c in range(C):
             w = w + wc[c]
+        f = lemma2_factor(s - w, eps)
         for c in range(C):
-            z[c] = wc[c] + (s - w) / C
+            z[c] = wc[c] + f * (s - w) / C
             lam[c] = lam[c] - gamma * (m[c] - z[c])
             x[c] = apply[c](z[c] + lam[c])
     return np.concatenate(x)
 
 
-def admm_dl_literal(Hu, s, C, rho, T, gamma=1.0):
+def project_ball_constraint(wall, s, D, eps):
+    """argmin_z 1/2||wall - z||^2 subject to ||s - D z|| <= eps, without Lemma 2.
+
+    If wall is feasible it is the answer.  Otherwise the constraint is active
+    and the KKT conditions give z(mu) = (I + mu D^H D)^{-1} (wall + mu D^H s)
+    for a multiplier mu > 0 with ||s - D z(mu)|| = eps; the residual falls
+    monotonically in mu, so mu is found by a bracketing root search.
+    """
+    from scipy.optimize import brentq
+
+    if np.linalg.norm(s - D @ wall) <= eps:
+        return wall.copy()
+    n = wall.size
+    DhD = D.conj().T @ D
+    Dhs = D.conj().T @ s
+
+    def z_of(mu):
+        return np.linalg.solve(np.eye(n) + mu * DhD, wall + mu * Dhs)
+
+    def g(mu):
+        return np.linalg.norm(s - D @ z_of(mu)) - eps
+
+    hi = 1.0
+    while g(hi) > 0.0:
+        hi *= 4.0
+    mu = brentq(g, 0.0, hi, xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
+    return z_of(mu)
+
+
+def admm_dl_literal(Hu, s, C, rho, T, gamma=1.0, eps=0.0):
     """Section IV-B steps written as argmin / projection problems.
 
     Start z_c = max(U/B, 1/C) s, lambda_c = 0, then
       (P1) x_c = argmin 1/2||x||^2 + rho/2||H_c x - z_c - lambda_c||^2, as the
            stacked least-squares [sqrt(rho) H_c; I] x ~ [sqrt(rho)(z_c+lambda_c); 0];
     and T - 1 times
-      (P2) z = orthogonal projection of (H_c x_c - lambda_c)_c onto the affine set
-           {z : sum_c z_c = s}, written with D = 1_{1 x C} kron I_U as
-           z = w_all + pinv(D) (s - D w_all);
+      (P2) z = orthogonal projection of (H_c x_c - lambda_c)_c onto
+           {z : ||s - sum_c z_c|| <= eps}, with D = 1_{1 x C} kron I_U: for
+           eps = 0 the affine projection z = w_all + pinv(D) (s - D w_all), for
+           eps > 0 ``project_ball_constraint``;
       (P3) lambda_c = lambda_c - gamma (H_c x_c - z_c);
       (P1) as above.
     """
@@ -410,21 +458,24 @@ def admm_dl_literal(Hu, s, C, rho, T, gamma=1.0):
     x = [p1(c) for c in range(C)]
     for _t in range(T - 1):
         wall = np.concatenate([Hd[c] @ x[c] - lam[c] for c in range(C)])
-        zall = wall + Dp @ (s - D @ wall)
+        if eps == 0.0:
+            zall = wall + Dp @ (s - D @ wall)
+        else:
+            zall = project_ball_constraint(wall, s, D, eps)
         z = [zall[c * U:(c + 1) * U] for c in range(C)]
         lam = [lam[c] - gamma * (Hd[c] @ x[c] - z[c]) for c in range(C)]
         x = [p1(c) for c in range(C)]
     return np.concatenate(x)
 
 
-def admm_dl_frame(Hu, s, C, rho, T, gamma=1.0, mode=None):
+def admm_dl_frame(Hu, s, C, rho, T, gamma=1.0, mode=None, eps=0.0):
     """Algorithm 3 over a frame: Hu [n_sc][B][U], s [n_sc][n_sym][U] -> x [n_sc][n_sym][B]."""
     n_sc, B, U = Hu.shape
     n_sym = s.shape[1]
     out = np.zeros((n_sc, n_sym, B), np.complex128)
     for k in range(n_sc):
         for n in range(n_sym):
-            out[k, n] = admm_dl(Hu[k], s[k, n], C, rho, T, gamma, mode)
+            out[k, n] = admm_dl(Hu[k], s[k, n], C, rho, T, gamma, mode, eps)
     return out
 
 
@@ -460,3 +511,32 @@ def zf_detect(H, y):
 def zf_precode(Hd, s):
     """Minimum-norm x with Hd x = s: x = Hd^H (Hd Hd^H)^{-1} s."""
     return np.linalg.pinv(np.asarray(Hd, dtype=np.complex128)) @ s
+
+
+def eps_precode(Hd, s, eps):
+    """Problem P0 for eps > 0: the minimum-norm x with ||s - Hd x|| <= eps.
+
+    x = 0 if ||s|| <= eps.  Otherwise the constraint is active and stationarity
+    of 1/2||x||^2 + nu/2 (||s - Hd x||^2 - eps^2) gives
+    x = Hd^H (Hd Hd^H + t I)^{-1} s with t = 1/nu > 0.  With Hd = Q diag(sig) V^H
+    and c = Q^H s the residual is ||s - Hd x||^2 = sum_i (t/(sig_i^2+t))^2 |c_i|^2
+    (Hd of full row rank), increasing in t; t is found by a bracketing root
+    search.
+    """
+    from scipy.optimize import brentq
+
+    Hd = np.asarray(Hd, dtype=np.complex128)
+    s = np.asarray(s, dtype=np.complex128)
+    if np.linalg.norm(s) <= eps:
+        return np.zeros(Hd.shape[1], np.complex128)
+    Q, sig, Vh = np.linalg.svd(Hd, full_matrices=False)
+    c = Q.conj().T @ s
+
+    def g(t):
+        return math.sqrt(float(np.sum((t / (sig ** 2 + t)) ** 2 * np.abs(c) ** 2))) - eps
+
+    hi = 1.0
+    while g(hi) < 0.0:
+        hi *= 4.0
+    t = brentq(g, 0.0, hi, xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
+    return Vh.conj().T @ (sig / (sig ** 2 + t) * c)

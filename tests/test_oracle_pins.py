@@ -252,6 +252,89 @@ def test_lemma2_projection_eps0():
     assert np.abs(z - sol[:C * U]).max() < 1e-13
 
 
+def _lemma2_z(wc, s, eps):
+    # the z-update of Lemma 2 as the oracle's Algorithm 3 applies it
+    w = wc.sum(axis=0)
+    f = O.lemma2_factor(s - w, eps)
+    return np.concatenate([wc[c] + f * (s - w) / len(wc) for c in range(len(wc))])
+
+
+@pytest.mark.parametrize("eps", [0.05, 0.4, 1.5, 50.0])
+def test_lemma2_projection_eps_positive_kkt(eps):
+    # the projection of w_all onto {z : ||s - D z|| <= eps}: z feasible, and
+    # either z = w_all (constraint inactive) or ||s - D z|| = eps with
+    # z - w_all = mu D^H (s - D z) for a real mu >= 0 (KKT, complementary slackness)
+    rng = np.random.default_rng(int(eps * 100))
+    U, C = 3, 4
+    wc, s = cn(rng, C, U), cn(rng, U)
+    D = np.kron(np.ones((1, C)), np.eye(U))
+    wall = wc.reshape(-1)
+    z = _lemma2_z(wc, s, eps)
+    r = s - D @ z
+    assert np.linalg.norm(r) <= eps * (1 + 1e-12)
+    if np.linalg.norm(s - D @ wall) <= eps:
+        assert np.abs(z - wall).max() == 0.0
+    else:
+        assert abs(np.linalg.norm(r) - eps) < 1e-12
+        g = D.conj().T @ r
+        mu = np.vdot(g, z - wall) / np.vdot(g, g)
+        assert abs(mu.imag) < 1e-12 and mu.real > 0
+        assert np.abs(z - wall - mu.real * g).max() < 1e-12
+
+
+def test_lemma2_projection_eps_positive_generic_solver():
+    # against a general constrained minimiser (SLSQP on real coordinates)
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(23)
+    U, C, eps = 2, 3, 0.3
+    wc, s = cn(rng, C, U), cn(rng, U)
+    wall = wc.reshape(-1)
+    n = C * U
+
+    def cz(v):
+        return v[:n] + 1j * v[n:]
+
+    def resid(v):
+        return s - cz(v).reshape(C, U).sum(axis=0)
+
+    cons = {"type": "ineq", "fun": lambda v: eps ** 2 - np.sum(np.abs(resid(v)) ** 2)}
+    x0 = np.concatenate([wall.real, wall.imag])
+    res = minimize(lambda v: 0.5 * np.sum(np.abs(cz(v) - wall) ** 2), x0, constraints=[cons],
+                   method="SLSQP", options={"ftol": 1e-14, "maxiter": 500})
+    assert np.linalg.norm(s - wall.reshape(C, U).sum(axis=0)) > eps     # the constraint is active
+    assert np.abs(_lemma2_z(wc, s, eps) - cz(res.x)).max() < 1e-6
+
+
+def test_lemma2_statement_denominator_is_infeasible():
+    # The statement of Lemma 2 divides eps by ||s - v|| with v = w / C; with
+    # that denominator the result leaves ||s - sum_c z_c|| above eps, while the
+    # proof's ||s - w|| lands on eps exactly.
+    rng = np.random.default_rng(24)
+    U, C, eps = 4, 4, 0.3
+    wc, s = cn(rng, C, U), cn(rng, U)
+    w = wc.sum(axis=0)
+    f_stmt = max(0.0, 1 - eps / np.linalg.norm(s - w / C))
+    z_stmt = wc + f_stmt * (s - w) / C
+    assert np.linalg.norm(s - z_stmt.sum(axis=0)) > eps * 1.01
+    z = _lemma2_z(wc, s, eps).reshape(C, U)
+    assert abs(np.linalg.norm(s - z.sum(axis=0)) - eps) < 1e-12
+
+
+@pytest.mark.parametrize("B,U,C", [(16, 4, 4), (32, 8, 8), (64, 16, 16), (16, 8, 2)])
+@pytest.mark.parametrize("eps", [0.02, 0.3, 1e6])
+def test_alg3_eps_equals_literal_and_branches(B, U, C, eps):
+    # Algorithm 3 with the Lemma 2 z-update against the steps (P1)-(P3) with
+    # (P2) solved through its Lagrange multiplier
+    rng = np.random.default_rng(B + 3 * U + C)
+    Hu, s = cn(rng, B, U), cn(rng, U)
+    for T in (1, 2, 5):
+        a = O.admm_dl(Hu, s, C, 1.0, T, mode="SS", eps=eps)
+        b = O.admm_dl(Hu, s, C, 1.0, T, mode="UU", eps=eps)
+        c = O.admm_dl_literal(Hu, s, C, 1.0, T, eps=eps)
+        assert np.abs(a - b).max() < 1e-12
+        assert np.abs(a - c).max() < 1e-10
+
+
 # --------------------------------------------------------------------------
 # Convergence limits (centralized closed forms)
 # --------------------------------------------------------------------------
@@ -306,6 +389,37 @@ def test_alg3_converges_to_zf_precoder(B, U, C, mode):
     x = O.admm_dl(Hu, s, C, 1.0, 3000, mode=mode)
     assert np.abs(x - O.zf_precode(Hu.T, s)).max() < 1e-9
     assert np.abs(Hu.T @ x - s).max() < 1e-9
+
+
+def test_eps_precode_is_the_p0_minimiser():
+    # the closed form of problem P0 with eps > 0 against a generic constrained
+    # minimiser, its residual on the boundary, and x = 0 once ||s|| <= eps
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(61)
+    U, B, eps = 2, 4, 0.4
+    Hd, s = cn(rng, U, B), cn(rng, U)
+
+    def cz(v):
+        return v[:B] + 1j * v[B:]
+
+    cons = {"type": "ineq", "fun": lambda v: eps ** 2 - np.sum(np.abs(s - Hd @ cz(v)) ** 2)}
+    x0 = np.concatenate([O.zf_precode(Hd, s).real, O.zf_precode(Hd, s).imag])
+    res = minimize(lambda v: 0.5 * np.sum(v ** 2), x0, constraints=[cons], method="SLSQP",
+                   options={"ftol": 1e-14, "maxiter": 500})
+    x = O.eps_precode(Hd, s, eps)
+    assert abs(np.linalg.norm(s - Hd @ x) - eps) < 1e-12
+    assert np.abs(x - cz(res.x)).max() < 1e-6
+    assert np.all(O.eps_precode(Hd, s, 1.01 * np.linalg.norm(s)) == 0)
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.6])
+def test_alg3_eps_converges_to_p0(eps):
+    rng = np.random.default_rng(62)
+    B, U, C = 16, 4, 4
+    Hu, s = cn(rng, B, U), cn(rng, U)
+    x = O.admm_dl(Hu, s, C, 1.0, 3000, eps=eps)
+    assert np.abs(x - O.eps_precode(Hu.T, s, eps)).max() < 1e-9
+    assert abs(np.linalg.norm(s - Hu.T @ x) - eps) < 1e-9
 
 
 # --------------------------------------------------------------------------
