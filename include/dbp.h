@@ -138,9 +138,9 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard,
                   int n_sc, int n_sym, int B, int U, int C, int T,
                   float N0, float Es, int reg, int qam, void* stream);
 
-/* Decentralized ADMM-based beamforming: Algorithm 3 (Section IV-C),
- * epsilon = 0, S x S branch (A_c = H_c^H H_c + rho^-1 I_S with the downlink
- * cluster channel H_c = (H^u_c)^T read from the uplink-layout H).
+/* Decentralized ADMM-based beamforming: Algorithm 3 (Section IV-C), S x S
+ * branch (A_c = H_c^H H_c + rho^-1 I_S with the downlink cluster channel
+ * H_c = (H^u_c)^T read from the uplink-layout H).
  *
  *   s      [n_sc][n_sym][U] complex64  precoding targets
  *   x      [n_sc][n_sym][B] complex64  output [x_1; ...; x_C]
@@ -151,11 +151,16 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard,
  *          meets its budget while H^d x = beta * H^d x_unscaled stays
  *          interference-free.
  *   T      number of x-updates (T - 1 consensus steps), T >= 1
+ *   eps    radius of the precoding constraint ||s - H^d x|| <= eps of
+ *          problem P0 (Section IV-A), eps >= 0.  eps = 0 is Algorithm 3 as
+ *          printed (z_c = w_c + (s - w)/C); eps > 0 uses the z-update of
+ *          Lemma 2, z_c = w_c + max{0, 1 - eps/||s - w||} (s - w)/C with
+ *          w = sum_c w_c (the norm of the lemma's proof).
  * Requires B % C == 0, S = B / C <= U, U in {8, 16, 32, 64}, C <= 16.
  */
 int dbp_precode_admm(const void* H, const void* s, void* x, float* beta,
                      const float* P_cluster, int n_sc, int n_sym, int B, int U,
-                     int C, int T, float rho, float gamma, void* stream);
+                     int C, int T, float rho, float gamma, float eps, void* stream);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of uplink detection frames (Algorithm 1).

@@ -116,8 +116,9 @@ def detect_factored(H, factors, y, N0, C, rho=1.0, T=5, *, reg="mmse", qam=16, E
     return s_hat, hd
 
 
-def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, P_cluster=None, out=None, stream=None):
-    """Decentralized ADMM beamforming (Algorithm 3, epsilon = 0).
+def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, eps=0.0, P_cluster=None, out=None, stream=None):
+    """Decentralized ADMM beamforming (Algorithm 3; ``eps`` > 0 uses the
+    z-update of Lemma 2 for the constraint ||s - H^d x|| <= eps).
 
     ``H`` is the uplink-layout channel [n_sc, B, U]; ``s`` the targets
     [n_sc, n_sym, U] (or [n_sc, U]).  ``P_cluster`` optional device float32
@@ -141,7 +142,8 @@ def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, P_cluster=None, out=None, strea
     L = _native.lib()
     code = L.dbp_precode_admm(H.data_ptr(), s.data_ptr(), x.data_ptr(), beta.data_ptr(),
                               P_cluster.data_ptr() if P_cluster is not None else None,
-                              n_sc, n_sym, B, U, C, T, float(rho), float(gamma), _stream(stream))
+                              n_sc, n_sym, B, U, C, T, float(rho), float(gamma), float(eps),
+                              _stream(stream))
     _native.check(code)
     return x, beta
 

@@ -281,12 +281,13 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int 
 }
 
 int dbp_precode_admm(const void* H, const void* s, void* x, float* beta, const float* P_cluster, int n_sc,
-                     int n_sym, int B, int U, int C, int T, float rho, float gamma, void* stream) {
+                     int n_sym, int B, int U, int C, int T, float rho, float gamma, float eps, void* stream) {
   const char* who = "dbp_precode_admm";
   int st = common_shape(who, n_sc, n_sym, B, U, C, T);
   if (st) return st;
   if (!(rho > 0.f) || !std::isfinite(rho)) return fail(DBP_ERR_INVALID, "%s: rho must be > 0", who);
   if (!(gamma > 0.f) || !std::isfinite(gamma)) return fail(DBP_ERR_INVALID, "%s: gamma must be > 0", who);
+  if (!(eps >= 0.f) || !std::isfinite(eps)) return fail(DBP_ERR_INVALID, "%s: eps must be >= 0", who);
   if (n_sc > 0 && (!H || !s || !x)) return fail(DBP_ERR_INVALID, "%s: null H, s or x", who);
   const int S = B / C;
   if (S > U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d > U=%d (U x U branch) not built", who, S, U);
@@ -310,6 +311,7 @@ int dbp_precode_admm(const void* H, const void* s, void* x, float* beta, const f
   a.gamma = gamma;
   a.invC = (float)(1.0 / C);
   a.f0 = (float)std::fmax((double)U / B, 1.0 / C);
+  a.eps = eps;
   return device_status(who, dbp::launch_admm_dl_f32(a, U, pl.nw, static_cast<hipStream_t>(stream)));
 }
 

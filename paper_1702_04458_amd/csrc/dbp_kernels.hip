@@ -1455,7 +1455,15 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
       const c32 wc = csub(m, lam);
       const c32 w = consensus(active ? wc : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
       buf ^= 1;
-      z = c32{fmaf(a.invC, s.re - w.re, wc.re), fmaf(a.invC, s.im - w.im, wc.im)};
+      // Lemma 2: z_c = w_c + f (s - w) / C, f = max{0, 1 - eps / ||s - w||}
+      // (f = 1 at eps = 0); every group holds the same s and w, one user per lane
+      float fC = a.invC;
+      if (a.eps > 0.f) {
+        const float dre = s.re - w.re, dim = s.im - w.im;
+        const float nd = sqrtf(group_sum<G>(dre * dre + dim * dim));
+        fC = nd > a.eps ? a.invC * (1.0f - a.eps / nd) : 0.f;
+      }
+      z = c32{fmaf(fC, s.re - w.re, wc.re), fmaf(fC, s.im - w.im, wc.im)};
       lam.re = fmaf(-a.gamma, m.re - z.re, lam.re);
       lam.im = fmaf(-a.gamma, m.im - z.im, lam.im);
       x = apply(cadd(z, lam));

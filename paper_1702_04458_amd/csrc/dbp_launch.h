@@ -35,6 +35,7 @@ struct DlArgs {
   int n_sc, n_sym, B, C, Cp, S, T;
   int sc_per_block;
   float rho, gamma, invC, f0;
+  float eps;          // radius of ||s - sum_c z_c|| <= eps (Lemma 2); 0 = equality (Alg. 3)
 };
 
 size_t smem_bytes(int nw);

@@ -75,9 +75,10 @@ def test_detect_cg_rejects():
 
 def test_precode_rejects():
     L = _native.lib()
-    ok = [1, 1, 1, None, None, 4, 1, 256, 32, 16, 5, 1.0, 1.0, None]
+    # (H, s, x, beta, P, n_sc, n_sym, B, U, C, T, rho, gamma, eps, stream)
+    ok = [1, 1, 1, None, None, 4, 1, 256, 32, 16, 5, 1.0, 1.0, 0.0, None]
     bad_S = list(ok)
-    bad_S[8] = 4          # C = 4 -> S = 64 > U = 32 (U x U branch)
+    bad_S[9] = 4          # C = 4 -> S = 64 > U = 32 (U x U branch)
     assert L.dbp_precode_admm(*bad_S) == 2
     bad_rho = list(ok)
     bad_rho[11] = 0.0
@@ -85,6 +86,10 @@ def test_precode_rejects():
     bad_ptr = list(ok)
     bad_ptr[2] = None
     assert L.dbp_precode_admm(*bad_ptr) == 1
+    for e in (-0.1, float("nan"), float("inf")):
+        bad_eps = list(ok)
+        bad_eps[13] = e
+        assert L.dbp_precode_admm(*bad_eps) == 1
 
 
 def test_factor_entry_points_reject():

@@ -243,14 +243,44 @@ def test_cfg3_precode(budget):
     assert per_vec_rel(x, ref) <= 1e-4
 
 
+# -- Lemma 2 with eps > 0 at the configuration-3 shape.  ||s - w|| runs about
+# 1.2 .. 2.1 on these frames, so eps = 1.5 leaves the constraint active on some
+# subcarriers and iterations and inactive on others; eps = 100 makes it
+# inactive everywhere (z_c = w_c).
+@pytest.mark.parametrize("eps", [0.5, 1.5, 100.0])
+def test_cfg3_precode_eps(eps):
+    say(f"[gpu] cfg3 precode eps={eps}")
+    B, U, C = 256, 32, 16
+    fr = inputs.downlink_frame(inputs.frame_seed(3, 1, 0), 29, B, U, 64)
+    H, s = to_dev(fr.H), to_dev(fr.s)
+    x, _ = api.precode(H, s, C, 1.0, 5, eps=eps)
+    torch.cuda.synchronize()
+    x = x.cpu().numpy()
+    ref = O.admm_dl_frame(fr.H, fr.s, C, 1.0, 5, eps=eps)
+    err = rel_err(x, ref)
+    say(f"    rel_err={err:.2e}")
+    assert err <= 1e-5
+    assert per_vec_rel(x, ref) <= 1e-4
+
+
+def test_precode_eps0_is_algorithm3():
+    fr = inputs.downlink_frame(inputs.frame_seed(3, 2, 0), 7, 128, 16, 16)
+    H, s = to_dev(fr.H), to_dev(fr.s)
+    a, _ = api.precode(H, s, 8, 1.0, 5)
+    b, _ = api.precode(H, s, 8, 1.0, 5, eps=0.0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("B,U,C", [(64, 8, 8), (128, 16, 8), (256, 32, 8), (64, 16, 8), (256, 64, 8)])
 def test_precode_shapes(B, U, C):
     say(f"[gpu] precode B={B} U={U} C={C}")
     fr = inputs.downlink_frame(inputs.frame_seed(11, B + U, C), 9, B, U, 16)
-    x, _ = api.precode(to_dev(fr.H), to_dev(fr.s), C, 1.0, 4)
-    torch.cuda.synchronize()
-    ref = O.admm_dl_frame(fr.H, fr.s, C, 1.0, 4)
-    assert rel_err(x.cpu().numpy(), ref) <= 1e-5
+    for eps in (0.0, 0.3):
+        x, _ = api.precode(to_dev(fr.H), to_dev(fr.s), C, 1.0, 4, eps=eps)
+        torch.cuda.synchronize()
+        ref = O.admm_dl_frame(fr.H, fr.s, C, 1.0, 4, eps=eps)
+        assert rel_err(x.cpu().numpy(), ref) <= 1e-5
 
 
 # -- mixed precision (split FP16 / BF16 Gram on the matrix cores), U = 32.
