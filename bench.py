@@ -33,6 +33,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP16_MFMA_PEAK_TFLOPS = 2500.0
 
+DEFAULT_FRAMES_PER_STEP = 32     # frames of one workload per timed launch
+
 WORKLOADS = {
     # name: (algo, B, U, C, qam, snr_db, T, n_sc)
     "admm_ul_B256_U32_C8": ("admm", 256, 32, 8, 64, 25.0, 5, 1200),
@@ -353,9 +355,87 @@ def static_channel_bench(api, frames, C, T, N0, qam, out, steps):
     e1.record()
     torch.cuda.synchronize()
     det_ms = e0.elapsed_time(e1) / steps
+    # mixed-precision resident form: H packed as complex FP16 (per-tile
+    # power-of-two scale), FP32 factors, FP32 iterations
+    B, U = H0.shape[1], H0.shape[2]
+    packed = api.pack_channel_h16(H0, C)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        api.pack_channel_h16(H0, C, out=packed)
+    e1.record()
+    torch.cuda.synchronize()
+    pack_ms = e0.elapsed_time(e1) / 5
+    for i in range(3):
+        api.detect_factored_h16(packed, fac, frames[i % len(frames)][1], N0, B, U, C, 1.0, T, qam=qam, out=out)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(steps):
+        api.detect_factored_h16(packed, fac, frames[i % len(frames)][1], N0, B, U, C, 1.0, T, qam=qam, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    h16_ms = e0.elapsed_time(e1) / steps
     return {"factor_us_per_step": round(factor_ms * 1e3, 2), "detect_factored_us_per_step": round(det_ms * 1e3, 2),
             "detect_factored_vectors_per_s": round(n_sc / (det_ms * 1e-3), 1),
-            "note": "B_c^{-1} formed once per channel; each received frame runs the iterations only"}
+            "pack_h16_us_per_step": round(pack_ms * 1e3, 2), "detect_h16_us_per_step": round(h16_ms * 1e3, 2),
+            "detect_h16_vectors_per_s": round(n_sc / (h16_ms * 1e-3), 1),
+            "note": "B_c^{-1} formed once per channel; each received frame runs the iterations only. h16: H resident "
+                    "as complex FP16 with a power-of-two scale per (subcarrier, cluster), FP32 factors and iterations "
+                    "(low-precision path, frame error <= 1e-3)"}
+
+
+def served_ratios(static, fp32_batched_us):
+    """Vectors/s of the resident (served) forms relative to the plain FP32
+    batched launch, when F received frames share one channel: per frame the
+    channel's one-time work (factorisation, packing) is spread over F frames."""
+    out = {}
+    for name, once, per in (("fp32_resident", static["factor_us_per_step"], static["detect_factored_us_per_step"]),
+                            ("h16_resident", static["factor_us_per_step"] + static["pack_h16_us_per_step"],
+                             static["detect_h16_us_per_step"])):
+        out[name] = {f"F={F}": round(fp32_batched_us / (once / F + per), 3) for F in (1, 7, 14, 70)}
+        out[name]["F=inf"] = round(fp32_batched_us / per, 3)
+    return out
+
+
+def graph_small_frames(api, n_frames=16, reps=50):
+    """Launch-bound small frames (B=64, U=8, C=4, 16 subcarriers, QPSK, T=3):
+    n_frames detection calls issued eagerly against the same calls captured
+    once in a HIP graph and replayed; microseconds per frame from events."""
+    import torch
+
+    B, U, C, n_sc, T = 64, 8, 4, 16, 3
+    frames, N0 = make_frames(n_frames, "admm", B, U, 4, 10.0, n_sc, seed=99)
+    outs = [(torch.empty((n_sc, 1, U), dtype=torch.complex64, device="cuda"),
+             torch.empty((n_sc, 1, U), dtype=torch.uint8, device="cuda")) for _ in range(n_frames)]
+
+    def body():
+        for (H, y), o in zip(frames, outs):
+            api.detect(H, y, N0, C, 1.0, T, qam=4, out=o)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        body()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        body()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for name, fn in (("eager", body), ("graph", g.replay)):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[f"{name}_us_per_frame"] = round(e0.elapsed_time(e1) * 1e3 / (reps * n_frames), 2)
+    res["frames_per_graph"] = n_frames
+    res["shape"] = f"B={B} U={U} C={C} n_sc={n_sc} QPSK T={T}"
+    return res
 
 
 def main():
@@ -370,7 +450,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-single-frame", action="store_true", help="skip the single-frame latency launches")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--frames-per-step", type=int, default=32,
+    ap.add_argument("--frames-per-step", type=int, default=DEFAULT_FRAMES_PER_STEP,
                     help="1200-subcarrier frames processed by one launch (one step); 32 frames keep the "
                          "wave-scheduling tail of the launch near 1 %%")
     ap.add_argument("--n-sc", type=int, default=0, help="subcarriers per step (overrides --frames-per-step)")
@@ -451,8 +531,10 @@ def main():
     achieved_tflops = flops_vec * n_sc / (avg_kernel_ms * 1e-3) / 1e12
     hbm_floor = bytes_vec * n_sc / (HBM_PEAK_GBS * 1e9)
     alu_floor = flops_vec * n_sc / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
+    # the profiles are taken at the default step (DEFAULT_FRAMES_PER_STEP frames, FP32, workload T)
     traffic = (profiled_traffic(args.workload)
-               if (args.prec == "fp32" and not args.n_sc and not args.T and args.frames_per_step == 8) else None)
+               if (args.prec == "fp32" and not args.n_sc and not args.T
+                   and args.frames_per_step == DEFAULT_FRAMES_PER_STEP) else None)
     if alu_floor > hbm_floor:
         roof = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic}
@@ -482,8 +564,16 @@ def main():
     static = None
     if algo == "admm" and not args.no_compare:
         static = static_channel_bench(api, frames, C, T, N0, qam, out, max(10, args.steps // 2))
+        static["served_vs_fp32_batched"] = served_ratios(static, ms_per_step * 1e3)
         print(f"[bench] static channel: factor {static['factor_us_per_step']} us, factored detect "
-              f"{static['detect_factored_us_per_step']} us/step", file=sys.stderr, flush=True)
+              f"{static['detect_factored_us_per_step']} us/step, h16 detect {static['detect_h16_us_per_step']} us/step",
+              file=sys.stderr, flush=True)
+
+    graph = None
+    if algo == "admm" and not args.no_compare:
+        graph = graph_small_frames(api)
+        print(f"[bench] small frames: eager {graph['eager_us_per_frame']} us, graph {graph['graph_us_per_frame']} us "
+              f"per frame", file=sys.stderr, flush=True)
 
     serving = None
     if not args.no_serve and algo == "admm":
@@ -522,6 +612,7 @@ def main():
             "single_frame": single,
             "mixed_precision": compare,
             "static_channel": static,
+            "small_frames_graph": graph,
             "serving": serving,
         },
         "roofline": roof,

@@ -128,6 +128,36 @@ int dbp_detect_admm_factored(const void* H, const void* factors, const void* y,
                              float rho, float gamma, float N0, float Es,
                              int reg, int qam, void* stream);
 
+/* Mixed-precision resident channel (served form of Algorithm 1 for a static
+ * channel): H is kept in HBM as complex FP16 with one power-of-two scale per
+ * (subcarrier, cluster) tile, the factors B_c^{-1} stay FP32, and the
+ * iterations run in FP32.  Per subcarrier the iterations then read
+ * 4 B U + 8 C U^2 bytes instead of 8 B U + 8 C U^2.
+ *
+ * dbp_channel_h16_bytes(n_sc, B, U, C) = 4 n_sc B U + 4 n_sc C: the size of a
+ *   packed channel (0 for malformed sizes).
+ * dbp_pack_channel_h16(H, packed, ...): H [n_sc][B][U] complex64 (device) ->
+ *   packed (device, caller-allocated, dbp_channel_h16_bytes): first
+ *   [n_sc][B][U] pairs of IEEE binary16 (real part in the low 16 bits of each
+ *   32-bit word) holding H * 2^-e rounded to nearest even, then [n_sc][C]
+ *   floats 2^e.  e = floor(log2 m) - 14 for the largest |real or imaginary
+ *   part| m of the S x U tile of cluster c on subcarrier k (e >= -126; e = 0
+ *   for an all-zero tile), so entries keep 11 significant bits.
+ * dbp_detect_admm_factored_h16(packed, factors, y, ...): as
+ *   dbp_detect_admm_factored, with H_c^H y_c formed from the packed channel
+ *   (entries widened to FP32, FP32 accumulation).  The rounding of H to 11
+ *   significant bits makes this a low-precision path: frame-level relative
+ *   error within 1e-3 of the exact result (about 2e-4 at B = 256, U = 32, C = 8,
+ *   25 dB, T = 5).
+ * Arguments, requirements and errors otherwise as dbp_detect_admm_factored. */
+size_t dbp_channel_h16_bytes(int n_sc, int B, int U, int C);
+int dbp_pack_channel_h16(const void* H, void* packed, int n_sc, int B, int U, int C, void* stream);
+int dbp_detect_admm_factored_h16(const void* packed, const void* factors, const void* y,
+                                 void* s_hat, uint8_t* hard,
+                                 int n_sc, int n_sym, int B, int U, int C, int T,
+                                 float rho, float gamma, float N0, float Es,
+                                 int reg, int qam, void* stream);
+
 /* Decentralized conjugate-gradient data detection: Algorithm 2 (Section
  * III-D) with the broadcast-w variant (every cluster keeps its own x, r, p).
  * The CG regulariser is N0/Es for DBP_REG_MMSE and 0 for DBP_REG_ZF; T >= 1
@@ -186,6 +216,7 @@ int dbp_precode_admm(const void* H, const void* s, void* x, float* beta,
  * ------------------------------------------------------------------------ */
 typedef struct dbp_server dbp_server;
 #define DBP_SERVE_DEVICE_IO 1
+#define DBP_CHANNEL_H16 2      /* dbp_channel_load: keep H as the packed FP16 channel */
 
 int dbp_server_create(int device, size_t hbm_budget_bytes, int n_slots, dbp_server** out);
 /* Waits for in-flight work, then frees the arena and streams. */
@@ -217,7 +248,13 @@ int dbp_server_stats(dbp_server* srv, size_t* peak_bytes, int* peak_inflight, ui
  * DBP_ERR_NOMEM if the channel does not fit in what is free of the budget now;
  * a frame that cannot fit beside the resident channels is refused with
  * DBP_ERR_NOMEM at submission.  y / s_hat / hard follow the rules of
- * dbp_server_submit. */
+ * dbp_server_submit.
+ * With flags | DBP_CHANNEL_H16 the channel keeps H in the packed FP16 form of
+ * dbp_pack_channel_h16 (dbp_channel_h16_bytes(n_sc, B, U, C) +
+ * dbp_factor_bytes(n_sc, U, C) bytes of the budget) and its frames run
+ * dbp_detect_admm_factored_h16 (low-precision path).  During such a load a
+ * temporary complex64 copy of H also takes n_sc*B*U*8 bytes of the budget,
+ * and the load returns only after packing and factorisation have finished. */
 int dbp_channel_load(dbp_server* srv, const void* H, int n_sc, int B, int U, int C,
                      float rho, int prec, int flags, uint64_t* channel);
 int dbp_channel_free(dbp_server* srv, uint64_t channel);

@@ -23,6 +23,10 @@ SIGNATURES = {
     "dbp_factor_bytes": (ctypes.c_size_t, [_i, _i, _i]),
     "dbp_factor_admm": (_i, [_vp, _vp, _i, _i, _i, _i, _f, _i, _vp]),
     "dbp_detect_admm_factored": (_i, [_vp, _vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i, _vp]),
+    "dbp_channel_h16_bytes": (ctypes.c_size_t, [_i, _i, _i, _i]),
+    "dbp_pack_channel_h16": (_i, [_vp, _vp, _i, _i, _i, _i, _vp]),
+    "dbp_detect_admm_factored_h16": (_i, [_vp, _vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i,
+                                          _vp]),
     "dbp_detect_cg": (_i, [_vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i, _vp]),
     "dbp_precode_admm": (_i, [_vp, _vp, _vp, _fp, _fp, _i, _i, _i, _i, _i, _i, _f, _f, _f, _vp]),
     "dbp_server_create": (_i, [_i, ctypes.c_size_t, _i, ctypes.POINTER(ctypes.c_void_p)]),

@@ -116,6 +116,52 @@ def detect_factored(H, factors, y, N0, C, rho=1.0, T=5, *, reg="mmse", qam=16, E
     return s_hat, hd
 
 
+def pack_channel_h16(H, C, *, out=None, stream=None):
+    """Packs the channel H [n_sc, B, U] into the library's mixed-precision
+    resident form (complex FP16 with one power-of-two scale per subcarrier and
+    cluster; ``dbp_pack_channel_h16``).  Returns a uint8 device tensor of
+    ``dbp_channel_h16_bytes`` bytes."""
+    _dev(H, "H")
+    n_sc, B, U = H.shape
+    nbytes = _native.lib().dbp_channel_h16_bytes(n_sc, B, U, C)
+    if nbytes == 0 and n_sc > 0:
+        raise ValueError("malformed (n_sc, B, U, C)")
+    p = out if out is not None else torch.empty(nbytes, dtype=torch.uint8, device=H.device)
+    if p.numel() * p.element_size() != nbytes or not p.is_contiguous():
+        raise ValueError("packed must be a contiguous buffer of dbp_channel_h16_bytes bytes")
+    _native.check(_native.lib().dbp_pack_channel_h16(H.data_ptr(), p.data_ptr(), n_sc, B, U, C, _stream(stream)))
+    return p
+
+
+def detect_factored_h16(packed, factors, y, N0, B, U, C, rho=1.0, T=5, *, reg="mmse", qam=16, Es=1.0, gamma=1.0,
+                        hard=True, out=None, stream=None):
+    """Algorithm 1's iterations against resident factors and the packed FP16
+    channel from :func:`pack_channel_h16` (low-precision path, <= 1e-3)."""
+    _dev(packed, "packed", torch.uint8)
+    _dev(y, "y")
+    _dev(factors, "factors")
+    if y.dim() == 2:
+        y = y.unsqueeze(1)
+    n_sc, n_sym = y.shape[0], y.shape[1]
+    if y.shape[2] != B or not y.is_contiguous():
+        raise ValueError("y must be a contiguous [n_sc, n_sym, B] tensor")
+    L = _native.lib()
+    if packed.numel() * packed.element_size() != L.dbp_channel_h16_bytes(n_sc, B, U, C):
+        raise ValueError("packed channel does not match (n_sc, B, U, C)")
+    if factors.numel() * 8 != L.dbp_factor_bytes(n_sc, U, C):
+        raise ValueError("factors do not match (n_sc, U, C)")
+    if out is None:
+        s_hat = torch.empty((n_sc, n_sym, U), dtype=torch.complex64, device=y.device)
+        hd = torch.empty((n_sc, n_sym, U), dtype=torch.uint8, device=y.device) if hard else None
+    else:
+        s_hat, hd = out
+    code = L.dbp_detect_admm_factored_h16(
+        packed.data_ptr(), factors.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hd.data_ptr() if hd is not None else None,
+        n_sc, n_sym, B, U, C, T, float(rho), float(gamma), float(N0), float(Es), REG[reg], qam, _stream(stream))
+    _native.check(code)
+    return s_hat, hd
+
+
 def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, eps=0.0, P_cluster=None, out=None, stream=None):
     """Decentralized ADMM beamforming (Algorithm 3; ``eps`` > 0 uses the
     z-update of Lemma 2 for the constraint ||s - H^d x|| <= eps).
@@ -187,9 +233,10 @@ class Server:
         _native.check(code)
         return tk.value
 
-    def load_channel(self, H, C, rho=1.0, *, prec="fp32", factor=None) -> int:
+    def load_channel(self, H, C, rho=1.0, *, prec="fp32", factor=None, h16=False) -> int:
         """Copy a static channel H (pinned host or device tensor) into the arena
-        and factor it once; returns a channel handle for :meth:`submit_factored`."""
+        and factor it once; returns a channel handle for :meth:`submit_factored`.
+        ``h16=True`` keeps H resident in the packed FP16 form (low-precision path)."""
         ct = self._ct
         if not H.is_contiguous():
             raise ValueError("H must be contiguous")
@@ -198,8 +245,8 @@ class Server:
         n_sc, B, U = H.shape
         ch = ct.c_uint64()
         _native.check(_native.lib().dbp_channel_load(self._h, H.data_ptr(), n_sc, B, U, C, float(rho),
-                                                     PREC[prec] | FACTOR[factor], 1 if H.is_cuda else 0,
-                                                     ct.byref(ch)))
+                                                     PREC[prec] | FACTOR[factor],
+                                                     (1 if H.is_cuda else 0) | (2 if h16 else 0), ct.byref(ch)))
         return ch.value
 
     def free_channel(self, channel: int):

@@ -245,6 +245,44 @@ int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, 
   return device_status(who, dbp::launch_admm_ul_factored(a, U, pl.nw, static_cast<hipStream_t>(stream)));
 }
 
+size_t dbp_channel_h16_bytes(int n_sc, int B, int U, int C) {
+  if (n_sc < 0 || B < 1 || U < 1 || C < 1 || B % C) return 0;
+  return (size_t)n_sc * B * U * 4 + (size_t)n_sc * C * 4;
+}
+
+int dbp_pack_channel_h16(const void* H, void* packed, int n_sc, int B, int U, int C, void* stream) {
+  const char* who = "dbp_pack_channel_h16";
+  int st = common_shape(who, n_sc, 1, B, U, C, 1);
+  if (st) return st;
+  if (n_sc > 0 && (!H || !packed)) return fail(DBP_ERR_INVALID, "%s: null H or packed", who);
+  if (n_sc == 0) return ok();
+  uint32_t* h16 = static_cast<uint32_t*>(packed);
+  float* scale = reinterpret_cast<float*>(h16 + (size_t)n_sc * B * U);
+  return device_status(who, dbp::launch_pack_h16(static_cast<const dbp::c32*>(H), h16, scale, n_sc, B, U, C,
+                                                 static_cast<hipStream_t>(stream)));
+}
+
+int dbp_detect_admm_factored_h16(const void* packed, const void* factors, const void* y, void* s_hat,
+                                 uint8_t* hard, int n_sc, int n_sym, int B, int U, int C, int T, float rho,
+                                 float gamma, float N0, float Es, int reg, int qam, void* stream) {
+  const char* who = "dbp_detect_admm_factored_h16";
+  dbp::UlArgs a;
+  int S = 0;
+  int st = admm_args(who, n_sc, n_sym, B, U, C, T, rho, gamma, N0, Es, reg, qam, &a, &S);
+  if (st) return st;
+  if (S < U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d < U=%d (S x S branch) not built", who, S, U);
+  if (n_sc > 0 && (!packed || !factors || !y || !s_hat)) return fail(DBP_ERR_INVALID, "%s: null pointer", who);
+  if (n_sc == 0) return ok();
+  a.H16 = static_cast<const uint32_t*>(packed);
+  a.hscale = reinterpret_cast<const float*>(a.H16 + (size_t)n_sc * B * U);
+  a.y = static_cast<const dbp::c32*>(y);
+  a.shat = static_cast<dbp::c32*>(s_hat);
+  a.hard = hard;
+  a.fac = const_cast<dbp::c32*>(static_cast<const dbp::c32*>(factors));
+  const Plan pl = make_plan(U, C);
+  return device_status(who, dbp::launch_admm_ul_factored_h16(a, U, pl.nw, static_cast<hipStream_t>(stream)));
+}
+
 int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int n_sc, int n_sym, int B, int U,
                   int C, int T, float N0, float Es, int reg, int qam, void* stream) {
   const char* who = "dbp_detect_cg";

@@ -108,6 +108,43 @@ __device__ __forceinline__ c32 cluster_pass(const c32* __restrict__ H, const c32
   return hy;
 }
 
+// Row u of H_c^H y_c for symbol n read from the packed FP16 channel: every
+// entry is widened to FP32 and the products are accumulated in FP32; the
+// tile's power-of-two scale is applied once at the end (exact).
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ c32 widen_h16(uint32_t w) {
+  const h16x2 v = __builtin_bit_cast(h16x2, w);
+  return c32{(float)v.x, (float)v.y};
+}
+
+template <int G>
+__device__ __forceinline__ c32 cluster_hy_h16(const UlArgs& a, int k, int c, int n, int u, int g, int wave,
+                                              bool active, const Smem& sm) {
+  constexpr int R = kStageRows;
+  c32 hy = cz();
+  c32* yst = sm.ystage + wave * R * 8;
+  const uint32_t* Hk = a.H16 + (size_t)k * a.B * G + (size_t)c * a.S * G;
+  const c32* yk = a.y + ((size_t)k * a.n_sym + n) * a.B + (size_t)c * a.S;
+  for (int s0 = 0; s0 < a.S; s0 += R) {
+    uint32_t h[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int s = s0 + r;
+      h[r] = (active && s < a.S) ? Hk[(size_t)s * G + u] : 0u;
+    }
+    if (u < R) {
+      const int s = s0 + u;
+      yst[u * 8 + g] = (active && s < a.S) ? yk[s] : cz();
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r) cmacc(hy, widen_h16(h[r]), yst[r * 8 + g]);
+    wave_lds_sync();
+  }
+  return cscale(hy, active ? a.hscale[(size_t)k * a.C + c] : 0.f);
+}
+
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // Gauss-Jordan inversion of the HPD matrix B = G + rho I in the 32x32
@@ -1183,7 +1220,7 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   c32 hy0 = cz();
   // resident factors of this problem: entry v of lane u's row at v * G + u
   const size_t fo = ((size_t)k * a.C + c) * G * G + u;
-  if constexpr (STAGE == 2) {
+  if constexpr (STAGE >= 2) {
     if (active) {
 #pragma unroll
       for (int v = 0; v < G; ++v) A[v] = a.fac[fo + (size_t)v * G];
@@ -1225,7 +1262,9 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   int buf = 0;
   for (int n = 0; n < a.n_sym; ++n) {
     c32 hy = hy0;
-    if (n > 0 || STAGE == 2)
+    if constexpr (STAGE == 3)
+      hy = cluster_hy_h16<G>(a, k, c, n, u, g, wave, active, sm);
+    else if (n > 0 || STAGE == 2)
       hy = cluster_pass<G, false>(a.H, a.y, A, k, c, n, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
     // y_c^reg = B_c^{-1} H_c^H y_c; z = y^reg; lambda = 0
     const c32 yreg = group_matvec<G>(A, hy, u, line, gbase);
@@ -1490,6 +1529,65 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Packed FP16 channel: one 256-lane workgroup per (subcarrier, cluster) tile
+// of S x U entries.  The tile's largest |component| m fixes the exponent
+// e = floor(log2 m) - 14 (at least -126), so that the scaled entries H * 2^-e
+// lie below 2^15 in magnitude (no overflow) and stay normal FP16 numbers (11
+// significant bits) down to 2^-28 m; each entry is rounded to nearest even, and
+// 2^e is stored as the tile's scale.  Tiles of up to 256 * kPackRegs entries
+// stay in registers between the two steps (one read of H); larger tiles read
+// the tile a second time.
+// ---------------------------------------------------------------------------
+constexpr int kPackRegs = 8;
+
+__device__ __forceinline__ uint32_t pack_pair(c32 v, int e) {
+  const h16x2 p = {(_Float16)ldexpf(v.re, -e), (_Float16)ldexpf(v.im, -e)};
+  return __builtin_bit_cast(uint32_t, p);
+}
+
+__global__ void __launch_bounds__(256) pack_h16(const c32* __restrict__ H, uint32_t* __restrict__ H16,
+                                                float* __restrict__ hscale, int B, int U, int C) {
+  __shared__ float wmax[4];
+  const int S = B / C;
+  const int k = blockIdx.x / C, c = blockIdx.x % C;
+  const size_t base = (size_t)k * B * U + (size_t)c * S * U;
+  const int n = S * U;
+  const bool cached = n <= 256 * kPackRegs;
+  c32 r[kPackRegs];
+  float m = 0.f;
+  if (cached) {
+#pragma unroll
+    for (int j = 0; j < kPackRegs; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      r[j] = i < n ? H[base + i] : cz();
+      m = fmaxf(m, fmaxf(fabsf(r[j].re), fabsf(r[j].im)));
+    }
+  } else {
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const c32 v = H[base + i];
+      m = fmaxf(m, fmaxf(fabsf(v.re), fabsf(v.im)));
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+  int e = 0;
+  if (m > 0.f && m <= 3.4028235e38f) e = min(max(ilogbf(m) - 14, -126), 113);
+  if (cached) {
+#pragma unroll
+    for (int j = 0; j < kPackRegs; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      if (i < n) H16[base + i] = pack_pair(r[j], e);
+    }
+  } else {
+    for (int i = threadIdx.x; i < n; i += 256) H16[base + i] = pack_pair(H[base + i], e);
+  }
+  if (threadIdx.x == 0) hscale[blockIdx.x] = ldexpf(1.f, e);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 template <typename K, typename Args>
@@ -1543,6 +1641,25 @@ hipError_t launch_admm_ul_factored(const UlArgs& a, int U, int nw, hipStream_t s
     case 64: return launch(admm_ul_f32<64, 0, 0, 2>, a, nw, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_admm_ul_factored_h16(const UlArgs& a, int U, int nw, hipStream_t st) {
+  switch (U) {
+    case 8: return launch(admm_ul_f32<8, 0, 0, 3>, a, nw, st);
+    case 16: return launch(admm_ul_f32<16, 0, 0, 3>, a, nw, st);
+    case 32: return launch(admm_ul_f32<32, 0, 0, 3>, a, nw, st);
+    case 64: return launch(admm_ul_f32<64, 0, 0, 3>, a, nw, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pack_h16(const c32* H, uint32_t* H16, float* hscale, int n_sc, int B, int U, int C,
+                           hipStream_t st) {
+  const size_t tiles = (size_t)n_sc * C;
+  if (tiles == 0) return hipSuccess;
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pack_h16, dim3((unsigned)tiles), dim3(256), 0, st, H, H16, hscale, B, U, C);
+  return hipGetLastError();
 }
 
 hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st) {

@@ -24,6 +24,8 @@ struct UlArgs {
   float box_r;
   float kappa;
   c32* fac;           // [n_sc][C][U][U] resident factors B_c^{-1} (column v of lane u at v*U + u), or null
+  const uint32_t* H16;  // [n_sc][B][U] packed FP16 channel (real part in the low half), or null
+  const float* hscale;  // [n_sc][C] power-of-two scale of each (subcarrier, cluster) tile of H16
 };
 
 struct DlArgs {
@@ -45,6 +47,11 @@ hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st, in
 hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, int inv, int nw, hipStream_t st, int stage = 0);
 // detection against resident factors a.fac (no Gram, no inverse)
 hipError_t launch_admm_ul_factored(const UlArgs& a, int U, int nw, hipStream_t st);
+// the same with H read from the packed FP16 channel a.H16 / a.hscale
+hipError_t launch_admm_ul_factored_h16(const UlArgs& a, int U, int nw, hipStream_t st);
+// H [n_sc][B][U] complex64 -> H16 (same layout, complex FP16) and hscale [n_sc][C]
+hipError_t launch_pack_h16(const c32* H, uint32_t* H16, float* hscale, int n_sc, int B, int U, int C,
+                           hipStream_t st);
 hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
 hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st);
 

@@ -84,8 +84,9 @@ class Arena {
 };
 
 struct Channel {
-  size_t off = 0, footprint = 0;     // arena block: H copy, then the factors
+  size_t off = 0, footprint = 0;     // arena block: H (complex64 or packed FP16), then the factors
   size_t bytes_H = 0;
+  bool h16 = false;                  // H kept as the packed FP16 channel
   int n_sc = 0, B = 0, U = 0, C = 0;
   float rho = 0.f;
   hipEvent_t ready = nullptr;        // recorded after the factorisation
@@ -158,8 +159,10 @@ int launch_factored(dbp_server* s, Frame& f, hipStream_t st) {
     so = ds;
     ho = f.hard_out ? reinterpret_cast<uint8_t*>(dh) : nullptr;
   }
-  int rc = dbp_detect_admm_factored(dH, dF, y, so, ho, f.n_sc, f.n_sym, f.B, f.U, f.C, f.T, f.rho, 1.0f, f.N0, 1.0f,
-                                    f.reg, f.qam, st);
+  int rc = ch.h16 ? dbp_detect_admm_factored_h16(dH, dF, y, so, ho, f.n_sc, f.n_sym, f.B, f.U, f.C, f.T, f.rho,
+                                                  1.0f, f.N0, 1.0f, f.reg, f.qam, st)
+                  : dbp_detect_admm_factored(dH, dF, y, so, ho, f.n_sc, f.n_sym, f.B, f.U, f.C, f.T, f.rho, 1.0f,
+                                             f.N0, 1.0f, f.reg, f.qam, st);
   if (rc != DBP_OK) return rc;
   if (!(f.flags & DBP_SERVE_DEVICE_IO)) {
     if (hipMemcpyAsync(f.s_out, so, f.bytes_s, hipMemcpyDeviceToHost, st) != hipSuccess) return DBP_ERR_DEVICE;
@@ -359,7 +362,8 @@ int dbp_server_submit(dbp_server* s, const void* H_host, const void* y_host, voi
 int dbp_channel_load(dbp_server* s, const void* H, int n_sc, int B, int U, int C, float rho, int prec, int flags,
                      uint64_t* channel) {
   if (!s || !H || !channel) return DBP_ERR_INVALID;
-  if (n_sc < 1 || B < 1 || U < 1 || C < 1 || B % C || U > B / C || !(rho > 0.f) || (flags & ~DBP_SERVE_DEVICE_IO))
+  if (n_sc < 1 || B < 1 || U < 1 || C < 1 || B % C || U > B / C || !(rho > 0.f) ||
+      (flags & ~(DBP_SERVE_DEVICE_IO | DBP_CHANNEL_H16)))
     return DBP_ERR_INVALID;
   Channel ch;
   ch.n_sc = n_sc;
@@ -367,27 +371,41 @@ int dbp_channel_load(dbp_server* s, const void* H, int n_sc, int B, int U, int C
   ch.U = U;
   ch.C = C;
   ch.rho = rho;
-  ch.bytes_H = size_t(n_sc) * B * U * 8;
+  ch.h16 = (flags & DBP_CHANNEL_H16) != 0;
+  const size_t bytes_H32 = size_t(n_sc) * B * U * 8;
+  ch.bytes_H = ch.h16 ? dbp_channel_h16_bytes(n_sc, B, U, C) : bytes_H32;
   ch.footprint = ((ch.bytes_H + 255) & ~size_t(255)) + dbp_factor_bytes(n_sc, U, C);
+  // a packed channel is made from a complex64 copy of H held in a second,
+  // temporary block until the packing and the factorisation have run
+  size_t tmp_off = 0;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (!s->arena->alloc(ch.footprint, &ch.off)) return DBP_ERR_NOMEM;
+    if (ch.h16 && !s->arena->alloc(bytes_H32, &tmp_off)) {
+      s->arena->release(ch.off, ch.footprint);
+      return DBP_ERR_NOMEM;
+    }
     s->peak_used = std::max(s->peak_used, s->arena->used());
   }
-  // The block is reserved and known to no one else yet: copy H outside the
+  // The blocks are reserved and known to no one else yet: copy H outside the
   // lock (synchronously, so the caller may release H on return), then queue
-  // the factorisation and mark its completion.
+  // the factorisation (and the packing) and mark its completion.
   char* d = static_cast<char*>(s->base) + ch.off;
+  char* d32 = ch.h16 ? static_cast<char*>(s->base) + tmp_off : d;
   void* dF = d + ((ch.bytes_H + 255) & ~size_t(255));
   const hipMemcpyKind kind = (flags & DBP_SERVE_DEVICE_IO) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   int rc = DBP_OK;
   if (hipEventCreateWithFlags(&ch.ready, hipEventDisableTiming) != hipSuccess ||
-      hipMemcpyAsync(d, H, ch.bytes_H, kind, s->load_stream) != hipSuccess ||
+      hipMemcpyAsync(d32, H, bytes_H32, kind, s->load_stream) != hipSuccess ||
       hipStreamSynchronize(s->load_stream) != hipSuccess)
     rc = DBP_ERR_DEVICE;
-  if (rc == DBP_OK) rc = dbp_factor_admm(d, dF, n_sc, B, U, C, rho, prec, s->load_stream);
+  if (rc == DBP_OK) rc = dbp_factor_admm(d32, dF, n_sc, B, U, C, rho, prec, s->load_stream);
+  if (rc == DBP_OK && ch.h16) rc = dbp_pack_channel_h16(d32, d, n_sc, B, U, C, s->load_stream);
   if (rc == DBP_OK && hipEventRecord(ch.ready, s->load_stream) != hipSuccess) rc = DBP_ERR_DEVICE;
+  // the temporary block is returned only once the load stream is past it
+  if (ch.h16 && hipStreamSynchronize(s->load_stream) != hipSuccess && rc == DBP_OK) rc = DBP_ERR_DEVICE;
   std::lock_guard<std::mutex> lk(s->mu);
+  if (ch.h16) s->arena->release(tmp_off, bytes_H32);
   if (rc != DBP_OK) {
     hipStreamSynchronize(s->load_stream);
     if (ch.ready) hipEventDestroy(ch.ready);

@@ -115,3 +115,23 @@ def test_factor_entry_points_reject():
     bad = list(ok)
     bad[8] = 12
     assert L.dbp_detect_admm_factored(*bad) == 2                               # U not built
+
+
+def test_h16_channel_entry_points_reject():
+    L = _native.lib()
+    assert L.dbp_channel_h16_bytes(1200, 256, 32, 8) == 1200 * 256 * 32 * 4 + 1200 * 8 * 4
+    assert L.dbp_channel_h16_bytes(4, 250, 32, 8) == 0                          # B % C
+    # dbp_pack_channel_h16(H, packed, n_sc, B, U, C, stream)
+    assert L.dbp_pack_channel_h16(1, None, 4, 256, 32, 8, None) == 1            # null packed
+    assert L.dbp_pack_channel_h16(1, 1, 4, 256, 24, 8, None) == 2               # U not built
+    assert L.dbp_pack_channel_h16(None, None, 0, 256, 32, 8, None) == 0         # empty: no-op
+    # dbp_detect_admm_factored_h16(packed, factors, y, s_hat, hard, n_sc, n_sym, B, U, C, T, rho, gamma, N0, Es,
+    #                              reg, qam, stream)
+    ok = [1, 1, 1, 1, None, 4, 1, 256, 32, 8, 5, 1.0, 1.0, 0.1, 1.0, 0, 64, None]
+    for i, v, code in ((1, None, 1), (11, 0.0, 1), (16, 8, 1), (8, 64, 2)):
+        bad = list(ok)
+        bad[i] = v
+        assert L.dbp_detect_admm_factored_h16(*bad) == code, (i, v)
+    small = list(ok)
+    small[9] = 16                                                                # S = 16 < U = 32
+    assert L.dbp_detect_admm_factored_h16(*small) == 2

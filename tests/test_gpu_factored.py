@@ -2,6 +2,7 @@
 GPU: a static channel is factored once and several received frames are
 detected against it; every result is checked against the FP64 oracle with the
 FP32 bars of test_gpu_parity, and against the one-shot dbp_detect_admm."""
+import math
 import sys
 
 import numpy as np
@@ -89,3 +90,87 @@ def test_factors_match_oracle_inverse():
             Binv = np.linalg.inv(Hc.conj().T @ Hc + 0.7 * np.eye(U))
             stored = fac[k, c].T                                     # [u][v] = row u, column v
             assert np.linalg.norm(stored - Binv) <= 1e-5 * np.linalg.norm(Binv)
+
+
+# -- mixed-precision resident channel: H packed as complex FP16 with one
+# power-of-two scale per (subcarrier, cluster) tile, FP32 factors and FP32
+# iterations (dbp_pack_channel_h16 + dbp_detect_admm_factored_h16).
+
+def decode_h16(packed, n_sc, B, U, C):
+    raw = packed.cpu().numpy()
+    n = n_sc * B * U
+    halves = raw[:4 * n].view(np.float16).astype(np.float64).reshape(n_sc, B, U, 2)   # real part in the low half
+    scale = raw[4 * n:].view(np.float32).reshape(n_sc, C)
+    return halves[..., 0] + 1j * halves[..., 1], scale
+
+
+@pytest.mark.parametrize("B,U,C,n_sc", [(128, 16, 8, 7), (1024, 64, 8, 5)])
+def test_pack_h16_format(B, U, C, n_sc):
+    """Bit-exact against the definition: e = floor(log2 m) - 14 for the tile's
+    largest |component| m (e = 0 for an all-zero tile), entries rounded to
+    nearest even in binary16 after scaling by 2^-e; tiles spanning 1e-30 .. 1e20,
+    held in registers (16 x 16 tiles) or read twice (128 x 64 tiles)."""
+    say(f"[gpu] pack_h16 format B={B} U={U} C={C}")
+    S = B // C
+    fr = inputs.uplink_frame(inputs.frame_seed(24, 0, 10), n_sc, B, U, 16, 10.0)
+    H = fr.H.astype(np.complex64)
+    H[2, S:2 * S] *= np.float32(1e-30)
+    H[3, 0:S] = 0
+    H[4, 2 * S:3 * S] *= np.float32(1e20)
+    packed = api.pack_channel_h16(to_dev(H), C)
+    torch.cuda.synchronize()
+    h16, scale = decode_h16(packed, n_sc, B, U, C)
+    for k in range(n_sc):
+        for c in range(C):
+            tile = H[k, c * S:(c + 1) * S]
+            m = float(max(np.abs(tile.real).max(), np.abs(tile.imag).max()))
+            e = 0 if m == 0 else max(math.floor(math.log2(m)) - 14, -126)
+            assert scale[k, c] == 2.0 ** e, (k, c, scale[k, c], e)
+            want_re = np.ldexp(tile.real.astype(np.float64), -e).astype(np.float16)
+            want_im = np.ldexp(tile.imag.astype(np.float64), -e).astype(np.float16)
+            got = h16[k, c * S:(c + 1) * S]
+            assert np.array_equal(got.real, want_re.astype(np.float64)), (k, c)
+            assert np.array_equal(got.imag, want_im.astype(np.float64)), (k, c)
+
+
+@pytest.mark.parametrize("B,U,C,n_sc,qam,snr", SHAPES)
+def test_factored_h16(B, U, C, n_sc, qam, snr):
+    """Low-precision bar (frame error <= 1e-3 against the FP64 oracle) and the
+    hard-decision rule of the FP32 path."""
+    say(f"[gpu] factored h16 B={B} U={U} C={C} n_sc={n_sc}")
+    fr = inputs.uplink_frame(inputs.frame_seed(25, B + U + C, int(snr)), n_sc, B, U, qam, snr, n_sym=2)
+    H = to_dev(fr.H)
+    fac = api.factor(H, C, 1.0)
+    packed = api.pack_channel_h16(H, C)
+    s, h = api.detect_factored_h16(packed, fac, to_dev(fr.y), fr.N0, B, U, C, 1.0, 5, qam=qam)
+    torch.cuda.synchronize()
+    s, h = s.cpu().numpy(), h.cpu().numpy()
+    ref = O.admm_ul_frame(fr.H, fr.y, C, 1.0, 5, fr.N0)
+    err = rel_err(s, ref)
+    say(f"    rel_err={err:.2e}")
+    assert err <= 1e-3
+    check_hard(s, h, ref, qam)
+
+
+def test_factored_h16_headline_and_scaling():
+    """B=256, U=32, C=8 at 25 dB: within 1e-3 of the oracle (about 2e-4
+    expected from rounding H to 11 significant bits), and bit-identical under
+    (H, y, N0, rho) -> (4H, 4y, 16N0, 16rho): the tile exponents absorb the
+    factor 4 exactly."""
+    say("[gpu] factored h16 headline shape")
+    fr = inputs.uplink_frame(inputs.frame_seed(26, 1, 25), 41, 256, 32, 64, 25.0)
+    outs = []
+    for f in (1.0, 4.0):
+        H = to_dev(fr.H) * f
+        fac = api.factor(H, 8, f * f)
+        packed = api.pack_channel_h16(H, 8)
+        outs.append(api.detect_factored_h16(packed, fac, to_dev(fr.y) * f, fr.N0 * f * f, 256, 32, 8, f * f, 5,
+                                            qam=64))
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    s, h = outs[0][0].cpu().numpy(), outs[0][1].cpu().numpy()
+    ref = O.admm_ul_frame(fr.H, fr.y, 8, 1.0, 5, fr.N0)
+    err = rel_err(s, ref)
+    say(f"    rel_err={err:.2e}")
+    assert err <= 1e-3
+    check_hard(s, h, ref, 64)

@@ -203,6 +203,52 @@ def test_empty_batch():
     assert s.shape == (0, 1, 8)
 
 
+# Largest shapes the kernels accept: every cluster group of a subcarrier
+# shares one 512-lane workgroup (C <= 8 at U = 64, C <= 16 below), B = 1024.
+@pytest.mark.parametrize("B,U,C", [(1024, 64, 8), (1024, 32, 16), (1024, 16, 16), (1024, 8, 16)])
+@pytest.mark.parametrize("algo", ["admm", "cg"])
+def test_max_shapes(B, U, C, algo):
+    say(f"[gpu] max shape B={B} U={U} C={C} {algo}")
+    fr = inputs.uplink_frame(inputs.frame_seed(12, B + U + C, 15), 5, B, U, 64, 15.0)
+    s, h = run_detect(fr, C, 5, algo)
+    ref = oracle_detect(fr, C, 5, algo)
+    assert rel_err(s, ref) <= 1e-5
+    check_hard(s, h, ref, 64)
+
+
+@pytest.mark.parametrize("B,U,C", [(512, 64, 8), (512, 32, 16)])
+def test_precode_max_shapes(B, U, C):
+    say(f"[gpu] precode max shape B={B} U={U} C={C}")
+    fr = inputs.downlink_frame(inputs.frame_seed(13, B + U, C), 5, B, U, 64)
+    x, _ = api.precode(to_dev(fr.H), to_dev(fr.s), C, 1.0, 5)
+    torch.cuda.synchronize()
+    assert rel_err(x.cpu().numpy(), O.admm_dl_frame(fr.H, fr.s, C, 1.0, 5)) <= 1e-5
+
+
+def test_degenerate_inputs():
+    """y = 0 gives s = 0 exactly (every step is linear in y); H = 0 leaves
+    B_c = rho I and also gives s = 0; a user whose channel column is zero gets
+    s_u = 0 while the others match the oracle."""
+    say("[gpu] degenerate inputs")
+    fr = inputs.uplink_frame(inputs.frame_seed(14, 0, 10), 9, 128, 16, 16, 10.0)
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    for algo in ("admm", "cg"):
+        s, h = api.detect(H, torch.zeros_like(y), fr.N0, 8, 1.0, 5, algo=algo, qam=16)
+        s0, _ = api.detect(torch.zeros_like(H), y, fr.N0, 8, 1.0, 5, algo=algo, qam=16)
+        torch.cuda.synchronize()
+        assert torch.count_nonzero(s).item() == 0
+        assert torch.count_nonzero(s0).item() == 0
+        assert np.array_equal(h.cpu().numpy(), O.slice_qam_f32(np.zeros(h.shape, np.complex64), 16))
+    Hz = fr.H.copy()
+    Hz[:, :, 3] = 0
+    s, _ = api.detect(to_dev(Hz), y, fr.N0, 8, 1.0, 5, qam=16)
+    torch.cuda.synchronize()
+    s = s.cpu().numpy()
+    ref = O.admm_ul_frame(Hz, fr.y, 8, 1.0, 5, fr.N0)
+    assert np.all(s[:, :, 3] == 0) and np.all(ref[:, :, 3] == 0)
+    assert rel_err(s, ref) <= 1e-5
+
+
 def test_launch_shape_independence():
     """Same inputs as one batch or split in pieces give identical bits."""
     say("[gpu] tiling independence")

@@ -112,23 +112,29 @@ def test_oversized_frame_refused():
 
 
 @pytest.mark.parametrize("pinned", [True, False])
-def test_resident_channel_frames(pinned):
-    """A static channel loaded once; four received frames against it, mixed
-    with ordinary frames, each bit-identical to the library's factored call."""
-    say(f"[gpu] serving resident channel pinned={pinned}")
+@pytest.mark.parametrize("h16", [False, True])
+def test_resident_channel_frames(pinned, h16):
+    """A static channel loaded once (complex64, or the packed FP16 form); four
+    received frames against it, mixed with ordinary frames, each bit-identical
+    to the library's factored call."""
+    say(f"[gpu] serving resident channel pinned={pinned} h16={h16}")
     B, U, C, n_sc = 256, 32, 8, 120
     fr = inputs.uplink_frame(inputs.frame_seed(5, 99, 25), n_sc, B, U, 64, 25.0, n_sym=4)
     Hd = torch.from_numpy(fr.H).cuda()
     fac = api.factor(Hd, C, 1.0)
+    packed = api.pack_channel_h16(Hd, C)
     srv = api.Server(hbm_budget_bytes=1 << 30, n_slots=4)
     H = torch.from_numpy(fr.H).pin_memory() if pinned else Hd
-    ch = srv.load_channel(H, C, 1.0)
+    ch = srv.load_channel(H, C, 1.0, h16=h16)
     others = make_frames(pinned)[:3]
     tickets, outs, refs = [], [], []
     for n in range(4):
         yn = torch.from_numpy(np.ascontiguousarray(fr.y[:, n:n + 1]))
         yd = yn.cuda()
-        r = api.detect_factored(Hd, fac, yd, fr.N0, C, 1.0, 5, qam=64)
+        if h16:
+            r = api.detect_factored_h16(packed, fac, yd, fr.N0, B, U, C, 1.0, 5, qam=64)
+        else:
+            r = api.detect_factored(Hd, fac, yd, fr.N0, C, 1.0, 5, qam=64)
         refs.append((r[0].cpu(), r[1].cpu()))
         y = yn.pin_memory() if pinned else yd
         s, h = out_bufs(dict(n_sc=n_sc, U=U), pinned)
