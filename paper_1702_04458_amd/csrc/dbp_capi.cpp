@@ -39,6 +39,13 @@ int qam_side(int qam) {
   return 0;
 }
 
+// Waves per workgroup when the clusters of one subcarrier need fewer (a
+// build-time tuning knob; 1, 2, 4 or 8): the workgroup then holds several
+// subcarriers.
+#ifndef DBP_MIN_WAVES
+#define DBP_MIN_WAVES 4
+#endif
+
 // Launch plan: a lane group of U lanes per (subcarrier, cluster) problem,
 // P = 64 / U problems per wave, the Cp >= C (power of two) cluster slots of a
 // subcarrier in one workgroup.
@@ -53,11 +60,11 @@ Plan make_plan(int U, int C) {
   while (p.Cp < C) p.Cp <<= 1;
   if (p.Cp >= P) {
     const int wps = p.Cp / P;
-    p.nw = wps > 4 ? wps : 4;
+    p.nw = wps > DBP_MIN_WAVES ? wps : DBP_MIN_WAVES;
     p.scpb = p.nw / wps;
   } else {
-    p.nw = 4;
-    p.scpb = 4 * (P / p.Cp);
+    p.nw = DBP_MIN_WAVES;
+    p.scpb = DBP_MIN_WAVES * (P / p.Cp);
   }
   return p;
 }
