@@ -202,7 +202,9 @@ int launch_frame(dbp_server* s, Frame& f) {
 }
 
 void scheduler(dbp_server* s) {
-  hipSetDevice(s->device);
+  // dbp_server_create made this device current successfully before starting
+  // the thread, so the call cannot fail here
+  (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop.load()) {
     bool progressed = false;
@@ -239,8 +241,10 @@ void scheduler(dbp_server* s) {
       s->queue.pop_front();
       const int rc = launch_frame(s, f);
       if (rc != DBP_OK) {
-        // nothing of this frame runs: release and report
-        hipStreamSynchronize(s->streams[f.slot]);
+        // nothing more of this frame runs: drain what was enqueued before the
+        // failure, then release and report (a failing drain leaves the error
+        // in f.status too)
+        (void)hipStreamSynchronize(s->streams[f.slot]);
         s->arena->release(f.off, f.footprint);
         if (f.channel) --s->channels[f.channel].refs;
         f.status = rc;
@@ -268,6 +272,22 @@ void scheduler(dbp_server* s) {
 
 int qam_ok(int q) { return q == 4 || q == 16 || q == 64; }
 
+// Releases everything a server holds (streams and events that exist, the
+// arena, the object).  Returns DBP_ERR_DEVICE if a release call failed.
+int release_server(dbp_server* s) {
+  bool ok = true;
+  for (auto st : s->streams)
+    if (st) ok &= hipStreamDestroy(st) == hipSuccess;
+  for (auto ev : s->events)
+    if (ev) ok &= hipEventDestroy(ev) == hipSuccess;
+  for (auto& kv : s->channels) ok &= hipEventDestroy(kv.second.ready) == hipSuccess;
+  if (s->load_stream) ok &= hipStreamDestroy(s->load_stream) == hipSuccess;
+  if (s->base) ok &= hipFree(s->base) == hipSuccess;
+  delete s->arena;
+  delete s;
+  return ok ? DBP_OK : DBP_ERR_DEVICE;
+}
+
 }  // namespace
 
 extern "C" {
@@ -279,20 +299,25 @@ int dbp_server_create(int device, size_t hbm_budget_bytes, int n_slots, dbp_serv
   auto* s = new dbp_server();
   s->device = device;
   if (hipMalloc(&s->base, hbm_budget_bytes) != hipSuccess) {
-    delete s;
+    s->base = nullptr;
+    release_server(s);
     return DBP_ERR_NOMEM;
   }
   s->arena = new Arena(hbm_budget_bytes);
-  s->streams.resize(n_slots);
-  s->events.resize(n_slots);
+  s->streams.assign(n_slots, nullptr);
+  s->events.assign(n_slots, nullptr);
   s->slot_frame.assign(n_slots, 0);
   for (int i = 0; i < n_slots; ++i) {
     if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming) != hipSuccess) {
+      release_server(s);
       return DBP_ERR_DEVICE;
     }
   }
-  if (hipStreamCreateWithFlags(&s->load_stream, hipStreamNonBlocking) != hipSuccess) return DBP_ERR_DEVICE;
+  if (hipStreamCreateWithFlags(&s->load_stream, hipStreamNonBlocking) != hipSuccess) {
+    release_server(s);
+    return DBP_ERR_DEVICE;
+  }
   s->worker = std::thread(scheduler, s);
   *out = s;
   return DBP_OK;
@@ -306,16 +331,11 @@ int dbp_server_destroy(dbp_server* s) {
   }
   s->cv.notify_all();
   s->worker.join();
-  for (auto st : s->streams) hipStreamSynchronize(st);
-  hipStreamSynchronize(s->load_stream);
-  for (auto st : s->streams) hipStreamDestroy(st);
-  for (auto ev : s->events) hipEventDestroy(ev);
-  for (auto& kv : s->channels) hipEventDestroy(kv.second.ready);
-  hipStreamDestroy(s->load_stream);
-  hipFree(s->base);
-  delete s->arena;
-  delete s;
-  return DBP_OK;
+  bool ok = true;
+  for (auto st : s->streams) ok &= hipStreamSynchronize(st) == hipSuccess;
+  ok &= hipStreamSynchronize(s->load_stream) == hipSuccess;
+  const int rc = release_server(s);
+  return ok ? rc : DBP_ERR_DEVICE;
 }
 
 int dbp_server_submit(dbp_server* s, const void* H_host, const void* y_host, void* s_hat_host, uint8_t* hard_host,
@@ -407,8 +427,10 @@ int dbp_channel_load(dbp_server* s, const void* H, int n_sc, int B, int U, int C
   std::lock_guard<std::mutex> lk(s->mu);
   if (ch.h16) s->arena->release(tmp_off, bytes_H32);
   if (rc != DBP_OK) {
-    hipStreamSynchronize(s->load_stream);
-    if (ch.ready) hipEventDestroy(ch.ready);
+    // drain the load stream before its block is handed out again; rc already
+    // reports the failure
+    (void)hipStreamSynchronize(s->load_stream);
+    if (ch.ready) (void)hipEventDestroy(ch.ready);
     s->arena->release(ch.off, ch.footprint);
     return rc;
   }
@@ -425,12 +447,12 @@ int dbp_channel_free(dbp_server* s, uint64_t channel) {
   if (it == s->channels.end()) return DBP_ERR_NOTFOUND;
   if (it->second.refs > 0) return DBP_ERR_BUSY;
   // the factorisation must be finished before its memory can be handed out again
-  hipEventSynchronize(it->second.ready);
-  hipEventDestroy(it->second.ready);
+  const bool ok = hipEventSynchronize(it->second.ready) == hipSuccess &&
+                  hipEventDestroy(it->second.ready) == hipSuccess;
   s->arena->release(it->second.off, it->second.footprint);
   s->channel_bytes -= (it->second.footprint + 255) & ~size_t(255);
   s->channels.erase(it);
-  return DBP_OK;
+  return ok ? DBP_OK : DBP_ERR_DEVICE;
 }
 
 int dbp_server_submit_factored(dbp_server* s, uint64_t channel, const void* y, void* s_hat, uint8_t* hard, int n_sym,
