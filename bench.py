@@ -46,17 +46,26 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(algo, B, U, C):
-    """HBM bytes one subcarrier-vector must move (complex64 in/out, uint8 hard)."""
+def algorithmic_bytes(algo, B, U, C, form="oneshot"):
+    """HBM bytes one subcarrier-vector must move (complex64 in/out, uint8 hard).
+    The resident forms also read the factors B_c^{-1} (complex64); the FP16
+    channel holds H in 4 bytes per entry plus one float scale per cluster."""
     if algo == "dl":
         return 8 * B * U + 8 * U + 8 * B
+    if form == "resident":
+        return 8 * B * U + 8 * C * U * U + 8 * B + 8 * U + U
+    if form == "resident_h16":
+        return 4 * B * U + 4 * C + 8 * C * U * U + 8 * B + 8 * U + U
     return 8 * B * U + 8 * B + 8 * U + U
 
 
-def algorithmic_flops(algo, B, U, C, T):
+def algorithmic_flops(algo, B, U, C, T, form="oneshot"):
     """Minimal real flops per vector (complex MAC = 8 flops; Hermitian Gram at
-    half cost; factorisation U^3/6 complex MACs; one U^2 solve per estimate)."""
+    half cost; factorisation U^3/6 complex MACs; one U^2 solve per estimate).
+    The resident forms form no Gram and no factorisation."""
     S = B // C
+    if algo == "admm" and form != "oneshot":
+        return 8.0 * (B * U + C * U * U + (T - 1) * C * U * U)
     if algo == "admm":
         cm = C * S * U * (U + 1) / 2 + C * U ** 3 / 6 + B * U + C * U * U + (T - 1) * C * U * U
     elif algo == "cg":
@@ -96,7 +105,16 @@ def make_frames(n_frames, algo, B, U, qam, snr_db, n_sc, seed):
     return frames, N0
 
 
-def run_step(api, frame, algo, C, T, N0, qam, out, prec="fp32", factor=None):
+def run_step(api, frame, algo, C, T, N0, qam, out, prec="fp32", factor=None, resident=None):
+    """One launch over one step's subcarriers.  ``resident`` = (form, channel
+    state, factors, B, U) runs the resident form against the frame's y only."""
+    if resident is not None:
+        form, chan, fac, B, U = resident
+        if form == "resident":
+            api.detect_factored(chan, fac, frame[1], N0, C, 1.0, T, qam=qam, out=out)
+        else:
+            api.detect_factored_h16(chan, fac, frame[1], N0, B, U, C, 1.0, T, qam=qam, out=out)
+        return
     if algo == "dl":
         api.precode(frame[0], frame[1], C, 1.0, T, out=out)
     else:
@@ -292,7 +310,7 @@ def profiled_traffic(workload: str):
     return traffic
 
 
-def time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, steps, warmup, n_streams=1):
+def time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, steps, warmup, n_streams=1, resident=None):
     """Runs warmup + steps launches rotating over the resident frames; returns
     (ms per step from the events bracketing all steps, sorted per-launch ms).
     With n_streams > 1 consecutive frames go to different streams (each with
@@ -305,7 +323,7 @@ def time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, steps, warmu
     streams = [main] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
     outs = [out] + [tuple(torch.empty_like(t) for t in out) for _ in range(n_streams - 1)]
     for i in range(warmup):
-        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out, prec, factor)
+        run_step(api, frames[i % n_frames], algo, C, T, N0, qam, out, prec, factor, resident)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     start_all = torch.cuda.Event(enable_timing=True)
@@ -318,7 +336,7 @@ def time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, steps, warmu
         j = i % n_streams
         with torch.cuda.stream(streams[j]):
             ev[i][0].record(streams[j])
-            run_step(api, frames[i % n_frames], algo, C, T, N0, qam, outs[j], prec, factor)
+            run_step(api, frames[i % n_frames], algo, C, T, N0, qam, outs[j], prec, factor, resident)
             ev[i][1].record(streams[j])
     for st in streams[1:]:
         main.wait_stream(st)
@@ -458,6 +476,10 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--streams", type=int, default=1, help="streams that consecutive frames alternate over")
     ap.add_argument("--factor", default=None, choices=["auto", "fp32", "fp64", "f16x2"])
+    ap.add_argument("--form", default="oneshot", choices=["oneshot", "resident", "resident_h16"],
+                    help="oneshot: every step forms Gram and inverse (default); resident: a static channel's "
+                         "factors (and for resident_h16 its FP16-packed H) are made once before timing and each "
+                         "step runs the iterations for a new received frame")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving benchmark")
     ap.add_argument("--serve-frames", type=int, default=300, help="frames per offered load in the serving run")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -490,8 +512,14 @@ def main():
     n_sc = args.n_sc or frame_sc * args.frames_per_step
     if args.T:
         T = args.T
-    bytes_vec = algorithmic_bytes(algo, B, U, C)
-    flops_vec = algorithmic_flops(algo, B, U, C, T)
+    if args.form != "oneshot":
+        if algo != "admm" or args.prec != "fp32":
+            print("--form resident* applies to the FP32 ADMM-UL workloads", file=sys.stderr)
+            sys.exit(2)
+        # the resident forms are measured on their own: no one-shot side legs
+        args.no_compare = args.no_serve = args.no_single_frame = True
+    bytes_vec = algorithmic_bytes(algo, B, U, C, args.form)
+    flops_vec = algorithmic_flops(algo, B, U, C, T, args.form)
     frame_bytes = n_sc * (8 * B * U + 8 * B)
     n_frames = args.frames or max(2, math.ceil(2.0e9 / frame_bytes))
     print(f"[bench] {args.workload}: generating {n_frames} resident frames "
@@ -503,11 +531,17 @@ def main():
     else:
         out = (torch.empty((n_sc, 1, U), dtype=torch.complex64, device="cuda"),
                torch.empty((n_sc, 1, U), dtype=torch.uint8, device="cuda"))
+    resident = None
+    if args.form != "oneshot":
+        H0 = frames[0][0]
+        fac = api.factor(H0, C, 1.0)
+        chan = H0 if args.form == "resident" else api.pack_channel_h16(H0, C)
+        resident = (args.form, chan, fac, B, U)
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()
     ms_per_step, per = time_steps(api, frames, algo, C, T, N0, qam, out, args.prec, args.factor,
-                                  args.steps, args.warmup, args.streams)
+                                  args.steps, args.warmup, args.streams, resident)
     wall = time.perf_counter() - t0
     avg_kernel_ms = sum(per) / len(per)
     vectors_per_s = n_sc / (ms_per_step * 1e-3)
@@ -532,7 +566,8 @@ def main():
     hbm_floor = bytes_vec * n_sc / (HBM_PEAK_GBS * 1e9)
     alu_floor = flops_vec * n_sc / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
     # the profiles are taken at the default step (DEFAULT_FRAMES_PER_STEP frames, FP32, workload T)
-    traffic = (profiled_traffic(args.workload)
+    profile_key = args.workload if args.form == "oneshot" else f"{args.workload}_{args.form}"
+    traffic = (profiled_traffic(profile_key)
                if (args.prec == "fp32" and not args.n_sc and not args.T
                    and args.frames_per_step == DEFAULT_FRAMES_PER_STEP) else None)
     if alu_floor > hbm_floor:
@@ -587,6 +622,8 @@ def main():
 
     metric = "detected subcarrier-vectors/s at B=256,U=32 (mixed vs FP32) + p99 frame latency"
     dtype = {"fp32": "f32", "fp16": "f16+f32", "bf16": "bf16+f32"}[args.prec]
+    if args.form == "resident_h16":
+        dtype = "f16+f32"
     line = {
         "metric": metric,
         "value": round(vectors_per_s, 1),
@@ -605,8 +642,12 @@ def main():
             "algorithm": {"admm": "Algorithm 1 (ADMM-UL)", "cg": "Algorithm 2 (CG-UL)", "dl": "Algorithm 3 (ADMM-DL)"}[algo],
             "B": B, "U": U, "C": C, "S": B // C, "n_sc": n_sc, "n_sym": 1, "T": T, "rho": 1.0, "qam": qam,
             "snr_db": snr, "precision": args.prec, "factor": args.factor or "auto", "frames_resident": n_frames,
+            "form": args.form,
             "step": f"one launch over {n_sc // frame_sc if n_sc % frame_sc == 0 else n_sc / frame_sc} frames "
-                    f"of {frame_sc} subcarriers ({n_sc} subcarrier-vectors), inputs resident in HBM",
+                    f"of {frame_sc} subcarriers ({n_sc} subcarrier-vectors), inputs resident in HBM"
+                    + ("" if args.form == "oneshot" else
+                       "; detection against a static channel whose factors (resident_h16: and FP16-packed H) "
+                       "were made once before timing"),
             "streams": args.streams,
             "p50_step_latency_us": round(p50 * 1e3, 2), "p99_step_latency_us": round(p99 * 1e3, 2),
             "single_frame": single,

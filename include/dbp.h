@@ -128,6 +128,21 @@ int dbp_detect_admm_factored(const void* H, const void* factors, const void* y,
                              float rho, float gamma, float N0, float Es,
                              int reg, int qam, void* stream);
 
+/* Per-subcarrier status of a result.  Non-finite outputs (NaN or infinite
+ * parts, e.g. from inputs whose Gram overflows FP32, or a ZF system that is
+ * singular) are not errors of the calls above; this reports them per
+ * subcarrier.
+ *   x       [n_sc][per_sc] complex64, device: any output of the library
+ *           (s_hat or x_hat with per_sc = n_sym * U, precoder x with
+ *           per_sc = n_sym * B)
+ *   status  [n_sc] int32, device, caller-allocated: every entry is written,
+ *           DBP_STATUS_NONFINITE if a real or imaginary part of subcarrier k
+ *           is NaN or infinite, else 0.
+ * Stream-ordered like the other calls; DBP_ERR_INVALID for n_sc < 0,
+ * per_sc < 1 or null pointers with n_sc > 0. */
+#define DBP_STATUS_NONFINITE 1
+int dbp_flag_nonfinite(const void* x, int n_sc, int per_sc, int32_t* status, void* stream);
+
 /* Mixed-precision resident channel (served form of Algorithm 1 for a static
  * channel): H is kept in HBM as complex FP16 with one power-of-two scale per
  * (subcarrier, cluster) tile, the factors B_c^{-1} stay FP32, and the

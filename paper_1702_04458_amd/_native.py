@@ -24,6 +24,7 @@ SIGNATURES = {
     "dbp_factor_admm": (_i, [_vp, _vp, _i, _i, _i, _i, _f, _i, _vp]),
     "dbp_detect_admm_factored": (_i, [_vp, _vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i, _vp]),
     "dbp_channel_h16_bytes": (ctypes.c_size_t, [_i, _i, _i, _i]),
+    "dbp_flag_nonfinite": (_i, [_vp, _i, _i, _vp, _vp]),
     "dbp_pack_channel_h16": (_i, [_vp, _vp, _i, _i, _i, _i, _vp]),
     "dbp_detect_admm_factored_h16": (_i, [_vp, _vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i,
                                           _vp]),

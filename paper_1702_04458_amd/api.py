@@ -116,6 +116,19 @@ def detect_factored(H, factors, y, N0, C, rho=1.0, T=5, *, reg="mmse", qam=16, E
     return s_hat, hd
 
 
+def nonfinite_status(x, *, out=None, stream=None):
+    """Per-subcarrier flags of a result x [n_sc, ...] (complex64, device):
+    int32 tensor [n_sc], 1 where any part of subcarrier k is NaN or infinite
+    (``dbp_flag_nonfinite``)."""
+    _dev(x, "x")
+    n_sc = x.shape[0]
+    per_sc = x.numel() // n_sc if n_sc else 1
+    st = out if out is not None else torch.empty(n_sc, dtype=torch.int32, device=x.device)
+    _dev(st, "status", torch.int32)
+    _native.check(_native.lib().dbp_flag_nonfinite(x.data_ptr(), n_sc, per_sc, st.data_ptr(), _stream(stream)))
+    return st
+
+
 def pack_channel_h16(H, C, *, out=None, stream=None):
     """Packs the channel H [n_sc, B, U] into the library's mixed-precision
     resident form (complex FP16 with one power-of-two scale per subcarrier and

@@ -252,6 +252,15 @@ int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, 
   return device_status(who, dbp::launch_admm_ul_factored(a, U, pl.nw, static_cast<hipStream_t>(stream)));
 }
 
+int dbp_flag_nonfinite(const void* x, int n_sc, int per_sc, int32_t* status, void* stream) {
+  const char* who = "dbp_flag_nonfinite";
+  if (n_sc < 0 || per_sc < 1) return fail(DBP_ERR_INVALID, "%s: n_sc must be >= 0 and per_sc >= 1", who);
+  if (n_sc > 0 && (!x || !status)) return fail(DBP_ERR_INVALID, "%s: null x or status", who);
+  if (n_sc == 0) return ok();
+  return device_status(who, dbp::launch_scan_nonfinite(static_cast<const float*>(x), 2 * (size_t)per_sc, n_sc,
+                                                       status, static_cast<hipStream_t>(stream)));
+}
+
 size_t dbp_channel_h16_bytes(int n_sc, int B, int U, int C) {
   if (n_sc < 0 || B < 1 || U < 1 || C < 1 || B % C) return 0;
   return (size_t)n_sc * B * U * 4 + (size_t)n_sc * C * 4;

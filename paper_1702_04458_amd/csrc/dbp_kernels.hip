@@ -1588,6 +1588,20 @@ __global__ void __launch_bounds__(256) pack_h16(const c32* __restrict__ H, uint3
 }
 
 // ---------------------------------------------------------------------------
+// Per-subcarrier status: one 256-lane workgroup per subcarrier ORs "not
+// finite" over the subcarrier's floats and writes the flag (every entry of
+// the status array is written, so it needs no clearing).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) scan_nonfinite(const float* __restrict__ x, size_t per_sc,
+                                                      int32_t* __restrict__ status) {
+  const float* p = x + (size_t)blockIdx.x * per_sc;
+  int bad = 0;
+  for (size_t i = threadIdx.x; i < per_sc; i += 256) bad |= !__builtin_isfinite(p[i]);
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) status[blockIdx.x] = bad ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 template <typename K, typename Args>
@@ -1659,6 +1673,13 @@ hipError_t launch_pack_h16(const c32* H, uint32_t* H16, float* hscale, int n_sc,
   if (tiles == 0) return hipSuccess;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(pack_h16, dim3((unsigned)tiles), dim3(256), 0, st, H, H16, hscale, B, U, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_nonfinite(const float* x, size_t floats_per_sc, int n_sc, int32_t* status,
+                                 hipStream_t st) {
+  if (n_sc == 0) return hipSuccess;
+  hipLaunchKernelGGL(scan_nonfinite, dim3((unsigned)n_sc), dim3(256), 0, st, x, floats_per_sc, status);
   return hipGetLastError();
 }
 

@@ -53,6 +53,9 @@ hipError_t launch_admm_ul_factored_h16(const UlArgs& a, int U, int nw, hipStream
 hipError_t launch_pack_h16(const c32* H, uint32_t* H16, float* hscale, int n_sc, int B, int U, int C,
                            hipStream_t st);
 hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
+// status[k] = 1 if any of the floats_per_sc floats of subcarrier k is NaN or infinite, else 0
+hipError_t launch_scan_nonfinite(const float* x, size_t floats_per_sc, int n_sc, int32_t* status,
+                                 hipStream_t st);
 hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st);
 
 }  // namespace dbp

@@ -135,3 +135,13 @@ def test_h16_channel_entry_points_reject():
     small = list(ok)
     small[9] = 16                                                                # S = 16 < U = 32
     assert L.dbp_detect_admm_factored_h16(*small) == 2
+
+
+def test_flag_nonfinite_rejects():
+    L = _native.lib()
+    # dbp_flag_nonfinite(x, n_sc, per_sc, status, stream)
+    assert L.dbp_flag_nonfinite(1, -1, 4, 1, None) == 1
+    assert L.dbp_flag_nonfinite(1, 4, 0, 1, None) == 1
+    assert L.dbp_flag_nonfinite(None, 4, 4, 1, None) == 1
+    assert L.dbp_flag_nonfinite(1, 4, 4, None, None) == 1
+    assert L.dbp_flag_nonfinite(None, 0, 4, None, None) == 0

@@ -249,6 +249,27 @@ def test_degenerate_inputs():
     assert rel_err(s, ref) <= 1e-5
 
 
+def test_nonfinite_status():
+    """Per-subcarrier flags are exact for planted NaN / infinite parts, zero
+    for a finite result, and set exactly on the subcarriers whose FP32 Gram
+    overflows (H scaled by 1e22 there)."""
+    say("[gpu] non-finite status")
+    x = torch.full((9, 2, 16), 1 + 1j, dtype=torch.complex64, device=DEV)
+    x[2, 1, 5] = complex(float("nan"), 0.0)
+    x[4, 0, 0] = complex(0.0, float("inf"))
+    x[8, 1, 15] = complex(-float("inf"), 1.0)
+    assert api.nonfinite_status(x).cpu().tolist() == [0, 0, 1, 0, 1, 0, 0, 0, 1]
+    fr = inputs.uplink_frame(inputs.frame_seed(15, 0, 10), 6, 128, 16, 16, 10.0)
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    s, _ = api.detect(H, y, fr.N0, 8, 1.0, 5, qam=16)
+    assert api.nonfinite_status(s).cpu().tolist() == [0] * 6
+    Hbig = H.clone()
+    Hbig[1:3] *= 1e22
+    s2, _ = api.detect(Hbig, y, fr.N0, 8, 1.0, 5, qam=16)
+    assert api.nonfinite_status(s2).cpu().tolist() == [0, 1, 1, 0, 0, 0]
+    assert torch.equal(s2[[0, 3, 4, 5]], s[[0, 3, 4, 5]])
+
+
 def test_launch_shape_independence():
     """Same inputs as one batch or split in pieces give identical bits."""
     say("[gpu] tiling independence")
