@@ -12,7 +12,7 @@ synthetic i.i.d. Rayleigh (generated on the device from a fixed seed) and stay
 resident in HBM; consecutive steps rotate over more distinct frames than the
 Infinity Cache holds, so every H byte is read from HBM.
 
-Prints one JSON line (rank 0).  ``--gpus`` above 1 is refused: this build
+Prints one JSON line (rank 0).  ``--gpus`` above 1 is refused: the benchmark
 measures one GPU's share of the work.
 """
 from __future__ import annotations
@@ -563,8 +563,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              f"(subcarrier sharding needs no exchange, see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(subcarriers shard across GPUs with no exchange: run one process per GPU on its share)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
