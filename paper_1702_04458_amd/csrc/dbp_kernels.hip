@@ -1387,7 +1387,7 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
 // row a of A_c^{-1}.
 // ---------------------------------------------------------------------------
 template <int G, int SG>
-__global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
+__device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   constexpr int P = 64 / G;
   extern __shared__ float4 smem_raw[];
   const int nw = blockDim.x >> 6;
@@ -1414,15 +1414,25 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
   const int ra = SPLIT ? (u % SG) : u;     // row of Hu_c held by this lane
   const int r0 = SPLIT ? RS * (u / SG) : 0;
   c32 hcol[SG], hrow[RS], A[SG];
+  // With the matrix-core Gram (which reads H_c itself) the register copies of
+  // H_c that the iterations use are loaded after the inverse, a second read
+  // of the same tile served by the caches, so they are not live during the
+  // Gram and the sweep.
+  constexpr bool LATE_H = (G == 32 && SG == 16);
+  if constexpr (!LATE_H) {
 #pragma unroll
-  for (int i = 0; i < SG; ++i) {
-    hcol[i] = (active && i < S) ? Hk[(size_t)i * G + u] : cz();
-    A[i] = cz();
+    for (int i = 0; i < SG; ++i) {
+      hcol[i] = (active && i < S) ? Hk[(size_t)i * G + u] : cz();
+      A[i] = cz();
+    }
+#pragma unroll
+    for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * G + r0 + i] : cz();
+  } else {
+#pragma unroll
+    for (int i = 0; i < SG; ++i) A[i] = cz();
   }
-#pragma unroll
-  for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * G + r0 + i] : cz();
   // A_c = H_c^H H_c + rho^{-1} I_S with (H_c^H H_c)[a][b] = sum_u conj(Hu[a][u]) Hu[b][u].
-  if constexpr (G == 32 && SG == 16) {
+  if constexpr (LATE_H) {
     gram_dl_mfma_s16_u32(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
   } else {
     // Row b of Hu_c is broadcast from the stage buffer of this wave.
@@ -1455,6 +1465,12 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
   for (int v = 0; v < SG; ++v)
     if (v == u) A[v].re += (u < S) ? irho : 1.0f;
   gj_invert<SG>(A, u, line, gbase);
+  if constexpr (LATE_H) {
+#pragma unroll
+    for (int i = 0; i < SG; ++i) hcol[i] = (active && i < S) ? Hk[(size_t)i * G + u] : cz();
+#pragma unroll
+    for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * G + r0 + i] : cz();
+  }
 
   int buf = 0;
   for (int n = 0; n < a.n_sym; ++n) {
@@ -1467,11 +1483,11 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
       wave_lds_sync();
       c32 acc = cz();
 #pragma unroll
-      for (int v0 = 0; v0 < RS; v0 += 8) {
-        c32 vv[8];
-        lds_read_vec<8>(line + gbase + r0 + v0, vv);
+      for (int v0 = 0; v0 < RS; v0 += 4) {
+        c32 vv[4];
+        lds_read_vec<4>(line + gbase + r0 + v0, vv);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) cmacc(acc, hrow[v0 + i], vv[i]);
+        for (int i = 0; i < 4; ++i) cmacc(acc, hrow[v0 + i], vv[i]);
       }
       wave_lds_sync();
       if (SPLIT) acc = cadd(acc, c32{__shfl_xor(acc.re, SG, 64), __shfl_xor(acc.im, SG, 64)});
@@ -1484,11 +1500,11 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
       wave_lds_sync();
       c32 m = cz();
 #pragma unroll
-      for (int v0 = 0; v0 < SG; v0 += 8) {
-        c32 xv[8];
-        lds_read_vec<8>(line + gbase + v0, xv);
+      for (int v0 = 0; v0 < SG; v0 += 4) {
+        c32 xv[4];
+        lds_read_vec<4>(line + gbase + v0, xv);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) cmac(m, hcol[v0 + i], xv[i]);
+        for (int i = 0; i < 4; ++i) cmac(m, hcol[v0 + i], xv[i]);
       }
       wave_lds_sync();
       const c32 wc = csub(m, lam);
@@ -1526,6 +1542,19 @@ __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
     if (active && u < S) a.x[vo * a.B + (size_t)c * S + u] = cscale(x, beta);
     if (active && c == 0 && u == 0 && a.beta) a.beta[vo] = beta;
   }
+}
+
+template <int G, int SG>
+__global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
+  admm_dl_body<G, SG>(a);
+}
+
+// The same with the register budget of four waves per SIMD: at B = 256,
+// U = 32, C = 16 a subcarrier's workgroup has eight waves, and 128 VGPRs let
+// two such workgroups share a CU instead of one.
+template <int G, int SG>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) admm_dl_f32_w4(DlArgs a) {
+  admm_dl_body<G, SG>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1701,7 +1730,7 @@ hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st) {
       return S <= 8 ? launch(admm_dl_f32<16, 8>, a, nw, st) : launch(admm_dl_f32<16, 16>, a, nw, st);
     case 32:
       if (S <= 8) return launch(admm_dl_f32<32, 8>, a, nw, st);
-      if (S <= 16) return launch(admm_dl_f32<32, 16>, a, nw, st);
+      if (S <= 16) return launch(admm_dl_f32_w4<32, 16>, a, nw, st);
       return launch(admm_dl_f32<32, 32>, a, nw, st);
     case 64:
       if (S <= 8) return launch(admm_dl_f32<64, 8>, a, nw, st);
