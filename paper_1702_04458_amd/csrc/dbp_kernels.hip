@@ -1472,6 +1472,14 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
     for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * G + r0 + i] : cz();
   }
 
+  // Broadcast line of the iterations, in the wave's stage buffer (free once
+  // the Gram is formed): group g at g (G + 8), and with split rows the second
+  // half of a group 4 entries further on, so that the (up to four) distinct
+  // 16-byte addresses a read instruction touches fall into different LDS
+  // banks.
+  c32* bl = sm.stage + wave * kStageRows * 64 + g * (G + 8);
+  const int bw = u + (SPLIT ? 4 * (u / RS) : 0);      // this lane's slot
+  const int br = r0 + (SPLIT ? 4 * (r0 / RS) : 0);    // start of the half this lane reads
   int buf = 0;
   for (int n = 0; n < a.n_sym; ++n) {
     const size_t vo = ((size_t)k * a.n_sym + n);
@@ -1479,13 +1487,13 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
     c32 z = cscale(s, a.f0), lam = cz();
     // x_c = A_c^{-1} H_c^H (z + lambda), entry a held by lane a < S
     auto apply = [&](c32 v) -> c32 {
-      line[gbase + u] = v;
+      bl[bw] = v;
       wave_lds_sync();
       c32 acc = cz();
 #pragma unroll
       for (int v0 = 0; v0 < RS; v0 += 4) {
         c32 vv[4];
-        lds_read_vec<4>(line + gbase + r0 + v0, vv);
+        lds_read_vec<4>(bl + br + v0, vv);
 #pragma unroll
         for (int i = 0; i < 4; ++i) cmacc(acc, hrow[v0 + i], vv[i]);
       }
@@ -1496,13 +1504,13 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
     c32 x = apply(z);
     for (int t = 2; t <= a.T; ++t) {
       // m_c = H_c x_c: m[u] = sum_a Hu[a][u] x[a]
-      line[gbase + u] = x;
+      bl[bw] = x;
       wave_lds_sync();
       c32 m = cz();
 #pragma unroll
       for (int v0 = 0; v0 < SG; v0 += 4) {
         c32 xv[4];
-        lds_read_vec<4>(line + gbase + v0, xv);
+        lds_read_vec<4>(bl + v0, xv);
 #pragma unroll
         for (int i = 0; i < 4; ++i) cmac(m, hcol[v0 + i], xv[i]);
       }
