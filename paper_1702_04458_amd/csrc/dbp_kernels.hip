@@ -235,9 +235,10 @@ __device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)
 // cores with v_mfma_f32_32x32x2f32, K running over pairs of antenna rows:
 //   Re G = sum_s Hr[s]^T Hr[s] + Hi[s]^T Hi[s],
 //   Im G = sum_s Hr[s]^T Hi[s] - Hi[s]^T Hr[s].
-// For the Gram of one problem lane l supplies H[s0 + l/32][l%32] as both the A
-// and the B operand; the imaginary part accumulates only M = Hr^T Hi (one
-// MFMA per row pair instead of two) and is antisymmetrised at the end.  The 32x32 result leaves lane l holding column l%32 for
+// For the Gram of one problem lane l supplies H[s0 + l/32][l%32] (or its
+// P = Hr + Hi) as both the A and the B operand.  Only P^T P and M = Hr^T Hi
+// are accumulated (two MFMAs per row pair instead of four), and
+// Re G = P^T P - M - M^T, Im G = M - M^T are formed at the end.  The 32x32 result leaves lane l holding column l%32 for
 // rows 8(r/4) + 4(l/32) + r%4 (r = 0..15); by Hermitian symmetry that is row
 // l%32 conjugated, for half h = l/32 of the columns.  With INVERT the
 // accumulators are replaced by (G + rho I)^{-1} on the matrix cores first.
@@ -290,9 +291,9 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         const c32 x = hv[p][q];
-        re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, x.re, re[p], 0, 0, 0);
-        re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.im, x.im, re[p], 0, 0, 0);
-        im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, x.im, im[p], 0, 0, 0);
+        const float pr = x.re + x.im;
+        re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(pr, pr, re[p], 0, 0, 0);       // P^T P, P = Hr + Hi
+        im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, x.im, im[p], 0, 0, 0);   // M = Hr^T Hi
         cmacc(hyp[p], x, yv[p][q]);
       }
     }
@@ -304,9 +305,11 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
         yv[p][q] = yn[p][q];
       }
   }
-  // im holds M = Hr^T Hi; Im G = M - M^T.  M goes through the wave's 4 KB
-  // stage buffer with an XOR-swizzled column (entry (i, j) at 32 i + (j ^ i)),
-  // conflict-free both for the row-wise write and the transposed read.
+  // re holds P^T P and im holds M = Hr^T Hi; since P^T P = Hr^T Hr + Hi^T Hi
+  // + M + M^T, Re G = P^T P - M - M^T and Im G = M - M^T (two MFMAs per row
+  // pair instead of three).  M goes through the wave's 4 KB stage buffer with
+  // an XOR-swizzled column (entry (i, j) at 32 i + (j ^ i)), conflict-free
+  // both for the row-wise write and the transposed read.
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
 #pragma unroll
@@ -318,7 +321,9 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r / 4) + 4 * h + (r % 4);
-      im[p][r] -= stage[32 * col + (i ^ col)];
+      const float mt = stage[32 * col + (i ^ col)];
+      re[p][r] -= im[p][r] + mt;
+      im[p][r] -= mt;
     }
     wave_lds_sync();
   }
@@ -682,9 +687,10 @@ __device__ __forceinline__ c32 gram_inv_mixed_u32(const UlArgs& a, c32 (&A)[32],
 
 // Gram matrices of the four problems of a wave for U = 16 (P = 4) on the
 // matrix cores with v_mfma_f32_16x16x4f32, K running over quadruples of
-// antenna rows: lane l supplies H[s0 + l/16][l%16] as both operands; the
-// imaginary part accumulates only M = Hr^T Hi (three MFMAs per row quadruple
-// instead of four) and Im G = M - M^T is formed in the transpose.  The
+// antenna rows: lane l supplies H[s0 + l/16][l%16] (or P = Hr + Hi) as both
+// operands.  Only P^T P and M = Hr^T Hi are accumulated (two MFMAs per row
+// quadruple instead of four); Re G = P^T P - M - M^T and Im G = M - M^T are
+// formed in the transpose.  The
 // 16x16 result leaves lane l holding column l%16 for rows 4(l/16) + r
 // (r = 0..3) of every problem; by Hermitian symmetry that is row l%16
 // conjugated, columns 4(l/16) .. 4(l/16)+3.  An LDS transpose (two problems
@@ -734,8 +740,8 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         const c32 x = hv[p][j];
-        re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, x.re, re[p], 0, 0, 0);
-        re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.im, x.im, re[p], 0, 0, 0);
+        const float pr = x.re + x.im;
+        re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, pr, re[p], 0, 0, 0);       // P^T P, P = Hr + Hi
         im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, x.im, im[p], 0, 0, 0);   // M = Hr^T Hi
         cmacc(hyp[p], x, yv[p][j]);
       }
@@ -750,7 +756,8 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
   }
   // Transpose through LDS, two problems per pass: entry (i, j) of problem pp at
   // (16 pp + i) 16 + (j ^ i) (XOR swizzle: conflict-free for the column read
-  // and for the transposed read).  im holds M = Hr^T Hi, and
+  // and for the transposed read).  re holds P^T P and im holds M = Hr^T Hi,
+  // so Re G[v][col] = (P^T P)[v][col] - M[v][col] - M[col][v] and
   // Im G[v][col] = M[v][col] - M[col][v].
   float* stf = reinterpret_cast<float*>(stage);
 #pragma unroll
@@ -769,7 +776,7 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
       for (int v = 0; v < 16; ++v) {
         const c32 g = stage[(16 * pp + v) * 16 + (col ^ v)];
         const float mt = stf[2 * ((16 * pp + col) * 16 + (v ^ col)) + 1];
-        A[v] = c32{g.re, mt - g.im};
+        A[v] = c32{g.re - g.im - mt, mt - g.im};
       }
     }
     wave_lds_sync();
@@ -790,8 +797,9 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
 
 // Downlink S x S Gram A_c[a][b] = sum_u conj(Hu[a][u]) Hu[b][u] (S <= 16,
 // U = 32 users as the contraction index, two problems per wave) on the matrix
-// cores with v_mfma_f32_16x16x4f32: lane l supplies Hu[l%16][u0 + l/16] as
-// both operands.  The 16x16 result (lane l: column l%16, rows 4(l/16)+r) goes
+// cores with v_mfma_f32_16x16x4f32: lane l supplies Hu[l%16][u0 + l/16] (or
+// its P = Hr + Hi) as both operands; only P P^T and M = Hr Hi^T are
+// accumulated (two MFMAs per four users instead of four).  The 16x16 result (lane l: column l%16, rows 4(l/16)+r) goes
 // through the wave's stage buffer so that lane b < 16 of each problem's lane
 // group reads row b.
 __device__ __forceinline__ void gram_dl_mfma_s16_u32(const DlArgs& a, c32 (&A)[16], int lane, int wave, c32* stage) {
@@ -811,10 +819,9 @@ __device__ __forceinline__ void gram_dl_mfma_s16_u32(const DlArgs& a, c32 (&A)[1
     im[p] = f32x4{};
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[j].re, x[j].re, re[p], 0, 0, 0);
-      re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[j].im, x[j].im, re[p], 0, 0, 0);
-      im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[j].re, x[j].im, im[p], 0, 0, 0);
-      im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(-x[j].im, x[j].re, im[p], 0, 0, 0);
+      const float pr = x[j].re + x[j].im;
+      re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, pr, re[p], 0, 0, 0);               // P P^T, P = Hr + Hi
+      im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[j].re, x[j].im, im[p], 0, 0, 0);   // M = Hr Hi^T
     }
   }
 #pragma unroll
@@ -822,14 +829,19 @@ __device__ __forceinline__ void gram_dl_mfma_s16_u32(const DlArgs& a, c32 (&A)[1
 #pragma unroll
     for (int r = 0; r < 4; ++r) stage[p * 256 + (4 * q + r) * 16 + r16] = c32{re[p][r], im[p][r]};
   wave_lds_sync();
+  // Re A[b][v] = (P P^T)[b][v] - M[b][v] - M[v][b], Im A[b][v] = M[b][v] - M[v][b]
   const int p = lane >> 5, b = lane & 31;
   if (b < 16) {
+    const float* stf = reinterpret_cast<const float*>(stage + p * 256);
 #pragma unroll
     for (int v0 = 0; v0 < 16; v0 += 8) {
       c32 row[8];
       lds_read_vec<8>(stage + p * 256 + b * 16 + v0, row);
 #pragma unroll
-      for (int v = 0; v < 8; ++v) A[v0 + v] = row[v];
+      for (int v = 0; v < 8; ++v) {
+        const float mt = stf[2 * ((v0 + v) * 16 + b) + 1];
+        A[v0 + v] = c32{row[v].re - row[v].im - mt, row[v].im - mt};
+      }
     }
   }
   wave_lds_sync();
@@ -953,7 +965,8 @@ __device__ __forceinline__ c32 combine_hy_u64(c32 e0, c32 e1, int h) {
 }
 
 template <bool INVERT>
-__device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave, float* line) {
+__device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave, float* line,
+                                             float* stage) {
   const int h = lane >> 5, col = lane & 31;
   f32x16 re[2][2], im[2][2];
   c32 hy0 = cz(), hy1 = cz();
@@ -983,14 +996,13 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
     c32 n0, n1, ny;
     if (s0 + 2 < a.S) fetch(s0 + 2, n0, n1, ny);
     const c32 xs[2] = {x0, x1};
+    const float ps[2] = {x0.re + x0.im, x1.re + x1.im};
 #pragma unroll
     for (int I = 0; I < 2; ++I)
 #pragma unroll
       for (int J = 0; J < 2; ++J) {
-        re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[I].re, xs[J].re, re[I][J], 0, 0, 0);
-        re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[I].im, xs[J].im, re[I][J], 0, 0, 0);
-        im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[I].re, xs[J].im, im[I][J], 0, 0, 0);
-        im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(-xs[I].im, xs[J].re, im[I][J], 0, 0, 0);
+        re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(ps[I], ps[J], re[I][J], 0, 0, 0);          // P^T P
+        im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[I].re, xs[J].im, im[I][J], 0, 0, 0);   // M
       }
     // entries col and 32 + col of H_c^H y_c over the rows of this lane's parity
     cmacc(hy0, x0, yv);
@@ -998,6 +1010,48 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
     x0 = n0;
     x1 = n1;
     yv = ny;
+  }
+  // Tile (I, J) holds P^T P and M = Hr^T Hi restricted to rows 32 I.. and
+  // columns 32 J..; Re G_IJ = (P^T P)_IJ - M_IJ - (M_JI)^T and
+  // Im G_IJ = M_IJ - (M_JI)^T.  The transposes go through the wave's 4 KB
+  // stage buffer, one 32 x 32 tile at a time, XOR-swizzled as for U = 32
+  // (entry (i, j) at 32 i + (j ^ i)); both off-diagonal transposes are read
+  // before either off-diagonal tile changes.
+  auto transposed = [&](const f32x16& m, float (&out)[16]) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      stage[32 * i + (col ^ i)] = m[r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      out[r] = stage[32 * col + (i ^ col)];
+    }
+    wave_lds_sync();
+  };
+  {
+    float t01[16], t10[16];
+    transposed(im[0][1], t01);
+    transposed(im[1][0], t10);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      re[0][1][r] -= im[0][1][r] + t10[r];
+      im[0][1][r] -= t10[r];
+      re[1][0][r] -= im[1][0][r] + t01[r];
+      im[1][0][r] -= t01[r];
+    }
+  }
+#pragma unroll
+  for (int D = 0; D < 2; ++D) {
+    float td[16];
+    transposed(im[D][D], td);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      re[D][D][r] -= im[D][D][r] + td[r];
+      im[D][D][r] -= td[r];
+    }
   }
   if (INVERT) gj_invert_mfma_u64(re, im, lane, a.rho, line);
   acc_to_rows_u64(re, im, A, h);
@@ -1239,7 +1293,8 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
       if (v == u) A[v].re += a.rho;
     gj_invert<G>(A, u, line, gbase);
   } else if constexpr (G == 64 && HALF == 0) {
-    hy0 = gram_mfma_u64<true>(a, A, lane, wave, reinterpret_cast<float*>(line));
+    hy0 = gram_mfma_u64<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
+                              reinterpret_cast<float*>(sm.stage + wave * kStageRows * 64));
   } else if constexpr (G == 64 && HALF == 1) {
     hy0 = gram_inv_mixed_u64<_Float16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line));
   } else if constexpr (G == 64 && HALF == 2) {
@@ -1336,7 +1391,8 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   else if constexpr (G == 16)
     hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
   else if constexpr (G == 64)
-    hy0 = gram_mfma_u64<false>(a, A, lane, wave, reinterpret_cast<float*>(line));
+    hy0 = gram_mfma_u64<false>(a, A, lane, wave, reinterpret_cast<float*>(line),
+                               reinterpret_cast<float*>(sm.stage + wave * kStageRows * 64));
   else
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 
