@@ -799,22 +799,28 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
 // U = 32 users as the contraction index, two problems per wave) on the matrix
 // cores with v_mfma_f32_16x16x4f32: lane l supplies Hu[l%16][u0 + l/16] (or
 // its P = Hr + Hi) as both operands; only P P^T and M = Hr Hi^T are
-// accumulated (two MFMAs per four users instead of four).  The 16x16 result (lane l: column l%16, rows 4(l/16)+r) goes
+// accumulated (two MFMAs per four users instead of four).  The operands come
+// from the register copy hcol (lane u of group g: Hu[i][u]) through LDS, so H
+// is read from memory once.  The 16x16 result (lane l: column l%16, rows 4(l/16)+r) goes
 // through the wave's stage buffer so that lane b < 16 of each problem's lane
 // group reads row b.
-__device__ __forceinline__ void gram_dl_mfma_s16_u32(const DlArgs& a, c32 (&A)[16], int lane, int wave, c32* stage) {
+__device__ __forceinline__ void gram_dl_mfma_s16_u32(const c32 (&hcol)[16], c32 (&A)[16], int lane, int g, int u,
+                                                     c32* stage) {
   const int q = lane >> 4, r16 = lane & 15;
   f32x4 re[2], im[2];
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
-    const int lp = wave * 2 + p;
-    const int ls = lp / a.Cp, c = lp % a.Cp;
-    const int k = blockIdx.x * a.sc_per_block + ls;
-    const bool act = (k < a.n_sc) && (c < a.C) && (r16 < a.S);
-    const c32* Hk = act ? a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32 + (size_t)r16 * 32 + q : a.H + q;
+    // problem p's tile (from the register copy hcol, zero past S) through
+    // the stage buffer: entry (i, w) at 32 i + ((w + 2 i) mod 32)
+    if (g == p) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) stage[i * 32 + ((u + 2 * i) & 31)] = hcol[i];
+    }
+    wave_lds_sync();
     c32 x[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = ld_or_zero(Hk + 4 * j, act);
+    for (int j = 0; j < 8; ++j) x[j] = stage[r16 * 32 + ((q + 4 * j + 2 * r16) & 31)];
+    wave_lds_sync();
     re[p] = f32x4{};
     im[p] = f32x4{};
 #pragma unroll
@@ -1470,26 +1476,22 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   const int ra = SPLIT ? (u % SG) : u;     // row of Hu_c held by this lane
   const int r0 = SPLIT ? RS * (u / SG) : 0;
   c32 hcol[SG], hrow[RS], A[SG];
-  // With the matrix-core Gram (which reads H_c itself) the register copies of
-  // H_c that the iterations use are loaded after the inverse, a second read
-  // of the same tile served by the caches, so they are not live during the
-  // Gram and the sweep.
+  // With the matrix-core Gram (U = 32, S <= 16) the row copy hrow is formed
+  // only after the inverse, from hcol through LDS, so that it is not live
+  // during the Gram and the sweep (register budget of four waves per SIMD).
   constexpr bool LATE_H = (G == 32 && SG == 16);
+#pragma unroll
+  for (int i = 0; i < SG; ++i) {
+    hcol[i] = (active && i < S) ? Hk[(size_t)i * G + u] : cz();
+    A[i] = cz();
+  }
   if constexpr (!LATE_H) {
 #pragma unroll
-    for (int i = 0; i < SG; ++i) {
-      hcol[i] = (active && i < S) ? Hk[(size_t)i * G + u] : cz();
-      A[i] = cz();
-    }
-#pragma unroll
     for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * G + r0 + i] : cz();
-  } else {
-#pragma unroll
-    for (int i = 0; i < SG; ++i) A[i] = cz();
   }
   // A_c = H_c^H H_c + rho^{-1} I_S with (H_c^H H_c)[a][b] = sum_u conj(Hu[a][u]) Hu[b][u].
   if constexpr (LATE_H) {
-    gram_dl_mfma_s16_u32(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
+    gram_dl_mfma_s16_u32(hcol, A, lane, g, u, sm.stage + wave * kStageRows * 64);
   } else {
     // Row b of Hu_c is broadcast from the stage buffer of this wave.
     c32* stage = sm.stage + wave * kStageRows * 64;
@@ -1522,10 +1524,27 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
     if (v == u) A[v].re += (u < S) ? irho : 1.0f;
   gj_invert<SG>(A, u, line, gbase);
   if constexpr (LATE_H) {
+    // Transpose the S x G tile of each problem through the wave's stage
+    // buffer, one problem at a time: entry (i, w) at i G + ((w + 2 i) mod G).
+    // The rotation keeps column pairs together (16-byte reads) and puts the
+    // rows that a read instruction touches into different LDS banks.
+    c32* tile = sm.stage + wave * kStageRows * 64;
+    for (int pp = 0; pp < P; ++pp) {
+      if (g == pp) {
 #pragma unroll
-    for (int i = 0; i < SG; ++i) hcol[i] = (active && i < S) ? Hk[(size_t)i * G + u] : cz();
+        for (int i = 0; i < SG; ++i) tile[i * G + ((u + 2 * i) & (G - 1))] = hcol[i];
+      }
+      wave_lds_sync();
+      if (g == pp) {
 #pragma unroll
-    for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * G + r0 + i] : cz();
+        for (int m = 0; m < RS / 2; ++m) {
+          const float4 v = *reinterpret_cast<const float4*>(tile + ra * G + ((r0 + 2 * m + 2 * ra) & (G - 1)));
+          hrow[2 * m] = c32{v.x, v.y};
+          hrow[2 * m + 1] = c32{v.z, v.w};
+        }
+      }
+      wave_lds_sync();
+    }
   }
 
   // Broadcast line of the iterations, in the wave's stage buffer (free once
