@@ -46,15 +46,17 @@ def device_frame(n_sc, B, U, qam, snr_db, seed):
 
 
 @pytest.mark.parametrize("algo,B,U,C,qam,snr", [("admm", 256, 32, 8, 64, 25.0), ("admm", 128, 16, 8, 16, 10.0),
-                                                ("cg", 128, 16, 8, 16, 10.0)])
+                                                ("cg", 128, 16, 8, 16, 10.0), ("admm", 512, 64, 8, 64, 25.0)])
 def test_bench_launch_sampled(algo, B, U, C, qam, snr):
-    """9600 subcarriers (eight 1200-subcarrier frames) in one launch, as the
-    benchmark step; 48 sampled subcarriers against the oracle."""
+    """38,400 subcarriers (32 frames of 1200) in one launch, the benchmark's
+    step; 48 sampled subcarriers, including the first and the last, against
+    the oracle."""
     say(f"[gpu] full-size launch {algo} B={B} U={U} C={C}")
-    H, y, N0 = device_frame(9600, B, U, qam, snr, seed=77 + U)
+    n_sc = 38400
+    H, y, N0 = device_frame(n_sc, B, U, qam, snr, seed=77 + U)
     s, h = api.detect(H, y, N0, C, 1.0, 5, algo=algo, qam=qam)
     torch.cuda.synchronize()
-    sel = np.sort(np.random.default_rng(U).choice(9600, 48, replace=False))
+    sel = np.unique(np.concatenate([[0, n_sc - 1], np.random.default_rng(U).choice(n_sc, 46, replace=False)]))
     Hs = H[sel].cpu().numpy()
     ys = y[sel].cpu().numpy()
     if algo == "admm":
@@ -66,6 +68,36 @@ def test_bench_launch_sampled(algo, B, U, C, qam, snr):
     say(f"    rel_err={err:.2e}")
     assert err <= 1e-5
     check_hard(ss, hs, ref, qam)
+
+
+def test_precode_bench_launch_sampled():
+    """Downlink at B=256, U=32, C=16: 38,400 subcarriers in one launch, the
+    benchmark's step, with per-cluster budgets; 48 sampled subcarriers
+    against the oracle."""
+    say("[gpu] full-size launch precode B=256 U=32 C=16")
+    n_sc, B, U, C = 38400, 256, 32, 16
+    g = torch.Generator(device="cuda")
+    g.manual_seed(91)
+    L, kappa = inputs.qam_side(64), inputs.qam_kappa(64)
+    sd = 0.5 ** 0.5
+    H = torch.complex(torch.randn(n_sc, B, U, device="cuda", generator=g) * sd,
+                      torch.randn(n_sc, B, U, device="cuda", generator=g) * sd).contiguous()
+    iI = torch.randint(0, L, (n_sc, 1, U), device="cuda", generator=g)
+    iQ = torch.randint(0, L, (n_sc, 1, U), device="cuda", generator=g)
+    s = torch.complex((2 * iI - (L - 1)).float() / kappa, (2 * iQ - (L - 1)).float() / kappa).contiguous()
+    Pc = [0.007] * C
+    x, beta = api.precode(H, s, C, 1.0, 5, P_cluster=torch.tensor(Pc, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    sel = np.unique(np.concatenate([[0, n_sc - 1], np.random.default_rng(5).choice(n_sc, 46, replace=False)]))
+    Hs, ss = H[sel].cpu().numpy(), s[sel].cpu().numpy()
+    ref = O.admm_dl_frame(Hs, ss, C, 1.0, 5)
+    refb = np.zeros((len(sel), 1))
+    for i in range(len(sel)):
+        ref[i, 0], refb[i, 0] = O.power_scale(ref[i, 0], C, Pc)
+    err = rel_err(x[sel].cpu().numpy(), ref)
+    say(f"    rel_err={err:.2e}")
+    assert err <= 1e-5
+    assert np.abs(beta[sel].cpu().numpy() - refb).max() <= 1e-5
 
 
 @pytest.mark.parametrize("B,U,C,qam,snr", [(256, 32, 8, 64, 15.0), (128, 16, 8, 16, 0.0)])
