@@ -108,9 +108,8 @@ __device__ __forceinline__ c32 cluster_pass(const c32* __restrict__ H, const c32
   return hy;
 }
 
-// Row u of H_c^H y_c for symbol n read from the packed FP16 channel: every
-// entry is widened to FP32 and the products are accumulated in FP32; the
-// tile's power-of-two scale is applied once at the end (exact).
+// Entries of the packed FP16 channel: a pair of binary16 values (real part in
+// the low half), widened to FP32 exactly.
 typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ c32 widen_h16(uint32_t w) {
@@ -118,31 +117,41 @@ __device__ __forceinline__ c32 widen_h16(uint32_t w) {
   return c32{(float)v.x, (float)v.y};
 }
 
-template <int G>
-__device__ __forceinline__ c32 cluster_hy_h16(const UlArgs& a, int k, int c, int n, int u, int g, int wave,
-                                              bool active, const Smem& sm) {
-  constexpr int R = kStageRows;
+// Row u of H_c^H y_c for symbol n for the resident forms (no Gram to share
+// the pass with): every lane reads its column entry of each row of H_c
+// (complex64, or the packed FP16 channel widened to FP32, the products
+// accumulated in FP32 and the tile's power-of-two scale applied once at the
+// end, which is exact) and the row's y entry directly (one address per lane
+// group), with no LDS staging, so the loads of several rows are in flight
+// together.  The FP16 channel uses it; for complex64 H the LDS-staged pass
+// measured the same.
+template <int G, bool H16>
+__device__ __forceinline__ c32 cluster_hy_direct(const UlArgs& a, int k, int c, int n, int u, bool active) {
   c32 hy = cz();
-  c32* yst = sm.ystage + wave * R * 8;
-  const uint32_t* Hk = a.H16 + (size_t)k * a.B * G + (size_t)c * a.S * G;
+  if (!active) return hy;
   const c32* yk = a.y + ((size_t)k * a.n_sym + n) * a.B + (size_t)c * a.S;
-  for (int s0 = 0; s0 < a.S; s0 += R) {
-    uint32_t h[R];
+  const size_t hb = (size_t)k * a.B * G + (size_t)c * a.S * G + u;
+  constexpr int CH = G >= 64 ? 4 : 8;   // rows in flight per lane (register budget at U = 64)
+  int s = 0;
+  for (; s + CH <= a.S; s += CH) {
+    c32 hv[CH], yv[CH];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int s = s0 + r;
-      h[r] = (active && s < a.S) ? Hk[(size_t)s * G + u] : 0u;
+    for (int r = 0; r < CH; ++r) {
+      if constexpr (H16)
+        hv[r] = widen_h16(a.H16[hb + (size_t)(s + r) * G]);
+      else
+        hv[r] = a.H[hb + (size_t)(s + r) * G];
+      yv[r] = yk[s + r];
     }
-    if (u < R) {
-      const int s = s0 + u;
-      yst[u * 8 + g] = (active && s < a.S) ? yk[s] : cz();
-    }
-    wave_lds_sync();
 #pragma unroll
-    for (int r = 0; r < R; ++r) cmacc(hy, widen_h16(h[r]), yst[r * 8 + g]);
-    wave_lds_sync();
+    for (int r = 0; r < CH; ++r) cmacc(hy, hv[r], yv[r]);
   }
-  return cscale(hy, active ? a.hscale[(size_t)k * a.C + c] : 0.f);
+  for (; s < a.S; ++s) {
+    const c32 h = H16 ? widen_h16(a.H16[hb + (size_t)s * G]) : a.H[hb + (size_t)s * G];
+    cmacc(hy, h, yk[s]);
+  }
+  if constexpr (H16) hy = cscale(hy, a.hscale[(size_t)k * a.C + c]);
+  return hy;
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -1324,7 +1333,7 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   for (int n = 0; n < a.n_sym; ++n) {
     c32 hy = hy0;
     if constexpr (STAGE == 3)
-      hy = cluster_hy_h16<G>(a, k, c, n, u, g, wave, active, sm);
+      hy = cluster_hy_direct<G, true>(a, k, c, n, u, active);
     else if (n > 0 || STAGE == 2)
       hy = cluster_pass<G, false>(a.H, a.y, A, k, c, n, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
     // y_c^reg = B_c^{-1} H_c^H y_c; z = y^reg; lambda = 0
