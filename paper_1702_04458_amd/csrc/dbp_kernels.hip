@@ -337,24 +337,23 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
     wave_lds_sync();
   }
   if (INVERT) gj_invert_mfma_u32(re, im, lane, a.rho, line);
-  // exchange halves: lanes < 32 keep problem 0, lanes >= 32 keep problem 1
+  // exchange halves: lanes < 32 keep problem 0, lanes >= 32 keep problem 1.
+  // v_permlane32_swap(X, Y) leaves [X of lanes 0-31 | Y of lanes 0-31] in its
+  // first result and [X of lanes 32-63 | Y of lanes 32-63] in its second, so
+  // with X = problem 0 and Y = problem 1 the first result is every lane's
+  // half-0 entry of its own problem and the second its half-1 entry.
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int m0 = 8 * (r / 4) + (r % 4);      // column of this slot in half 0
-    const float sr = h ? re[0][r] : re[1][r];
-    const float si = h ? im[0][r] : im[1][r];
-    const float tr = __shfl_xor(sr, 32, 64);
-    const float ti = __shfl_xor(si, 32, 64);
-    const float h0r = h ? tr : re[0][r], h0i = h ? ti : im[0][r];
-    const float h1r = h ? re[1][r] : tr, h1i = h ? im[1][r] : ti;
-    A[m0] = c32{h0r, -h0i};
-    A[m0 + 4] = c32{h1r, -h1i};
+    const auto xr = __builtin_amdgcn_permlane32_swap(__float_as_uint(re[0][r]), __float_as_uint(re[1][r]), false, false);
+    const auto xi = __builtin_amdgcn_permlane32_swap(__float_as_uint(im[0][r]), __float_as_uint(im[1][r]), false, false);
+    A[m0] = c32{__uint_as_float(xr[0]), -__uint_as_float(xi[0])};
+    A[m0 + 4] = c32{__uint_as_float(xr[1]), -__uint_as_float(xi[1])};
   }
-  const c32 send = h ? hyp[0] : hyp[1];
-  const c32 got = c32{__shfl_xor(send.re, 32, 64), __shfl_xor(send.im, 32, 64)};
-  const c32 mine = h ? hyp[1] : hyp[0];
-  // rows of parity 0 first, then parity 1 (same order on every lane)
-  return h ? cadd(got, mine) : cadd(mine, got);
+  // rows of parity 0 (first result) plus rows of parity 1 (second result)
+  const auto yr = __builtin_amdgcn_permlane32_swap(__float_as_uint(hyp[0].re), __float_as_uint(hyp[1].re), false, false);
+  const auto yi = __builtin_amdgcn_permlane32_swap(__float_as_uint(hyp[0].im), __float_as_uint(hyp[1].im), false, false);
+  return c32{__uint_as_float(yr[0]) + __uint_as_float(yr[1]), __uint_as_float(yi[0]) + __uint_as_float(yi[1])};
 }
 
 // ---------------------------------------------------------------------------
