@@ -240,6 +240,19 @@ __device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)
   for (int p = 0; p < 2; ++p) gj_unscale_u32(re[p], im[p], pvv[p], 1.f, lane, line);
 }
 
+// Exchange between the wave's two 32-lane halves: v_permlane32_swap(X, Y)
+// leaves [X of lanes 0-31 | Y of lanes 0-31] in its first result and
+// [X of lanes 32-63 | Y of lanes 32-63] in its second.  With X and Y the two
+// halves' accumulators of tile columns 0 and 1 (or problems 0 and 1), the
+// first result is every lane's half-0 entry and the second its half-1 entry.
+struct f32pair {
+  float lo, hi;
+};
+__device__ __forceinline__ f32pair swap_halves(float x, float y) {
+  const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return f32pair{__uint_as_float(s[0]), __uint_as_float(s[1])};
+}
+
 // Gram matrices of the two problems of a wave (U = 32, P = 2) on the matrix
 // cores with v_mfma_f32_32x32x2f32, K running over pairs of antenna rows:
 //   Re G = sum_s Hr[s]^T Hr[s] + Hi[s]^T Hi[s],
@@ -337,23 +350,19 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
     wave_lds_sync();
   }
   if (INVERT) gj_invert_mfma_u32(re, im, lane, a.rho, line);
-  // exchange halves: lanes < 32 keep problem 0, lanes >= 32 keep problem 1.
-  // v_permlane32_swap(X, Y) leaves [X of lanes 0-31 | Y of lanes 0-31] in its
-  // first result and [X of lanes 32-63 | Y of lanes 32-63] in its second, so
-  // with X = problem 0 and Y = problem 1 the first result is every lane's
-  // half-0 entry of its own problem and the second its half-1 entry.
+  // exchange halves: lanes < 32 keep problem 0, lanes >= 32 keep problem 1
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int m0 = 8 * (r / 4) + (r % 4);      // column of this slot in half 0
-    const auto xr = __builtin_amdgcn_permlane32_swap(__float_as_uint(re[0][r]), __float_as_uint(re[1][r]), false, false);
-    const auto xi = __builtin_amdgcn_permlane32_swap(__float_as_uint(im[0][r]), __float_as_uint(im[1][r]), false, false);
-    A[m0] = c32{__uint_as_float(xr[0]), -__uint_as_float(xi[0])};
-    A[m0 + 4] = c32{__uint_as_float(xr[1]), -__uint_as_float(xi[1])};
+    const f32pair xr = swap_halves(re[0][r], re[1][r]);
+    const f32pair xi = swap_halves(im[0][r], im[1][r]);
+    A[m0] = c32{xr.lo, -xi.lo};
+    A[m0 + 4] = c32{xr.hi, -xi.hi};
   }
   // rows of parity 0 (first result) plus rows of parity 1 (second result)
-  const auto yr = __builtin_amdgcn_permlane32_swap(__float_as_uint(hyp[0].re), __float_as_uint(hyp[1].re), false, false);
-  const auto yi = __builtin_amdgcn_permlane32_swap(__float_as_uint(hyp[0].im), __float_as_uint(hyp[1].im), false, false);
-  return c32{__uint_as_float(yr[0]) + __uint_as_float(yr[1]), __uint_as_float(yi[0]) + __uint_as_float(yi[1])};
+  const f32pair yr = swap_halves(hyp[0].re, hyp[1].re);
+  const f32pair yi = swap_halves(hyp[0].im, hyp[1].im);
+  return c32{yr.lo + yr.hi, yi.lo + yi.hi};
 }
 
 // ---------------------------------------------------------------------------
@@ -513,25 +522,23 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
 
 // Accumulator layout -> lane-row layout (lanes < 32: problem 0, >= 32: problem 1)
 __device__ __forceinline__ void acc_to_rows_u32(const f32x16 (&re)[2], const f32x16 (&im)[2], c32 (&A)[32], int h) {
+  (void)h;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int m0 = 8 * (r / 4) + (r % 4);
-    const float sr = h ? re[0][r] : re[1][r];
-    const float si = h ? im[0][r] : im[1][r];
-    const float tr = __shfl_xor(sr, 32, 64);
-    const float ti = __shfl_xor(si, 32, 64);
-    const float h0r = h ? tr : re[0][r], h0i = h ? ti : im[0][r];
-    const float h1r = h ? re[1][r] : tr, h1i = h ? im[1][r] : ti;
-    A[m0] = c32{h0r, -h0i};
-    A[m0 + 4] = c32{h1r, -h1i};
+    const f32pair xr = swap_halves(re[0][r], re[1][r]);
+    const f32pair xi = swap_halves(im[0][r], im[1][r]);
+    A[m0] = c32{xr.lo, -xi.lo};
+    A[m0 + 4] = c32{xr.hi, -xi.hi};
   }
 }
 
+// rows of parity 0 plus rows of parity 1 of H_c^H y_c, for this lane's problem
 __device__ __forceinline__ c32 combine_hy(const c32 (&hyp)[2], int h) {
-  const c32 send = h ? hyp[0] : hyp[1];
-  const c32 got = c32{__shfl_xor(send.re, 32, 64), __shfl_xor(send.im, 32, 64)};
-  const c32 mine = h ? hyp[1] : hyp[0];
-  return h ? cadd(got, mine) : cadd(mine, got);
+  (void)h;
+  const f32pair yr = swap_halves(hyp[0].re, hyp[1].re);
+  const f32pair yi = swap_halves(hyp[0].im, hyp[1].im);
+  return c32{yr.lo + yr.hi, yi.lo + yi.hi};
 }
 
 // Regularised inverse in FP64 on the VALU (lane-row layout, rotated
@@ -959,23 +966,21 @@ __device__ __forceinline__ void acc_to_rows_u64(const f32x16 (&re)[2][2], const 
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int m0 = 32 * I + 8 * (r / 4) + (r % 4);
-      const float sr = h ? re[I][0][r] : re[I][1][r];
-      const float si = h ? im[I][0][r] : im[I][1][r];
-      const float tr = __shfl_xor(sr, 32, 64);
-      const float ti = __shfl_xor(si, 32, 64);
-      const float h0r = h ? tr : re[I][0][r], h0i = h ? ti : im[I][0][r];
-      const float h1r = h ? re[I][1][r] : tr, h1i = h ? im[I][1][r] : ti;
-      A[m0] = c32{h0r, -h0i};
-      A[m0 + 4] = c32{h1r, -h1i};
+      const f32pair xr = swap_halves(re[I][0][r], re[I][1][r]);
+      const f32pair xi = swap_halves(im[I][0][r], im[I][1][r]);
+      A[m0] = c32{xr.lo, -xi.lo};
+      A[m0 + 4] = c32{xr.hi, -xi.hi};
     }
+  (void)h;
 }
 
 // lane u < 32 owns entry u of H_c^H y_c, lane 32 + u entry 32 + u; e0 / e1 are
 // this lane's partial sums of entries col / 32 + col over its half of the rows
 __device__ __forceinline__ c32 combine_hy_u64(c32 e0, c32 e1, int h) {
-  const c32 send = h ? e0 : e1;
-  const c32 got = c32{__shfl_xor(send.re, 32, 64), __shfl_xor(send.im, 32, 64)};
-  return h ? cadd(got, e1) : cadd(e0, got);
+  (void)h;
+  const f32pair yr = swap_halves(e0.re, e1.re);
+  const f32pair yi = swap_halves(e0.im, e1.im);
+  return c32{yr.lo + yr.hi, yi.lo + yi.hi};
 }
 
 template <bool INVERT>
