@@ -72,8 +72,10 @@ __device__ __forceinline__ void lds_read_vec(const c32* p, c32* r) {
 // pair of operands on both partners at every level).
 // Within a row of 16 lanes the butterfly uses DPP: quad_perm [1,0,3,2]
 // (xor 1), quad_perm [2,3,0,1] (xor 2), row_half_mirror and row_mirror (which
-// pair the already uniform quads / half-rows); wider groups add a swizzle
-// across rows and a swap of wave halves.
+// pair the already uniform quads / half-rows); wider groups add a swap of
+// odd and even rows (v_permlane16_swap) and of wave halves
+// (v_permlane32_swap), each of which gives a lane its partner's value beside
+// its own.
 // Every control used here (quad_perm, row mirrors, row_newbcast) reads a valid
 // lane of the same row for every lane, so no "old" value is needed and the
 // move carries no initialisation of its destination.
@@ -88,7 +90,10 @@ __device__ __forceinline__ float group_sum(float v) {
   if constexpr (G >= 4) v += dpp<0x4E>(v);
   if constexpr (G >= 8) v += dpp<0x141>(v);
   if constexpr (G >= 16) v += dpp<0x140>(v);
-  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 32) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
   if constexpr (G >= 64) {
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
     v = __uint_as_float(r[0]) + __uint_as_float(r[1]);

@@ -253,6 +253,22 @@ __device__ __forceinline__ f32pair swap_halves(float x, float y) {
   return f32pair{__uint_as_float(s[0]), __uint_as_float(s[1])};
 }
 
+// v(lane) + v(lane ^ D) for D = 16 (odd and even rows of 16 lanes swapped by
+// v_permlane16_swap) or D = 32 (wave halves, v_permlane32_swap); any other D
+// goes through a lane shuffle.
+template <int D>
+__device__ __forceinline__ float pair_sum(float v) {
+  if constexpr (D == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  } else if constexpr (D == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  } else {
+    return v + __shfl_xor(v, D, 64);
+  }
+}
+
 // Gram matrices of the two problems of a wave (U = 32, P = 2) on the matrix
 // cores with v_mfma_f32_32x32x2f32, K running over pairs of antenna rows:
 //   Re G = sum_s Hr[s]^T Hr[s] + Hi[s]^T Hi[s],
@@ -1525,7 +1541,7 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
         for (int v = 0; v < 8; ++v) cmacc(acc, hrow[v0 + v], row[v]);
       }
       wave_lds_sync();
-      if (SPLIT) acc = cadd(acc, c32{__shfl_xor(acc.re, SG, 64), __shfl_xor(acc.im, SG, 64)});
+      if (SPLIT) acc = c32{pair_sum<SG>(acc.re), pair_sum<SG>(acc.im)};
 #pragma unroll
       for (int i = 0; i < SG; ++i)
         if (i == b) A[i] = (u < S) ? acc : cz();
@@ -1586,7 +1602,7 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
         for (int i = 0; i < 4; ++i) cmacc(acc, hrow[v0 + i], vv[i]);
       }
       wave_lds_sync();
-      if (SPLIT) acc = cadd(acc, c32{__shfl_xor(acc.re, SG, 64), __shfl_xor(acc.im, SG, 64)});
+      if (SPLIT) acc = c32{pair_sum<SG>(acc.re), pair_sum<SG>(acc.im)};
       return group_matvec<SG>(A, (u < S) ? acc : cz(), u, line, gbase);
     };
     c32 x = apply(z);
