@@ -816,11 +816,8 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
   c32 out = cz();
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
-    float hr = hyp[p].re, hi = hyp[p].im;
-    hr += __shfl_xor(hr, 16, 64);
-    hi += __shfl_xor(hi, 16, 64);
-    hr += __shfl_xor(hr, 32, 64);
-    hi += __shfl_xor(hi, 32, 64);
+    const float hr = pair_sum<32>(pair_sum<16>(hyp[p].re));
+    const float hi = pair_sum<32>(pair_sum<16>(hyp[p].im));
     if (p == q) out = c32{hr, hi};
   }
   return out;
