@@ -70,6 +70,33 @@ extern "C" {
 #define DBP_FACTOR_FP64 0x20
 #define DBP_FACTOR_F16X2 0x30
 
+/* Per-subcarrier status bits (status arrays of the detection calls and of
+ * dbp_flag_nonfinite). */
+#define DBP_STATUS_NONFINITE 1   /* a real or imaginary part of an output is NaN or infinite      */
+#define DBP_STATUS_RESLICED 2    /* recomputed in FP64 for exact hard decisions (see below)       */
+
+/* Exact hard decisions.  Slicing (Section III-A) takes the nearest point of
+ * the constellation; an FP32 soft value that lies within rounding distance of
+ * a decision threshold could be sliced differently from an exact evaluation.
+ * Every detection call that returns hard decisions (hard != NULL) therefore
+ * flags each subcarrier that has a soft value within a guard of a threshold
+ * -- 2^-12 in the slicer's units t = (kappa x + L) / 2 (thresholds at the
+ * integers 1 .. L-1), about 35x the largest FP32 error measured against an
+ * FP64 evaluation; 2^-8 with the BF16 split Gram and 2^-4 with the split-FP16
+ * inverse -- and recomputes the flagged subcarriers entirely in FP64 on the
+ * GPU (Gram, regularised inverse or CG, every iteration), overwriting their
+ * soft outputs (FP64 result rounded to FP32) and their hard decisions (taken
+ * in FP64).  Such subcarriers carry DBP_STATUS_RESLICED.  The FP64 pass keeps
+ * its state in a caller-provided device workspace:
+ *
+ * dbp_detect_workspace_bytes(n_sc, U, C): bytes of workspace a call with hard
+ *   decisions needs (0 for malformed sizes): a flag per subcarrier plus up to
+ *   256 blocks of C U^2 complex FP64.  The workspace must be 256-byte aligned;
+ *   its contents need no initialisation and are garbage afterwards.  Calls
+ *   that share one workspace must not overlap in time.
+ */
+size_t dbp_detect_workspace_bytes(int n_sc, int U, int C);
+
 const char* dbp_version(void);
 const char* dbp_strerror(int status);
 /* Reason for the most recent failed call on this thread ("" if none). */
@@ -84,7 +111,13 @@ const char* dbp_last_error(void);
  *   s_hat  [n_sc][n_sym][U] complex64  output: s^(T) of Algorithm 1
  *   hard   [n_sc][n_sym][U] uint8 or NULL  output: nearest unit-energy square
  *          QAM point per entry, as index iI + L*iQ (L = sqrt(qam); level i of a
- *          dimension is (2i - (L-1)) / sqrt(2 (qam-1) / 3); ties go up)
+ *          dimension is (2i - (L-1)) / sqrt(2 (qam-1) / 3); ties go up), exact
+ *          by the FP64 re-slice above
+ *   status [n_sc] int32 or NULL  output: DBP_STATUS_* bits of every subcarrier
+ *   workspace, workspace_bytes  device workspace of at least
+ *          dbp_detect_workspace_bytes(n_sc, U, C) bytes when hard != NULL
+ *          (may be NULL when hard == NULL); DBP_ERR_INVALID if missing,
+ *          smaller or not 256-byte aligned
  *   T      number of estimates s^(1..T) (T - 1 ADMM iterations after the
  *          initial consensus), T >= 1
  *   rho    ADMM penalty > 0;  gamma  dual step > 0 (the paper uses 1)
@@ -97,9 +130,11 @@ const char* dbp_last_error(void);
  *          U = 64; other U return DBP_ERR_UNSUPPORTED).
  * Requires B % C == 0, S = B / C >= U (the U x U branch, S > U in the paper;
  * at S = U the S x S and U x U branches coincide), U in {8, 16, 32, 64},
- * C <= 16, n_sc >= 0 (0 is a no-op), n_sym >= 1.
+ * C <= 16, n_sc >= 0 (0 validates every other argument and queues no work),
+ * n_sym >= 1.
  */
 int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard,
+                    int32_t* status, void* workspace, size_t workspace_bytes,
                     int n_sc, int n_sym, int B, int U, int C, int T,
                     float rho, float gamma, float N0, float Es,
                     int reg, int qam, int prec, void* stream);
@@ -116,22 +151,26 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard,
  *   prec (factor only)  as for dbp_detect_admm: the Gram and inverse
  *          precision of the stored B_c^{-1};
  *   rho    must be the value the factors were made with (not checked).
- * Other arguments, requirements and errors are those of dbp_detect_admm.
+ * Other arguments (hard decisions, status and workspace included),
+ * requirements and errors are those of dbp_detect_admm; the FP64 re-slice
+ * recomputes flagged subcarriers from H (guard 2^-12, for FP32 factors).
  * The result equals dbp_detect_admm up to the rounding of H_c^H y_c, which
  * the factored path forms on the vector units. */
 size_t dbp_factor_bytes(int n_sc, int U, int C);
 int dbp_factor_admm(const void* H, void* factors, int n_sc, int B, int U, int C,
                     float rho, int prec, void* stream);
 int dbp_detect_admm_factored(const void* H, const void* factors, const void* y,
-                             void* s_hat, uint8_t* hard,
+                             void* s_hat, uint8_t* hard, int32_t* status,
+                             void* workspace, size_t workspace_bytes,
                              int n_sc, int n_sym, int B, int U, int C, int T,
                              float rho, float gamma, float N0, float Es,
                              int reg, int qam, void* stream);
 
-/* Per-subcarrier status of a result.  Non-finite outputs (NaN or infinite
+/* Per-subcarrier status of any result.  Non-finite outputs (NaN or infinite
  * parts, e.g. from inputs whose Gram overflows FP32, or a ZF system that is
- * singular) are not errors of the calls above; this reports them per
- * subcarrier.
+ * singular) are not errors of the calls above; the detection calls report
+ * them in their status output, and this call reports them for any output
+ * array (e.g. the precoder's x).
  *   x       [n_sc][per_sc] complex64, device: any output of the library
  *           (s_hat or x_hat with per_sc = n_sym * U, precoder x with
  *           per_sc = n_sym * B)
@@ -140,7 +179,6 @@ int dbp_detect_admm_factored(const void* H, const void* factors, const void* y,
  *           is NaN or infinite, else 0.
  * Stream-ordered like the other calls; DBP_ERR_INVALID for n_sc < 0,
  * per_sc < 1 or null pointers with n_sc > 0. */
-#define DBP_STATUS_NONFINITE 1
 int dbp_flag_nonfinite(const void* x, int n_sc, int per_sc, int32_t* status, void* stream);
 
 /* Mixed-precision resident channel (served form of Algorithm 1 for a static
@@ -163,12 +201,14 @@ int dbp_flag_nonfinite(const void* x, int n_sc, int per_sc, int32_t* status, voi
  *   (entries widened to FP32, FP32 accumulation).  The rounding of H to 11
  *   significant bits makes this a low-precision path: frame-level relative
  *   error within 1e-3 of the exact result (about 2e-4 at B = 256, U = 32, C = 8,
- *   25 dB, T = 5).
+ *   25 dB, T = 5).  Being a low-precision path it is not re-sliced: its hard
+ *   decisions are those of its own soft output, and `status` (may be NULL)
+ *   carries the non-finite bit only.
  * Arguments, requirements and errors otherwise as dbp_detect_admm_factored. */
 size_t dbp_channel_h16_bytes(int n_sc, int B, int U, int C);
 int dbp_pack_channel_h16(const void* H, void* packed, int n_sc, int B, int U, int C, void* stream);
 int dbp_detect_admm_factored_h16(const void* packed, const void* factors, const void* y,
-                                 void* s_hat, uint8_t* hard,
+                                 void* s_hat, uint8_t* hard, int32_t* status,
                                  int n_sc, int n_sym, int B, int U, int C, int T,
                                  float rho, float gamma, float N0, float Es,
                                  int reg, int qam, void* stream);
@@ -176,10 +216,12 @@ int dbp_detect_admm_factored_h16(const void* packed, const void* factors, const 
 /* Decentralized conjugate-gradient data detection: Algorithm 2 (Section
  * III-D) with the broadcast-w variant (every cluster keeps its own x, r, p).
  * The CG regulariser is N0/Es for DBP_REG_MMSE and 0 for DBP_REG_ZF; T >= 1
- * CG iterations.  x_hat [n_sc][n_sym][U] complex64; hard as above.
+ * CG iterations.  x_hat [n_sc][n_sym][U] complex64; hard, status and
+ * workspace as for dbp_detect_admm (the FP64 re-slice runs Algorithm 2 again).
  * Requires B % C == 0, U in {8, 16, 32, 64}, C <= 16.
  */
 int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard,
+                  int32_t* status, void* workspace, size_t workspace_bytes,
                   int n_sc, int n_sym, int B, int U, int C, int T,
                   float N0, float Es, int reg, int qam, void* stream);
 

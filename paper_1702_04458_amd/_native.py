@@ -19,16 +19,20 @@ SIGNATURES = {
     "dbp_version": (ctypes.c_char_p, []),
     "dbp_strerror": (ctypes.c_char_p, [_i]),
     "dbp_last_error": (ctypes.c_char_p, []),
-    "dbp_detect_admm": (_i, [_vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i, _i, _vp]),
+    "dbp_detect_workspace_bytes": (ctypes.c_size_t, [_i, _i, _i]),
+    "dbp_detect_admm": (_i, [_vp, _vp, _vp, _u8p, _vp, _vp, ctypes.c_size_t, _i, _i, _i, _i, _i, _i,
+                             _f, _f, _f, _f, _i, _i, _i, _vp]),
     "dbp_factor_bytes": (ctypes.c_size_t, [_i, _i, _i]),
     "dbp_factor_admm": (_i, [_vp, _vp, _i, _i, _i, _i, _f, _i, _vp]),
-    "dbp_detect_admm_factored": (_i, [_vp, _vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i, _vp]),
+    "dbp_detect_admm_factored": (_i, [_vp, _vp, _vp, _vp, _u8p, _vp, _vp, ctypes.c_size_t, _i, _i, _i, _i, _i, _i,
+                                      _f, _f, _f, _f, _i, _i, _vp]),
     "dbp_channel_h16_bytes": (ctypes.c_size_t, [_i, _i, _i, _i]),
     "dbp_flag_nonfinite": (_i, [_vp, _i, _i, _vp, _vp]),
     "dbp_pack_channel_h16": (_i, [_vp, _vp, _i, _i, _i, _i, _vp]),
-    "dbp_detect_admm_factored_h16": (_i, [_vp, _vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i,
-                                          _vp]),
-    "dbp_detect_cg": (_i, [_vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i, _vp]),
+    "dbp_detect_admm_factored_h16": (_i, [_vp, _vp, _vp, _vp, _u8p, _vp, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f,
+                                          _i, _i, _vp]),
+    "dbp_detect_cg": (_i, [_vp, _vp, _vp, _u8p, _vp, _vp, ctypes.c_size_t, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i,
+                           _vp]),
     "dbp_precode_admm": (_i, [_vp, _vp, _vp, _fp, _fp, _i, _i, _i, _i, _i, _i, _f, _f, _f, _vp]),
     "dbp_server_create": (_i, [_i, ctypes.c_size_t, _i, ctypes.POINTER(ctypes.c_void_p)]),
     "dbp_server_destroy": (_i, [_vp]),

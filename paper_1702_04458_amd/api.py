@@ -45,38 +45,93 @@ def _shapes(H, y):
     return n_sc, y.shape[1], B, U, y
 
 
+def _check_out(t, name, shape, dtype, device):
+    """An output buffer the kernels write in full: exact shape, dtype, device
+    and contiguity (a wrong buffer would be written out of bounds)."""
+    _dev(t, name, dtype)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}")
+    return t
+
+
+def _outputs(out, n_sc, n_sym, U, device, hard, status):
+    """(s_hat, hard, status) buffers: from ``out`` (a tuple of 2 or 3 tensors,
+    None entries allowed for hard / status) or freshly allocated."""
+    shape = (n_sc, n_sym, U)
+    if out is None:
+        s_hat = torch.empty(shape, dtype=torch.complex64, device=device)
+        hd = torch.empty(shape, dtype=torch.uint8, device=device) if hard else None
+        stt = torch.empty(n_sc, dtype=torch.int32, device=device) if status else None
+        return s_hat, hd, stt
+    s_hat, hd = out[0], out[1]
+    stt = out[2] if len(out) > 2 else None
+    _check_out(s_hat, "s_hat", shape, torch.complex64, device)
+    if hd is not None:
+        _check_out(hd, "hard", shape, torch.uint8, device)
+    if stt is not None:
+        _check_out(stt, "status", (n_sc,), torch.int32, device)
+    return s_hat, hd, stt
+
+
+def workspace(n_sc, U, C, device="cuda"):
+    """Device workspace of the FP64 re-slice (``dbp_detect_workspace_bytes``),
+    reusable across calls of the same or smaller size that do not overlap."""
+    nbytes = _native.lib().dbp_detect_workspace_bytes(n_sc, U, C)
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def _workspace(ws, hd, n_sc, U, C, device):
+    """(pointer, bytes) of the re-slice workspace: needed with hard decisions."""
+    if hd is None:
+        return None, 0
+    need = _native.lib().dbp_detect_workspace_bytes(n_sc, U, C)
+    if ws is None:
+        ws = workspace(n_sc, U, C, device)
+    _dev(ws, "workspace", torch.uint8)
+    if ws.device != device or ws.numel() < need:
+        raise ValueError(f"workspace must be a device uint8 tensor of >= {need} bytes on {device}")
+    return ws.data_ptr(), ws.numel()
+
+
+def _ret(s_hat, hd, stt, status):
+    return (s_hat, hd, stt) if status else (s_hat, hd)
+
+
 def detect(H, y, N0, C, rho=1.0, T=5, *, algo="admm", reg="mmse", qam=16, Es=1.0, gamma=1.0,
-           prec="fp32", factor=None, hard=True, out=None, stream=None):
+           prec="fp32", factor=None, hard=True, status=False, out=None, workspace=None, stream=None):
     """Decentralized uplink detection.
 
     ``algo="admm"`` runs Algorithm 1 (``rho`` is the ADMM penalty),
     ``algo="cg"`` runs Algorithm 2 (regulariser N0/Es, ``rho`` unused).
     ``prec`` selects the Gram arithmetic ("fp32", "fp16", "bf16"); in the mixed
     modes ``factor`` ("auto", "fp32", "fp64", "f16x2") selects the inverse's precision.
-    Returns ``(s_hat [n_sc, n_sym, U] complex64, hard [n_sc, n_sym, U] uint8 or None)``.
+    Hard decisions are exact (near-threshold subcarriers recomputed in FP64,
+    which needs a ``workspace``; one is allocated when none is given).
+    Returns ``(s_hat [n_sc, n_sym, U] complex64, hard [n_sc, n_sym, U] uint8 or None)``,
+    plus ``status [n_sc] int32`` (DBP_STATUS_* bits) with ``status=True``.
     """
     _dev(H, "H")
     _dev(y, "y")
     n_sc, n_sym, B, U, y = _shapes(H, y)
-    if out is None:
-        s_hat = torch.empty((n_sc, n_sym, U), dtype=torch.complex64, device=H.device)
-        hd = torch.empty((n_sc, n_sym, U), dtype=torch.uint8, device=H.device) if hard else None
-    else:
-        s_hat, hd = out
+    s_hat, hd, stt = _outputs(out, n_sc, n_sym, U, H.device, hard, status)
+    wp, wb = _workspace(workspace, hd, n_sc, U, C, H.device)
     L = _native.lib()
     st = _stream(stream)
     hp = hd.data_ptr() if hd is not None else None
+    sp = stt.data_ptr() if stt is not None else None
     if algo == "admm":
-        code = L.dbp_detect_admm(H.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hp, n_sc, n_sym, B, U, C, T,
-                                 float(rho), float(gamma), float(N0), float(Es), REG[reg], qam,
+        code = L.dbp_detect_admm(H.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hp, sp, wp, wb, n_sc, n_sym, B, U,
+                                 C, T, float(rho), float(gamma), float(N0), float(Es), REG[reg], qam,
                                  PREC[prec] | FACTOR[factor], st)
     elif algo == "cg":
-        code = L.dbp_detect_cg(H.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hp, n_sc, n_sym, B, U, C, T,
-                               float(N0), float(Es), REG[reg], qam, st)
+        code = L.dbp_detect_cg(H.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hp, sp, wp, wb, n_sc, n_sym, B, U, C,
+                               T, float(N0), float(Es), REG[reg], qam, st)
     else:
         raise ValueError(algo)
     _native.check(code)
-    return s_hat, hd
+    return _ret(s_hat, hd, stt, status)
 
 
 def factor(H, C, rho=1.0, *, prec="fp32", factor=None, out=None, stream=None):
@@ -87,6 +142,8 @@ def factor(H, C, rho=1.0, *, prec="fp32", factor=None, out=None, stream=None):
     n_sc, B, U = H.shape
     f = out if out is not None else torch.empty((n_sc, C, U, U), dtype=torch.complex64, device=H.device)
     _dev(f, "factors")
+    if f.device != H.device:
+        raise ValueError(f"factors must be on {H.device}")
     if f.numel() * 8 != _native.lib().dbp_factor_bytes(n_sc, U, C):
         raise ValueError("factors must hold n_sc * C * U * U complex64")
     _native.check(_native.lib().dbp_factor_admm(H.data_ptr(), f.data_ptr(), n_sc, B, U, C, float(rho),
@@ -95,25 +152,23 @@ def factor(H, C, rho=1.0, *, prec="fp32", factor=None, out=None, stream=None):
 
 
 def detect_factored(H, factors, y, N0, C, rho=1.0, T=5, *, reg="mmse", qam=16, Es=1.0, gamma=1.0, hard=True,
-                    out=None, stream=None):
+                    status=False, out=None, workspace=None, stream=None):
     """Algorithm 1's iterations against resident factors from :func:`factor`
-    (same ``rho``); forms no Gram and no inverse."""
+    (same ``rho``); forms no Gram and no inverse.  Outputs as :func:`detect`."""
     _dev(H, "H")
     _dev(y, "y")
     _dev(factors, "factors")
     n_sc, n_sym, B, U, y = _shapes(H, y)
     if factors.numel() * 8 != _native.lib().dbp_factor_bytes(n_sc, U, C):
         raise ValueError("factors do not match (n_sc, U, C)")
-    if out is None:
-        s_hat = torch.empty((n_sc, n_sym, U), dtype=torch.complex64, device=H.device)
-        hd = torch.empty((n_sc, n_sym, U), dtype=torch.uint8, device=H.device) if hard else None
-    else:
-        s_hat, hd = out
+    s_hat, hd, stt = _outputs(out, n_sc, n_sym, U, H.device, hard, status)
+    wp, wb = _workspace(workspace, hd, n_sc, U, C, H.device)
     code = _native.lib().dbp_detect_admm_factored(
         H.data_ptr(), factors.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hd.data_ptr() if hd is not None else None,
+        stt.data_ptr() if stt is not None else None, wp, wb,
         n_sc, n_sym, B, U, C, T, float(rho), float(gamma), float(N0), float(Es), REG[reg], qam, _stream(stream))
     _native.check(code)
-    return s_hat, hd
+    return _ret(s_hat, hd, stt, status)
 
 
 def nonfinite_status(x, *, out=None, stream=None):
@@ -124,7 +179,7 @@ def nonfinite_status(x, *, out=None, stream=None):
     n_sc = x.shape[0]
     per_sc = x.numel() // n_sc if n_sc else 1
     st = out if out is not None else torch.empty(n_sc, dtype=torch.int32, device=x.device)
-    _dev(st, "status", torch.int32)
+    _check_out(st, "status", (n_sc,), torch.int32, x.device)
     _native.check(_native.lib().dbp_flag_nonfinite(x.data_ptr(), n_sc, per_sc, st.data_ptr(), _stream(stream)))
     return st
 
@@ -147,7 +202,7 @@ def pack_channel_h16(H, C, *, out=None, stream=None):
 
 
 def detect_factored_h16(packed, factors, y, N0, B, U, C, rho=1.0, T=5, *, reg="mmse", qam=16, Es=1.0, gamma=1.0,
-                        hard=True, out=None, stream=None):
+                        hard=True, status=False, out=None, stream=None):
     """Algorithm 1's iterations against resident factors and the packed FP16
     channel from :func:`pack_channel_h16` (low-precision path, <= 1e-3)."""
     _dev(packed, "packed", torch.uint8)
@@ -163,16 +218,13 @@ def detect_factored_h16(packed, factors, y, N0, B, U, C, rho=1.0, T=5, *, reg="m
         raise ValueError("packed channel does not match (n_sc, B, U, C)")
     if factors.numel() * 8 != L.dbp_factor_bytes(n_sc, U, C):
         raise ValueError("factors do not match (n_sc, U, C)")
-    if out is None:
-        s_hat = torch.empty((n_sc, n_sym, U), dtype=torch.complex64, device=y.device)
-        hd = torch.empty((n_sc, n_sym, U), dtype=torch.uint8, device=y.device) if hard else None
-    else:
-        s_hat, hd = out
+    s_hat, hd, stt = _outputs(out, n_sc, n_sym, U, y.device, hard, status)
     code = L.dbp_detect_admm_factored_h16(
         packed.data_ptr(), factors.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hd.data_ptr() if hd is not None else None,
+        stt.data_ptr() if stt is not None else None,
         n_sc, n_sym, B, U, C, T, float(rho), float(gamma), float(N0), float(Es), REG[reg], qam, _stream(stream))
     _native.check(code)
-    return s_hat, hd
+    return _ret(s_hat, hd, stt, status)
 
 
 def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, eps=0.0, P_cluster=None, out=None, stream=None):
@@ -193,11 +245,15 @@ def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, eps=0.0, P_cluster=None, out=No
         raise ValueError("s must be [n_sc, n_sym, U]")
     if P_cluster is not None:
         _dev(P_cluster, "P_cluster", torch.float32)
+        if P_cluster.numel() != C or P_cluster.device != H.device:
+            raise ValueError(f"P_cluster must hold C = {C} budgets on {H.device}")
     if out is None:
         x = torch.empty((n_sc, n_sym, B), dtype=torch.complex64, device=H.device)
         beta = torch.empty((n_sc, n_sym), dtype=torch.float32, device=H.device)
     else:
         x, beta = out
+        _check_out(x, "x", (n_sc, n_sym, B), torch.complex64, H.device)
+        _check_out(beta, "beta", (n_sc, n_sym), torch.float32, H.device)
     L = _native.lib()
     code = L.dbp_precode_admm(H.data_ptr(), s.data_ptr(), x.data_ptr(), beta.data_ptr(),
                               P_cluster.data_ptr() if P_cluster is not None else None,

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <cstdint>
 
 #include "../../include/dbp.h"
 #include "dbp_launch.h"
@@ -184,14 +185,100 @@ hipError_t launch_preprocessing(const dbp::UlArgs& a, int U, int C, int gram_pre
   return dbp::launch_admm_ul_mixed(a, U, gram_prec, inv, pl.nw, st, stage);
 }
 
+// Re-slice guard (slicer units t = (kappa x + L) / 2, thresholds at the
+// integers) of a preprocessing mode: about 35x (FP32 Gram and inverse, FP16
+// split Gram) the largest FP32 soft-value error measured against the FP64
+// oracle at any configuration (7e-6 at B = 512, U = 64), and correspondingly
+// wider for the BF16 split Gram and the split-FP16 inverse.
+float reslice_guard(int gram_prec, int inv) {
+  if (inv == 2) return 0x1p-4f;
+  if (gram_prec == DBP_PREC_MIXED_BF16) return 0x1p-8f;
+  return 0x1p-12f;
+}
+
+size_t flags_region(int n_sc) { return ((size_t)n_sc * 4 + 255) & ~size_t(255); }
+
+// Status and exact re-slicing of a detection call.  Without hard decisions
+// only the optional status is written (non-finite bit).  With them the FP32
+// kernel flags near-threshold subcarriers into `status` (or, without it, the
+// workspace's flag region) and the FP64 pass recomputes them; `slots` is the
+// number of FP64 slots of slot_bytes the workspace holds after the flags.
+int setup_reslice(const char* who, dbp::UlArgs& a, dbp::FixArgs& f, int32_t* status, void* ws, size_t ws_bytes,
+                  float guard, size_t slot_bytes, int max_slots) {
+  a.flags = status;
+  a.guard = 0.f;
+  f = dbp::FixArgs{};
+  if (!a.hard) return DBP_OK;
+  const size_t fb = status ? 0 : flags_region(a.n_sc);
+  if (!ws) return fail(DBP_ERR_INVALID, "%s: hard decisions need a workspace (dbp_detect_workspace_bytes)", who);
+  if (reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail(DBP_ERR_INVALID, "%s: workspace must be 256-byte aligned", who);
+  int slots = max_slots;
+  if (slot_bytes) {
+    const size_t avail = ws_bytes > fb ? ws_bytes - fb : 0;
+    if ((size_t)slots * slot_bytes > avail) slots = (int)(avail / slot_bytes);
+  } else if (ws_bytes < fb) {
+    slots = 0;
+  }
+  if (slots < 1) return fail(DBP_ERR_INVALID, "%s: workspace of %zu bytes is too small", who, ws_bytes);
+  a.flags = status ? status : static_cast<int32_t*>(ws);
+  a.guard = guard;
+  f.flags = a.flags;
+  f.ws = static_cast<char*>(ws) + fb;
+  f.n_slots = slots;
+  f.H = a.H;
+  f.y = a.y;
+  f.shat = a.shat;
+  f.hard = a.hard;
+  f.n_sc = a.n_sc;
+  f.n_sym = a.n_sym;
+  f.B = a.B;
+  f.C = a.C;
+  f.S = a.S;
+  f.T = a.T;
+  f.reg = a.reg;
+  f.L = a.L;
+  return DBP_OK;
+}
+
+// FP64 parameters of the re-slice pass, from the caller's FP32 arguments.
+void fix_params(dbp::FixArgs& f, int U, float rho, float gamma, float N0, float Es, int reg, int qam, bool admm) {
+  f.U = U;
+  f.gamma = gamma;
+  if (admm) {
+    f.rho = rho;
+    const double nu = (reg == DBP_REG_MMSE) ? (double)N0 / ((double)rho * (double)Es) : 0.0;
+    f.inv_den = nu + f.C;   // the denominator itself (the FP64 pass divides)
+  } else {
+    f.rho = (reg == DBP_REG_MMSE) ? (double)N0 / (double)Es : 0.0;
+  }
+  f.invC = 1.0 / f.C;
+  const double kappa = std::sqrt(2.0 * (qam - 1) / 3.0);
+  f.kappa = kappa;
+  f.box_r = (f.L - 1) / kappa;
+}
+
+// Slots of the ADMM re-slice a workspace of the documented size holds.
+int full_slots(int n_sc) { return n_sc < dbp::kFixMaxSlots ? (n_sc > 0 ? n_sc : 1) : dbp::kFixMaxSlots; }
+
 }  // namespace
 
 extern "C" {
 
-int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, int n_sc, int n_sym, int B, int U,
-                    int C, int T, float rho, float gamma, float N0, float Es, int reg, int qam, int prec,
-                    void* stream) {
-  const char* who = "dbp_detect_admm";
+size_t dbp_detect_workspace_bytes(int n_sc, int U, int C) {
+  if (n_sc < 0 || U < 1 || C < 1) return 0;
+  return flags_region(n_sc) + (size_t)full_slots(n_sc) * dbp::fix64_slot_bytes(U, C);
+}
+
+}  // extern "C"
+
+namespace dbp {
+
+// dbp_detect_admm with the re-slice workspace bounded by max_slots FP64 slots
+// (the entry point without workspace argument passes its static scratch).
+int detect_admm_impl(const char* who, const void* H, const void* y, void* s_hat, uint8_t* hard, int32_t* status,
+                     void* workspace, size_t workspace_bytes, int max_slots, int n_sc, int n_sym, int B, int U, int C,
+                     int T, float rho, float gamma, float N0, float Es, int reg, int qam, int prec, void* stream) {
   dbp::UlArgs a;
   int S = 0;
   int st = admm_args(who, n_sc, n_sym, B, U, C, T, rho, gamma, N0, Es, reg, qam, &a, &S);
@@ -205,7 +292,29 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
   a.y = static_cast<const dbp::c32*>(y);
   a.shat = static_cast<dbp::c32*>(s_hat);
   a.hard = hard;
-  return device_status(who, launch_preprocessing(a, U, C, gram_prec, inv, static_cast<hipStream_t>(stream), 0));
+  dbp::FixArgs f;
+  st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(gram_prec, inv),
+                     dbp::fix64_slot_bytes(U, C), max_slots < full_slots(n_sc) ? max_slots : full_slots(n_sc));
+  if (st) return st;
+  const hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = device_status(who, launch_preprocessing(a, U, C, gram_prec, inv, hs, 0));
+  if (st || !hard) return st;
+  fix_params(f, U, rho, gamma, N0, Es, reg, qam, true);
+  return device_status(who, dbp::launch_admm_ul_fix64(f, hs));
+}
+
+}  // namespace dbp
+
+extern "C" {
+
+int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, int32_t* status, void* workspace,
+                    size_t workspace_bytes, int n_sc, int n_sym, int B, int U, int C, int T, float rho, float gamma,
+                    float N0, float Es, int reg, int qam, int prec, void* stream) {
+  if (hard && workspace && workspace_bytes < dbp_detect_workspace_bytes(n_sc, U, C))
+    return fail(DBP_ERR_INVALID, "dbp_detect_admm: workspace of %zu bytes, %zu needed", workspace_bytes,
+                dbp_detect_workspace_bytes(n_sc, U, C));
+  return dbp::detect_admm_impl("dbp_detect_admm", H, y, s_hat, hard, status, workspace, workspace_bytes,
+                               dbp::kFixMaxSlots, n_sc, n_sym, B, U, C, T, rho, gamma, N0, Es, reg, qam, prec, stream);
 }
 
 size_t dbp_factor_bytes(int n_sc, int U, int C) {
@@ -232,9 +341,10 @@ int dbp_factor_admm(const void* H, void* factors, int n_sc, int B, int U, int C,
   return device_status(who, launch_preprocessing(a, U, C, gram_prec, inv, static_cast<hipStream_t>(stream), 1));
 }
 
-int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, void* s_hat, uint8_t* hard, int n_sc,
-                             int n_sym, int B, int U, int C, int T, float rho, float gamma, float N0, float Es,
-                             int reg, int qam, void* stream) {
+int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, void* s_hat, uint8_t* hard,
+                             int32_t* status, void* workspace, size_t workspace_bytes, int n_sc, int n_sym, int B,
+                             int U, int C, int T, float rho, float gamma, float N0, float Es, int reg, int qam,
+                             void* stream) {
   const char* who = "dbp_detect_admm_factored";
   dbp::UlArgs a;
   int S = 0;
@@ -243,13 +353,24 @@ int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, 
   if (S < U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d < U=%d (S x S branch) not built", who, S, U);
   if (n_sc > 0 && (!H || !factors || !y || !s_hat)) return fail(DBP_ERR_INVALID, "%s: null pointer", who);
   if (n_sc == 0) return ok();
+  if (hard && workspace && workspace_bytes < dbp_detect_workspace_bytes(n_sc, U, C))
+    return fail(DBP_ERR_INVALID, "%s: workspace of %zu bytes, %zu needed", who, workspace_bytes,
+                dbp_detect_workspace_bytes(n_sc, U, C));
   a.H = static_cast<const dbp::c32*>(H);
   a.y = static_cast<const dbp::c32*>(y);
   a.shat = static_cast<dbp::c32*>(s_hat);
   a.hard = hard;
   a.fac = const_cast<dbp::c32*>(static_cast<const dbp::c32*>(factors));
+  dbp::FixArgs f;
+  st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(DBP_PREC_FP32, 0),
+                     dbp::fix64_slot_bytes(U, C), full_slots(n_sc));
+  if (st) return st;
   const Plan pl = make_plan(U, C);
-  return device_status(who, dbp::launch_admm_ul_factored(a, U, pl.nw, static_cast<hipStream_t>(stream)));
+  const hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = device_status(who, dbp::launch_admm_ul_factored(a, U, pl.nw, hs));
+  if (st || !hard) return st;
+  fix_params(f, U, rho, gamma, N0, Es, reg, qam, true);
+  return device_status(who, dbp::launch_admm_ul_fix64(f, hs));
 }
 
 int dbp_flag_nonfinite(const void* x, int n_sc, int per_sc, int32_t* status, void* stream) {
@@ -279,8 +400,8 @@ int dbp_pack_channel_h16(const void* H, void* packed, int n_sc, int B, int U, in
 }
 
 int dbp_detect_admm_factored_h16(const void* packed, const void* factors, const void* y, void* s_hat,
-                                 uint8_t* hard, int n_sc, int n_sym, int B, int U, int C, int T, float rho,
-                                 float gamma, float N0, float Es, int reg, int qam, void* stream) {
+                                 uint8_t* hard, int32_t* status, int n_sc, int n_sym, int B, int U, int C, int T,
+                                 float rho, float gamma, float N0, float Es, int reg, int qam, void* stream) {
   const char* who = "dbp_detect_admm_factored_h16";
   dbp::UlArgs a;
   int S = 0;
@@ -295,12 +416,15 @@ int dbp_detect_admm_factored_h16(const void* packed, const void* factors, const 
   a.shat = static_cast<dbp::c32*>(s_hat);
   a.hard = hard;
   a.fac = const_cast<dbp::c32*>(static_cast<const dbp::c32*>(factors));
+  a.flags = status;   // non-finite bit only: the low-precision path is not re-sliced
+  a.guard = 0.f;
   const Plan pl = make_plan(U, C);
   return device_status(who, dbp::launch_admm_ul_factored_h16(a, U, pl.nw, static_cast<hipStream_t>(stream)));
 }
 
-int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int n_sc, int n_sym, int B, int U,
-                  int C, int T, float N0, float Es, int reg, int qam, void* stream) {
+int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int32_t* status, void* workspace,
+                  size_t workspace_bytes, int n_sc, int n_sym, int B, int U, int C, int T, float N0, float Es,
+                  int reg, int qam, void* stream) {
   const char* who = "dbp_detect_cg";
   int st = common_shape(who, n_sc, n_sym, B, U, C, T);
   if (st) return st;
@@ -331,7 +455,18 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int 
   a.rho = (reg == DBP_REG_MMSE) ? (float)((double)N0 / (double)Es) : 0.f;
   a.gamma = 1.f;
   a.kappa = (float)std::sqrt(2.0 * (qam - 1) / 3.0);
-  return device_status(who, dbp::launch_dcg_ul_f32(a, U, pl.nw, static_cast<hipStream_t>(stream)));
+  if (hard && workspace && workspace_bytes < dbp_detect_workspace_bytes(n_sc, U, C))
+    return fail(DBP_ERR_INVALID, "%s: workspace of %zu bytes, %zu needed", who, workspace_bytes,
+                dbp_detect_workspace_bytes(n_sc, U, C));
+  dbp::FixArgs f;
+  st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(DBP_PREC_FP32, 0), 0,
+                     full_slots(n_sc));
+  if (st) return st;
+  const hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = device_status(who, dbp::launch_dcg_ul_f32(a, U, pl.nw, hs));
+  if (st || !hard) return st;
+  fix_params(f, U, 1.0f, 1.0f, N0, Es, reg, qam, false);
+  return device_status(who, dbp::launch_dcg_ul_fix64(f, hs));
 }
 
 int dbp_precode_admm(const void* H, const void* s, void* x, float* beta, const float* P_cluster, int n_sc,

@@ -304,4 +304,24 @@ __device__ __forceinline__ int slice_dim(float x, float kappa, int L) {
   return (int)f;
 }
 
+// True when x lies within `guard` (in the slicer's units t = (kappa x + L) / 2,
+// where the thresholds are the integers 1 .. L-1) of a decision threshold.
+// NaN is never near.
+__device__ __forceinline__ bool near_threshold(float x, float kappa, int L, float guard) {
+  const float h = __fadd_rn(__fmul_rn(x, kappa), (float)L) * 0.5f;
+  const float j = fminf(fmaxf(rintf(h), 1.f), (float)(L - 1));
+  return fabsf(h - j) < guard;
+}
+
+__device__ __forceinline__ bool nonfinite(c32 v) { return !(isfinite(v.re) && isfinite(v.im)); }
+
+// Status bits of one subcarrier from the per-lane bits of the G lanes of lane
+// group g (bit 0 non-finite, bit 1 re-slice); every lane of the wave must call.
+template <int G>
+__device__ __forceinline__ int group_flags(int fl, int g) {
+  const unsigned long long gm = (G == 64) ? ~0ull : (((1ull << G) - 1) << (g * G));
+  const unsigned long long m1 = __ballot(fl & 1), m2 = __ballot(fl & 2);
+  return ((m1 & gm) ? 1 : 0) | ((m2 & gm) ? 2 : 0);
+}
+
 }  // namespace dbp

@@ -1,0 +1,336 @@
+// Exact hard decisions: FP64 recomputation of the subcarriers whose FP32
+// result lies near a decision threshold.
+//
+// The FP32 detection kernels flag every subcarrier with a soft value within a
+// guard of a slicing threshold (Section III-A: nearest-point slicing of the
+// equalized estimate; the guard is a stated multiple of the FP32 path's
+// measured error).  For those subcarriers these kernels run the whole method
+// again in FP64 -- Algorithm 1 (U x U branch: B_c = H_c^H H_c + rho I,
+// y_c^reg, Lemma 1's consensus, the proximal steps E2-MMSE / E2-ZF / E2-BOX)
+// or Algorithm 2 (decentralized CG, residual update with e^(t)) -- and
+// overwrite the soft output (rounded to FP32) and the hard decision (taken in
+// FP64).  The decisions then agree with an FP64 evaluation of the method
+// everywhere except within about 1e-14 of a threshold.
+//
+// Work split: workgroup g of the n_slots workgroups owns subcarriers
+// k = g, g + n_slots, g + 2 n_slots, ...; it reads their flags 256 at a time,
+// lists the flagged ones in LDS and recomputes them one after another with all
+// 256 threads.  The ADMM pass keeps the C regularised inverses of the current
+// subcarrier (C U^2 complex FP64) in the workgroup's slot of the workspace;
+// every entry of a slot is written before it is read, so the workspace needs
+// no clearing.
+#include <hip/hip_runtime.h>
+
+#include "dbp_device.h"
+#include "dbp_launch.h"
+
+namespace dbp {
+namespace {
+
+constexpr int kFixThreads = 256;
+
+struct d2 {
+  double re, im;
+};
+
+__device__ __forceinline__ d2 dzero() { return d2{0.0, 0.0}; }
+__device__ __forceinline__ d2 dld(const c32* p) {
+  const c32 v = *p;
+  return d2{(double)v.re, (double)v.im};
+}
+// acc += conj(x) * y
+__device__ __forceinline__ void dmacc(d2& acc, d2 x, d2 y) {
+  acc.re += x.re * y.re + x.im * y.im;
+  acc.im += x.re * y.im - x.im * y.re;
+}
+// acc += x * y
+__device__ __forceinline__ void dmac(d2& acc, d2 x, d2 y) {
+  acc.re += x.re * y.re - x.im * y.im;
+  acc.im += x.re * y.im + x.im * y.re;
+}
+
+// i = clamp(floor((kappa x + L) / 2), 0, L - 1) in FP64, ties up
+__device__ __forceinline__ int slice64(double x, double kappa, int L) {
+  double i = floor((kappa * x + (double)L) / 2.0);
+  i = fmin(fmax(i, 0.0), (double)(L - 1));
+  return (int)i;
+}
+
+// Collects the flagged subcarriers among the next 256 this workgroup owns
+// (round r) into list[0 .. n); returns n (same value in every thread).
+__device__ int collect_round(const FixArgs& f, long r, int* list, int* cnt) {
+  __syncthreads();   // every thread has read the previous round's count
+  if (threadIdx.x == 0) *cnt = 0;
+  __syncthreads();
+  const long j = r * kFixThreads + threadIdx.x;
+  const long k = (long)blockIdx.x + j * (long)gridDim.x;
+  if (k < f.n_sc && (f.flags[k] & kStatusReslice)) list[atomicAdd(cnt, 1)] = (int)k;
+  __syncthreads();
+  return *cnt;
+}
+
+// Proximal step of Lemma 1 on the summed vector w (E2-MMSE / E2-ZF: w / den,
+// den = N0 / (rho Es) + C; E2-BOX: clip of w / C to the QAM box).
+__device__ __forceinline__ d2 prox64(const FixArgs& f, d2 w) {
+  if (f.reg == 2) {
+    const double vr = w.re * f.invC, vi = w.im * f.invC;
+    return d2{fmin(fmax(vr, -f.box_r), f.box_r), fmin(fmax(vi, -f.box_r), f.box_r)};
+  }
+  return d2{w.re / f.inv_den, w.im / f.inv_den};
+}
+
+__device__ __forceinline__ void write_out(const FixArgs& f, int k, int n, int u, d2 s) {
+  const size_t o = ((size_t)k * f.n_sym + n) * f.U + u;
+  f.shat[o] = c32{(float)s.re, (float)s.im};
+  f.hard[o] = (uint8_t)(slice64(s.re, f.kappa, f.L) + f.L * slice64(s.im, f.kappa, f.L));
+}
+
+}  // namespace
+
+// Algorithm 1 in FP64 for the flagged subcarriers.  f.inv_den holds the
+// denominator N0 / (rho Es) + C itself (FP64 divides by it).
+__global__ void __launch_bounds__(kFixThreads) admm_ul_fix64(FixArgs f) {
+  extern __shared__ d2 fsm[];
+  const int U = f.U, C = f.C, S = f.S, CU = C * U, UU = U * U, n_ent = C * UU;
+  d2* Y = fsm;            // y_c^reg (first H_c^H y_c)
+  d2* Z = Y + CU;         // z_c (Gauss-Jordan: pivot columns)
+  d2* LM = Z + CU;        // lambda_c (Gauss-Jordan: pivot rows)
+  d2* Sv = LM + CU;       // s
+  int* list = reinterpret_cast<int*>(Sv + U);
+  int* cnt = list + kFixThreads;
+  d2* M = static_cast<d2*>(f.ws) + (size_t)blockIdx.x * n_ent;   // [C][U][U]
+  const int tid = threadIdx.x;
+
+  for (long r = 0; (long)blockIdx.x + r * kFixThreads * (long)gridDim.x < f.n_sc; ++r) {
+    const int nl = collect_round(f, r, list, cnt);
+    for (int q = 0; q < nl; ++q) {
+      const int k = list[q];
+      const c32* Hk = f.H + (size_t)k * f.B * U;
+      // B_c = H_c^H H_c + rho I
+      for (int e = tid; e < n_ent; e += kFixThreads) {
+        const int c = e / UU, rr = e - c * UU, i = rr / U, j = rr - i * U;
+        const c32* Hc = Hk + (size_t)c * S * U;
+        d2 acc = dzero();
+        for (int s = 0; s < S; ++s) dmacc(acc, dld(Hc + (size_t)s * U + i), dld(Hc + (size_t)s * U + j));
+        if (i == j) acc.re += f.rho;
+        M[e] = acc;
+      }
+      __syncthreads();
+      // B_c^{-1} by Gauss-Jordan elimination without pivoting (HPD), all
+      // clusters at once; the pivot d is the real positive Schur complement
+      for (int p = 0; p < U; ++p) {
+        for (int e = tid; e < CU; e += kFixThreads) {
+          const int c = e / U, i = e - c * U;
+          Z[e] = M[(size_t)c * UU + i * U + p];
+          LM[e] = M[(size_t)c * UU + p * U + i];
+        }
+        __syncthreads();
+        for (int e = tid; e < n_ent; e += kFixThreads) {
+          const int c = e / UU, rr = e - c * UU, i = rr / U, j = rr - i * U;
+          const double inv = 1.0 / LM[c * U + p].re;
+          const d2 ci = Z[c * U + i], rj = LM[c * U + j];
+          d2 v;
+          if (i != p && j != p) {
+            v = M[e];
+            v.re -= (ci.re * rj.re - ci.im * rj.im) * inv;
+            v.im -= (ci.re * rj.im + ci.im * rj.re) * inv;
+          } else if (i == p && j != p) {
+            v = d2{rj.re * inv, rj.im * inv};
+          } else if (i != p) {
+            v = d2{-ci.re * inv, -ci.im * inv};
+          } else {
+            v = d2{inv, 0.0};
+          }
+          M[e] = v;
+        }
+        __syncthreads();
+      }
+      for (int n = 0; n < f.n_sym; ++n) {
+        const c32* yk = f.y + ((size_t)k * f.n_sym + n) * f.B;
+        // H_c^H y_c
+        for (int e = tid; e < CU; e += kFixThreads) {
+          const int c = e / U, i = e - c * U;
+          const c32* Hc = Hk + (size_t)c * S * U;
+          d2 acc = dzero();
+          for (int s = 0; s < S; ++s) dmacc(acc, dld(Hc + (size_t)s * U + i), dld(yk + (size_t)c * S + s));
+          Z[e] = acc;
+        }
+        __syncthreads();
+        // y_c^reg = B_c^{-1} H_c^H y_c
+        for (int e = tid; e < CU; e += kFixThreads) {
+          const int c = e / U, i = e - c * U;
+          const d2* Mi = M + (size_t)c * UU + i * U;
+          d2 acc = dzero();
+          for (int j = 0; j < U; ++j) dmac(acc, Mi[j], Z[c * U + j]);
+          Y[e] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < CU; e += kFixThreads) {
+          Z[e] = Y[e];
+          LM[e] = dzero();
+        }
+        __syncthreads();
+        for (int i = tid; i < U; i += kFixThreads) {
+          d2 w = dzero();
+          for (int c = 0; c < C; ++c) {
+            w.re += Z[c * U + i].re;
+            w.im += Z[c * U + i].im;
+          }
+          Sv[i] = prox64(f, w);
+        }
+        __syncthreads();
+        for (int t = 2; t <= f.T; ++t) {
+          // lambda_c += gamma (z_c - s)
+          for (int e = tid; e < CU; e += kFixThreads) {
+            const int i = e % U;
+            LM[e].re += f.gamma * (Z[e].re - Sv[i].re);
+            LM[e].im += f.gamma * (Z[e].im - Sv[i].im);
+          }
+          __syncthreads();
+          // z_c = y_c^reg + rho B_c^{-1} (s - lambda_c)
+          for (int e = tid; e < CU; e += kFixThreads) {
+            const int c = e / U, i = e - c * U;
+            const d2* Mi = M + (size_t)c * UU + i * U;
+            d2 acc = dzero();
+            for (int j = 0; j < U; ++j)
+              dmac(acc, Mi[j], d2{Sv[j].re - LM[c * U + j].re, Sv[j].im - LM[c * U + j].im});
+            Z[e] = d2{Y[e].re + f.rho * acc.re, Y[e].im + f.rho * acc.im};
+          }
+          __syncthreads();
+          // s = prox(sum_c (z_c + lambda_c))
+          for (int i = tid; i < U; i += kFixThreads) {
+            d2 w = dzero();
+            for (int c = 0; c < C; ++c) {
+              w.re += Z[c * U + i].re + LM[c * U + i].re;
+              w.im += Z[c * U + i].im + LM[c * U + i].im;
+            }
+            Sv[i] = prox64(f, w);
+          }
+          __syncthreads();
+        }
+        for (int i = tid; i < U; i += kFixThreads) write_out(f, k, n, i, Sv[i]);
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// Algorithm 2 in FP64 for the flagged subcarriers (f.rho = N0 / Es, or 0 for
+// ZF).  w = sum_c H_c^H (H_c p) is formed cluster by cluster, H_c p in chunks
+// of up to 1024 rows.
+__global__ void __launch_bounds__(kFixThreads) dcg_ul_fix64(FixArgs f) {
+  extern __shared__ d2 fsm[];
+  constexpr int kChunk = 1024;
+  const int U = f.U, C = f.C, S = f.S;
+  d2* R = fsm;
+  d2* P = R + U;
+  d2* X = P + U;
+  d2* W = X + U;
+  d2* Hp = W + U;                // kChunk entries
+  double* red = reinterpret_cast<double*>(Hp + kChunk);   // [0] rr, [1] pe / rr_new
+  int* list = reinterpret_cast<int*>(red + 4);
+  int* cnt = list + kFixThreads;
+  const int tid = threadIdx.x;
+
+  for (long r = 0; (long)blockIdx.x + r * kFixThreads * (long)gridDim.x < f.n_sc; ++r) {
+    const int nl = collect_round(f, r, list, cnt);
+    for (int q = 0; q < nl; ++q) {
+      const int k = list[q];
+      const c32* Hk = f.H + (size_t)k * f.B * U;
+      for (int n = 0; n < f.n_sym; ++n) {
+        const c32* yk = f.y + ((size_t)k * f.n_sym + n) * f.B;
+        // y^MRC = sum_c H_c^H y_c; r = p = y^MRC; x = 0
+        for (int i = tid; i < U; i += kFixThreads) {
+          d2 acc = dzero();
+          for (int c = 0; c < C; ++c) {
+            d2 part = dzero();
+            for (int s = 0; s < S; ++s)
+              dmacc(part, dld(Hk + ((size_t)c * S + s) * U + i), dld(yk + (size_t)c * S + s));
+            acc.re += part.re;
+            acc.im += part.im;
+          }
+          R[i] = acc;
+          P[i] = acc;
+          X[i] = dzero();
+        }
+        __syncthreads();
+        if (tid == 0) {
+          double rr = 0.0;
+          for (int i = 0; i < U; ++i) rr += R[i].re * R[i].re + R[i].im * R[i].im;
+          red[0] = rr;
+        }
+        __syncthreads();
+        for (int t = 1; t <= f.T; ++t) {
+          const double rr = red[0];
+          if (rr == 0.0) break;   // uniform: every thread read the same value
+          for (int i = tid; i < U; i += kFixThreads) W[i] = dzero();
+          __syncthreads();
+          for (int c = 0; c < C; ++c) {
+            for (int s0 = 0; s0 < S; s0 += kChunk) {
+              const int ns = (S - s0 < kChunk) ? S - s0 : kChunk;
+              for (int s = tid; s < ns; s += kFixThreads) {
+                const c32* row = Hk + ((size_t)c * S + s0 + s) * U;
+                d2 acc = dzero();
+                for (int u = 0; u < U; ++u) dmac(acc, dld(row + u), P[u]);
+                Hp[s] = acc;
+              }
+              __syncthreads();
+              for (int i = tid; i < U; i += kFixThreads) {
+                d2 acc = dzero();
+                for (int s = 0; s < ns; ++s) dmacc(acc, dld(Hk + ((size_t)c * S + s0 + s) * U + i), Hp[s]);
+                W[i].re += acc.re;
+                W[i].im += acc.im;
+              }
+              __syncthreads();
+            }
+          }
+          // e = rho p + w (kept in W); alpha = ||r||^2 / Re(p^H e)
+          for (int i = tid; i < U; i += kFixThreads) W[i] = d2{f.rho * P[i].re + W[i].re, f.rho * P[i].im + W[i].im};
+          __syncthreads();
+          if (tid == 0) {
+            double pe = 0.0;
+            for (int i = 0; i < U; ++i) pe += P[i].re * W[i].re + P[i].im * W[i].im;
+            red[1] = pe;
+          }
+          __syncthreads();
+          const double alpha = rr / red[1];
+          for (int i = tid; i < U; i += kFixThreads) {
+            X[i] = d2{X[i].re + alpha * P[i].re, X[i].im + alpha * P[i].im};
+            R[i] = d2{R[i].re - alpha * W[i].re, R[i].im - alpha * W[i].im};
+          }
+          __syncthreads();
+          if (tid == 0) {
+            double rn = 0.0;
+            for (int i = 0; i < U; ++i) rn += R[i].re * R[i].re + R[i].im * R[i].im;
+            red[2] = rn;
+          }
+          __syncthreads();
+          const double rr_new = red[2];
+          const double beta = rr_new / rr;
+          for (int i = tid; i < U; i += kFixThreads) P[i] = d2{R[i].re + beta * P[i].re, R[i].im + beta * P[i].im};
+          __syncthreads();
+          if (tid == 0) red[0] = rr_new;
+          __syncthreads();
+        }
+        for (int i = tid; i < U; i += kFixThreads) write_out(f, k, n, i, X[i]);
+        __syncthreads();
+      }
+    }
+  }
+}
+
+size_t fix64_slot_bytes(int U, int C) { return (size_t)C * U * U * sizeof(d2); }
+
+hipError_t launch_admm_ul_fix64(const FixArgs& f, hipStream_t st) {
+  const size_t lds = (size_t)(3 * f.C * f.U + f.U) * sizeof(d2) + (kFixThreads + 4) * sizeof(int);
+  hipLaunchKernelGGL(admm_ul_fix64, dim3((unsigned)f.n_slots), dim3(kFixThreads), lds, st, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_dcg_ul_fix64(const FixArgs& f, hipStream_t st) {
+  const size_t lds = (size_t)(4 * f.U + 1024) * sizeof(d2) + 4 * sizeof(double) + (kFixThreads + 4) * sizeof(int);
+  hipLaunchKernelGGL(dcg_ul_fix64, dim3((unsigned)f.n_slots), dim3(kFixThreads), lds, st, f);
+  return hipGetLastError();
+}
+
+}  // namespace dbp

@@ -1347,6 +1347,7 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   }
 
   int buf = 0;
+  int fl = 0;   // status bits of this lane's outputs (bit 0 non-finite, bit 1 re-slice)
   for (int n = 0; n < a.n_sym; ++n) {
     c32 hy = hy0;
     if constexpr (STAGE == 3)
@@ -1386,8 +1387,14 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
       if (a.hard) {
         const int iI = slice_dim(s.re, a.kappa, a.L), iQ = slice_dim(s.im, a.kappa, a.L);
         a.hard[o] = (uint8_t)(iI + a.L * iQ);
+        if (near_threshold(s.re, a.kappa, a.L, a.guard) || near_threshold(s.im, a.kappa, a.L, a.guard)) fl |= 2;
       }
+      if (nonfinite(s)) fl |= 1;
     }
+  }
+  if (a.flags) {
+    const int bits = group_flags<G>(fl, g);
+    if (c == 0 && u == 0 && k < a.n_sc) a.flags[k] = bits;
   }
 }
 
@@ -1429,6 +1436,7 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 
   int buf = 0;
+  int fl = 0;   // status bits of this lane's outputs (bit 0 non-finite, bit 1 re-slice)
   for (int n = 0; n < a.n_sym; ++n) {
     c32 hy = hy0;
     if (n > 0) hy = cluster_pass<G, false>(a.H, a.y, A, k, c, n, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
@@ -1461,8 +1469,14 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
       if (a.hard) {
         const int iI = slice_dim(x.re, a.kappa, a.L), iQ = slice_dim(x.im, a.kappa, a.L);
         a.hard[o] = (uint8_t)(iI + a.L * iQ);
+        if (near_threshold(x.re, a.kappa, a.L, a.guard) || near_threshold(x.im, a.kappa, a.L, a.guard)) fl |= 2;
       }
+      if (nonfinite(x)) fl |= 1;
     }
+  }
+  if (a.flags) {
+    const int bits = group_flags<G>(fl, g);
+    if (c == 0 && u == 0 && k < a.n_sc) a.flags[k] = bits;
   }
 }
 

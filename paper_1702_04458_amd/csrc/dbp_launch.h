@@ -8,6 +8,12 @@ namespace dbp {
 
 struct c32;
 
+// per-subcarrier status bits (the values of DBP_STATUS_NONFINITE / DBP_STATUS_RESLICED)
+constexpr int kStatusNonfinite = 1;
+constexpr int kStatusReslice = 2;
+// workgroups (FP64 slots) of the re-slice pass at most
+constexpr int kFixMaxSlots = 256;
+
 struct UlArgs {
   const c32* H;       // [n_sc][B][U]
   const c32* y;       // [n_sc][n_sym][B]
@@ -26,6 +32,23 @@ struct UlArgs {
   c32* fac;           // [n_sc][C][U][U] resident factors B_c^{-1} (column v of lane u at v*U + u), or null
   const uint32_t* H16;  // [n_sc][B][U] packed FP16 channel (real part in the low half), or null
   const float* hscale;  // [n_sc][C] power-of-two scale of each (subcarrier, cluster) tile of H16
+  int32_t* flags;     // [n_sc] per-subcarrier status bits written by the detection kernels, or null
+  float guard;        // re-slice guard in slicer units t = (kappa x + L) / 2; 0: no re-slice
+};
+
+// Exact re-slicing: the subcarriers the FP32 kernel flagged (a soft value
+// within the guard of a decision threshold) are recomputed in FP64 and their
+// outputs overwritten.
+struct FixArgs {
+  const c32* H;       // [n_sc][B][U]
+  const c32* y;       // [n_sc][n_sym][B]
+  c32* shat;          // [n_sc][n_sym][U]
+  uint8_t* hard;      // [n_sc][n_sym][U]
+  int32_t* flags;     // [n_sc] status bits of the FP32 pass (read; the re-slice bit is kept)
+  void* ws;           // n_slots blocks of C U^2 complex FP64 (ADMM), or null (CG)
+  int n_sc, n_sym, B, U, C, S, T, reg, L, n_slots;
+  double rho;         // ADMM penalty (Alg. 1) or N0/Es (Alg. 2)
+  double gamma, inv_den, invC, box_r, kappa;
 };
 
 struct DlArgs {
@@ -57,5 +80,11 @@ hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st);
 hipError_t launch_scan_nonfinite(const float* x, size_t floats_per_sc, int n_sc, int32_t* status,
                                  hipStream_t st);
 hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st);
+
+// FP64 recomputation of the flagged subcarriers (Algorithm 1 or 2), n_slots workgroups
+hipError_t launch_admm_ul_fix64(const FixArgs& f, hipStream_t st);
+hipError_t launch_dcg_ul_fix64(const FixArgs& f, hipStream_t st);
+// bytes of one FP64 slot of the ADMM re-slice (C blocks of U x U complex FP64)
+size_t fix64_slot_bytes(int U, int C);
 
 }  // namespace dbp

@@ -102,7 +102,7 @@ struct Frame {
   uint8_t* hard_out;
   int n_sc, n_sym, B, U, C, T, qam, prec, reg, flags;
   float rho, N0;
-  size_t bytes_H, bytes_y, bytes_s, bytes_hard, footprint;
+  size_t bytes_H, bytes_y, bytes_s, bytes_hard, bytes_ws, footprint;
   size_t off = 0;
   int slot = -1;
   int status = DBP_OK;
@@ -149,7 +149,8 @@ int launch_factored(dbp_server* s, Frame& f, hipStream_t st) {
   const void* y = f.y;
   void* so = f.s_out;
   uint8_t* ho = f.hard_out;
-  char* d = static_cast<char*>(s->base) + f.off;
+  char* ws = static_cast<char*>(s->base) + f.off;   // re-slice workspace first in the frame's block
+  char* d = ws + f.bytes_ws;
   if (!(f.flags & DBP_SERVE_DEVICE_IO)) {
     char* dy = d;
     char* ds = dy + ((f.bytes_y + 255) & ~size_t(255));
@@ -159,10 +160,11 @@ int launch_factored(dbp_server* s, Frame& f, hipStream_t st) {
     so = ds;
     ho = f.hard_out ? reinterpret_cast<uint8_t*>(dh) : nullptr;
   }
-  int rc = ch.h16 ? dbp_detect_admm_factored_h16(dH, dF, y, so, ho, f.n_sc, f.n_sym, f.B, f.U, f.C, f.T, f.rho,
-                                                  1.0f, f.N0, 1.0f, f.reg, f.qam, st)
-                  : dbp_detect_admm_factored(dH, dF, y, so, ho, f.n_sc, f.n_sym, f.B, f.U, f.C, f.T, f.rho, 1.0f,
-                                             f.N0, 1.0f, f.reg, f.qam, st);
+  int rc = ch.h16 ? dbp_detect_admm_factored_h16(dH, dF, y, so, ho, nullptr, f.n_sc, f.n_sym, f.B, f.U, f.C, f.T,
+                                                  f.rho, 1.0f, f.N0, 1.0f, f.reg, f.qam, st)
+                  : dbp_detect_admm_factored(dH, dF, y, so, ho, nullptr, f.bytes_ws ? ws : nullptr, f.bytes_ws,
+                                             f.n_sc, f.n_sym, f.B, f.U, f.C, f.T, f.rho, 1.0f, f.N0, 1.0f, f.reg,
+                                             f.qam, st);
   if (rc != DBP_OK) return rc;
   if (!(f.flags & DBP_SERVE_DEVICE_IO)) {
     if (hipMemcpyAsync(f.s_out, so, f.bytes_s, hipMemcpyDeviceToHost, st) != hipSuccess) return DBP_ERR_DEVICE;
@@ -176,23 +178,26 @@ int launch_factored(dbp_server* s, Frame& f, hipStream_t st) {
 int launch_frame(dbp_server* s, Frame& f) {
   hipStream_t st = s->streams[f.slot];
   if (f.channel) return launch_factored(s, f, st);
+  char* ws = static_cast<char*>(s->base) + f.off;   // re-slice workspace first in the frame's block
+  void* wsp = f.bytes_ws ? ws : nullptr;
   if (f.flags & DBP_SERVE_DEVICE_IO) {
-    // inputs and outputs already in device memory: the arena space only
-    // accounts for the frame's share of the budget
-    int rc = dbp_detect_admm(f.H, f.y, f.s_out, f.hard_out, f.n_sc, f.n_sym, f.B, f.U, f.C, f.T, f.rho, 1.0f, f.N0,
-                             1.0f, f.reg, f.qam, f.prec, st);
+    // inputs and outputs already in device memory: beyond the workspace the
+    // arena space only accounts for the frame's share of the budget
+    int rc = dbp_detect_admm(f.H, f.y, f.s_out, f.hard_out, nullptr, wsp, f.bytes_ws, f.n_sc, f.n_sym, f.B, f.U,
+                             f.C, f.T, f.rho, 1.0f, f.N0, 1.0f, f.reg, f.qam, f.prec, st);
     if (rc != DBP_OK) return rc;
     return hipEventRecord(s->events[f.slot], st) == hipSuccess ? DBP_OK : DBP_ERR_DEVICE;
   }
-  char* d = static_cast<char*>(s->base) + f.off;
+  char* d = ws + f.bytes_ws;
   char* dH = d;
   char* dy = dH + ((f.bytes_H + 255) & ~size_t(255));
   char* ds = dy + ((f.bytes_y + 255) & ~size_t(255));
   char* dh = ds + ((f.bytes_s + 255) & ~size_t(255));
   if (hipMemcpyAsync(dH, f.H, f.bytes_H, hipMemcpyHostToDevice, st) != hipSuccess) return DBP_ERR_DEVICE;
   if (hipMemcpyAsync(dy, f.y, f.bytes_y, hipMemcpyHostToDevice, st) != hipSuccess) return DBP_ERR_DEVICE;
-  int rc = dbp_detect_admm(dH, dy, ds, f.hard_out ? reinterpret_cast<uint8_t*>(dh) : nullptr, f.n_sc, f.n_sym, f.B,
-                           f.U, f.C, f.T, f.rho, 1.0f, f.N0, 1.0f, f.reg, f.qam, f.prec, st);
+  int rc = dbp_detect_admm(dH, dy, ds, f.hard_out ? reinterpret_cast<uint8_t*>(dh) : nullptr, nullptr, wsp,
+                           f.bytes_ws, f.n_sc, f.n_sym, f.B, f.U, f.C, f.T, f.rho, 1.0f, f.N0, 1.0f, f.reg, f.qam,
+                           f.prec, st);
   if (rc != DBP_OK) return rc;
   if (hipMemcpyAsync(f.s_out, ds, f.bytes_s, hipMemcpyDeviceToHost, st) != hipSuccess) return DBP_ERR_DEVICE;
   if (f.hard_out && hipMemcpyAsync(f.hard_out, dh, f.bytes_hard, hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -250,6 +255,7 @@ void scheduler(dbp_server* s) {
         f.status = rc;
         f.done = true;
         f.t_done = Clock::now();
+        progressed = true;   // wakes a caller waiting on this ticket
         continue;
       }
       *free_slot = f.ticket;
@@ -262,9 +268,10 @@ void scheduler(dbp_server* s) {
     if (inflight == 0 && s->queue.empty()) {
       s->cv.wait(lk, [&] { return s->stop.load() || !s->queue.empty(); });
     } else {
-      // poll completions at a fine granularity without holding the lock
+      // poll completions without holding the lock; yielding (instead of a
+      // timed sleep) keeps completion timestamps within about a microsecond
       lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(5));
+      std::this_thread::yield();
       lk.lock();
     }
   }
@@ -345,6 +352,12 @@ int dbp_server_submit(dbp_server* s, const void* H_host, const void* y_host, voi
   if (n_sc < 1 || n_sym < 1 || B < 1 || U < 1 || C < 1 || B % C || U > B / C || T < 1 || !qam_ok(qam) ||
       !(rho > 0.f) || !(N0 >= 0.f) || (flags & ~DBP_SERVE_DEVICE_IO))
     return DBP_ERR_INVALID;
+  // every other argument check of the detection call (precision, regulariser,
+  // built shapes): with n_sc = 0 it validates and queues nothing, so a frame
+  // the library would refuse is refused here instead of at admission
+  const int vrc = dbp_detect_admm(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, n_sym, B, U, C, T, rho,
+                                  1.0f, N0, 1.0f, reg, qam, prec, nullptr);
+  if (vrc != DBP_OK) return vrc;
   Frame f{};
   f.H = H_host;
   f.y = y_host;
@@ -367,7 +380,8 @@ int dbp_server_submit(dbp_server* s, const void* H_host, const void* y_host, voi
   f.bytes_s = size_t(n_sc) * n_sym * U * 8;
   f.bytes_hard = size_t(n_sc) * n_sym * U;
   auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
-  f.footprint = al(f.bytes_H) + al(f.bytes_y) + al(f.bytes_s) + al(f.bytes_hard);
+  f.bytes_ws = hard_host ? al(dbp_detect_workspace_bytes(n_sc, U, C)) : 0;
+  f.footprint = f.bytes_ws + al(f.bytes_H) + al(f.bytes_y) + al(f.bytes_s) + al(f.bytes_hard);
   f.t_arrive = Clock::now();
   std::lock_guard<std::mutex> lk(s->mu);
   if (f.footprint > s->arena->size() - s->channel_bytes) return DBP_ERR_NOMEM;   // can never be admitted
@@ -463,6 +477,10 @@ int dbp_server_submit_factored(dbp_server* s, uint64_t channel, const void* y, v
   auto it = s->channels.find(channel);
   if (it == s->channels.end()) return DBP_ERR_NOTFOUND;
   Channel& ch = it->second;
+  // argument checks of the detection call (n_sc = 0: validation only)
+  const int vrc = dbp_detect_admm_factored(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, n_sym,
+                                           ch.B, ch.U, ch.C, T, ch.rho, 1.0f, N0, 1.0f, reg, qam, nullptr);
+  if (vrc != DBP_OK) return vrc;
   Frame f{};
   f.channel = channel;
   f.H = nullptr;
@@ -486,7 +504,8 @@ int dbp_server_submit_factored(dbp_server* s, uint64_t channel, const void* y, v
   f.bytes_s = size_t(f.n_sc) * n_sym * f.U * 8;
   f.bytes_hard = size_t(f.n_sc) * n_sym * f.U;
   auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
-  f.footprint = al(f.bytes_y) + al(f.bytes_s) + al(f.bytes_hard);
+  f.bytes_ws = (hard && !ch.h16) ? al(dbp_detect_workspace_bytes(f.n_sc, f.U, f.C)) : 0;
+  f.footprint = f.bytes_ws + al(f.bytes_y) + al(f.bytes_s) + al(f.bytes_hard);
   f.t_arrive = Clock::now();
   // a frame that does not fit beside the resident channels could never be admitted
   if (f.footprint > s->arena->size() - s->channel_bytes) return DBP_ERR_NOMEM;

@@ -39,11 +39,12 @@ def test_version_and_strerror():
 
 
 def _admm(**kw):
-    args = dict(H=1, y=1, s=1, hard=None, n_sc=4, n_sym=1, B=64, U=8, C=4, T=3, rho=1.0, gamma=1.0,
-                N0=0.1, Es=1.0, reg=0, qam=4, prec=0)
+    args = dict(H=1, y=1, s=1, hard=None, status=None, ws=None, ws_bytes=0, n_sc=4, n_sym=1, B=64, U=8, C=4, T=3,
+                rho=1.0, gamma=1.0, N0=0.1, Es=1.0, reg=0, qam=4, prec=0)
     args.update(kw)
     L = _native.lib()
-    return L.dbp_detect_admm(args["H"], args["y"], args["s"], args["hard"], args["n_sc"], args["n_sym"],
+    return L.dbp_detect_admm(args["H"], args["y"], args["s"], args["hard"], args["status"], args["ws"],
+                             args["ws_bytes"], args["n_sc"], args["n_sym"],
                              args["B"], args["U"], args["C"], args["T"], args["rho"], args["gamma"],
                              args["N0"], args["Es"], args["reg"], args["qam"], args["prec"], None)
 
@@ -63,14 +64,43 @@ def test_detect_admm_rejects(kw, code):
 
 def test_detect_admm_empty_is_noop():
     assert _admm(n_sc=0, H=None, y=None, s=None) == 0
+    # n_sc = 0 still validates every other argument (the serving loop relies on it)
+    assert _admm(n_sc=0, H=None, y=None, s=None, prec=1, U=16, B=128, C=8) == 2
+
+
+def test_workspace_bytes():
+    L = _native.lib()
+    # a 256-byte aligned flag region of n_sc int32, then min(n_sc, 256) blocks of C U^2 complex FP64
+    assert L.dbp_detect_workspace_bytes(1200, 32, 8) == 4864 + 256 * 8 * 32 * 32 * 16
+    assert L.dbp_detect_workspace_bytes(16, 8, 4) == 256 + 16 * 4 * 8 * 8 * 16
+    assert L.dbp_detect_workspace_bytes(0, 8, 4) == 256 * 0 + 1 * 4 * 8 * 8 * 16
+    assert L.dbp_detect_workspace_bytes(-1, 8, 4) == 0
+
+
+def test_hard_decisions_need_a_workspace():
+    need = _native.lib().dbp_detect_workspace_bytes(4, 8, 4)
+    assert _admm(hard=1) == 1                                    # no workspace
+    assert "workspace" in _native.lib().dbp_last_error().decode()
+    assert _admm(hard=1, ws=256, ws_bytes=need - 1) == 1         # too small
+    assert _admm(hard=1, ws=257, ws_bytes=need) == 1             # misaligned
 
 
 def test_detect_cg_rejects():
     L = _native.lib()
-    base = [1, 1, 1, None, 4, 1, 64, 8, 4, 3, 0.1, 1.0, 0, 4, None]
-    assert L.dbp_detect_cg(*base[:12], 2, 4, None) == 1            # BOX is not quadratic
-    assert L.dbp_detect_cg(1, 1, 1, None, 4, 1, 64, 8, 3, 3, 0.1, 1.0, 0, 4, None) == 1   # B % C
-    assert L.dbp_detect_cg(1, 1, None, None, 4, 1, 64, 8, 4, 3, 0.1, 1.0, 0, 4, None) == 1
+    # (H, y, x, hard, status, ws, ws_bytes, n_sc, n_sym, B, U, C, T, N0, Es, reg, qam, stream)
+    base = [1, 1, 1, None, None, None, 0, 4, 1, 64, 8, 4, 3, 0.1, 1.0, 0, 4, None]
+    bad = list(base)
+    bad[15] = 2
+    assert L.dbp_detect_cg(*bad) == 1                                          # BOX is not quadratic
+    bad = list(base)
+    bad[11] = 3
+    assert L.dbp_detect_cg(*bad) == 1                                          # B % C
+    bad = list(base)
+    bad[2] = None
+    assert L.dbp_detect_cg(*bad) == 1                                          # null x
+    bad = list(base)
+    bad[3] = 1
+    assert L.dbp_detect_cg(*bad) == 1                                          # hard without workspace
 
 
 def test_precode_rejects():
@@ -101,20 +131,13 @@ def test_factor_entry_points_reject():
     assert L.dbp_factor_admm(1, 1, 4, 256, 32, 16, 1.0, 0, None) == 2         # S = 16 < U
     assert L.dbp_factor_admm(1, 1, 4, 256, 32, 8, 1.0, 0x20, None) == 2       # FP64 inverse needs a mixed Gram
     assert L.dbp_factor_admm(None, None, 0, 256, 32, 8, 1.0, 0, None) == 0    # empty is a no-op
-    # dbp_detect_admm_factored(H, F, y, s, hard, n_sc, n_sym, B, U, C, T, rho, gamma, N0, Es, reg, qam, stream)
-    ok = [1, 1, 1, 1, None, 4, 1, 256, 32, 8, 5, 1.0, 1.0, 0.1, 1.0, 0, 64, None]
-    bad = list(ok)
-    bad[1] = None
-    assert L.dbp_detect_admm_factored(*bad) == 1
-    bad = list(ok)
-    bad[10] = 0
-    assert L.dbp_detect_admm_factored(*bad) == 1                               # T < 1
-    bad = list(ok)
-    bad[16] = 8
-    assert L.dbp_detect_admm_factored(*bad) == 1                               # qam
-    bad = list(ok)
-    bad[8] = 12
-    assert L.dbp_detect_admm_factored(*bad) == 2                               # U not built
+    # dbp_detect_admm_factored(H, F, y, s, hard, status, ws, ws_bytes, n_sc, n_sym, B, U, C, T, rho, gamma, N0,
+    #                          Es, reg, qam, stream)
+    ok = [1, 1, 1, 1, None, None, None, 0, 4, 1, 256, 32, 8, 5, 1.0, 1.0, 0.1, 1.0, 0, 64, None]
+    for i, v, code in ((1, None, 1), (13, 0, 1), (19, 8, 1), (11, 12, 2), (4, 1, 1)):
+        bad = list(ok)
+        bad[i] = v
+        assert L.dbp_detect_admm_factored(*bad) == code, (i, v)
 
 
 def test_h16_channel_entry_points_reject():
@@ -125,15 +148,15 @@ def test_h16_channel_entry_points_reject():
     assert L.dbp_pack_channel_h16(1, None, 4, 256, 32, 8, None) == 1            # null packed
     assert L.dbp_pack_channel_h16(1, 1, 4, 256, 24, 8, None) == 2               # U not built
     assert L.dbp_pack_channel_h16(None, None, 0, 256, 32, 8, None) == 0         # empty: no-op
-    # dbp_detect_admm_factored_h16(packed, factors, y, s_hat, hard, n_sc, n_sym, B, U, C, T, rho, gamma, N0, Es,
-    #                              reg, qam, stream)
-    ok = [1, 1, 1, 1, None, 4, 1, 256, 32, 8, 5, 1.0, 1.0, 0.1, 1.0, 0, 64, None]
-    for i, v, code in ((1, None, 1), (11, 0.0, 1), (16, 8, 1), (8, 64, 2)):
+    # dbp_detect_admm_factored_h16(packed, factors, y, s_hat, hard, status, n_sc, n_sym, B, U, C, T, rho, gamma,
+    #                              N0, Es, reg, qam, stream)
+    ok = [1, 1, 1, 1, None, None, 4, 1, 256, 32, 8, 5, 1.0, 1.0, 0.1, 1.0, 0, 64, None]
+    for i, v, code in ((1, None, 1), (12, 0.0, 1), (17, 8, 1), (9, 64, 2)):
         bad = list(ok)
         bad[i] = v
         assert L.dbp_detect_admm_factored_h16(*bad) == code, (i, v)
     small = list(ok)
-    small[9] = 16                                                                # S = 16 < U = 32
+    small[10] = 16                                                               # S = 16 < U = 32
     assert L.dbp_detect_admm_factored_h16(*small) == 2
 
 

@@ -45,10 +45,13 @@ def test_graph_replay_matches_eager():
     s_f = torch.empty_like(s_a)
     x = torch.empty((n_sc, 1, B), dtype=torch.complex64, device="cuda")
     beta = torch.empty((n_sc, 1), dtype=torch.float32, device="cuda")
+    h_c = torch.empty_like(h_a)
+    st_a = torch.empty(n_sc, dtype=torch.int32, device="cuda")
+    ws = api.workspace(n_sc, U, C)              # FP64 re-slice workspace, shared by the two detections
 
     def body():
-        api.detect(H, y, N0, C, 1.0, 5, qam=4, out=(s_a, h_a))
-        api.detect(H, y, N0, C, 1.0, 5, algo="cg", hard=False, qam=4, out=(s_c, None))
+        api.detect(H, y, N0, C, 1.0, 5, qam=4, out=(s_a, h_a, st_a), workspace=ws)
+        api.detect(H, y, N0, C, 1.0, 5, algo="cg", qam=4, out=(s_c, h_c), workspace=ws)
         api.factor(H, C, 1.0, out=fac)
         api.detect_factored(H, fac, y, N0, C, 1.0, 5, hard=False, qam=4, out=(s_f, None))
         api.precode(Hd, sd, CD, 1.0, 5, eps=0.2, out=(x, beta))
@@ -72,12 +75,13 @@ def test_graph_replay_matches_eager():
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        ea, eh = api.detect(H, y, N0, C, 1.0, 5, qam=4)
-        ec, _ = api.detect(H, y, N0, C, 1.0, 5, algo="cg", hard=False, qam=4)
+        ea, eh, est = api.detect(H, y, N0, C, 1.0, 5, qam=4, status=True)
+        ec, ech = api.detect(H, y, N0, C, 1.0, 5, algo="cg", qam=4)
         ex, eb = api.precode(Hd, sd, CD, 1.0, 5, eps=0.2)
         torch.cuda.synchronize()
         assert torch.equal(s_a, ea) and torch.equal(h_a, eh), f"replay {i}: ADMM differs from eager"
-        assert torch.equal(s_c, ec), f"replay {i}: CG differs from eager"
+        assert torch.equal(st_a, est), f"replay {i}: status differs from eager"
+        assert torch.equal(s_c, ec) and torch.equal(h_c, ech), f"replay {i}: CG differs from eager"
         assert torch.equal(x, ex) and torch.equal(beta, eb), f"replay {i}: precode differs from eager"
         ref = O.admm_ul_frame(fr.H, fr.y, C, 1.0, 5, fr.N0)
         assert rel_err(s_a.cpu().numpy(), ref) <= 1e-5

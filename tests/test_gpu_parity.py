@@ -4,11 +4,14 @@ same seeded inputs.
 Bars (FP32 path):
 * soft outputs: frame-level relative Frobenius error ||gpu - oracle|| / ||oracle||
   <= 1e-5, and every vector within 1e-4 relative;
-* hard decisions: the kernel's decision equals the FP32 slicer applied to the
-  kernel's own soft output bit for bit, and equals the oracle's FP64 decision on
-  every symbol whose oracle soft value is farther than a guard band (1e-3 in
-  kappa-scaled units) from a decision threshold; at most 1e-4 of all symbols may
-  sit inside the guard band and differ.
+* hard decisions: identical to the oracle's FP64 decisions on every symbol.
+  The library makes them exact by recomputing in FP64 every subcarrier with a
+  soft value within a guard of a decision threshold (DBP_STATUS_RESLICED); the
+  oracle is evaluated with the kernel's own FP32 value of N0.  On subcarriers
+  that were not recomputed the decision is also the FP32 slicer applied to the
+  kernel's soft output, bit for bit, and that soft output lies well inside the
+  guard (its largest error, in the slicer's units, is below a quarter of the
+  guard).
 """
 import math
 import sys
@@ -60,21 +63,60 @@ def threshold_gap(x, M):
     return np.minimum(gap(x.real), gap(x.imag))
 
 
-def check_hard(shat, hard, ref, M, guard=1e-3):
-    assert np.array_equal(hard, O.slice_qam_f32(shat, M)), "kernel slicer differs from FP32 slicer"
+GUARD_T = 2.0 ** -12      # re-slice guard of the FP32 path, slicer units
+STATUS_NONFINITE, STATUS_RESLICED = 1, 2
+
+
+def t_units(x, M):
+    return (math.sqrt(2 * (M - 1) / 3) * x + int(math.sqrt(M))) / 2
+
+
+def check_hard(shat, hard, ref, M, status=None, guard=GUARD_T):
+    """Exact hard decisions (see the module docstring).  Returns the number of
+    re-sliced subcarriers."""
     ref_hard = O.slice_qam(ref, M)
     diff = hard != ref_hard
+    assert not np.any(diff), f"{int(np.sum(diff))} hard decisions differ from the FP64 oracle"
+    if status is None:
+        return 0
+    plain = (status & STATUS_RESLICED) == 0
+    assert np.array_equal(hard[plain], O.slice_qam_f32(shat[plain], M)), "kernel slicer differs from FP32 slicer"
+    if np.any(plain):
+        err = np.maximum(np.abs(t_units(shat[plain].real, M) - t_units(ref[plain].real, M)),
+                         np.abs(t_units(shat[plain].imag, M) - t_units(ref[plain].imag, M)))
+        assert err.max() < guard / 4, f"FP32 error {err.max():.2e} too close to the guard {guard:.2e}"
+    # a subcarrier that was not re-sliced has no soft value inside the guard
+    gap = threshold_gap(shat[plain].astype(np.complex128), M)
+    assert np.all(gap >= guard * (1 - 1e-3))
+    return int(np.sum(~plain))
+
+
+def check_hard_low_precision(shat, hard, ref, M, guard=1e-3):
+    """Hard-decision rule of the low-precision paths that are not re-sliced
+    (the FP16 resident channel, factors made with a BF16 Gram): the decision
+    is the FP32 slicer applied to the kernel's own soft output bit for bit,
+    and equals the oracle's FP64 decision on every symbol whose oracle value
+    lies farther than `guard` (slicer units) from a threshold; at most 1e-4 of
+    the symbols may differ (identical decisions on >= 99.99 %)."""
+    assert np.array_equal(hard, O.slice_qam_f32(shat, M)), "kernel slicer differs from FP32 slicer"
+    diff = hard != O.slice_qam(ref, M)
     near = threshold_gap(ref, M) < guard
     assert not np.any(diff & ~near), f"{int(np.sum(diff & ~near))} hard decisions differ away from thresholds"
     assert np.sum(diff) <= max(1, 1e-4 * diff.size)
 
 
+def n0_f32(N0):
+    """The kernel receives N0 as an FP32 argument; the oracle takes that value."""
+    return float(np.float32(N0))
+
+
 def run_detect(fr, C, T, algo, reg="mmse", rho=1.0, sel=None):
     H, y = to_dev(fr.H), to_dev(fr.y)
-    s, h = api.detect(H, y, fr.N0, C, rho, T, algo=algo, reg=reg, qam=fr.qam)
+    s, h, st = api.detect(H, y, fr.N0, C, rho, T, algo=algo, reg=reg, qam=fr.qam, status=True)
     torch.cuda.synchronize()
-    s, h = s.cpu().numpy(), h.cpu().numpy()
-    return s, h
+    s, h, st = s.cpu().numpy(), h.cpu().numpy(), st.cpu().numpy()
+    assert not np.any(st & STATUS_NONFINITE)
+    return s, h, st
 
 
 def oracle_detect(fr, C, T, algo, reg="mmse", rho=1.0, sel=None):
@@ -82,8 +124,8 @@ def oracle_detect(fr, C, T, algo, reg="mmse", rho=1.0, sel=None):
     ys = fr.y if sel is None else fr.y[sel]
     box_r = O.box_radius(fr.qam)
     if algo == "admm":
-        return O.admm_ul_frame(Hs, ys, C, rho, T, fr.N0, reg=reg, box_r=box_r)
-    return O.dcg_ul_frame(Hs, ys, C, T, fr.N0, reg=reg)
+        return O.admm_ul_frame(Hs, ys, C, rho, T, n0_f32(fr.N0), reg=reg, box_r=box_r)
+    return O.dcg_ul_frame(Hs, ys, C, T, n0_f32(fr.N0), reg=reg)
 
 
 # -- configuration 1: B=64, C=4, U=8, 16 subcarriers, QPSK, 10 dB, rho=1, T=3, 4 seeds
@@ -91,11 +133,11 @@ def oracle_detect(fr, C, T, algo, reg="mmse", rho=1.0, sel=None):
 def test_cfg1_admm(seed):
     say(f"[gpu] cfg1 admm seed={seed}")
     fr = inputs.uplink_frame(inputs.frame_seed(1, seed, 10), 16, 64, 8, 4, 10.0)
-    s, h = run_detect(fr, 4, 3, "admm")
+    s, h, st = run_detect(fr, 4, 3, "admm")
     ref = oracle_detect(fr, 4, 3, "admm")
     assert rel_err(s, ref) <= 1e-5
     assert per_vec_rel(s, ref) <= 1e-4
-    check_hard(s, h, ref, 4)
+    check_hard(s, h, ref, 4, st)
 
 
 # -- configuration 2: B=128, C=8, U=16, 16-QAM, SNR 0..20, T=5; ADMM and DCG side by side.
@@ -105,11 +147,12 @@ def test_cfg1_admm(seed):
 def test_cfg2(snr, algo):
     say(f"[gpu] cfg2 {algo} snr={snr}")
     fr = inputs.uplink_frame(inputs.frame_seed(2, 0, snr), 75, 128, 16, 16, float(snr))
-    s, h = run_detect(fr, 8, 5, algo)
+    s, h, st = run_detect(fr, 8, 5, algo)
     ref = oracle_detect(fr, 8, 5, algo)
     assert rel_err(s, ref) <= 1e-5
     assert per_vec_rel(s, ref) <= 1e-4
-    check_hard(s, h, ref, 16)
+    nres = check_hard(s, h, ref, 16, st)
+    say(f"    re-sliced {nres} of {len(st)} subcarriers")
 
 
 def test_cfg2_full_size_sampled():
@@ -119,10 +162,10 @@ def test_cfg2_full_size_sampled():
     rng = np.random.default_rng(0)
     sel = np.sort(rng.choice(1200, 48, replace=False))
     for algo in ("admm", "cg"):
-        s, h = run_detect(fr, 8, 5, algo)
+        s, h, st = run_detect(fr, 8, 5, algo)
         ref = oracle_detect(fr, 8, 5, algo, sel=sel)
         assert rel_err(s[sel], ref) <= 1e-5
-        check_hard(s[sel], h[sel], ref, 16)
+        check_hard(s[sel], h[sel], ref, 16, st[sel])
 
 
 # -- headline shape: B=256, U=32, 64-QAM, 25 dB, T=5, C=8 (S=32) and C=4 (S=64)
@@ -130,11 +173,11 @@ def test_cfg2_full_size_sampled():
 def test_headline_shape(C):
     say(f"[gpu] headline C={C}")
     fr = inputs.uplink_frame(inputs.frame_seed(6, C, 25), 41, 256, 32, 64, 25.0)
-    s, h = run_detect(fr, C, 5, "admm")
+    s, h, st = run_detect(fr, C, 5, "admm")
     ref = oracle_detect(fr, C, 5, "admm")
     assert rel_err(s, ref) <= 1e-5
     assert per_vec_rel(s, ref) <= 1e-4
-    check_hard(s, h, ref, 64)
+    check_hard(s, h, ref, 64, st)
 
 
 # -- configuration 4 shape (B=512, C=8, U=64), FP32 path, i.i.d. and correlated
@@ -142,28 +185,29 @@ def test_headline_shape(C):
 def test_cfg4_shape_fp32(corr):
     say(f"[gpu] cfg4 fp32 corr={corr}")
     fr = inputs.uplink_frame(inputs.frame_seed(4, 0, 25), 9, 512, 64, 64, 25.0, corr=corr)
-    s, h = run_detect(fr, 8, 5, "admm")
+    s, h, st = run_detect(fr, 8, 5, "admm")
     ref = oracle_detect(fr, 8, 5, "admm")
     assert rel_err(s, ref) <= 1e-5
-    check_hard(s, h, ref, 64)
+    check_hard(s, h, ref, 64, st)
 
 
 @pytest.mark.parametrize("reg", ["zf", "box"])
 def test_other_regularisers(reg):
     say(f"[gpu] reg={reg}")
     fr = inputs.uplink_frame(inputs.frame_seed(7, 0, 15), 21, 64, 8, 16, 15.0)
-    s, h = run_detect(fr, 4, 4, "admm", reg=reg)
+    s, h, st = run_detect(fr, 4, 4, "admm", reg=reg)
     ref = oracle_detect(fr, 4, 4, "admm", reg=reg)
     assert rel_err(s, ref) <= 1e-5
-    check_hard(s, h, ref, 16)
+    check_hard(s, h, ref, 16, st)
 
 
 def test_cg_zf():
     say("[gpu] cg zf")
     fr = inputs.uplink_frame(inputs.frame_seed(7, 1, 15), 13, 64, 8, 16, 15.0)
-    s, h = run_detect(fr, 4, 4, "cg", reg="zf")
+    s, h, st = run_detect(fr, 4, 4, "cg", reg="zf")
     ref = oracle_detect(fr, 4, 4, "cg", reg="zf")
     assert rel_err(s, ref) <= 1e-5
+    check_hard(s, h, ref, 16, st)
 
 
 @pytest.mark.parametrize("B,U,C", [(64, 16, 4), (128, 32, 4), (512, 64, 8), (128, 8, 16), (96, 8, 3)])
@@ -171,9 +215,10 @@ def test_cg_zf():
 def test_shapes(B, U, C, algo):
     say(f"[gpu] shape B={B} U={U} C={C} {algo}")
     fr = inputs.uplink_frame(inputs.frame_seed(8, B + U + C, 10), 11, B, U, 16, 10.0)
-    s, h = run_detect(fr, C, 3, algo)
+    s, h, st = run_detect(fr, C, 3, algo)
     ref = oracle_detect(fr, C, 3, algo)
     assert rel_err(s, ref) <= 1e-5
+    check_hard(s, h, ref, 16, st)
 
 
 def test_multi_symbol_reuse():
@@ -181,19 +226,21 @@ def test_multi_symbol_reuse():
     say("[gpu] n_sym=3")
     fr = inputs.uplink_frame(inputs.frame_seed(9, 0, 10), 10, 128, 16, 16, 10.0, n_sym=3)
     for algo in ("admm", "cg"):
-        s, h = run_detect(fr, 8, 4, algo)
+        s, h, st = run_detect(fr, 8, 4, algo)
         ref = oracle_detect(fr, 8, 4, algo)
         assert rel_err(s, ref) <= 1e-5
+        check_hard(s, h, ref, 16, st)
 
 
 def test_T1_and_C1():
     say("[gpu] T=1, C=1")
     fr = inputs.uplink_frame(inputs.frame_seed(9, 1, 10), 7, 32, 8, 4, 10.0)
     for C, T in ((1, 1), (1, 4), (4, 1)):
-        s, _ = run_detect(fr, C, T, "admm")
-        assert rel_err(s, oracle_detect(fr, C, T, "admm")) <= 1e-5
-        s, _ = run_detect(fr, C, T, "cg")
-        assert rel_err(s, oracle_detect(fr, C, T, "cg")) <= 1e-5
+        for algo in ("admm", "cg"):
+            s, h, st = run_detect(fr, C, T, algo)
+            ref = oracle_detect(fr, C, T, algo)
+            assert rel_err(s, ref) <= 1e-5
+            check_hard(s, h, ref, 4, st)
 
 
 def test_empty_batch():
@@ -210,10 +257,10 @@ def test_empty_batch():
 def test_max_shapes(B, U, C, algo):
     say(f"[gpu] max shape B={B} U={U} C={C} {algo}")
     fr = inputs.uplink_frame(inputs.frame_seed(12, B + U + C, 15), 5, B, U, 64, 15.0)
-    s, h = run_detect(fr, C, 5, algo)
+    s, h, st = run_detect(fr, C, 5, algo)
     ref = oracle_detect(fr, C, 5, algo)
     assert rel_err(s, ref) <= 1e-5
-    check_hard(s, h, ref, 64)
+    check_hard(s, h, ref, 64, st)
 
 
 def fp32_conditioning_bar(Hu, C, rho):
@@ -378,14 +425,24 @@ def test_mixed_headline_shape(prec, C, factor):
     say(f"[gpu] mixed prec={prec} C={C} factor={factor}")
     fr = inputs.uplink_frame(inputs.frame_seed(6, 10 + C, 25), 41, 256, 32, 64, 25.0)
     H, y = to_dev(fr.H), to_dev(fr.y)
-    s, h = api.detect(H, y, fr.N0, C, 1.0, 5, qam=64, prec=prec, factor=factor)
+    s, h, st = api.detect(H, y, fr.N0, C, 1.0, 5, qam=64, prec=prec, factor=factor, status=True)
     torch.cuda.synchronize()
-    s, h = s.cpu().numpy(), h.cpu().numpy()
-    ref = O.admm_ul_frame(fr.H, fr.y, C, 1.0, 5, fr.N0)
+    s, h, st = s.cpu().numpy(), h.cpu().numpy(), st.cpu().numpy()
+    ref = O.admm_ul_frame(fr.H, fr.y, C, 1.0, 5, n0_f32(fr.N0))
     err = rel_err(s, ref)
     say(f"    rel_err={err:.2e}")
     assert err <= mixed_bar(prec, factor)
-    check_hard(s, h, ref, 64)
+    check_hard(s, h, ref, 64, st, mixed_guard(prec, factor))
+
+
+def mixed_guard(prec, factor):
+    """Re-slice guard of a mixed mode (slicer units): wider than the FP32
+    path's for the split-FP16 inverse and the BF16 Gram."""
+    if factor == "f16x2":
+        return 2.0 ** -4
+    if prec == "bf16":
+        return 2.0 ** -8
+    return GUARD_T
 
 
 def mixed_bar(prec, factor):
@@ -403,11 +460,11 @@ def mixed_bar(prec, factor):
 def test_mixed_correlated_channel(prec):
     say(f"[gpu] mixed correlated prec={prec}")
     fr = inputs.uplink_frame(inputs.frame_seed(4, 1, 25), 23, 256, 32, 64, 25.0, corr=0.7)
-    s, h = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, 8, 1.0, 5, qam=64, prec=prec)
+    s, h, st = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, 8, 1.0, 5, qam=64, prec=prec, status=True)
     torch.cuda.synchronize()
-    ref = O.admm_ul_frame(fr.H, fr.y, 8, 1.0, 5, fr.N0)
+    ref = O.admm_ul_frame(fr.H, fr.y, 8, 1.0, 5, n0_f32(fr.N0))
     assert rel_err(s.cpu().numpy(), ref) <= 1e-3
-    check_hard(s.cpu().numpy(), h.cpu().numpy(), ref, 64)
+    check_hard(s.cpu().numpy(), h.cpu().numpy(), ref, 64, st.cpu().numpy(), mixed_guard(prec, "auto"))
 
 
 @pytest.mark.parametrize("prec,factor", [("fp32", None), ("fp16", "auto"), ("bf16", "fp32"), ("fp16", "f16x2"),
@@ -435,11 +492,72 @@ def test_power_of_two_scaling_bit_exact(prec, factor):
 def test_cfg4_mixed(prec, corr, factor):
     say(f"[gpu] cfg4 mixed prec={prec} corr={corr} factor={factor}")
     fr = inputs.uplink_frame(inputs.frame_seed(4, 2, 25), 9, 512, 64, 64, 25.0, corr=corr)
-    s, h = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, 8, 1.0, 5, qam=64, prec=prec, factor=factor)
+    s, h, st = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, 8, 1.0, 5, qam=64, prec=prec, factor=factor,
+                          status=True)
     torch.cuda.synchronize()
-    s, h = s.cpu().numpy(), h.cpu().numpy()
-    ref = O.admm_ul_frame(fr.H, fr.y, 8, 1.0, 5, fr.N0)
+    s, h, st = s.cpu().numpy(), h.cpu().numpy(), st.cpu().numpy()
+    ref = O.admm_ul_frame(fr.H, fr.y, 8, 1.0, 5, n0_f32(fr.N0))
     err = rel_err(s, ref)
     say(f"    rel_err={err:.2e}")
     assert err <= mixed_bar(prec, factor)
-    check_hard(s, h, ref, 64)
+    check_hard(s, h, ref, 64, st, mixed_guard(prec, factor))
+
+
+def test_output_buffers_validated_before_launch():
+    """Output buffers of the wrong shape, dtype or device, a short P_cluster
+    or a small workspace are refused on the host (ValueError / TypeError)
+    before any kernel is queued."""
+    say("[gpu] output buffer validation")
+    fr = inputs.uplink_frame(inputs.frame_seed(16, 0, 10), 8, 64, 8, 4, 10.0)
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    good_s = torch.empty((8, 1, 8), dtype=torch.complex64, device=DEV)
+    good_h = torch.empty((8, 1, 8), dtype=torch.uint8, device=DEV)
+    for bad in ((torch.empty((7, 1, 8), dtype=torch.complex64, device=DEV), good_h),
+                (good_s, torch.empty((8, 1, 4), dtype=torch.uint8, device=DEV)),
+                (good_s.to(torch.complex128), good_h),
+                (good_s, good_h, torch.empty(3, dtype=torch.int32, device=DEV)),
+                (good_s.cpu(), good_h)):
+        with pytest.raises((ValueError, TypeError)):
+            api.detect(H, y, fr.N0, 4, 1.0, 3, qam=4, out=bad)
+    with pytest.raises(ValueError):
+        api.detect(H, y, fr.N0, 4, 1.0, 3, qam=4, workspace=torch.empty(16, dtype=torch.uint8, device=DEV))
+    dl = inputs.downlink_frame(inputs.frame_seed(16, 1, 0), 8, 64, 8, 16)
+    with pytest.raises(ValueError):
+        api.precode(to_dev(dl.H), to_dev(dl.s), 8, 1.0, 3, P_cluster=torch.ones(4, device=DEV))
+    with pytest.raises(ValueError):
+        api.precode(to_dev(dl.H), to_dev(dl.s), 8, 1.0, 3,
+                    out=(torch.empty((8, 1, 32), dtype=torch.complex64, device=DEV),
+                         torch.empty((8, 1), dtype=torch.float32, device=DEV)))
+    # the good buffers still work
+    s, h = api.detect(H, y, fr.N0, 4, 1.0, 3, qam=4, out=(good_s, good_h))
+    torch.cuda.synchronize()
+    assert rel_err(s.cpu().numpy(), O.admm_ul_frame(fr.H, fr.y, 4, 1.0, 3, fr.N0)) <= 1e-5
+
+
+def test_reslice_recomputes_in_fp64():
+    """A guard-band subcarrier is recomputed in FP64: planted receive vectors
+    whose exact soft value sits on a decision threshold (y = H s with s a
+    midpoint between two points, ZF, so that s_hat = s exactly in exact
+    arithmetic) are flagged, and their soft outputs equal the FP64 oracle's
+    rounded to FP32 while the others keep the FP32 path's result."""
+    say("[gpu] re-slice of planted threshold values")
+    B, U, C, n_sc = 128, 16, 4, 24       # T = 60 brings these within 6e-5 of the threshold (slicer units)
+    fr = inputs.uplink_frame(inputs.frame_seed(17, 0, 20), n_sc, B, U, 16, 20.0)
+    Hs = fr.H.astype(np.complex128)
+    y = fr.y.copy()
+    mid = 2.0 / math.sqrt(10.0)           # 16-QAM threshold between the two upper levels
+    planted = [3, 11, 17]
+    for k in planted:
+        s = np.full(U, 0.3 + 0.3j)
+        s[5] = mid + 0.1j
+        y[k, 0] = (Hs[k] @ s).astype(np.complex64)
+    s_hat, h, st = api.detect(to_dev(fr.H), to_dev(y), 0.0, C, 1.0, 60, reg="zf", qam=16, status=True)
+    torch.cuda.synchronize()
+    s_hat, h, st = s_hat.cpu().numpy(), h.cpu().numpy(), st.cpu().numpy()
+    for k in planted:
+        assert st[k] & STATUS_RESLICED, k
+    ref = O.admm_ul_frame(fr.H, y, C, 1.0, 60, 0.0, reg="zf")
+    for k in np.flatnonzero(st & STATUS_RESLICED):
+        assert np.array_equal(s_hat[k], ref[k].astype(np.complex64)) or \
+            np.abs(s_hat[k] - ref[k]).max() <= 2.0 ** -23 * np.abs(ref[k]).max()
+    assert np.array_equal(h, O.slice_qam(ref, 16))

@@ -88,7 +88,8 @@ def test_budget_admission_serialises():
     for f in frames:
         n_sc, B, U = f["H"].shape
         al = lambda n: (n + 255) // 256 * 256  # noqa: E731
-        sizes.append(al(n_sc * B * U * 8) + al(n_sc * B * 8) + al(n_sc * U * 8) + al(n_sc * U))
+        ws = _native.lib().dbp_detect_workspace_bytes(n_sc, U, f["C"])     # FP64 re-slice workspace
+        sizes.append(al(ws) + al(n_sc * B * U * 8) + al(n_sc * B * 8) + al(n_sc * U * 8) + al(n_sc * U))
     budget = max(sizes)
     srv = api.Server(hbm_budget_bytes=budget, n_slots=4)
     outs = [out_bufs(f, True) for f in frames]
@@ -168,4 +169,24 @@ def test_channel_too_large_refused():
     with pytest.raises(_native.DbpError) as e:
         srv.load_channel(f["H"], f["C"], 1.0)
     assert e.value.code == 3
+    srv.close()
+
+
+def test_refused_configuration_fails_at_submit():
+    """A frame the library would refuse (mixed precision is built for U = 32
+    and 64 only; a regulariser code out of range) is refused by submit itself
+    with the library's error, so no caller waits on a frame that cannot run;
+    the server keeps serving valid frames afterwards."""
+    say("[gpu] serving refused configuration")
+    f = make_frames(True)[1]                      # B = 128, U = 16, C = 8
+    srv = api.Server(hbm_budget_bytes=1 << 30, n_slots=2)
+    s, h = out_bufs(f, True)
+    with pytest.raises(_native.DbpError) as e:
+        srv.submit(f["H"], f["y"], s, h, f["C"], 5, 1.0, f["N0"], qam=16, prec="fp16")
+    assert e.value.code == 2
+    with pytest.raises(KeyError):
+        srv.submit(f["H"], f["y"], s, h, f["C"], 5, 1.0, f["N0"], qam=16, reg="lasso")
+    t = srv.submit(f["H"], f["y"], s, h, f["C"], 5, 1.0, f["N0"], qam=16)
+    lat, _ = srv.wait(t)
+    assert lat > 0
     srv.close()

@@ -499,6 +499,21 @@ def test_box_vertex_certificate_equals_ml():
     assert hits >= 10
 
 
+def _power_scale_is_tight(x, C, P, xs, beta):
+    """The common gain of the per-cluster budget reading is the LARGEST gain in
+    (0, 1] under which every cluster meets its budget: with beta < 1 the
+    cluster that sets it meets its budget with equality, and beta = 1 exactly
+    when every cluster is within budget unscaled."""
+    S = len(x) // C
+    e = [float(np.real(np.vdot(x[c * S:(c + 1) * S], x[c * S:(c + 1) * S]))) for c in range(C)]
+    es = [float(np.real(np.vdot(xs[c * S:(c + 1) * S], xs[c * S:(c + 1) * S]))) for c in range(C)]
+    if not all(es[c] <= P[c] * (1 + 1e-12) for c in range(C)):
+        return False
+    if all(e[c] <= P[c] for c in range(C)):
+        return beta == 1.0
+    return beta < 1.0 and min(abs(es[c] - P[c]) / P[c] for c in range(C)) <= 1e-12
+
+
 def test_power_scale_meets_budgets():
     rng = np.random.default_rng(75)
     B, U, C = 64, 8, 8
@@ -511,3 +526,37 @@ def test_power_scale_meets_budgets():
         seg = xs[c * 8:(c + 1) * 8]
         assert np.real(np.vdot(seg, seg)) <= P[c] * (1 + 1e-12)
     assert np.abs(Hu.T @ xs - beta * (Hu.T @ x)).max() < 1e-12
+
+
+@pytest.mark.parametrize("budget", [0.02, 0.2, 1.0, 50.0])
+def test_power_scale_is_tight(budget):
+    # beta is pinned by two facts independent of its formula: no cluster may
+    # exceed its budget, and no larger common gain would do.  Unequal budgets
+    # make a different cluster bind than the one with the most energy.
+    rng = np.random.default_rng(76)
+    B, U, C = 64, 8, 8
+    for trial in range(5):
+        Hu, s = cn(rng, B, U), cn(rng, U)
+        x = O.admm_dl(Hu, s, C, 1.0, 5)
+        S = B // C
+        emax = max(float(np.real(np.vdot(x[c * S:(c + 1) * S], x[c * S:(c + 1) * S]))) for c in range(C))
+        P = [budget * emax * (1.0 + 0.5 * rng.random()) for _ in range(C)]
+        xs, beta = O.power_scale(x, C, P)
+        assert _power_scale_is_tight(x, C, P, xs, beta)
+
+
+def test_power_scale_tightness_check_rejects_a_gain_without_square_root():
+    # the tightness check above must catch the plausible mistake of a gain
+    # min(1, P_c / ||x_c||^2) (energy scaled to P^2/e < P when the budget binds)
+    rng = np.random.default_rng(77)
+    B, U, C = 64, 8, 8
+    Hu, s = cn(rng, B, U), cn(rng, U)
+    x = O.admm_dl(Hu, s, C, 1.0, 5)
+    S = B // C
+    e = [float(np.real(np.vdot(x[c * S:(c + 1) * S], x[c * S:(c + 1) * S]))) for c in range(C)]
+    P = [0.25 * min(e)] * C
+    bad = min(1.0, min(P[c] / e[c] for c in range(C)))
+    assert bad < 1.0
+    assert not _power_scale_is_tight(x, C, P, bad * x, bad)
+    xs, beta = O.power_scale(x, C, P)
+    assert _power_scale_is_tight(x, C, P, xs, beta)
