@@ -139,6 +139,24 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard,
                     float rho, float gamma, float N0, float Es,
                     int reg, int qam, int prec, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * dbp_detect_admm without the workspace arguments.  The FP64 re-slice takes
+ * its workspace from a static device array of dbp_noalloc_scratch_bytes()
+ * bytes (16 MiB) that each GPU the library runs on holds until the process
+ * ends; the call allocates nothing.  Every call on one GPU shares that GPU's
+ * array, so calls that overlap in time on one GPU race; nothing in it needs
+ * clearing between calls.  Returns DBP_ERR_UNSUPPORTED when hard decisions
+ * are requested and the flags of n_sc subcarriers (4 n_sc bytes, none when
+ * `status` is given) plus one FP64 block of C U^2 complex values (16 C U^2
+ * bytes) exceed the array.  Arguments, outputs and errors otherwise as
+ * dbp_detect_admm; the results are bit-identical to it. */
+size_t dbp_noalloc_scratch_bytes(void);
+int dbp_detect_admm_noalloc(const void* H, const void* y, void* s_hat, uint8_t* hard,
+                            int32_t* status, int n_sc, int n_sym, int B, int U, int C, int T,
+                            float rho, float gamma, float N0, float Es,
+                            int reg, int qam, int prec, void* stream);
+
 /* Resident factorisation for a static channel.  Algorithm 1's preprocessing
  * (Section III-B, the U x U form of step E1: B_c = H_c^H H_c + rho I_U and its
  * inverse) depends on H and rho only; the paper precomputes B_c^{-1} once per

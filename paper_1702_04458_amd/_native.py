@@ -22,6 +22,9 @@ SIGNATURES = {
     "dbp_detect_workspace_bytes": (ctypes.c_size_t, [_i, _i, _i]),
     "dbp_detect_admm": (_i, [_vp, _vp, _vp, _u8p, _vp, _vp, ctypes.c_size_t, _i, _i, _i, _i, _i, _i,
                              _f, _f, _f, _f, _i, _i, _i, _vp]),
+    "dbp_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "dbp_detect_admm_noalloc": (_i, [_vp, _vp, _vp, _u8p, _vp, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i, _i,
+                                     _vp]),
     "dbp_factor_bytes": (ctypes.c_size_t, [_i, _i, _i]),
     "dbp_factor_admm": (_i, [_vp, _vp, _i, _i, _i, _i, _f, _i, _vp]),
     "dbp_detect_admm_factored": (_i, [_vp, _vp, _vp, _vp, _u8p, _vp, _vp, ctypes.c_size_t, _i, _i, _i, _i, _i, _i,

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdbp.so")
 
-SOURCES = ["dbp_kernels.hip", "dbp_fix64.hip", "dbp_capi.cpp", "dbp_serve.cpp"]
+SOURCES = ["dbp_kernels.hip", "dbp_fix64.hip", "dbp_noalloc.hip", "dbp_capi.cpp", "dbp_serve.cpp"]
 OBJDIR = os.path.join(HERE, "_build")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

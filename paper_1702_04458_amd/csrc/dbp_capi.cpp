@@ -274,6 +274,12 @@ size_t dbp_detect_workspace_bytes(int n_sc, int U, int C) {
 
 namespace dbp {
 
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+size_t reslice_bytes_min(int n_sc, int U, int C, bool with_status) {
+  return (with_status ? 0 : flags_region(n_sc)) + fix64_slot_bytes(U, C);
+}
+
 // dbp_detect_admm with the re-slice workspace bounded by max_slots FP64 slots
 // (the entry point without workspace argument passes its static scratch).
 int detect_admm_impl(const char* who, const void* H, const void* y, void* s_hat, uint8_t* hard, int32_t* status,

@@ -81,6 +81,15 @@ hipError_t launch_scan_nonfinite(const float* x, size_t floats_per_sc, int n_sc,
                                  hipStream_t st);
 hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st);
 
+// Library-internal pieces of the C entry points (dbp_capi.cpp).
+int set_error(int code, const char* msg);   // records msg for dbp_last_error, returns code
+// smallest re-slice workspace of a call with hard decisions: the flag region
+// (none when the caller passes a status array) and one FP64 slot
+size_t reslice_bytes_min(int n_sc, int U, int C, bool with_status);
+int detect_admm_impl(const char* who, const void* H, const void* y, void* s_hat, uint8_t* hard, int32_t* status,
+                     void* workspace, size_t workspace_bytes, int max_slots, int n_sc, int n_sym, int B, int U, int C,
+                     int T, float rho, float gamma, float N0, float Es, int reg, int qam, int prec, void* stream);
+
 // FP64 recomputation of the flagged subcarriers (Algorithm 1 or 2), n_slots workgroups
 hipError_t launch_admm_ul_fix64(const FixArgs& f, hipStream_t st);
 hipError_t launch_dcg_ul_fix64(const FixArgs& f, hipStream_t st);
