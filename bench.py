@@ -2,9 +2,10 @@
 
 A step is one pass of the whole detection path -- load H and y, per-cluster Gram
 and regularised inverse, T decentralized ADMM iterations with their consensus
-sums, slicing -- over one launch of 8 frames x 1200 subcarriers (9600
+sums, slicing -- over one launch of 32 frames x 1200 subcarriers (38,400
 independent subcarrier-vectors, each with its own channel; the paper's GPU
-batches 1200 x 7 vectors).  Single-frame (1200-subcarrier) launch latency is
+batches 1200 x 7 vectors), followed by the FP64 re-slice pass over the
+subcarriers it flagged.  Single-frame (1200-subcarrier) launch latency is
 reported beside it, and the serving run reports latency under load.  The default workload is
 decentralized ADMM uplink detection (Algorithm 1) at B=256 antennas, U=32
 users, C=8 clusters (S=32), 64-QAM, 25 dB, rho=1, T=5, N_sym=1.  Frames are
@@ -116,6 +117,31 @@ def _ws(api, n_sc, U, C):
     return _WS[key]
 
 
+def received_over(H, n_frames, qam, snr_db, seed):
+    """Received frames y = H s + n over one static channel H [n_sc, B, U]
+    (fresh symbols and noise per frame, same recipe as make_frames): the
+    workload of the resident (static-channel) forms."""
+    import torch
+
+    from paper_1702_04458_amd import inputs
+
+    n_sc, B, U = H.shape
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    L = inputs.qam_side(qam)
+    kappa = inputs.qam_kappa(qam)
+    N0 = U / (10.0 ** (snr_db / 10.0))
+    ys = []
+    for _ in range(n_frames):
+        iI = torch.randint(0, L, (n_sc, 1, U), generator=g, device="cuda")
+        iQ = torch.randint(0, L, (n_sc, 1, U), generator=g, device="cuda")
+        s = torch.complex((2 * iI - (L - 1)).float(), (2 * iQ - (L - 1)).float()) / kappa
+        n = torch.complex(torch.randn((n_sc, 1, B), generator=g, device="cuda"),
+                          torch.randn((n_sc, 1, B), generator=g, device="cuda")) * math.sqrt(N0 / 2.0)
+        ys.append((torch.matmul(H, s.transpose(1, 2).contiguous()).transpose(1, 2) + n).contiguous())
+    return ys
+
+
 def run_step(api, frame, algo, C, T, N0, qam, out, prec="fp32", factor=None, resident=None):
     """One detection call over one step's subcarriers (the FP32 kernel, then
     the FP64 re-slice pass over its flags).  ``resident`` = (form, channel
@@ -133,6 +159,15 @@ def run_step(api, frame, algo, C, T, N0, qam, out, prec="fp32", factor=None, res
     else:
         api.detect(frame[0], frame[1], N0, C, 1.0, T, algo=algo, qam=qam, out=out, prec=prec, factor=factor,
                    workspace=_ws(api, n_sc, U, C))
+
+
+def _blas_threads():
+    """BLAS / OpenMP threads numpy actually uses in this process (threadpoolctl)."""
+    try:
+        from threadpoolctl import threadpool_info
+        return max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:
+        return None
 
 
 def _oracle_worker(args):
@@ -159,21 +194,59 @@ def _oracle_worker(args):
         busy += time.perf_counter() - t1
         done += 4
         k += 1
-    return done, busy
+    return done, busy, _blas_threads()
+
+
+def host_info():
+    """Logical CPUs of the host, CPUs this process may run on, CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count() or 1, "usable_cpus": usable, "cpu_model": model}
+
+
+# The GPU host gives one GPU's job a share of 16 CPU cores, whatever the
+# machine's core count: the process pools below use at most that many.
+CPU_SHARE = 16
+
+
+def _single_thread_pool(workers):
+    """A spawn pool whose workers start with one BLAS / OpenMP thread each (the
+    variables are set before the workers import numpy)."""
+    import multiprocessing as mp
+
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        pool = mp.get_context("spawn").Pool(workers)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return pool
 
 
 def cpu_baseline(algo, B, U, C, qam, snr, T, budget_s=12.0):
     """FP64 oracle on the host cores, subcarrier-parallel over worker processes
-    (one BLAS thread each); input generation is inside the budget but small."""
-    import multiprocessing as mp
-
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
-    os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
-    os.environ.setdefault("MKL_NUM_THREADS", "1")
-    workers = max(1, min(os.cpu_count() or 1, 16))
-    ctx = mp.get_context("spawn")
+    (one BLAS thread each, CPU_SHARE processes at most); input generation is
+    excluded from the measured time."""
+    host = host_info()
+    workers = max(1, min(host["usable_cpus"], CPU_SHARE))
     t0 = time.perf_counter()
-    with ctx.Pool(workers) as pool:
+    with _single_thread_pool(workers) as pool:
         res = pool.map(_oracle_worker, [(algo, B, U, C, qam, snr, T, 5000 + 97 * i, budget_s) for i in range(workers)])
     wall = time.perf_counter() - t0
     vecs = sum(r[0] for r in res)
@@ -181,28 +254,30 @@ def cpu_baseline(algo, B, U, C, qam, snr, T, budget_s=12.0):
     # workers' own rates (oracle time only, input generation excluded)
     value = sum(r[0] / r[1] for r in res)
     out = {"value": value, "unit": "vectors/s", "cores": workers, "kind": "oracle",
-           "per_core_value": value / workers,
+           "per_core_value": value / workers, "threads_per_process": max(r[2] or 1 for r in res),
+           "host_nproc": host["nproc"], "host_usable_cpus": host["usable_cpus"], "cpu_model": host["cpu_model"],
            "sample": f"{vecs} subcarrier-vectors of the same shape (fresh seeded frames), "
-                     f"{workers} worker processes x {budget_s:.0f} s, FP64 numpy oracle, input generation "
-                     f"excluded; wall {wall:.1f} s"}
+                     f"{workers} worker processes (the {CPU_SHARE}-core CPU share of one GPU) x {budget_s:.0f} s, "
+                     f"FP64 numpy oracle, input generation excluded; wall {wall:.1f} s"}
     if algo == "admm":
-        out["vectorized"] = cpu_vectorized_admm(B, U, C, qam, snr, T)
+        out["vectorized"] = cpu_vectorized_admm(B, U, C, qam, snr, T, workers)
     return out
 
 
-def cpu_vectorized_admm(B, U, C, qam, snr, T, n_sc=1200, reps=3):
-    """A batched numpy form of Algorithm 1 (U x U branch, MMSE, rho = 1) over a
-    whole frame in FP64, so that the CPU figure is not limited by the oracle's
-    per-vector loops: batched inverses of all B_c, then T iterations as batched
-    matrix-vector products.  Measurement aid only; checked against the oracle
-    on a few subcarriers before timing."""
+def _vectorized_worker(args):
+    """Batched numpy form of Algorithm 1 (U x U branch, MMSE, rho = 1) over a
+    whole frame in FP64: batched inverses of all B_c, then T iterations as
+    batched matrix-vector products.  Measurement aid only (not the oracle);
+    checked against the oracle on a few subcarriers before timing.  Returns
+    (vectors, seconds, BLAS threads)."""
     import numpy as np
 
     from oracle import dbp_oracle as O
     from paper_1702_04458_amd import inputs
 
+    B, U, C, qam, snr, T, n_sc, reps, seed = args
     S = B // C
-    fr = inputs.uplink_frame(777, n_sc, B, U, qam, snr)
+    fr = inputs.uplink_frame(seed, n_sc, B, U, qam, snr)
     H = fr.H.astype(np.complex128).reshape(n_sc, C, S, U)
     y = fr.y[:, 0].astype(np.complex128).reshape(n_sc, C, S)
     den = fr.N0 + C            # N0 / (rho Es) + C with rho = Es = 1
@@ -225,9 +300,21 @@ def cpu_vectorized_admm(B, U, C, qam, snr, T, n_sc=1200, reps=3):
     t0 = time.perf_counter()
     for _ in range(reps):
         run()
-    dt = (time.perf_counter() - t0) / reps
-    return {"value": round(n_sc / dt, 1), "unit": "vectors/s", "threads": "numpy default (BLAS threads)",
-            "sample": f"{n_sc} subcarriers x {reps} repetitions, FP64, batched numpy (not the oracle)"}
+    return n_sc * reps, time.perf_counter() - t0, _blas_threads()
+
+
+def cpu_vectorized_admm(B, U, C, qam, snr, T, workers, n_sc=1200, reps=3):
+    """The batched form over `workers` processes with one BLAS thread each (its
+    small batched matrices gain nothing from threads inside one process), each
+    on its own frame; the rate sums the workers' own rates."""
+    with _single_thread_pool(workers) as pool:
+        res = pool.map(_vectorized_worker, [(B, U, C, qam, snr, T, n_sc, reps, 777 + i) for i in range(workers)])
+    value = sum(r[0] / r[1] for r in res)
+    return {"value": round(value, 1), "unit": "vectors/s", "processes": workers,
+            "threads_per_process": max(r[2] or 1 for r in res),
+            "per_process_value": round(value / workers, 1),
+            "sample": f"{workers} processes x {n_sc} subcarriers x {reps} repetitions, FP64, batched numpy "
+                      f"(not the oracle)"}
 
 
 def serve_bench(loads=(0.25, 0.5, 0.7, 0.85, 0.95), frames_per_load=300, pool=40, n_slots=8,
@@ -411,14 +498,17 @@ def time_steps(api, frames, algo, C, T, N0, qam, out, prec, factor, steps, warmu
     return start_all.elapsed_time(end_all) / steps, per
 
 
-def static_channel_bench(api, frames, C, T, N0, qam, out, steps):
+def static_channel_bench(api, frames, C, T, N0, qam, snr_db, out, steps):
     """Static channel over the coherence interval: B_c^{-1} is formed once per
     channel (dbp_factor_admm) and every received frame runs only Algorithm 1's
     iterations against it (dbp_detect_admm_factored).  Times the factorisation
-    and the factored detection of one step's subcarriers."""
+    and the factored detection of one step's subcarriers; the received frames
+    are generated over that one channel."""
     import torch
 
     H0 = frames[0][0]
+    ys = received_over(H0, 4, qam, snr_db, seed=4321)
+    frames = [(H0, y) for y in ys]
     n_sc = H0.shape[0]
     fac = api.factor(H0, C, 1.0)
     torch.cuda.synchronize()
@@ -625,7 +715,9 @@ def main():
                torch.empty((n_sc, 1, U), dtype=torch.uint8, device="cuda"))
     resident = None
     if args.form != "oneshot":
+        # frames received over one static channel (the channel whose factors are resident)
         H0 = frames[0][0]
+        frames = [(H0, y) for y in received_over(H0, len(frames), qam, snr, seed=4321)]
         fac = api.factor(H0, C, 1.0)
         chan = H0 if args.form == "resident" else api.pack_channel_h16(H0, C)
         resident = (args.form, chan, fac, B, U)
@@ -693,7 +785,7 @@ def main():
 
     static = None
     if algo == "admm" and not args.no_compare:
-        static = static_channel_bench(api, frames, C, T, N0, qam, out, max(10, args.steps // 2))
+        static = static_channel_bench(api, frames, C, T, N0, qam, snr, out, max(10, args.steps // 2))
         static["served_vs_fp32_batched"] = served_ratios(static, ms_per_step * 1e3)
         print(f"[bench] static channel: factor {static['factor_us_per_step']} us, factored detect "
               f"{static['detect_factored_us_per_step']} us/step, h16 detect {static['detect_h16_us_per_step']} us/step",

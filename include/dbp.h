@@ -80,9 +80,10 @@ extern "C" {
  * a decision threshold could be sliced differently from an exact evaluation.
  * Every detection call that returns hard decisions (hard != NULL) therefore
  * flags each subcarrier that has a soft value within a guard of a threshold
- * -- 2^-12 in the slicer's units t = (kappa x + L) / 2 (thresholds at the
- * integers 1 .. L-1), about 35x the largest FP32 error measured against an
- * FP64 evaluation; 2^-8 with the BF16 split Gram and 2^-4 with the split-FP16
+ * -- in the slicer's units t = (kappa x + L) / 2 (thresholds at the
+ * integers 1 .. L-1), 2^-14 for U <= 16, 2^-13 for U = 32 and 2^-12 for
+ * U = 64, at least 7.5x the largest FP32 error measured against an FP64
+ * evaluation at each U; 2^-8 with the BF16 split Gram and 2^-4 with the split-FP16
  * inverse -- and recomputes the flagged subcarriers entirely in FP64 on the
  * GPU (Gram, regularised inverse or CG, every iteration), overwriting their
  * soft outputs (FP64 result rounded to FP32) and their hard decisions (taken
@@ -171,7 +172,7 @@ int dbp_detect_admm_noalloc(const void* H, const void* y, void* s_hat, uint8_t* 
  *   rho    must be the value the factors were made with (not checked).
  * Other arguments (hard decisions, status and workspace included),
  * requirements and errors are those of dbp_detect_admm; the FP64 re-slice
- * recomputes flagged subcarriers from H (guard 2^-12, for FP32 factors).
+ * recomputes flagged subcarriers from H (the FP32 guards, for FP32 factors).
  * The result equals dbp_detect_admm up to the rounding of H_c^H y_c, which
  * the factored path forms on the vector units. */
 size_t dbp_factor_bytes(int n_sc, int U, int C);

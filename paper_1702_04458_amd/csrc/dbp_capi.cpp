@@ -186,14 +186,17 @@ hipError_t launch_preprocessing(const dbp::UlArgs& a, int U, int C, int gram_pre
 }
 
 // Re-slice guard (slicer units t = (kappa x + L) / 2, thresholds at the
-// integers) of a preprocessing mode: about 35x (FP32 Gram and inverse, FP16
-// split Gram) the largest FP32 soft-value error measured against the FP64
-// oracle at any configuration (7e-6 at B = 512, U = 64), and correspondingly
-// wider for the BF16 split Gram and the split-FP16 inverse.
-float reslice_guard(int gram_prec, int inv) {
+// integers) of a preprocessing mode and user count.  The FP32 soft-value
+// error against the FP64 oracle grows with U (the conditioning of the U x U
+// regularised Grams): largest measured errors 2.4e-6 (U <= 16), 8.1e-6
+// (U = 32) and 1.6e-5 (U = 64), so the guard is 2^-14, 2^-13 and 2^-12
+// (at least 7.5x the measured error) for the FP32 Gram and inverse and the
+// FP16 split Gram; the BF16 split Gram and the split-FP16 inverse (errors up
+// to 4e-3) take 2^-8 and 2^-4.
+float reslice_guard(int gram_prec, int inv, int U) {
   if (inv == 2) return 0x1p-4f;
   if (gram_prec == DBP_PREC_MIXED_BF16) return 0x1p-8f;
-  return 0x1p-12f;
+  return U <= 16 ? 0x1p-14f : (U == 32 ? 0x1p-13f : 0x1p-12f);
 }
 
 size_t flags_region(int n_sc) { return ((size_t)n_sc * 4 + 255) & ~size_t(255); }
@@ -299,7 +302,7 @@ int detect_admm_impl(const char* who, const void* H, const void* y, void* s_hat,
   a.shat = static_cast<dbp::c32*>(s_hat);
   a.hard = hard;
   dbp::FixArgs f;
-  st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(gram_prec, inv),
+  st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(gram_prec, inv, U),
                      dbp::fix64_slot_bytes(U, C), max_slots < full_slots(n_sc) ? max_slots : full_slots(n_sc));
   if (st) return st;
   const hipStream_t hs = static_cast<hipStream_t>(stream);
@@ -368,7 +371,7 @@ int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, 
   a.hard = hard;
   a.fac = const_cast<dbp::c32*>(static_cast<const dbp::c32*>(factors));
   dbp::FixArgs f;
-  st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(DBP_PREC_FP32, 0),
+  st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(DBP_PREC_FP32, 0, U),
                      dbp::fix64_slot_bytes(U, C), full_slots(n_sc));
   if (st) return st;
   const Plan pl = make_plan(U, C);
@@ -465,7 +468,7 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int3
     return fail(DBP_ERR_INVALID, "%s: workspace of %zu bytes, %zu needed", who, workspace_bytes,
                 dbp_detect_workspace_bytes(n_sc, U, C));
   dbp::FixArgs f;
-  st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(DBP_PREC_FP32, 0), 0,
+  st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(DBP_PREC_FP32, 0, U), 0,
                      full_slots(n_sc));
   if (st) return st;
   const hipStream_t hs = static_cast<hipStream_t>(stream);

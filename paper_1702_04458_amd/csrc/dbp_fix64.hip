@@ -13,9 +13,9 @@
 // everywhere except within about 1e-14 of a threshold.
 //
 // Work split: workgroup g of the n_slots workgroups owns subcarriers
-// k = g, g + n_slots, g + 2 n_slots, ...; it reads their flags 256 at a time,
+// k = g, g + n_slots, g + 2 n_slots, ...; it reads their flags 1024 at a time,
 // lists the flagged ones in LDS and recomputes them one after another with all
-// 256 threads.  The ADMM pass keeps the C regularised inverses of the current
+// 1024 threads.  The ADMM pass keeps the C regularised inverses of the current
 // subcarrier (C U^2 complex FP64) in the workgroup's slot of the workspace;
 // every entry of a slot is written before it is read, so the workspace needs
 // no clearing.
@@ -27,7 +27,7 @@
 namespace dbp {
 namespace {
 
-constexpr int kFixThreads = 256;
+constexpr int kFixThreads = 1024;
 
 struct d2 {
   double re, im;
@@ -87,64 +87,131 @@ __device__ __forceinline__ void write_out(const FixArgs& f, int k, int n, int u,
 
 }  // namespace
 
-// Algorithm 1 in FP64 for the flagged subcarriers.  f.inv_den holds the
-// denominator N0 / (rho Es) + C itself (FP64 divides by it).
+// Algorithm 1 in FP64 for the flagged subcarriers, 1024 threads per
+// workgroup.  The regularised Grams are formed and inverted in registers:
+// thread t owns a TI x TI tile of one cluster's U x U matrix (TI = 1, 2, 4, 4
+// for U = 8, 16, 32, 64), CG = 1024 / (U / TI)^2 clusters at a time (16, or 4
+// at U = 64).  Gram: each thread accumulates its tile over the S rows of H_c
+// straight from memory (the lanes of a wave that share tile rows read the
+// same addresses).  Inverse: Gauss-Jordan elimination without pivoting (HPD)
+// on all CG clusters at once; per pivot p the owners of row p and column p
+// publish them through LDS and every thread updates its tile.  The finished
+// inverses go to the workgroup's slot of the workspace, where the iterations
+// read them.  f.inv_den holds the denominator N0 / (rho Es) + C itself (FP64
+// divides by it).
+template <int U>
 __global__ void __launch_bounds__(kFixThreads) admm_ul_fix64(FixArgs f) {
+  constexpr int TI = (U >= 32) ? 4 : U / 8;
+  constexpr int NT = U / TI;           // tiles per matrix side
+  constexpr int T2 = NT * NT;          // tiles per cluster
+  constexpr int CG = kFixThreads / T2; // clusters per group
+  constexpr int UU = U * U;
   extern __shared__ d2 fsm[];
-  const int U = f.U, C = f.C, S = f.S, CU = C * U, UU = U * U, n_ent = C * UU;
+  const int C = f.C, S = f.S, CU = C * U;
+  // LDS: the iteration vectors, overlaid during the inversion by the pivot
+  // rows and columns of the group's clusters
   d2* Y = fsm;            // y_c^reg (first H_c^H y_c)
-  d2* Z = Y + CU;         // z_c (Gauss-Jordan: pivot columns)
-  d2* LM = Z + CU;        // lambda_c (Gauss-Jordan: pivot rows)
+  d2* Z = Y + CU;         // z_c
+  d2* LM = Z + CU;        // lambda_c
   d2* Sv = LM + CU;       // s
-  int* list = reinterpret_cast<int*>(Sv + U);
+  d2* colp = fsm;         // [CG][U] pivot columns
+  d2* rowp = fsm + CG * U;   // [CG][U] pivot rows
+  int* list = reinterpret_cast<int*>(fsm + (3 * CU + U > 2 * CG * U ? 3 * CU + U : 2 * CG * U));
   int* cnt = list + kFixThreads;
-  d2* M = static_cast<d2*>(f.ws) + (size_t)blockIdx.x * n_ent;   // [C][U][U]
+  d2* Mslot = static_cast<d2*>(f.ws) + (size_t)blockIdx.x * C * UU;   // [C][U][U]
   const int tid = threadIdx.x;
+  const int cl = tid / T2, tt = tid % T2, i0 = (tt / NT) * TI, j0 = (tt % NT) * TI;
 
   for (long r = 0; (long)blockIdx.x + r * kFixThreads * (long)gridDim.x < f.n_sc; ++r) {
     const int nl = collect_round(f, r, list, cnt);
     for (int q = 0; q < nl; ++q) {
       const int k = list[q];
       const c32* Hk = f.H + (size_t)k * f.B * U;
-      // B_c = H_c^H H_c + rho I
-      for (int e = tid; e < n_ent; e += kFixThreads) {
-        const int c = e / UU, rr = e - c * UU, i = rr / U, j = rr - i * U;
-        const c32* Hc = Hk + (size_t)c * S * U;
-        d2 acc = dzero();
-        for (int s = 0; s < S; ++s) dmacc(acc, dld(Hc + (size_t)s * U + i), dld(Hc + (size_t)s * U + j));
-        if (i == j) acc.re += f.rho;
-        M[e] = acc;
-      }
-      __syncthreads();
-      // B_c^{-1} by Gauss-Jordan elimination without pivoting (HPD), all
-      // clusters at once; the pivot d is the real positive Schur complement
-      for (int p = 0; p < U; ++p) {
-        for (int e = tid; e < CU; e += kFixThreads) {
-          const int c = e / U, i = e - c * U;
-          Z[e] = M[(size_t)c * UU + i * U + p];
-          LM[e] = M[(size_t)c * UU + p * U + i];
-        }
-        __syncthreads();
-        for (int e = tid; e < n_ent; e += kFixThreads) {
-          const int c = e / UU, rr = e - c * UU, i = rr / U, j = rr - i * U;
-          const double inv = 1.0 / LM[c * U + p].re;
-          const d2 ci = Z[c * U + i], rj = LM[c * U + j];
-          d2 v;
-          if (i != p && j != p) {
-            v = M[e];
-            v.re -= (ci.re * rj.re - ci.im * rj.im) * inv;
-            v.im -= (ci.re * rj.im + ci.im * rj.re) * inv;
-          } else if (i == p && j != p) {
-            v = d2{rj.re * inv, rj.im * inv};
-          } else if (i != p) {
-            v = d2{-ci.re * inv, -ci.im * inv};
-          } else {
-            v = d2{inv, 0.0};
+      for (int cb = 0; cb < C; cb += CG) {
+        const int c = cb + cl;
+        const bool own = c < C;            // this thread's cluster exists
+        d2 M[TI][TI];
+        // B_c = H_c^H H_c + rho I, tile rows i0.., columns j0..
+#pragma unroll
+        for (int a = 0; a < TI; ++a)
+#pragma unroll
+          for (int b = 0; b < TI; ++b) M[a][b] = dzero();
+        if (own) {
+          const c32* Hc = Hk + (size_t)c * S * U;
+          for (int s = 0; s < S; ++s) {
+            const c32* row = Hc + (size_t)s * U;
+            d2 hj[TI];
+#pragma unroll
+            for (int b = 0; b < TI; ++b) hj[b] = dld(row + j0 + b);
+#pragma unroll
+            for (int a = 0; a < TI; ++a) {
+              const d2 hi = dld(row + i0 + a);
+#pragma unroll
+              for (int b = 0; b < TI; ++b) dmacc(M[a][b], hi, hj[b]);
+            }
           }
-          M[e] = v;
+#pragma unroll
+          for (int a = 0; a < TI; ++a)
+#pragma unroll
+            for (int b = 0; b < TI; ++b)
+              if (i0 + a == j0 + b) M[a][b].re += f.rho;
         }
-        __syncthreads();
+        // Gauss-Jordan: after pivot p, M[p][p] = 1/d, M[p][j] = B[p][j]/d,
+        // M[i][p] = -B[i][p]/d and M[i][j] -= B[i][p] B[p][j]/d elsewhere
+        for (int p = 0; p < U; ++p) {
+          __syncthreads();   // the previous step's readers are done with colp / rowp
+          if (own && j0 <= p && p < j0 + TI) {
+#pragma unroll
+            for (int a = 0; a < TI; ++a)
+#pragma unroll
+              for (int b = 0; b < TI; ++b)
+                if (j0 + b == p) colp[cl * U + i0 + a] = M[a][b];
+          }
+          if (own && i0 <= p && p < i0 + TI) {
+#pragma unroll
+            for (int a = 0; a < TI; ++a)
+#pragma unroll
+              for (int b = 0; b < TI; ++b)
+                if (i0 + a == p) rowp[cl * U + j0 + b] = M[a][b];
+          }
+          __syncthreads();
+          if (own) {
+            const double inv = 1.0 / rowp[cl * U + p].re;
+            d2 rj[TI];
+#pragma unroll
+            for (int b = 0; b < TI; ++b) rj[b] = rowp[cl * U + j0 + b];
+#pragma unroll
+            for (int a = 0; a < TI; ++a) {
+              const d2 ci = colp[cl * U + i0 + a];
+              // the multiplier B[i][p] / d, once per row
+              const d2 m = d2{ci.re * inv, ci.im * inv};
+#pragma unroll
+              for (int b = 0; b < TI; ++b) {
+                const bool ip = (i0 + a == p), jp = (j0 + b == p);
+                d2 v = M[a][b];
+                if (!ip && !jp) {
+                  v.re -= m.re * rj[b].re - m.im * rj[b].im;
+                  v.im -= m.re * rj[b].im + m.im * rj[b].re;
+                } else if (ip && !jp) {
+                  v = d2{rj[b].re * inv, rj[b].im * inv};
+                } else if (!ip) {
+                  v = d2{-m.re, -m.im};
+                } else {
+                  v = d2{inv, 0.0};
+                }
+                M[a][b] = v;
+              }
+            }
+          }
+        }
+        if (own) {
+#pragma unroll
+          for (int a = 0; a < TI; ++a)
+#pragma unroll
+            for (int b = 0; b < TI; ++b) Mslot[(size_t)c * UU + (i0 + a) * U + j0 + b] = M[a][b];
+        }
       }
+      __syncthreads();   // inverses in the slot; the LDS overlay is free again
       for (int n = 0; n < f.n_sym; ++n) {
         const c32* yk = f.y + ((size_t)k * f.n_sym + n) * f.B;
         // H_c^H y_c
@@ -159,7 +226,7 @@ __global__ void __launch_bounds__(kFixThreads) admm_ul_fix64(FixArgs f) {
         // y_c^reg = B_c^{-1} H_c^H y_c
         for (int e = tid; e < CU; e += kFixThreads) {
           const int c = e / U, i = e - c * U;
-          const d2* Mi = M + (size_t)c * UU + i * U;
+          const d2* Mi = Mslot + (size_t)c * UU + i * U;
           d2 acc = dzero();
           for (int j = 0; j < U; ++j) dmac(acc, Mi[j], Z[c * U + j]);
           Y[e] = acc;
@@ -190,7 +257,7 @@ __global__ void __launch_bounds__(kFixThreads) admm_ul_fix64(FixArgs f) {
           // z_c = y_c^reg + rho B_c^{-1} (s - lambda_c)
           for (int e = tid; e < CU; e += kFixThreads) {
             const int c = e / U, i = e - c * U;
-            const d2* Mi = M + (size_t)c * UU + i * U;
+            const d2* Mi = Mslot + (size_t)c * UU + i * U;
             d2 acc = dzero();
             for (int j = 0; j < U; ++j)
               dmac(acc, Mi[j], d2{Sv[j].re - LM[c * U + j].re, Sv[j].im - LM[c * U + j].im});
@@ -322,8 +389,19 @@ __global__ void __launch_bounds__(kFixThreads) dcg_ul_fix64(FixArgs f) {
 size_t fix64_slot_bytes(int U, int C) { return (size_t)C * U * U * sizeof(d2); }
 
 hipError_t launch_admm_ul_fix64(const FixArgs& f, hipStream_t st) {
-  const size_t lds = (size_t)(3 * f.C * f.U + f.U) * sizeof(d2) + (kFixThreads + 4) * sizeof(int);
-  hipLaunchKernelGGL(admm_ul_fix64, dim3((unsigned)f.n_slots), dim3(kFixThreads), lds, st, f);
+  const int U = f.U, CU = f.C * f.U;
+  const int TI = (U >= 32) ? 4 : U / 8;
+  const int CG = kFixThreads / ((U / TI) * (U / TI));
+  const int vec = 3 * CU + U, piv = 2 * CG * U;
+  const size_t lds = (size_t)(vec > piv ? vec : piv) * sizeof(d2) + (kFixThreads + 4) * sizeof(int);
+  const dim3 grid((unsigned)f.n_slots), block(kFixThreads);
+  switch (U) {
+    case 8: hipLaunchKernelGGL(admm_ul_fix64<8>, grid, block, lds, st, f); break;
+    case 16: hipLaunchKernelGGL(admm_ul_fix64<16>, grid, block, lds, st, f); break;
+    case 32: hipLaunchKernelGGL(admm_ul_fix64<32>, grid, block, lds, st, f); break;
+    case 64: hipLaunchKernelGGL(admm_ul_fix64<64>, grid, block, lds, st, f); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -1600,8 +1600,8 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
     const size_t vo = ((size_t)k * a.n_sym + n);
     const c32 s = (k < a.n_sc) ? a.s[vo * G + u] : cz();
     c32 z = cscale(s, a.f0), lam = cz();
-    // x_c = A_c^{-1} H_c^H (z + lambda), entry a held by lane a < S
-    auto apply = [&](c32 v) -> c32 {
+    // H_c^H v: entry a held by lane a < S
+    auto hhv = [&](c32 v) -> c32 {
       bl[bw] = v;
       wave_lds_sync();
       c32 acc = cz();
@@ -1614,7 +1614,34 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
       }
       wave_lds_sync();
       if (SPLIT) acc = c32{pair_sum<SG>(acc.re), pair_sum<SG>(acc.im)};
-      return group_matvec<SG>(A, (u < S) ? acc : cz(), u, line, gbase);
+      return (u < S) ? acc : cz();
+    };
+    // x_c = A_c^{-1} H_c^H (z + lambda), entry a held by lane a < S.  At
+    // S = U (SG = G) the regularised Gram is as poorly conditioned as it gets
+    // (condition numbers of a few hundred at S = U = 64), and the FP32 Gram
+    // and Gauss-Jordan inverse lose about a factor three against an exactly
+    // rounded solve there; one step of refinement whose residual is formed
+    // from H itself, r - H_c^H (H_c x) - x / rho, wins it back.
+    auto apply = [&](c32 v) -> c32 {
+      const c32 r = hhv(v);
+      c32 xa = group_matvec<SG>(A, r, u, line, gbase);
+      if constexpr (SG == G) {
+        bl[bw] = xa;
+        wave_lds_sync();
+        c32 m = cz();
+#pragma unroll
+        for (int v0 = 0; v0 < SG; v0 += 4) {
+          c32 xv[4];
+          lds_read_vec<4>(bl + v0, xv);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) cmac(m, hcol[v0 + i], xv[i]);
+        }
+        wave_lds_sync();
+        const c32 q = hhv(m);
+        const c32 res = (u < S) ? c32{fmaf(-irho, xa.re, r.re - q.re), fmaf(-irho, xa.im, r.im - q.im)} : cz();
+        xa = cadd(xa, group_matvec<SG>(A, res, u, line, gbase));
+      }
+      return xa;
     };
     c32 x = apply(z);
     for (int t = 2; t <= a.T; ++t) {
