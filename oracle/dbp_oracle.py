@@ -19,6 +19,10 @@ Baseband Processing for Massive MU-MIMO Systems" (arXiv:1702.04458):
 * ``admm_dl``      -- Algorithm 3 (decentralized ADMM beamforming, Section IV),
                       A_c (S x S) and B_c (U x U) branches; epsilon = 0 as in the
                       algorithm, or epsilon > 0 with the z-update of Lemma 2.
+* ``p1_budget``    -- step (P1) under a per-cluster transmit-energy budget
+                      ||x_c||^2 <= P_c (problem P0 with the budgets added;
+                      the paper has none): the constrained least-squares
+                      minimiser through its Lagrange multiplier.
 * ``admm_dl_literal`` -- the steps (P1), (P2), (P3) of Section IV-B written as
                       argmin / projection problems (P2 for epsilon > 0 solved
                       through its Lagrange multiplier); used to pin ``admm_dl``.
@@ -63,7 +67,7 @@ __all__ = [
     "partition_rows", "admm_ul", "admm_ul_literal", "admm_ul_frame",
     "dcg_ul", "dcg_ul_frame", "admm_dl", "admm_dl_literal", "admm_dl_frame",
     "mmse_detect", "zf_detect", "zf_precode", "eps_precode", "lemma2_factor",
-    "project_ball_constraint", "slice_qam", "slice_qam_f32",
+    "project_ball_constraint", "slice_qam", "slice_qam_f32", "p1_budget",
     "qam_levels", "box_radius", "power_scale", "prox",
 ]
 
@@ -345,7 +349,45 @@ def lemma2_factor(d, eps):
     return max(0.0, 1.0 - eps / nd) if nd > 0.0 else 0.0
 
 
-def admm_dl(Hu, s, C, rho, T, gamma=1.0, mode=None, eps=0.0):
+def p1_budget(Hc, v, rho, P):
+    """Step (P1) of Section IV-B with a per-cluster transmit-energy budget:
+
+        x_c = argmin_x 1/2||x||^2 + rho/2||H_c x - v||^2  subject to ||x||^2 <= P
+
+    (v = z_c + lambda_c, H_c the U x S downlink block).  Without the budget
+    the minimiser is x(1/rho) with x(tau) = (H_c^H H_c + tau I)^{-1} H_c^H v.
+    When ||x(1/rho)||^2 > P the budget is active: stationarity of the
+    Lagrangian 1/2||x||^2 + rho/2||H_c x - v||^2 + mu/2 (||x||^2 - P) gives
+    x = x(tau) with tau = (1 + mu) / rho > 1/rho, and tau solves
+    ||x(tau)||^2 = P.  With H_c^H H_c = V diag(sig) V^H and b = V^H H_c^H v,
+    ||x(tau)||^2 = sum_i |b_i|^2 / (sig_i + tau)^2 decreases strictly in tau,
+    so the root is unique; it is found by a bracketing root search.
+    Returns (x, tau)."""
+    from scipy.optimize import brentq
+
+    Hc = np.asarray(Hc, dtype=np.complex128)
+    v = np.asarray(v, dtype=np.complex128)
+    S = Hc.shape[1]
+    G = Hc.conj().T @ Hc
+    h = Hc.conj().T @ v
+    tau0 = 1.0 / rho
+    x0 = np.linalg.solve(G + tau0 * np.eye(S), h)
+    if float(np.real(np.vdot(x0, x0))) <= P:
+        return x0, tau0
+    sig, V = np.linalg.eigh(G)
+    b2 = np.abs(V.conj().T @ h) ** 2
+
+    def f(tau):
+        return float(np.sum(b2 / (sig + tau) ** 2)) - P
+
+    hi = 2.0 * tau0
+    while f(hi) > 0.0:
+        hi *= 2.0
+    tau = brentq(f, tau0, hi, xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
+    return np.linalg.solve(G + tau * np.eye(S), h), tau
+
+
+def admm_dl(Hu, s, C, rho, T, gamma=1.0, mode=None, eps=0.0, P=None):
     """Algorithm 3 for one target vector s (U,).
 
     ``Hu`` is the uplink channel (B, U); by reciprocity the downlink channel is
@@ -358,6 +400,9 @@ def admm_dl(Hu, s, C, rho, T, gamma=1.0, mode=None, eps=0.0):
                    x_c = apply(z_c + lambda_c).
     f = 1 for eps = 0 (Algorithm 3); f = max{0, 1 - eps/||s - w||} for
     eps > 0 (Lemma 2, the z-update of problem P0 with ||s - H x|| <= eps).
+    With per-cluster budgets P (length C) every x-update is the budgeted
+    step (P1) of ``p1_budget`` instead (the constraint ||x_c||^2 <= P_c added
+    to problem P0 and kept inside the cluster's own step).
     Returns x = [x_1; ...; x_C] (B,).
     """
     Hu = np.asarray(Hu, dtype=np.complex128)
@@ -378,6 +423,8 @@ def admm_dl(Hu, s, C, rho, T, gamma=1.0, mode=None, eps=0.0):
             apply.append(lambda v, Hk=Hk, Bm=Bm: Hk.conj().T @ np.linalg.solve(Bm, v))
         else:
             raise ValueError(mode)
+    if P is not None:
+        apply = [lambda v, c=c: p1_budget(Hd[c], v, rho, P[c])[0] for c in range(C)]
     z0 = max(U / B, 1.0 / C) * s
     z = [z0.copy() for _ in range(C)]
     lam = [np.zeros(U, np.complex128) for _ in range(C)]
@@ -425,7 +472,7 @@ def project_ball_constraint(wall, s, D, eps):
     return z_of(mu)
 
 
-def admm_dl_literal(Hu, s, C, rho, T, gamma=1.0, eps=0.0):
+def admm_dl_literal(Hu, s, C, rho, T, gamma=1.0, eps=0.0, P=None):
     """Section IV-B steps written as argmin / projection problems.
 
     Start z_c = max(U/B, 1/C) s, lambda_c = 0, then
@@ -438,6 +485,9 @@ def admm_dl_literal(Hu, s, C, rho, T, gamma=1.0, eps=0.0):
            eps > 0 ``project_ball_constraint``;
       (P3) lambda_c = lambda_c - gamma (H_c x_c - z_c);
       (P1) as above.
+    With per-cluster budgets P, (P1) is the same objective minimised over
+    ||x||^2 <= P_c by a generic constrained solver (SLSQP on the real and
+    imaginary parts), without the closed form of ``p1_budget``.
     """
     Hu = np.asarray(Hu, dtype=np.complex128)
     s = np.asarray(s, dtype=np.complex128)
@@ -453,7 +503,10 @@ def admm_dl_literal(Hu, s, C, rho, T, gamma=1.0, eps=0.0):
     def p1(c):
         Amat = np.vstack([sq * Hd[c], np.eye(S)])
         bvec = np.concatenate([sq * (z[c] + lam[c]), np.zeros(S)])
-        return np.linalg.lstsq(Amat, bvec, rcond=None)[0]
+        x = np.linalg.lstsq(Amat, bvec, rcond=None)[0]
+        if P is None or float(np.real(np.vdot(x, x))) <= P[c]:
+            return x
+        return _slsqp_budget_p1(Hd[c], z[c] + lam[c], rho, P[c], x)
 
     x = [p1(c) for c in range(C)]
     for _t in range(T - 1):
@@ -468,14 +521,42 @@ def admm_dl_literal(Hu, s, C, rho, T, gamma=1.0, eps=0.0):
     return np.concatenate(x)
 
 
-def admm_dl_frame(Hu, s, C, rho, T, gamma=1.0, mode=None, eps=0.0):
-    """Algorithm 3 over a frame: Hu [n_sc][B][U], s [n_sc][n_sym][U] -> x [n_sc][n_sym][B]."""
+def _slsqp_budget_p1(Hc, v, rho, P, x_start):
+    """1/2||x||^2 + rho/2||H_c x - v||^2 over ||x||^2 <= P by SLSQP on the
+    stacked real vector [Re x; Im x] (a generic solver, for pinning only)."""
+    from scipy.optimize import minimize
+
+    S = Hc.shape[1]
+
+    def unpack(r):
+        return r[:S] + 1j * r[S:]
+
+    def obj(r):
+        x = unpack(r)
+        e = Hc @ x - v
+        return 0.5 * float(np.real(np.vdot(x, x))) + 0.5 * rho * float(np.real(np.vdot(e, e)))
+
+    def grad(r):
+        x = unpack(r)
+        g = x + rho * (Hc.conj().T @ (Hc @ x - v))
+        return np.concatenate([g.real, g.imag])
+
+    x0 = x_start * math.sqrt(P / float(np.real(np.vdot(x_start, x_start))))
+    cons = {"type": "ineq", "fun": lambda r: P - float(r @ r), "jac": lambda r: -2.0 * r}
+    res = minimize(obj, np.concatenate([x0.real, x0.imag]), jac=grad, constraints=[cons], method="SLSQP",
+                   options={"ftol": 1e-15, "maxiter": 1000})
+    return unpack(res.x)
+
+
+def admm_dl_frame(Hu, s, C, rho, T, gamma=1.0, mode=None, eps=0.0, P=None):
+    """Algorithm 3 over a frame: Hu [n_sc][B][U], s [n_sc][n_sym][U] -> x [n_sc][n_sym][B]
+    (optional per-cluster budgets P, the budgeted step (P1))."""
     n_sc, B, U = Hu.shape
     n_sym = s.shape[1]
     out = np.zeros((n_sc, n_sym, B), np.complex128)
     for k in range(n_sc):
         for n in range(n_sym):
-            out[k, n] = admm_dl(Hu[k], s[k, n], C, rho, T, gamma, mode, eps)
+            out[k, n] = admm_dl(Hu[k], s[k, n], C, rho, T, gamma, mode, eps, P)
     return out
 
 

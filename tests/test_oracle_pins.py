@@ -560,3 +560,125 @@ def test_power_scale_tightness_check_rejects_a_gain_without_square_root():
     assert not _power_scale_is_tight(x, C, P, bad * x, bad)
     xs, beta = O.power_scale(x, C, P)
     assert _power_scale_is_tight(x, C, P, xs, beta)
+
+
+# -- Step (P1) under a per-cluster budget ||x_c||^2 <= P_c ----------------------
+
+def _p1_kkt_ok(Hc, v, rho, P, x, tol=1e-9):
+    """KKT conditions of min 1/2||x||^2 + rho/2||H x - v||^2 s.t. ||x||^2 <= P:
+    primal feasibility, and a multiplier mu >= 0 with
+    (1 + mu) x + rho H^H (H x - v) = 0 and mu (||x||^2 - P) = 0."""
+    e = float(np.real(np.vdot(x, x)))
+    if e > P * (1 + tol):
+        return False
+    g = rho * (Hc.conj().T @ (Hc @ x - v))          # = -(1 + mu) x
+    if np.linalg.norm(x) == 0:
+        return np.linalg.norm(g) <= tol
+    one_mu = -float(np.real(np.vdot(x, g))) / e
+    mu = one_mu - 1.0
+    stat = np.linalg.norm(one_mu * x + g) / max(np.linalg.norm(g), 1e-300)
+    if mu < -tol or stat > tol:
+        return False
+    return abs(mu * (e - P)) <= tol * max(1.0, P) * max(1.0, abs(mu))
+
+
+@pytest.mark.parametrize("scale", [0.05, 0.5, 0.95, 2.0])
+def test_p1_budget_kkt(scale):
+    # budgets from far below to above the unconstrained step's energy
+    rng = np.random.default_rng(80)
+    for trial in range(6):
+        U, S, rho = 6, 4, 0.7
+        Hc, v = cn(rng, U, S), cn(rng, U)
+        x0 = np.linalg.solve(Hc.conj().T @ Hc + np.eye(S) / rho, Hc.conj().T @ v)
+        P = scale * float(np.real(np.vdot(x0, x0)))
+        x, tau = O.p1_budget(Hc, v, rho, P)
+        assert _p1_kkt_ok(Hc, v, rho, P, x)
+        if scale >= 1.0:
+            assert np.array_equal(x, x0) and tau == 1.0 / rho
+        else:
+            assert abs(float(np.real(np.vdot(x, x))) - P) <= 1e-12 * P and tau > 1.0 / rho
+
+
+def test_p1_budget_kkt_check_rejects_a_rescaled_step():
+    # the plausible shortcut of scaling the unconstrained step onto the ball
+    # is feasible but not the minimiser: the KKT check must reject it
+    rng = np.random.default_rng(81)
+    U, S, rho = 6, 4, 1.0
+    Hc, v = cn(rng, U, S), cn(rng, U)
+    x0 = np.linalg.solve(Hc.conj().T @ Hc + np.eye(S) / rho, Hc.conj().T @ v)
+    P = 0.3 * float(np.real(np.vdot(x0, x0)))
+    assert not _p1_kkt_ok(Hc, v, rho, P, x0 * math.sqrt(P / float(np.real(np.vdot(x0, x0)))))
+    assert _p1_kkt_ok(Hc, v, rho, P, O.p1_budget(Hc, v, rho, P)[0])
+
+
+def test_p1_budget_equals_generic_solver():
+    from scipy.optimize import minimize
+
+    rng = np.random.default_rng(82)
+    for trial in range(5):
+        U, S, rho = 5, 3, 1.3
+        Hc, v = cn(rng, U, S), cn(rng, U)
+        P = 0.2
+        x, _ = O.p1_budget(Hc, v, rho, P)
+
+        def f(r):
+            z = r[:S] + 1j * r[S:]
+            e = Hc @ z - v
+            return 0.5 * np.sum(np.abs(z) ** 2) + 0.5 * rho * np.sum(np.abs(e) ** 2)
+
+        res = minimize(f, np.zeros(2 * S), constraints=[{"type": "ineq", "fun": lambda r: P - r @ r}],
+                       method="SLSQP", options={"ftol": 1e-14, "maxiter": 500})
+        assert np.abs(res.x[:S] + 1j * res.x[S:] - x).max() < 1e-6
+
+
+def test_alg3_budget_equals_literal_steps():
+    rng = np.random.default_rng(83)
+    B, U, C = 16, 4, 2
+    for T in (1, 3, 5):
+        Hu, s = cn(rng, B, U), cn(rng, U)
+        x = O.admm_dl(Hu, s, C, 1.0, T)
+        S = B // C
+        P = [0.6 * float(np.real(np.vdot(x[c * S:(c + 1) * S], x[c * S:(c + 1) * S]))) for c in range(C)]
+        a = O.admm_dl(Hu, s, C, 1.0, T, P=P)
+        b = O.admm_dl_literal(Hu, s, C, 1.0, T, P=P)
+        assert np.abs(a - b).max() < 1e-7 * np.abs(a).max()
+        for c in range(C):
+            assert float(np.real(np.vdot(a[c * S:(c + 1) * S], a[c * S:(c + 1) * S]))) <= P[c] * (1 + 1e-12)
+
+
+def test_alg3_budget_inactive_is_algorithm3():
+    rng = np.random.default_rng(84)
+    B, U, C = 32, 8, 4
+    Hu, s = cn(rng, B, U), cn(rng, U)
+    assert np.array_equal(O.admm_dl(Hu, s, C, 1.0, 5, P=[1e9] * C), O.admm_dl(Hu, s, C, 1.0, 5))
+
+
+def test_alg3_budget_converges_to_the_constrained_p0():
+    # T -> infinity: the minimum-energy x with H x = s and ||x_c||^2 <= P_c,
+    # found independently by SLSQP on the centralized problem
+    from scipy.optimize import minimize
+
+    rng = np.random.default_rng(85)
+    B, U, C = 12, 3, 3
+    S = B // C
+    Hu, s = cn(rng, B, U), cn(rng, U)
+    Hd = Hu.T
+    xzf = O.zf_precode(Hd, s)
+    e = [float(np.real(np.vdot(xzf[c * S:(c + 1) * S], xzf[c * S:(c + 1) * S]))) for c in range(C)]
+    cmax = int(np.argmax(e))
+    P = [10.0 * max(e)] * C
+    P[cmax] = 0.7 * e[cmax]                      # the ZF precoder violates this budget
+    x = O.admm_dl(Hu, s, C, 1.0, 4000, P=P)
+
+    def unpack(r):
+        return r[:B] + 1j * r[B:]
+
+    cons = [{"type": "eq", "fun": lambda r: np.concatenate([(Hd @ unpack(r) - s).real, (Hd @ unpack(r) - s).imag])}]
+    for c in range(C):
+        cons.append({"type": "ineq", "fun": lambda r, c=c: P[c] - np.sum(np.abs(unpack(r)[c * S:(c + 1) * S]) ** 2)})
+    res = minimize(lambda r: 0.5 * r @ r, np.concatenate([xzf.real, xzf.imag]), constraints=cons, method="SLSQP",
+                   options={"ftol": 1e-15, "maxiter": 2000})
+    assert res.success
+    ref = unpack(res.x)
+    assert np.abs(Hd @ x - s).max() < 1e-6
+    assert np.abs(x - ref).max() < 1e-5 * np.abs(ref).max()
