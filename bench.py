@@ -317,7 +317,12 @@ def cpu_vectorized_admm(B, U, C, qam, snr, T, workers, n_sc=1200, reps=3):
                       f"(not the oracle)"}
 
 
-def serve_bench(loads=(0.25, 0.5, 0.7, 0.85, 0.95), frames_per_load=300, pool=40, n_slots=8,
+def _pctl(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
+
+
+def serve_bench(loads=(0.25, 0.5, 0.7, 0.85, 0.95), frames_per_load=10000, pool=40, n_slots=8,
                 budget_gb=32.0, seed=99, log=sys.stderr):
     """Continuous-batching serving run: Poisson arrivals of uplink frames whose
     (B, U, C) is uniform over the valid triples with U <= S = B/C, n_sc uniform
@@ -427,6 +432,169 @@ def serve_bench(loads=(0.25, 0.5, 0.7, 0.85, 0.95), frames_per_load=300, pool=40
             "saturation_vectors_per_s": round(sat_fps * vec_per_frame, 1),
             "mean_subcarriers_per_frame": round(vec_per_frame, 1), "slots": n_slots, "budget_gb": budget_gb,
             "peak_inflight": st["peak_inflight"], "loads": results}
+
+
+def serve_h16_bench(api, F=7, loads=(0.5, 0.85), intervals_per_load=600, n_channels=8, B=256, U=32, C=8,
+                    n_sc=1200, qam=64, snr=25.0, n_slots=8, budget_gb=32.0, seed=7, log=sys.stderr):
+    """The mixed-precision served form under Poisson arrivals: uplink frames
+    over static channels, F frames per channel (a coherence interval of F
+    OFDM symbols).  The first frame of every interval loads its channel into
+    the server (dbp_channel_load with DBP_CHANNEL_H16: H packed as complex
+    FP16 and B_c^{-1} formed once), the F frames run the FP32 iterations
+    against it (dbp_server_submit_factored), and the channel is freed once
+    its frames are done.  A frame's latency runs from its Poisson arrival to
+    its completion, so the channel load and any queueing count.  Saturation
+    is measured closed-loop first."""
+    import random
+    import threading
+
+    import torch
+
+    rng = random.Random(seed)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    Hs = [(torch.complex(torch.randn((n_sc, B, U), generator=g, device="cuda"),
+                         torch.randn((n_sc, B, U), generator=g, device="cuda")) / math.sqrt(2.0)).contiguous()
+          for _ in range(n_channels)]
+    ys = [received_over(H, F, qam, snr, seed + 1 + i) for i, H in enumerate(Hs)]
+    N0 = U / (10.0 ** (snr / 10.0))
+    outs = [[(torch.empty((n_sc, 1, U), dtype=torch.complex64, device="cuda"),
+              torch.empty((n_sc, 1, U), dtype=torch.uint8, device="cuda")) for _ in range(F)]
+            for _ in range(n_channels)]
+    torch.cuda.synchronize()
+    srv = api.Server(hbm_budget_bytes=int(budget_gb * 2 ** 30), n_slots=n_slots)
+
+    def run(n_intervals, rate):
+        """rate None: closed loop.  Returns (frames, seconds, latencies_us)."""
+        lat = []
+        pend = []             # (arrival, submit, ticket, interval)
+        lock = threading.Lock()
+        state = {"done": False}
+        left = {}             # interval -> frames not yet completed
+        chans = {}
+
+        def waiter():
+            while True:
+                with lock:
+                    item = pend.pop(0) if pend else None
+                if item is None:
+                    if state["done"]:
+                        with lock:
+                            if not pend:
+                                return
+                    time.sleep(0.0001)
+                    continue
+                arr, sub, tk, iv = item
+                l_us, _ = srv.wait(tk)
+                lat.append((sub - arr) * 1e6 + l_us)
+                with lock:
+                    left[iv] -= 1
+                    free = left[iv] == 0
+                if free:
+                    srv.free_channel(chans.pop(iv))
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        t_next = t0
+        for iv in range(n_intervals):
+            ci = iv % n_channels
+            for f in range(F):
+                if rate is not None:
+                    t_next += rng.expovariate(rate)
+                    while time.perf_counter() < t_next:
+                        pass
+                arr = t_next if rate is not None else time.perf_counter()
+                if f == 0:
+                    # keep at most n_channels - 1 intervals resident (their buffers are reused)
+                    while True:
+                        with lock:
+                            busy = len(chans)
+                        if busy < n_channels - 1:
+                            break
+                        time.sleep(0.00005)
+                    ch = srv.load_channel(Hs[ci], C, 1.0, h16=True)
+                    with lock:
+                        chans[iv] = ch
+                        left[iv] = F
+                o = outs[ci][f]
+                tk = srv.submit_factored(chans[iv], ys[ci][f], o[0], o[1], 5, N0, qam=qam)
+                with lock:
+                    pend.append((arr, time.perf_counter(), tk, iv))
+        state["done"] = True
+        th.join()
+        return n_intervals * F, time.perf_counter() - t0, lat
+
+    run(2 * n_channels, None)                                   # warm-up
+    nf, dt, _ = run(max(40, intervals_per_load // 4), None)
+    sat_fps = nf / dt
+    print(f"[serve-h16] saturation {sat_fps:.0f} frames/s ({sat_fps * n_sc / 1e6:.2f} M vectors/s)", file=log,
+          flush=True)
+    res = []
+    for load in loads:
+        nf, dt, lat = run(intervals_per_load, load * sat_fps)
+        res.append({"load": load, "offered_fps": round(load * sat_fps, 1), "achieved_fps": round(nf / dt, 1),
+                    "vectors_per_s": round(nf * n_sc / dt, 1), "p50_us": round(_pctl(lat, 0.5), 1),
+                    "p99_us": round(_pctl(lat, 0.99), 1), "frames": nf})
+        print(f"[serve-h16] load {load:.2f}: p50 {res[-1]['p50_us']:.0f} us, p99 {res[-1]['p99_us']:.0f} us",
+              file=log, flush=True)
+    srv.close()
+    return {"shape": f"B={B} U={U} C={C} n_sc={n_sc} {qam}-QAM {snr:g} dB T=5", "frames_per_channel": F,
+            "saturation_fps": round(sat_fps, 1), "saturation_vectors_per_s": round(sat_fps * n_sc, 1),
+            "loads": res}
+
+
+def nsym_bench(api, B, U, C, qam, snr, T, n_sym=7, n_vectors=38400, steps=30, log=sys.stderr):
+    """The static-channel GPU workload of the paper's measurements: N_sym
+    received vectors per subcarrier share one channel, so one launch forms
+    every B_c^{-1} once and runs Algorithm 1 for all N_sym symbols."""
+    import torch
+
+    n_sc = n_vectors // n_sym
+    frames = []
+    for i in range(3):
+        H = make_frames(1, "admm", B, U, qam, snr, n_sc, seed=555 + i)[0][0][0]
+        ys = received_over(H, n_sym, qam, snr, seed=777 + i)
+        frames.append((H, torch.cat(ys, dim=1).contiguous()))
+    out = (torch.empty((n_sc, n_sym, U), dtype=torch.complex64, device="cuda"),
+           torch.empty((n_sc, n_sym, U), dtype=torch.uint8, device="cuda"))
+    N0 = U / (10.0 ** (snr / 10.0))
+    ms, per = time_steps(api, frames, "admm", C, T, N0, qam, out, "fp32", None, steps, 5)
+    vec = n_sc * n_sym
+    bytes_vec = (8 * B * U + n_sym * (8 * B + 8 * U + U)) / n_sym
+    avg_ms = sum(per) / len(per)
+    print(f"[bench] N_sym={n_sym}: {ms * 1e3:.1f} us/step, {vec / (ms * 1e-3) / 1e6:.1f} M vectors/s", file=log,
+          flush=True)
+    return {"n_sym": n_sym, "n_sc": n_sc, "vectors": vec, "us_per_step": round(ms * 1e3, 2),
+            "vectors_per_s": round(vec / (ms * 1e-3), 1), "bytes_per_vector": round(bytes_vec, 1),
+            "hbm_frac": round(bytes_vec * vec / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def dl_budget_bench(api, frames, C, T, out, steps, P=0.013, log=sys.stderr):
+    """Configuration 3 with per-cluster budgets P_c (binding on about half of
+    the clusters at this shape): the common gain after Algorithm 3, and the
+    budgeted step (P1) in every x-update."""
+    import torch
+
+    res = {"P_c": P}
+    Pt = torch.full((C,), P, dtype=torch.float32, device="cuda")
+    for mode in ("common_gain", "per_cluster"):
+        for i in range(3):
+            api.precode(frames[i % len(frames)][0], frames[i % len(frames)][1], C, 1.0, T, P_cluster=Pt, power=mode,
+                        out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(steps):
+            api.precode(frames[i % len(frames)][0], frames[i % len(frames)][1], C, 1.0, T, P_cluster=Pt, power=mode,
+                        out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        n_sc = frames[0][0].shape[0]
+        res[mode] = {"us_per_step": round(ms * 1e3, 2), "vectors_per_s": round(n_sc / (ms * 1e-3), 1)}
+        print(f"[bench] downlink budget {mode}: {ms * 1e3:.1f} us/step", file=log, flush=True)
+    return res
 
 
 def source_digest() -> str:
@@ -662,7 +830,7 @@ def main():
                          "factors (and for resident_h16 its FP16-packed H) are made once before timing and each "
                          "step runs the iterations for a new received frame")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving benchmark")
-    ap.add_argument("--serve-frames", type=int, default=300, help="frames per offered load in the serving run")
+    ap.add_argument("--serve-frames", type=int, default=10000, help="frames per offered load in the serving run")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run only a plain device-to-device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -800,7 +968,19 @@ def main():
     serving = None
     if not args.no_serve and algo == "admm":
         print("[bench] serving run", file=sys.stderr, flush=True)
-        serving = serve_bench(loads=(0.5, 0.85), frames_per_load=args.serve_frames, pool=24)
+        serving = serve_bench(frames_per_load=args.serve_frames, pool=40)
+        if U == 32 and args.form == "oneshot":
+            serving["served_h16"] = serve_h16_bench(api, B=B, U=U, C=C, qam=qam, snr=snr)
+            sat = serving["served_h16"]["saturation_vectors_per_s"]
+            serving["served_h16"]["vs_fp32_batched"] = round(sat / vectors_per_s, 3)
+
+    nsym7 = None
+    if algo == "admm" and not args.no_compare and args.form == "oneshot" and args.prec == "fp32":
+        nsym7 = nsym_bench(api, B, U, C, qam, snr, T)
+
+    budget = None
+    if algo == "dl" and not args.no_compare:
+        budget = dl_budget_bench(api, frames, C, T, out, max(10, args.steps // 2))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -841,6 +1021,8 @@ def main():
             "mixed_precision": compare,
             "static_channel": static,
             "small_frames_graph": graph,
+            "n_sym7": nsym7,
+            "downlink_budgets": budget,
             "serving": serving,
         },
         "roofline": roof,

@@ -251,11 +251,19 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard,
  *   s      [n_sc][n_sym][U] complex64  precoding targets
  *   x      [n_sc][n_sym][B] complex64  output [x_1; ...; x_C]
  *   beta   [n_sc][n_sym] float or NULL  output common gain (1 without budgets)
- *   P_cluster  [C] float DEVICE array of per-cluster transmit-energy budgets,
- *          or NULL.  When given, x is scaled by
+ *   P_cluster  [C] float DEVICE array of per-cluster transmit-energy budgets
+ *          P_c > 0, or NULL (no budgets).  The paper's problem P0 has no such
+ *          budgets; power_mode selects how they are met:
+ *   power_mode DBP_POWER_COMMON_GAIN: after Algorithm 3, x is scaled by
  *          beta = min(1, min_c sqrt(P_c / ||x_c||^2)) so that every cluster
  *          meets its budget while H^d x = beta * H^d x_unscaled stays
- *          interference-free.
+ *          interference-free;
+ *          DBP_POWER_PER_CLUSTER: every x-update is step (P1) of Section
+ *          IV-B solved exactly under ||x_c||^2 <= P_c (problem P0 with the
+ *          budgets added as constraints; the unconstrained step when it fits
+ *          the budget, else the minimiser on the budget sphere through the
+ *          Lagrange multiplier, found by Newton's method on the shifted
+ *          regularised Gram), and beta = 1.  Ignored without P_cluster.
  *   T      number of x-updates (T - 1 consensus steps), T >= 1
  *   eps    radius of the precoding constraint ||s - H^d x|| <= eps of
  *          problem P0 (Section IV-A), eps >= 0.  eps = 0 is Algorithm 3 as
@@ -264,8 +272,10 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard,
  *          w = sum_c w_c (the norm of the lemma's proof).
  * Requires B % C == 0, S = B / C <= U, U in {8, 16, 32, 64}, C <= 16.
  */
+#define DBP_POWER_COMMON_GAIN 0
+#define DBP_POWER_PER_CLUSTER 1
 int dbp_precode_admm(const void* H, const void* s, void* x, float* beta,
-                     const float* P_cluster, int n_sc, int n_sym, int B, int U,
+                     const float* P_cluster, int power_mode, int n_sc, int n_sym, int B, int U,
                      int C, int T, float rho, float gamma, float eps, void* stream);
 
 /* ------------------------------------------------------------------------

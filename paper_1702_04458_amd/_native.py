@@ -36,7 +36,7 @@ SIGNATURES = {
                                           _i, _i, _vp]),
     "dbp_detect_cg": (_i, [_vp, _vp, _vp, _u8p, _vp, _vp, ctypes.c_size_t, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i,
                            _vp]),
-    "dbp_precode_admm": (_i, [_vp, _vp, _vp, _fp, _fp, _i, _i, _i, _i, _i, _i, _f, _f, _f, _vp]),
+    "dbp_precode_admm": (_i, [_vp, _vp, _vp, _fp, _fp, _i, _i, _i, _i, _i, _i, _i, _f, _f, _f, _vp]),
     "dbp_server_create": (_i, [_i, ctypes.c_size_t, _i, ctypes.POINTER(ctypes.c_void_p)]),
     "dbp_server_destroy": (_i, [_vp]),
     "dbp_server_submit": (_i, [_vp, _vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i, _i, _i,

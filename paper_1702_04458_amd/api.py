@@ -227,13 +227,19 @@ def detect_factored_h16(packed, factors, y, N0, B, U, C, rho=1.0, T=5, *, reg="m
     return _ret(s_hat, hd, stt, status)
 
 
-def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, eps=0.0, P_cluster=None, out=None, stream=None):
+POWER = {"common_gain": 0, "per_cluster": 1}
+
+
+def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, eps=0.0, P_cluster=None, power="common_gain", out=None,
+            stream=None):
     """Decentralized ADMM beamforming (Algorithm 3; ``eps`` > 0 uses the
     z-update of Lemma 2 for the constraint ||s - H^d x|| <= eps).
 
     ``H`` is the uplink-layout channel [n_sc, B, U]; ``s`` the targets
     [n_sc, n_sym, U] (or [n_sc, U]).  ``P_cluster`` optional device float32
-    tensor [C] of per-cluster budgets.  Returns ``(x [n_sc, n_sym, B], beta [n_sc, n_sym])``.
+    tensor [C] of per-cluster budgets, met by a common gain after the
+    algorithm (``power="common_gain"``) or by the budgeted step (P1) in every
+    x-update (``power="per_cluster"``).  Returns ``(x [n_sc, n_sym, B], beta [n_sc, n_sym])``.
     """
     _dev(H, "H")
     _dev(s, "s")
@@ -256,7 +262,7 @@ def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, eps=0.0, P_cluster=None, out=No
         _check_out(beta, "beta", (n_sc, n_sym), torch.float32, H.device)
     L = _native.lib()
     code = L.dbp_precode_admm(H.data_ptr(), s.data_ptr(), x.data_ptr(), beta.data_ptr(),
-                              P_cluster.data_ptr() if P_cluster is not None else None,
+                              P_cluster.data_ptr() if P_cluster is not None else None, POWER[power],
                               n_sc, n_sym, B, U, C, T, float(rho), float(gamma), float(eps),
                               _stream(stream))
     _native.check(code)

@@ -478,11 +478,14 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int3
   return device_status(who, dbp::launch_dcg_ul_fix64(f, hs));
 }
 
-int dbp_precode_admm(const void* H, const void* s, void* x, float* beta, const float* P_cluster, int n_sc,
-                     int n_sym, int B, int U, int C, int T, float rho, float gamma, float eps, void* stream) {
+int dbp_precode_admm(const void* H, const void* s, void* x, float* beta, const float* P_cluster, int power_mode,
+                     int n_sc, int n_sym, int B, int U, int C, int T, float rho, float gamma, float eps,
+                     void* stream) {
   const char* who = "dbp_precode_admm";
   int st = common_shape(who, n_sc, n_sym, B, U, C, T);
   if (st) return st;
+  if (power_mode != DBP_POWER_COMMON_GAIN && power_mode != DBP_POWER_PER_CLUSTER)
+    return fail(DBP_ERR_INVALID, "%s: power_mode=%d", who, power_mode);
   if (!(rho > 0.f) || !std::isfinite(rho)) return fail(DBP_ERR_INVALID, "%s: rho must be > 0", who);
   if (!(gamma > 0.f) || !std::isfinite(gamma)) return fail(DBP_ERR_INVALID, "%s: gamma must be > 0", who);
   if (!(eps >= 0.f) || !std::isfinite(eps)) return fail(DBP_ERR_INVALID, "%s: eps must be >= 0", who);
@@ -510,6 +513,7 @@ int dbp_precode_admm(const void* H, const void* s, void* x, float* beta, const f
   a.invC = (float)(1.0 / C);
   a.f0 = (float)std::fmax((double)U / B, 1.0 / C);
   a.eps = eps;
+  a.budget = (power_mode == DBP_POWER_PER_CLUSTER) ? 1 : 0;
   return device_status(who, dbp::launch_admm_dl_f32(a, U, pl.nw, static_cast<hipStream_t>(stream)));
 }
 

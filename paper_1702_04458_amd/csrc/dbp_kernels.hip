@@ -1480,6 +1480,10 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   }
 }
 
+// Newton steps of the budgeted (P1) at most (quadratic convergence from
+// below: about four to six steps reach FP32 accuracy).
+constexpr int kBudgetNewton = 12;
+
 // ---------------------------------------------------------------------------
 // Algorithm 3 (decentralized ADMM beamforming, epsilon = 0), S x S branch
 // (S <= U), FP32.  Group size G = U.  The downlink cluster channel is
@@ -1488,7 +1492,15 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
 // a < S) for m_c = H_c x_c; lane a < S holds row a of Hu_c for H_c^H v and
 // row a of A_c^{-1}.
 // ---------------------------------------------------------------------------
-template <int G, int SG>
+// BUDGET: every x-update is the budgeted step (P1) with ||x_c||^2 <= P_c.
+// When the unconstrained step exceeds the budget, x = (H_c^H H_c + tau I)^{-1}
+// H_c^H v with tau > 1/rho the root of ||x(tau)|| = sqrt(P_c) (the Lagrange
+// multiplier of the budget is rho tau - 1): Newton's method on
+// 1/||x(tau)|| - 1/sqrt(P_c), which is concave and increasing in tau, so the
+// iterates from tau = 1/rho rise monotonically to the root (the trust-region
+// update tau += ||x||^2 (||x|| - sqrt(P)) / (sqrt(P) x^H (G + tau I)^{-1} x)).
+// Each step forms the Gram again and inverts the shifted matrix.
+template <int G, int SG, bool BUDGET = false>
 __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   constexpr int P = 64 / G;
   extern __shared__ float4 smem_raw[];
@@ -1529,35 +1541,40 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
 #pragma unroll
     for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * G + r0 + i] : cz();
   }
-  // A_c = H_c^H H_c + rho^{-1} I_S with (H_c^H H_c)[a][b] = sum_u conj(Hu[a][u]) Hu[b][u].
-  if constexpr (LATE_H) {
-    gram_dl_mfma_s16_u32(hcol, A, lane, g, u, sm.stage + wave * kStageRows * 64);
-  } else {
-    // Row b of Hu_c is broadcast from the stage buffer of this wave.
-    c32* stage = sm.stage + wave * kStageRows * 64;
-    for (int b = 0; b < S; ++b) {
-      // lane u of the group publishes Hu[b][u] = hcol[b]
-      c32 hb = cz();
+  // The Gram H_c^H H_c, (H_c^H H_c)[a][b] = sum_u conj(Hu[a][u]) Hu[b][u], into
+  // M (rows a < S; M must hold zeros).  Every lane of the wave takes part.
+  auto gram_into = [&](c32 (&M)[SG]) {
+    if constexpr (LATE_H) {
+      gram_dl_mfma_s16_u32(hcol, M, lane, g, u, sm.stage + wave * kStageRows * 64);
+    } else {
+      // Row b of Hu_c is broadcast from the stage buffer of this wave.
+      c32* stage = sm.stage + wave * kStageRows * 64;
+      for (int b = 0; b < S; ++b) {
+        // lane u of the group publishes Hu[b][u] = hcol[b]
+        c32 hb = cz();
 #pragma unroll
-      for (int i = 0; i < SG; ++i)
-        if (i == b) hb = hcol[i];
-      stage[lane] = hb;
-      wave_lds_sync();
-      c32 acc = cz();
+        for (int i = 0; i < SG; ++i)
+          if (i == b) hb = hcol[i];
+        stage[lane] = hb;
+        wave_lds_sync();
+        c32 acc = cz();
 #pragma unroll
-      for (int v0 = 0; v0 < RS; v0 += 8) {
-        c32 row[8];
-        lds_read_vec<8>(stage + gbase + r0 + v0, row);
+        for (int v0 = 0; v0 < RS; v0 += 8) {
+          c32 row[8];
+          lds_read_vec<8>(stage + gbase + r0 + v0, row);
 #pragma unroll
-        for (int v = 0; v < 8; ++v) cmacc(acc, hrow[v0 + v], row[v]);
+          for (int v = 0; v < 8; ++v) cmacc(acc, hrow[v0 + v], row[v]);
+        }
+        wave_lds_sync();
+        if (SPLIT) acc = c32{pair_sum<SG>(acc.re), pair_sum<SG>(acc.im)};
+#pragma unroll
+        for (int i = 0; i < SG; ++i)
+          if (i == b) M[i] = (u < S) ? acc : cz();
       }
-      wave_lds_sync();
-      if (SPLIT) acc = c32{pair_sum<SG>(acc.re), pair_sum<SG>(acc.im)};
-#pragma unroll
-      for (int i = 0; i < SG; ++i)
-        if (i == b) A[i] = (u < S) ? acc : cz();
     }
-  }
+  };
+  // A_c = H_c^H H_c + rho^{-1} I_S
+  gram_into(A);
   const float irho = 1.0f / a.rho;
 #pragma unroll
   for (int v = 0; v < SG; ++v)
@@ -1641,6 +1658,38 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
         const c32 res = (u < S) ? c32{fmaf(-irho, xa.re, r.re - q.re), fmaf(-irho, xa.im, r.im - q.im)} : cz();
         xa = cadd(xa, group_matvec<SG>(A, res, u, line, gbase));
       }
+      if constexpr (BUDGET) {
+        // padding cluster slots carry no budget
+        const float Pc = active ? a.P[c] : 0.f;
+        const float e = group_sum<G>((u < S) ? xa.re * xa.re + xa.im * xa.im : 0.f);
+        const bool need = active && e > Pc;
+        if (__ballot(need)) {   // wave-uniform: the Gram and sweep below are wave operations
+          const float sp = sqrtf(Pc);
+          float tau = irho, et = e;
+          c32 xn = xa;
+          for (int it = 0; it < kBudgetNewton; ++it) {
+            c32 Mt[SG];
+#pragma unroll
+            for (int v = 0; v < SG; ++v) Mt[v] = cz();
+            gram_into(Mt);
+#pragma unroll
+            for (int v = 0; v < SG; ++v)
+              if (v == u) Mt[v].re += (u < S) ? tau : 1.0f;
+            gj_invert<SG>(Mt, u, line, gbase);
+            xn = group_matvec<SG>(Mt, r, u, line, gbase);
+            const c32 mx = group_matvec<SG>(Mt, xn, u, line, gbase);
+            et = group_sum<G>((u < S) ? xn.re * xn.re + xn.im * xn.im : 0.f);
+            const float w2 = group_sum<G>((u < S) ? xn.re * mx.re + xn.im * mx.im : 0.f);
+            const float sq = sqrtf(et);
+            const bool go = need && sq - sp > 1e-6f * sp && w2 > 0.f;
+            if (go) tau += et * (sq - sp) / (sp * w2);
+            if (!__ballot(go)) break;
+          }
+          // the last iterate lies on the budget up to rounding; a final
+          // scale keeps it feasible
+          if (need) xa = (et > Pc) ? cscale(xn, sqrtf(Pc / et)) : xn;
+        }
+      }
       return xa;
     };
     c32 x = apply(z);
@@ -1674,8 +1723,9 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
       x = apply(cadd(z, lam));
     }
     // optional common power scaling: beta = min(1, min_c sqrt(P_c / ||x_c||^2))
+    // (with the budgeted step the budgets are met by every x-update instead)
     float beta = 1.0f;
-    if (a.P) {
+    if (a.P && !BUDGET) {
       const float e = group_sum<G>((u < S) ? (x.re * x.re + x.im * x.im) : 0.f);
       float ratio = 1.0f;
       if (active && e > 0.f) ratio = fminf(1.0f, sqrtf(a.P[c] / e));
@@ -1694,9 +1744,9 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   }
 }
 
-template <int G, int SG>
+template <int G, int SG, bool BUDGET = false>
 __global__ void __launch_bounds__(512) admm_dl_f32(DlArgs a) {
-  admm_dl_body<G, SG>(a);
+  admm_dl_body<G, SG, BUDGET>(a);
 }
 
 // The same with the register budget of four waves per SIMD: at B = 256,
@@ -1872,23 +1922,32 @@ hipError_t launch_dcg_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st) {
+template <bool BUDGET>
+static hipError_t launch_dl(const DlArgs& a, int U, int nw, hipStream_t st) {
   const int S = a.S;
   switch (U) {
-    case 8: return launch(admm_dl_f32<8, 8>, a, nw, st);
+    case 8: return launch(admm_dl_f32<8, 8, BUDGET>, a, nw, st);
     case 16:
-      return S <= 8 ? launch(admm_dl_f32<16, 8>, a, nw, st) : launch(admm_dl_f32<16, 16>, a, nw, st);
+      return S <= 8 ? launch(admm_dl_f32<16, 8, BUDGET>, a, nw, st) : launch(admm_dl_f32<16, 16, BUDGET>, a, nw, st);
     case 32:
-      if (S <= 8) return launch(admm_dl_f32<32, 8>, a, nw, st);
-      if (S <= 16) return launch(admm_dl_f32_w4<32, 16>, a, nw, st);
-      return launch(admm_dl_f32<32, 32>, a, nw, st);
+      if (S <= 8) return launch(admm_dl_f32<32, 8, BUDGET>, a, nw, st);
+      if (S <= 16) {
+        // the budgeted form keeps a second S x S matrix live: no 128-register cap
+        if constexpr (BUDGET) return launch(admm_dl_f32<32, 16, true>, a, nw, st);
+        return launch(admm_dl_f32_w4<32, 16>, a, nw, st);
+      }
+      return launch(admm_dl_f32<32, 32, BUDGET>, a, nw, st);
     case 64:
-      if (S <= 8) return launch(admm_dl_f32<64, 8>, a, nw, st);
-      if (S <= 16) return launch(admm_dl_f32<64, 16>, a, nw, st);
-      if (S <= 32) return launch(admm_dl_f32<64, 32>, a, nw, st);
-      return launch(admm_dl_f32<64, 64>, a, nw, st);
+      if (S <= 8) return launch(admm_dl_f32<64, 8, BUDGET>, a, nw, st);
+      if (S <= 16) return launch(admm_dl_f32<64, 16, BUDGET>, a, nw, st);
+      if (S <= 32) return launch(admm_dl_f32<64, 32, BUDGET>, a, nw, st);
+      return launch(admm_dl_f32<64, 64, BUDGET>, a, nw, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_admm_dl_f32(const DlArgs& a, int U, int nw, hipStream_t st) {
+  return (a.P && a.budget) ? launch_dl<true>(a, U, nw, st) : launch_dl<false>(a, U, nw, st);
 }
 
 }  // namespace dbp

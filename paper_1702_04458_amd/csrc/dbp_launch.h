@@ -61,6 +61,7 @@ struct DlArgs {
   int sc_per_block;
   float rho, gamma, invC, f0;
   float eps;          // radius of ||s - sum_c z_c|| <= eps (Lemma 2); 0 = equality (Alg. 3)
+  int budget;         // with P: 0 common gain after Algorithm 3, 1 budgeted step (P1) in every x-update
 };
 
 size_t smem_bytes(int nw);

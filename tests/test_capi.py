@@ -105,21 +105,24 @@ def test_detect_cg_rejects():
 
 def test_precode_rejects():
     L = _native.lib()
-    # (H, s, x, beta, P, n_sc, n_sym, B, U, C, T, rho, gamma, eps, stream)
-    ok = [1, 1, 1, None, None, 4, 1, 256, 32, 16, 5, 1.0, 1.0, 0.0, None]
+    # (H, s, x, beta, P, power_mode, n_sc, n_sym, B, U, C, T, rho, gamma, eps, stream)
+    ok = [1, 1, 1, None, None, 0, 4, 1, 256, 32, 16, 5, 1.0, 1.0, 0.0, None]
     bad_S = list(ok)
-    bad_S[9] = 4          # C = 4 -> S = 64 > U = 32 (U x U branch)
+    bad_S[10] = 4         # C = 4 -> S = 64 > U = 32 (U x U branch)
     assert L.dbp_precode_admm(*bad_S) == 2
     bad_rho = list(ok)
-    bad_rho[11] = 0.0
+    bad_rho[12] = 0.0
     assert L.dbp_precode_admm(*bad_rho) == 1
     bad_ptr = list(ok)
     bad_ptr[2] = None
     assert L.dbp_precode_admm(*bad_ptr) == 1
     for e in (-0.1, float("nan"), float("inf")):
         bad_eps = list(ok)
-        bad_eps[13] = e
+        bad_eps[14] = e
         assert L.dbp_precode_admm(*bad_eps) == 1
+    bad_mode = list(ok)
+    bad_mode[5] = 2
+    assert L.dbp_precode_admm(*bad_mode) == 1
 
 
 def test_factor_entry_points_reject():

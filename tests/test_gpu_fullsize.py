@@ -106,6 +106,31 @@ def test_precode_bench_launch_sampled():
     assert np.abs(beta[sel].cpu().numpy() - refb).max() <= 1e-5
 
 
+def test_precode_budget_bench_launch_sampled():
+    """Configuration 3 with the budgeted step (P1): 38,400 subcarriers in one
+    launch, 48 sampled subcarriers against the oracle."""
+    say("[gpu] full-size launch budgeted precode B=256 U=32 C=16")
+    n_sc, B, U, C = 38400, 256, 32, 16
+    g = torch.Generator(device="cuda")
+    g.manual_seed(92)
+    L, kappa = inputs.qam_side(64), inputs.qam_kappa(64)
+    sd = 0.5 ** 0.5
+    H = torch.complex(torch.randn(n_sc, B, U, device="cuda", generator=g) * sd,
+                      torch.randn(n_sc, B, U, device="cuda", generator=g) * sd).contiguous()
+    iI = torch.randint(0, L, (n_sc, 1, U), device="cuda", generator=g)
+    iQ = torch.randint(0, L, (n_sc, 1, U), device="cuda", generator=g)
+    s = torch.complex((2 * iI - (L - 1)).float() / kappa, (2 * iQ - (L - 1)).float() / kappa).contiguous()
+    Pc = [0.005] * C
+    x, _ = api.precode(H, s, C, 1.0, 5, P_cluster=torch.tensor(Pc, dtype=torch.float32, device="cuda"),
+                       power="per_cluster")
+    torch.cuda.synchronize()
+    sel = np.unique(np.concatenate([[0, n_sc - 1], np.random.default_rng(6).choice(n_sc, 46, replace=False)]))
+    ref = O.admm_dl_frame(H[sel].cpu().numpy(), s[sel].cpu().numpy(), C, 1.0, 5, P=Pc)
+    err = rel_err(x[sel].cpu().numpy(), ref)
+    say(f"    rel_err={err:.2e}")
+    assert err <= 1e-5
+
+
 WHOLE_FRAMES = ([("admm", 128, 16, 8, 16, snr) for snr in (0.0, 5.0, 10.0, 15.0, 20.0)]
                 + [("cg", 128, 16, 8, 16, snr) for snr in (0.0, 5.0, 10.0, 15.0, 20.0)]
                 + [("admm", 256, 32, 8, 64, 25.0), ("admm", 256, 32, 8, 64, 15.0), ("admm", 64, 8, 4, 4, 10.0)])

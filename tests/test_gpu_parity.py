@@ -555,3 +555,42 @@ def test_reslice_recomputes_in_fp64():
         assert np.array_equal(s_hat[k], ref[k].astype(np.complex64)) or \
             np.abs(s_hat[k] - ref[k]).max() <= 2.0 ** -23 * np.abs(ref[k]).max()
     assert np.array_equal(h, O.slice_qam(ref, 16))
+
+
+# -- budgeted step (P1): every x-update meets ||x_c||^2 <= P_c exactly
+@pytest.mark.parametrize("B,U,C", [(256, 32, 16), (128, 16, 16), (64, 8, 8), (128, 16, 8), (256, 64, 8)])
+def test_precode_per_cluster_budget(B, U, C):
+    say(f"[gpu] precode budgeted P1 B={B} U={U} C={C}")
+    S = B // C
+    fr = inputs.downlink_frame(inputs.frame_seed(18, B + U, C), 23, B, U, 64)
+    # budgets below the unconstrained per-cluster energy on most subcarriers
+    free = O.admm_dl_frame(fr.H[:6], fr.s[:6], C, 1.0, 5)
+    e = np.array([[np.sum(np.abs(free[k, 0, c * S:(c + 1) * S]) ** 2) for c in range(C)] for k in range(6)])
+    Pc = [float(np.float32(0.5 * np.median(e) * (1.0 + 0.2 * (c % 3)))) for c in range(C)]
+    P = torch.tensor(Pc, dtype=torch.float32, device=DEV)
+    x, beta = api.precode(to_dev(fr.H), to_dev(fr.s), C, 1.0, 5, P_cluster=P, power="per_cluster")
+    torch.cuda.synchronize()
+    x, beta = x.cpu().numpy(), beta.cpu().numpy()
+    ref = O.admm_dl_frame(fr.H, fr.s, C, 1.0, 5, P=Pc)
+    err = rel_err(x, ref)
+    en = np.array([[np.sum(np.abs(ref[k, 0, c * S:(c + 1) * S]) ** 2) for c in range(C)] for k in range(23)])
+    active = np.mean(en >= np.array(Pc) * (1 - 1e-9))
+    say(f"    rel_err={err:.2e}, budget active on {active:.0%} of (subcarrier, cluster) at the last step")
+    assert active > 0.3
+    assert err <= 1e-5
+    assert per_vec_rel(x, ref) <= 1e-4
+    assert np.all(beta == 1.0)
+    for k in range(23):
+        for c in range(C):
+            assert np.sum(np.abs(x[k, 0, c * S:(c + 1) * S]) ** 2) <= Pc[c] * (1 + 1e-5)
+
+
+def test_precode_budget_that_never_binds():
+    """Budgets far above every cluster's energy: the budgeted form takes the
+    unconstrained step everywhere (Algorithm 3)."""
+    fr = inputs.downlink_frame(inputs.frame_seed(18, 1, 0), 17, 256, 32, 64)
+    P = torch.full((16,), 1e6, dtype=torch.float32, device=DEV)
+    x, _ = api.precode(to_dev(fr.H), to_dev(fr.s), 16, 1.0, 5, P_cluster=P, power="per_cluster")
+    x0, _ = api.precode(to_dev(fr.H), to_dev(fr.s), 16, 1.0, 5)
+    torch.cuda.synchronize()
+    assert rel_err(x.cpu().numpy(), x0.cpu().numpy()) <= 1e-6
