@@ -12,10 +12,10 @@
 // FP64).  The decisions then agree with an FP64 evaluation of the method
 // everywhere except within about 1e-14 of a threshold.
 //
-// Work split: workgroup g of the n_slots workgroups owns subcarriers
-// k = g, g + n_slots, g + 2 n_slots, ...; it reads their flags 1024 at a time,
-// lists the flagged ones in LDS and recomputes them one after another with all
-// 1024 threads.  The ADMM pass keeps the C regularised inverses of the current
+// Work split: the flags are scanned in windows of up to 16,384 subcarriers;
+// the flagged subcarriers of a window are ranked in index order and dealt
+// out round-robin over the n_slots workgroups, each of which recomputes its
+// share one subcarrier after another with all 1024 threads.  The ADMM pass keeps the C regularised inverses of the current
 // subcarrier (C U^2 complex FP64) in the workgroup's slot of the workspace;
 // every entry of a slot is written before it is read, so the workspace needs
 // no clearing.
@@ -56,17 +56,68 @@ __device__ __forceinline__ int slice64(double x, double kappa, int L) {
   return (int)i;
 }
 
-// Collects the flagged subcarriers among the next 256 this workgroup owns
-// (round r) into list[0 .. n); returns n (same value in every thread).
-__device__ int collect_round(const FixArgs& f, long r, int* list, int* cnt) {
-  __syncthreads();   // every thread has read the previous round's count
-  if (threadIdx.x == 0) *cnt = 0;
+// Flags per thread in one scan of the flag array, and the LDS list capacity.
+constexpr int kPerThread = 16;
+constexpr int kListCap = kFixThreads;
+
+// Subcarriers per round: every workgroup scans the whole window, so that the
+// flagged subcarriers can be shared out evenly; the window is small enough
+// that a workgroup's share fits the LDS list.
+__device__ __forceinline__ long fix_window() {
+  const long w = (long)kFixThreads * kPerThread, cap = (long)kListCap * gridDim.x;
+  return w < cap ? w : cap;
+}
+
+// Round r covers subcarriers [r W, (r + 1) W).  Every workgroup ranks the
+// flagged subcarriers of the window in index order (a block-wide prefix sum
+// of per-thread counts) and takes those of rank q with (q + r) mod G = g
+// (G workgroups, this one g), in rank order, into list[0 .. n); returns n.
+// The flagged subcarriers of a window are thus spread over the workgroups,
+// at most ceil(count / G) per workgroup.  wsum: LDS scratch of
+// kFixThreads / 64 + 1 ints.
+__device__ int collect_round(const FixArgs& f, long r, long W, int* list, int* wsum) {
+  __syncthreads();   // the previous round's list and sums are no longer read
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nwv = kFixThreads / 64;
+  const long end = ((r + 1) * W < f.n_sc) ? (r + 1) * W : f.n_sc;
+  const long base = r * W + (long)t * kPerThread;
+  unsigned bits = 0;
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const long k = base + i;
+    if (k < end && (f.flags[k] & kStatusReslice)) bits |= 1u << i;
+  }
+  const int mine = __popc(bits);
+  int incl = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  if (lane == 63) wsum[wv] = incl;
   __syncthreads();
-  const long j = r * kFixThreads + threadIdx.x;
-  const long k = (long)blockIdx.x + j * (long)gridDim.x;
-  if (k < f.n_sc && (f.flags[k] & kStatusReslice)) list[atomicAdd(cnt, 1)] = (int)k;
+  if (t == 0) {
+    int acc = 0;
+    for (int w = 0; w < nwv; ++w) {
+      const int v = wsum[w];
+      wsum[w] = acc;
+      acc += v;
+    }
+    wsum[nwv] = acc;
+  }
   __syncthreads();
-  return *cnt;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int q0 = (int)(((long)g - r % G + G) % G);   // first rank this workgroup takes
+  int q = wsum[wv] + incl - mine;                    // rank of this thread's first flagged subcarrier
+  const int total = wsum[nwv];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    if ((bits >> i) & 1u) {
+      if (q >= q0 && (q - q0) % G == 0) list[(q - q0) / G] = (int)(base + i);
+      ++q;
+    }
+  }
+  __syncthreads();
+  return total > q0 ? (total - q0 + G - 1) / G : 0;
 }
 
 // Proximal step of Lemma 1 on the summed vector w (E2-MMSE / E2-ZF: w / den,
@@ -117,13 +168,14 @@ __global__ void __launch_bounds__(kFixThreads) admm_ul_fix64(FixArgs f) {
   d2* colp = fsm;         // [CG][U] pivot columns
   d2* rowp = fsm + CG * U;   // [CG][U] pivot rows
   int* list = reinterpret_cast<int*>(fsm + (3 * CU + U > 2 * CG * U ? 3 * CU + U : 2 * CG * U));
-  int* cnt = list + kFixThreads;
+  int* wsum = list + kListCap;
   d2* Mslot = static_cast<d2*>(f.ws) + (size_t)blockIdx.x * C * UU;   // [C][U][U]
   const int tid = threadIdx.x;
   const int cl = tid / T2, tt = tid % T2, i0 = (tt / NT) * TI, j0 = (tt % NT) * TI;
 
-  for (long r = 0; (long)blockIdx.x + r * kFixThreads * (long)gridDim.x < f.n_sc; ++r) {
-    const int nl = collect_round(f, r, list, cnt);
+  const long W = fix_window();
+  for (long r = 0; r * W < f.n_sc; ++r) {
+    const int nl = collect_round(f, r, W, list, wsum);
     for (int q = 0; q < nl; ++q) {
       const int k = list[q];
       const c32* Hk = f.H + (size_t)k * f.B * U;
@@ -180,27 +232,35 @@ __global__ void __launch_bounds__(kFixThreads) admm_ul_fix64(FixArgs f) {
             d2 rj[TI];
 #pragma unroll
             for (int b = 0; b < TI; ++b) rj[b] = rowp[cl * U + j0 + b];
+            // the rank-1 update on every entry of the tile (straight-line
+            // code); the entries of pivot row p and column p are then
+            // overwritten, by the few threads whose tile holds them
+            d2 m[TI];
 #pragma unroll
             for (int a = 0; a < TI; ++a) {
               const d2 ci = colp[cl * U + i0 + a];
-              // the multiplier B[i][p] / d, once per row
-              const d2 m = d2{ci.re * inv, ci.im * inv};
+              m[a] = d2{ci.re * inv, ci.im * inv};   // the multiplier B[i][p] / d
 #pragma unroll
               for (int b = 0; b < TI; ++b) {
-                const bool ip = (i0 + a == p), jp = (j0 + b == p);
-                d2 v = M[a][b];
-                if (!ip && !jp) {
-                  v.re -= m.re * rj[b].re - m.im * rj[b].im;
-                  v.im -= m.re * rj[b].im + m.im * rj[b].re;
-                } else if (ip && !jp) {
-                  v = d2{rj[b].re * inv, rj[b].im * inv};
-                } else if (!ip) {
-                  v = d2{-m.re, -m.im};
-                } else {
-                  v = d2{inv, 0.0};
-                }
-                M[a][b] = v;
+                M[a][b].re -= m[a].re * rj[b].re - m[a].im * rj[b].im;
+                M[a][b].im -= m[a].re * rj[b].im + m[a].im * rj[b].re;
               }
+            }
+            if (i0 <= p && p < i0 + TI) {
+#pragma unroll
+              for (int a = 0; a < TI; ++a)
+                if (i0 + a == p) {
+#pragma unroll
+                  for (int b = 0; b < TI; ++b) M[a][b] = d2{rj[b].re * inv, rj[b].im * inv};
+                }
+            }
+            if (j0 <= p && p < j0 + TI) {
+#pragma unroll
+              for (int b = 0; b < TI; ++b)
+                if (j0 + b == p) {
+#pragma unroll
+                  for (int a = 0; a < TI; ++a) M[a][b] = (i0 + a == p) ? d2{inv, 0.0} : d2{-m[a].re, -m[a].im};
+                }
             }
           }
         }
@@ -296,11 +356,12 @@ __global__ void __launch_bounds__(kFixThreads) dcg_ul_fix64(FixArgs f) {
   d2* Hp = W + U;                // kChunk entries
   double* red = reinterpret_cast<double*>(Hp + kChunk);   // [0] rr, [1] pe / rr_new
   int* list = reinterpret_cast<int*>(red + 4);
-  int* cnt = list + kFixThreads;
+  int* wsum = list + kListCap;
   const int tid = threadIdx.x;
 
-  for (long r = 0; (long)blockIdx.x + r * kFixThreads * (long)gridDim.x < f.n_sc; ++r) {
-    const int nl = collect_round(f, r, list, cnt);
+  const long win = fix_window();
+  for (long r = 0; r * win < f.n_sc; ++r) {
+    const int nl = collect_round(f, r, win, list, wsum);
     for (int q = 0; q < nl; ++q) {
       const int k = list[q];
       const c32* Hk = f.H + (size_t)k * f.B * U;
@@ -393,7 +454,7 @@ hipError_t launch_admm_ul_fix64(const FixArgs& f, hipStream_t st) {
   const int TI = (U >= 32) ? 4 : U / 8;
   const int CG = kFixThreads / ((U / TI) * (U / TI));
   const int vec = 3 * CU + U, piv = 2 * CG * U;
-  const size_t lds = (size_t)(vec > piv ? vec : piv) * sizeof(d2) + (kFixThreads + 4) * sizeof(int);
+  const size_t lds = (size_t)(vec > piv ? vec : piv) * sizeof(d2) + (kListCap + kFixThreads / 64 + 4) * sizeof(int);
   const dim3 grid((unsigned)f.n_slots), block(kFixThreads);
   switch (U) {
     case 8: hipLaunchKernelGGL(admm_ul_fix64<8>, grid, block, lds, st, f); break;
@@ -406,7 +467,7 @@ hipError_t launch_admm_ul_fix64(const FixArgs& f, hipStream_t st) {
 }
 
 hipError_t launch_dcg_ul_fix64(const FixArgs& f, hipStream_t st) {
-  const size_t lds = (size_t)(4 * f.U + 1024) * sizeof(d2) + 4 * sizeof(double) + (kFixThreads + 4) * sizeof(int);
+  const size_t lds = (size_t)(4 * f.U + 1024) * sizeof(d2) + 4 * sizeof(double) + (kListCap + kFixThreads / 64 + 4) * sizeof(int);
   hipLaunchKernelGGL(dcg_ul_fix64, dim3((unsigned)f.n_slots), dim3(kFixThreads), lds, st, f);
   return hipGetLastError();
 }
