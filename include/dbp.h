@@ -246,8 +246,13 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard,
 
 /* Decentralized ADMM-based beamforming: Algorithm 3 (Section IV-C), S x S
  * branch (A_c = H_c^H H_c + rho^-1 I_S with the downlink cluster channel
- * H_c = (H^u_c)^T read from the uplink-layout H).
+ * H_c, U x S: columns cS .. cS+S-1 of the downlink channel H^d).
  *
+ *   H, h_layout  the channel, device: DBP_LAYOUT_UPLINK: the uplink channel
+ *          [n_sc][B][U] (complex64), taken in place as H^d = H^T (channel
+ *          reciprocity, Section II-B1); DBP_LAYOUT_DOWNLINK: the downlink
+ *          channel H^d itself, [n_sc][U][B] row-major.  DBP_ERR_INVALID for
+ *          any other value.
  *   s      [n_sc][n_sym][U] complex64  precoding targets
  *   x      [n_sc][n_sym][B] complex64  output [x_1; ...; x_C]
  *   beta   [n_sc][n_sym] float or NULL  output common gain (1 without budgets)
@@ -274,9 +279,36 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard,
  */
 #define DBP_POWER_COMMON_GAIN 0
 #define DBP_POWER_PER_CLUSTER 1
-int dbp_precode_admm(const void* H, const void* s, void* x, float* beta,
+#define DBP_LAYOUT_UPLINK 0
+#define DBP_LAYOUT_DOWNLINK 1
+int dbp_precode_admm(const void* H, int h_layout, const void* s, void* x, float* beta,
                      const float* P_cluster, int power_mode, int n_sc, int n_sym, int B, int U,
                      int C, int T, float rho, float gamma, float eps, void* stream);
+
+/* Launch-plan autotuner.  All clusters of a subcarrier share one workgroup;
+ * when they need fewer waves than the plan's minimum, a workgroup holds
+ * several subcarriers.  dbp_autotune times the candidate minimums 1, 2, 4
+ * and 8 waves (those giving distinct workgroups) on the caller's data, reps
+ * launches each, and keeps the fastest for every later call of that kernel
+ * family with the same U and padded cluster count (process-wide, all
+ * devices).  It synchronises the stream: a set-up call, not for the hot
+ * path.  Results of the detection and precoding calls do not depend on the
+ * plan.
+ *   kind  DBP_TUNE_ADMM (dbp_detect_admm and its factored forms),
+ *         DBP_TUNE_CG (dbp_detect_cg), DBP_TUNE_PRECODE (dbp_precode_admm)
+ *   H     [n_sc][B][U] device; in: y [n_sc][1][B] (ADMM, CG) or the targets
+ *         s [n_sc][1][U] (precode); out: s_hat [n_sc][1][U] or x [n_sc][1][B]
+ *         (overwritten with results of the tuned kernel: MMSE with N0 = 0.1,
+ *         rho = 1, no budgets)
+ *   best_waves  output (may be NULL): the chosen minimum
+ * dbp_autotune_get returns the minimum in use for (kind, U, C), -1 for
+ * malformed arguments. */
+#define DBP_TUNE_ADMM 0
+#define DBP_TUNE_CG 1
+#define DBP_TUNE_PRECODE 2
+int dbp_autotune(int kind, const void* H, const void* in, void* out, int n_sc, int B, int U, int C, int T,
+                 int reps, void* stream, int* best_waves);
+int dbp_autotune_get(int kind, int U, int C);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of uplink detection frames (Algorithm 1).

@@ -25,6 +25,8 @@ SIGNATURES = {
     "dbp_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "dbp_detect_admm_noalloc": (_i, [_vp, _vp, _vp, _u8p, _vp, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f, _i, _i, _i,
                                      _vp]),
+    "dbp_autotune": (_i, [_i, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _vp, ctypes.POINTER(_i)]),
+    "dbp_autotune_get": (_i, [_i, _i, _i]),
     "dbp_factor_bytes": (ctypes.c_size_t, [_i, _i, _i]),
     "dbp_factor_admm": (_i, [_vp, _vp, _i, _i, _i, _i, _f, _i, _vp]),
     "dbp_detect_admm_factored": (_i, [_vp, _vp, _vp, _vp, _u8p, _vp, _vp, ctypes.c_size_t, _i, _i, _i, _i, _i, _i,
@@ -36,7 +38,7 @@ SIGNATURES = {
                                           _i, _i, _vp]),
     "dbp_detect_cg": (_i, [_vp, _vp, _vp, _u8p, _vp, _vp, ctypes.c_size_t, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i,
                            _vp]),
-    "dbp_precode_admm": (_i, [_vp, _vp, _vp, _fp, _fp, _i, _i, _i, _i, _i, _i, _i, _f, _f, _f, _vp]),
+    "dbp_precode_admm": (_i, [_vp, _i, _vp, _vp, _fp, _fp, _i, _i, _i, _i, _i, _i, _i, _f, _f, _f, _vp]),
     "dbp_server_create": (_i, [_i, ctypes.c_size_t, _i, ctypes.POINTER(ctypes.c_void_p)]),
     "dbp_server_destroy": (_i, [_vp]),
     "dbp_server_submit": (_i, [_vp, _vp, _vp, _vp, _u8p, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i, _i, _i,

@@ -230,20 +230,28 @@ def detect_factored_h16(packed, factors, y, N0, B, U, C, rho=1.0, T=5, *, reg="m
 POWER = {"common_gain": 0, "per_cluster": 1}
 
 
-def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, eps=0.0, P_cluster=None, power="common_gain", out=None,
-            stream=None):
+def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, eps=0.0, P_cluster=None, power="common_gain", layout="uplink",
+            out=None, stream=None):
     """Decentralized ADMM beamforming (Algorithm 3; ``eps`` > 0 uses the
     z-update of Lemma 2 for the constraint ||s - H^d x|| <= eps).
 
-    ``H`` is the uplink-layout channel [n_sc, B, U]; ``s`` the targets
-    [n_sc, n_sym, U] (or [n_sc, U]).  ``P_cluster`` optional device float32
+    ``H`` is the uplink-layout channel [n_sc, B, U] (``layout="uplink"``,
+    used as H^d = H^T) or the downlink channel H^d [n_sc, U, B]
+    (``layout="downlink"``); ``s`` the targets [n_sc, n_sym, U] (or [n_sc, U]).  ``P_cluster`` optional device float32
     tensor [C] of per-cluster budgets, met by a common gain after the
     algorithm (``power="common_gain"``) or by the budgeted step (P1) in every
     x-update (``power="per_cluster"``).  Returns ``(x [n_sc, n_sym, B], beta [n_sc, n_sym])``.
     """
     _dev(H, "H")
     _dev(s, "s")
-    n_sc, B, U = H.shape
+    if H.dim() != 3:
+        raise ValueError("H must be [n_sc, B, U] (uplink) or [n_sc, U, B] (downlink)")
+    if layout == "uplink":
+        n_sc, B, U = H.shape
+    elif layout == "downlink":
+        n_sc, U, B = H.shape
+    else:
+        raise ValueError(layout)
     if s.dim() == 2:
         s = s.unsqueeze(1)
     n_sym = s.shape[1]
@@ -261,7 +269,7 @@ def precode(H, s, C, rho=1.0, T=5, *, gamma=1.0, eps=0.0, P_cluster=None, power=
         _check_out(x, "x", (n_sc, n_sym, B), torch.complex64, H.device)
         _check_out(beta, "beta", (n_sc, n_sym), torch.float32, H.device)
     L = _native.lib()
-    code = L.dbp_precode_admm(H.data_ptr(), s.data_ptr(), x.data_ptr(), beta.data_ptr(),
+    code = L.dbp_precode_admm(H.data_ptr(), 0 if layout == "uplink" else 1, s.data_ptr(), x.data_ptr(), beta.data_ptr(),
                               P_cluster.data_ptr() if P_cluster is not None else None, POWER[power],
                               n_sc, n_sym, B, U, C, T, float(rho), float(gamma), float(eps),
                               _stream(stream))
@@ -373,3 +381,27 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+TUNE = {"admm": 0, "cg": 1, "precode": 2}
+
+
+def autotune(kind, H, inp, out, C, T=5, reps=10, stream=None):
+    """Times the launch-plan candidates of a kernel family on the given device
+    data and keeps the fastest for later calls (``dbp_autotune``); returns
+    the chosen minimum waves per workgroup.  ``inp`` is y [n_sc, 1, B] (ADMM,
+    CG) or the targets s [n_sc, 1, U] (precode); ``out`` the matching output
+    buffer, overwritten."""
+    import ctypes
+
+    for t, n in ((H, "H"), (inp, "input"), (out, "output")):
+        _dev(t, n)
+    n_sc, B, U = H.shape
+    best = ctypes.c_int()
+    _native.check(_native.lib().dbp_autotune(TUNE[kind], H.data_ptr(), inp.data_ptr(), out.data_ptr(), n_sc, B, U,
+                                             C, T, reps, _stream(stream), ctypes.byref(best)))
+    return best.value
+
+
+def autotune_get(kind, U, C):
+    return _native.lib().dbp_autotune_get(TUNE[kind], U, C)

@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <atomic>
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/dbp.h"
 #include "dbp_launch.h"
@@ -40,32 +42,60 @@ int qam_side(int qam) {
   return 0;
 }
 
-// Waves per workgroup when the clusters of one subcarrier need fewer (a
-// build-time tuning knob; 1, 2, 4 or 8): the workgroup then holds several
-// subcarriers.
+// Waves per workgroup when the clusters of one subcarrier need fewer (1, 2,
+// 4 or 8): the workgroup then holds several subcarriers.  The default is a
+// build-time knob; dbp_autotune replaces it per (kernel family, U, Cp) by
+// the fastest measured value.  Results do not depend on the choice (the
+// consensus sums run in fixed cluster order inside one workgroup).
 #ifndef DBP_MIN_WAVES
 #define DBP_MIN_WAVES 4
 #endif
 
+enum PlanKind { kPlanAdmm = 0, kPlanCg = 1, kPlanDl = 2, kPlanKinds = 3 };
+
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+std::atomic<int> g_min_waves[kPlanKinds][4][5];   // [kind][log2 U - 3][log2 Cp]
+
+void init_min_waves() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (auto& k : g_min_waves)
+      for (auto& u : k)
+        for (auto& c : u) c.store(DBP_MIN_WAVES, std::memory_order_relaxed);
+  });
+}
+
+int min_waves(int kind, int U, int Cp) {
+  init_min_waves();
+  return g_min_waves[kind][log2i(U) - 3][log2i(Cp)].load(std::memory_order_relaxed);
+}
+
 // Launch plan: a lane group of U lanes per (subcarrier, cluster) problem,
 // P = 64 / U problems per wave, the Cp >= C (power of two) cluster slots of a
-// subcarrier in one workgroup.
+// subcarrier in one workgroup of nw waves holding scpb subcarriers.  The
+// plan is made once per call (the kernels' index mapping depends on it).
 struct Plan {
   int Cp, nw, scpb;
 };
 
-Plan make_plan(int U, int C) {
+Plan make_plan(int U, int C, int kind, int mw = 0) {
   Plan p;
   const int P = 64 / U;
   p.Cp = 1;
   while (p.Cp < C) p.Cp <<= 1;
+  if (mw <= 0) mw = min_waves(kind, U, p.Cp);
   if (p.Cp >= P) {
     const int wps = p.Cp / P;
-    p.nw = wps > DBP_MIN_WAVES ? wps : DBP_MIN_WAVES;
+    p.nw = wps > mw ? wps : mw;
     p.scpb = p.nw / wps;
   } else {
-    p.nw = DBP_MIN_WAVES;
-    p.scpb = DBP_MIN_WAVES * (P / p.Cp);
+    p.nw = mw;
+    p.scpb = mw * (P / p.Cp);
   }
   return p;
 }
@@ -132,8 +162,9 @@ int admm_args(const char* who, int n_sc, int n_sym, int B, int U, int C, int T, 
   if (!L) return fail(DBP_ERR_INVALID, "%s: qam=%d not in {4,16,64}", who, qam);
   const int S = B / C;
   *Sout = S;
-  const Plan pl = make_plan(U, C);
+  const Plan pl = make_plan(U, C, kPlanAdmm);
   *a = dbp::UlArgs{};
+  a->nw = pl.nw;
   a->n_sc = n_sc;
   a->n_sym = n_sym;
   a->B = B;
@@ -178,11 +209,9 @@ int admm_prec(const char* who, int prec, int U, int S, int* gram_prec, int* inv)
   return DBP_OK;
 }
 
-hipError_t launch_preprocessing(const dbp::UlArgs& a, int U, int C, int gram_prec, int inv, hipStream_t st,
-                                int stage) {
-  const Plan pl = make_plan(U, C);
-  if (gram_prec == DBP_PREC_FP32) return dbp::launch_admm_ul_f32(a, U, pl.nw, st, stage);
-  return dbp::launch_admm_ul_mixed(a, U, gram_prec, inv, pl.nw, st, stage);
+hipError_t launch_preprocessing(const dbp::UlArgs& a, int U, int gram_prec, int inv, hipStream_t st, int stage) {
+  if (gram_prec == DBP_PREC_FP32) return dbp::launch_admm_ul_f32(a, U, a.nw, st, stage);
+  return dbp::launch_admm_ul_mixed(a, U, gram_prec, inv, a.nw, st, stage);
 }
 
 // Re-slice guard (slicer units t = (kappa x + L) / 2, thresholds at the
@@ -306,7 +335,7 @@ int detect_admm_impl(const char* who, const void* H, const void* y, void* s_hat,
                      dbp::fix64_slot_bytes(U, C), max_slots < full_slots(n_sc) ? max_slots : full_slots(n_sc));
   if (st) return st;
   const hipStream_t hs = static_cast<hipStream_t>(stream);
-  st = device_status(who, launch_preprocessing(a, U, C, gram_prec, inv, hs, 0));
+  st = device_status(who, launch_preprocessing(a, U, gram_prec, inv, hs, 0));
   if (st || !hard) return st;
   fix_params(f, U, rho, gamma, N0, Es, reg, qam, true);
   return device_status(who, dbp::launch_admm_ul_fix64(f, hs));
@@ -347,7 +376,7 @@ int dbp_factor_admm(const void* H, void* factors, int n_sc, int B, int U, int C,
   // serves as a readable stand-in for y (n_sym = 1 keeps every read inside it)
   a.y = a.H;
   a.fac = static_cast<dbp::c32*>(factors);
-  return device_status(who, launch_preprocessing(a, U, C, gram_prec, inv, static_cast<hipStream_t>(stream), 1));
+  return device_status(who, launch_preprocessing(a, U, gram_prec, inv, static_cast<hipStream_t>(stream), 1));
 }
 
 int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, void* s_hat, uint8_t* hard,
@@ -374,9 +403,8 @@ int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, 
   st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(DBP_PREC_FP32, 0, U),
                      dbp::fix64_slot_bytes(U, C), full_slots(n_sc));
   if (st) return st;
-  const Plan pl = make_plan(U, C);
   const hipStream_t hs = static_cast<hipStream_t>(stream);
-  st = device_status(who, dbp::launch_admm_ul_factored(a, U, pl.nw, hs));
+  st = device_status(who, dbp::launch_admm_ul_factored(a, U, a.nw, hs));
   if (st || !hard) return st;
   fix_params(f, U, rho, gamma, N0, Es, reg, qam, true);
   return device_status(who, dbp::launch_admm_ul_fix64(f, hs));
@@ -427,8 +455,7 @@ int dbp_detect_admm_factored_h16(const void* packed, const void* factors, const 
   a.fac = const_cast<dbp::c32*>(static_cast<const dbp::c32*>(factors));
   a.flags = status;   // non-finite bit only: the low-precision path is not re-sliced
   a.guard = 0.f;
-  const Plan pl = make_plan(U, C);
-  return device_status(who, dbp::launch_admm_ul_factored_h16(a, U, pl.nw, static_cast<hipStream_t>(stream)));
+  return device_status(who, dbp::launch_admm_ul_factored_h16(a, U, a.nw, static_cast<hipStream_t>(stream)));
 }
 
 int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int32_t* status, void* workspace,
@@ -445,7 +472,7 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int3
   if (!L) return fail(DBP_ERR_INVALID, "%s: qam=%d not in {4,16,64}", who, qam);
   if (n_sc > 0 && (!H || !y || !x_hat)) return fail(DBP_ERR_INVALID, "%s: null H, y or x_hat", who);
   if (n_sc == 0) return ok();
-  const Plan pl = make_plan(U, C);
+  const Plan pl = make_plan(U, C, kPlanCg);
   dbp::UlArgs a{};
   a.H = static_cast<const dbp::c32*>(H);
   a.y = static_cast<const dbp::c32*>(y);
@@ -478,12 +505,14 @@ int dbp_detect_cg(const void* H, const void* y, void* x_hat, uint8_t* hard, int3
   return device_status(who, dbp::launch_dcg_ul_fix64(f, hs));
 }
 
-int dbp_precode_admm(const void* H, const void* s, void* x, float* beta, const float* P_cluster, int power_mode,
-                     int n_sc, int n_sym, int B, int U, int C, int T, float rho, float gamma, float eps,
-                     void* stream) {
+int dbp_precode_admm(const void* H, int h_layout, const void* s, void* x, float* beta, const float* P_cluster,
+                     int power_mode, int n_sc, int n_sym, int B, int U, int C, int T, float rho, float gamma,
+                     float eps, void* stream) {
   const char* who = "dbp_precode_admm";
   int st = common_shape(who, n_sc, n_sym, B, U, C, T);
   if (st) return st;
+  if (h_layout != DBP_LAYOUT_UPLINK && h_layout != DBP_LAYOUT_DOWNLINK)
+    return fail(DBP_ERR_INVALID, "%s: h_layout=%d", who, h_layout);
   if (power_mode != DBP_POWER_COMMON_GAIN && power_mode != DBP_POWER_PER_CLUSTER)
     return fail(DBP_ERR_INVALID, "%s: power_mode=%d", who, power_mode);
   if (!(rho > 0.f) || !std::isfinite(rho)) return fail(DBP_ERR_INVALID, "%s: rho must be > 0", who);
@@ -493,7 +522,7 @@ int dbp_precode_admm(const void* H, const void* s, void* x, float* beta, const f
   const int S = B / C;
   if (S > U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d > U=%d (U x U branch) not built", who, S, U);
   if (n_sc == 0) return ok();
-  const Plan pl = make_plan(U, C);
+  const Plan pl = make_plan(U, C, kPlanDl);
   dbp::DlArgs a{};
   a.H = static_cast<const dbp::c32*>(H);
   a.s = static_cast<const dbp::c32*>(s);
@@ -514,7 +543,81 @@ int dbp_precode_admm(const void* H, const void* s, void* x, float* beta, const f
   a.f0 = (float)std::fmax((double)U / B, 1.0 / C);
   a.eps = eps;
   a.budget = (power_mode == DBP_POWER_PER_CLUSTER) ? 1 : 0;
+  a.h_layout = h_layout;
   return device_status(who, dbp::launch_admm_dl_f32(a, U, pl.nw, static_cast<hipStream_t>(stream)));
+}
+
+int dbp_autotune(int kind, const void* H, const void* in, void* out, int n_sc, int B, int U, int C, int T,
+                 int reps, void* stream, int* best_waves) {
+  const char* who = "dbp_autotune";
+  if (kind < DBP_TUNE_ADMM || kind > DBP_TUNE_PRECODE) return fail(DBP_ERR_INVALID, "%s: kind=%d", who, kind);
+  if (reps < 1 || n_sc < 1) return fail(DBP_ERR_INVALID, "%s: reps and n_sc must be >= 1", who);
+  if (!H || !in || !out) return fail(DBP_ERR_INVALID, "%s: null H, input or output", who);
+  int st = common_shape(who, n_sc, 1, B, U, C, T);
+  if (st) return st;
+  const hipStream_t hs = static_cast<hipStream_t>(stream);
+  auto run = [&]() -> int {
+    switch (kind) {
+      case DBP_TUNE_ADMM:
+        return dbp_detect_admm(H, in, out, nullptr, nullptr, nullptr, 0, n_sc, 1, B, U, C, T, 1.0f, 1.0f, 0.1f, 1.0f,
+                               DBP_REG_MMSE, 16, DBP_PREC_FP32, stream);
+      case DBP_TUNE_CG:
+        return dbp_detect_cg(H, in, out, nullptr, nullptr, nullptr, 0, n_sc, 1, B, U, C, T, 0.1f, 1.0f,
+                             DBP_REG_MMSE, 16, stream);
+      default:
+        return dbp_precode_admm(H, DBP_LAYOUT_UPLINK, in, out, nullptr, nullptr, DBP_POWER_COMMON_GAIN, n_sc, 1, B,
+                                U, C, T, 1.0f, 1.0f, 0.0f, stream);
+    }
+  };
+  const int pk = kind == DBP_TUNE_ADMM ? kPlanAdmm : (kind == DBP_TUNE_CG ? kPlanCg : kPlanDl);
+  int Cp = 1;
+  while (Cp < C) Cp <<= 1;
+  init_min_waves();
+  std::atomic<int>& slot = g_min_waves[pk][log2i(U) - 3][log2i(Cp)];
+  const int before = slot.load();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(DBP_ERR_DEVICE, "%s: hipEventCreate failed", who);
+  }
+  float best_ms = 0.f;
+  int best = before, last_nw = -1;
+  for (int mw : {1, 2, 4, 8}) {
+    // candidates that give the same workgroup as one already timed are skipped
+    const int nw = make_plan(U, C, pk, mw).nw;
+    if (nw == last_nw) continue;
+    last_nw = nw;
+    slot.store(mw);
+    st = run();                                        // warm-up
+    if (st) break;
+    if (hipEventRecord(e0, hs) != hipSuccess) { st = fail(DBP_ERR_DEVICE, "%s: hipEventRecord", who); break; }
+    for (int r = 0; r < reps && !st; ++r) st = run();
+    if (st) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(DBP_ERR_DEVICE, "%s: event timing failed", who);
+      break;
+    }
+    if (best_ms == 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = mw;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  slot.store(st ? before : best);
+  if (st) return st;
+  if (best_waves) *best_waves = best;
+  return ok();
+}
+
+int dbp_autotune_get(int kind, int U, int C) {
+  if (kind < DBP_TUNE_ADMM || kind > DBP_TUNE_PRECODE || !supported_u(U) || C < 1 || C > 16) return -1;
+  int Cp = 1;
+  while (Cp < C) Cp <<= 1;
+  const int pk = kind == DBP_TUNE_ADMM ? kPlanAdmm : (kind == DBP_TUNE_CG ? kPlanCg : kPlanDl);
+  return min_waves(pk, U, Cp);
 }
 
 }  // extern "C"

@@ -1517,7 +1517,12 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   c32* line = sm.line + wave * 64;
   const int gbase = g * G;
   const int S = a.S;
-  const c32* Hk = a.H + (size_t)k * a.B * G + (size_t)c * S * G;
+  // Entry (a, u) of the S x U uplink block Hu_c: row-major in the uplink
+  // layout [n_sc][B][U] (strides U and 1), or read from the downlink layout
+  // H^d [n_sc][U][B] (strides 1 and B).
+  const bool dl_layout = a.h_layout == 1;
+  const c32* Hk = a.H + (size_t)k * a.B * G + (dl_layout ? (size_t)c * S : (size_t)c * S * G);
+  const size_t sa = dl_layout ? 1 : G, su = dl_layout ? (size_t)a.B : 1;
 
   // When SG = G / 2 the row of Hu_c that H_c^H v needs is split over two
   // lanes: lane u holds entries RS * (u / SG) .. + RS - 1 of row u % SG, and
@@ -1534,12 +1539,12 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   constexpr bool LATE_H = (G == 32 && SG == 16);
 #pragma unroll
   for (int i = 0; i < SG; ++i) {
-    hcol[i] = (active && i < S) ? Hk[(size_t)i * G + u] : cz();
+    hcol[i] = (active && i < S) ? Hk[(size_t)i * sa + (size_t)u * su] : cz();
     A[i] = cz();
   }
   if constexpr (!LATE_H) {
 #pragma unroll
-    for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * G + r0 + i] : cz();
+    for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * sa + (size_t)(r0 + i) * su] : cz();
   }
   // The Gram H_c^H H_c, (H_c^H H_c)[a][b] = sum_u conj(Hu[a][u]) Hu[b][u], into
   // M (rows a < S; M must hold zeros).  Every lane of the wave takes part.

@@ -34,6 +34,7 @@ struct UlArgs {
   const float* hscale;  // [n_sc][C] power-of-two scale of each (subcarrier, cluster) tile of H16
   int32_t* flags;     // [n_sc] per-subcarrier status bits written by the detection kernels, or null
   float guard;        // re-slice guard in slicer units t = (kappa x + L) / 2; 0: no re-slice
+  int nw;             // waves per workgroup of the call's launch plan
 };
 
 // Exact re-slicing: the subcarriers the FP32 kernel flagged (a soft value
@@ -62,6 +63,7 @@ struct DlArgs {
   float rho, gamma, invC, f0;
   float eps;          // radius of ||s - sum_c z_c|| <= eps (Lemma 2); 0 = equality (Alg. 3)
   int budget;         // with P: 0 common gain after Algorithm 3, 1 budgeted step (P1) in every x-update
+  int h_layout;       // 0: H in the uplink layout [n_sc][B][U]; 1: downlink layout [n_sc][U][B]
 };
 
 size_t smem_bytes(int nw);

@@ -105,24 +105,27 @@ def test_detect_cg_rejects():
 
 def test_precode_rejects():
     L = _native.lib()
-    # (H, s, x, beta, P, power_mode, n_sc, n_sym, B, U, C, T, rho, gamma, eps, stream)
-    ok = [1, 1, 1, None, None, 0, 4, 1, 256, 32, 16, 5, 1.0, 1.0, 0.0, None]
+    # (H, h_layout, s, x, beta, P, power_mode, n_sc, n_sym, B, U, C, T, rho, gamma, eps, stream)
+    ok = [1, 0, 1, 1, None, None, 0, 4, 1, 256, 32, 16, 5, 1.0, 1.0, 0.0, None]
     bad_S = list(ok)
-    bad_S[10] = 4         # C = 4 -> S = 64 > U = 32 (U x U branch)
+    bad_S[11] = 4         # C = 4 -> S = 64 > U = 32 (U x U branch)
     assert L.dbp_precode_admm(*bad_S) == 2
     bad_rho = list(ok)
-    bad_rho[12] = 0.0
+    bad_rho[13] = 0.0
     assert L.dbp_precode_admm(*bad_rho) == 1
     bad_ptr = list(ok)
-    bad_ptr[2] = None
+    bad_ptr[3] = None
     assert L.dbp_precode_admm(*bad_ptr) == 1
     for e in (-0.1, float("nan"), float("inf")):
         bad_eps = list(ok)
-        bad_eps[14] = e
+        bad_eps[15] = e
         assert L.dbp_precode_admm(*bad_eps) == 1
     bad_mode = list(ok)
-    bad_mode[5] = 2
+    bad_mode[6] = 2
     assert L.dbp_precode_admm(*bad_mode) == 1
+    bad_layout = list(ok)
+    bad_layout[1] = 2
+    assert L.dbp_precode_admm(*bad_layout) == 1
 
 
 def test_factor_entry_points_reject():
@@ -171,3 +174,17 @@ def test_flag_nonfinite_rejects():
     assert L.dbp_flag_nonfinite(None, 4, 4, 1, None) == 1
     assert L.dbp_flag_nonfinite(1, 4, 4, None, None) == 1
     assert L.dbp_flag_nonfinite(None, 0, 4, None, None) == 0
+
+
+def test_autotune_rejects_and_defaults():
+    L = _native.lib()
+    # dbp_autotune(kind, H, in, out, n_sc, B, U, C, T, reps, stream, best)
+    assert L.dbp_autotune(7, 1, 1, 1, 4, 128, 16, 8, 5, 3, None, None) == 1       # kind
+    assert L.dbp_autotune(0, None, 1, 1, 4, 128, 16, 8, 5, 3, None, None) == 1    # null H
+    assert L.dbp_autotune(0, 1, 1, 1, 4, 128, 16, 8, 5, 0, None, None) == 1       # reps
+    assert L.dbp_autotune(0, 1, 1, 1, 4, 128, 12, 8, 5, 3, None, None) == 2       # U not built
+    # the build-time default plan: at least four waves per workgroup
+    assert L.dbp_autotune_get(0, 16, 8) == 4
+    assert L.dbp_autotune_get(1, 32, 8) == 4
+    assert L.dbp_autotune_get(2, 32, 16) == 4
+    assert L.dbp_autotune_get(0, 12, 8) == -1

@@ -594,3 +594,42 @@ def test_precode_budget_that_never_binds():
     x0, _ = api.precode(to_dev(fr.H), to_dev(fr.s), 16, 1.0, 5)
     torch.cuda.synchronize()
     assert rel_err(x.cpu().numpy(), x0.cpu().numpy()) <= 1e-6
+
+
+@pytest.mark.parametrize("B,U,C", [(256, 32, 16), (128, 16, 8), (256, 64, 8)])
+def test_precode_downlink_layout(B, U, C):
+    """H given as the downlink channel H^d [n_sc][U][B] (the transpose of the
+    uplink layout, made contiguous) gives the same precoder output as the
+    uplink layout read in place, with and without budgets."""
+    say(f"[gpu] precode downlink-native layout B={B} U={U} C={C}")
+    fr = inputs.downlink_frame(inputs.frame_seed(19, B + U, C), 13, B, U, 64)
+    Hu = to_dev(fr.H)
+    Hd = Hu.transpose(1, 2).contiguous()
+    s = to_dev(fr.s)
+    P = torch.full((C,), 0.01, dtype=torch.float32, device=DEV)
+    for kw in ({}, {"P_cluster": P, "power": "per_cluster"}, {"eps": 0.3}):
+        xu, _ = api.precode(Hu, s, C, 1.0, 5, **kw)
+        xd, _ = api.precode(Hd, s, C, 1.0, 5, layout="downlink", **kw)
+        torch.cuda.synchronize()
+        assert rel_err(xd.cpu().numpy(), xu.cpu().numpy()) <= 1e-6
+    ref = O.admm_dl_frame(fr.H, fr.s, C, 1.0, 5)
+    xd, _ = api.precode(Hd, s, C, 1.0, 5, layout="downlink")
+    torch.cuda.synchronize()
+    assert rel_err(xd.cpu().numpy(), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["admm", "cg"])
+def test_autotune_keeps_results(kind):
+    """The autotuner picks a launch plan by timing; detection results are the
+    same bits under every plan."""
+    say(f"[gpu] autotune {kind}")
+    fr = inputs.uplink_frame(inputs.frame_seed(20, 0, 10), 600, 128, 16, 16, 10.0)
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    before, hb = api.detect(H, y, fr.N0, 8, 1.0, 5, algo=kind, qam=16)
+    scratch = torch.empty_like(before)
+    best = api.autotune(kind, H, y, scratch, 8, 5, reps=3)
+    assert best in (1, 2, 4, 8) and api.autotune_get(kind, 16, 8) == best
+    after, ha = api.detect(H, y, fr.N0, 8, 1.0, 5, algo=kind, qam=16)
+    torch.cuda.synchronize()
+    say(f"    chose {best} waves minimum")
+    assert torch.equal(before, after) and torch.equal(hb, ha)
