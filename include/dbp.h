@@ -285,6 +285,30 @@ int dbp_precode_admm(const void* H, int h_layout, const void* s, void* x, float*
                      const float* P_cluster, int power_mode, int n_sc, int n_sym, int B, int U,
                      int C, int T, float rho, float gamma, float eps, void* stream);
 
+/* Uneven batches in one launch: up to DBP_MAX_BATCH frames of ADMM
+ * detection (Algorithm 1, FP32) that share U but may differ in every other
+ * shape and parameter (n_sc, n_sym, B, C, T, regulariser, QAM, rho, N0) run
+ * in one persistent kernel over all their subcarriers, followed by one FP64
+ * re-slice pass over the frames with hard decisions.  Each dbp_frame holds
+ * what dbp_detect_admm takes for one frame (device pointers, caller-owned;
+ * workspace as there, needed with hard decisions).  Results are
+ * bit-identical to dbp_detect_admm on each frame alone.  Frames are
+ * validated first (DBP_ERR_INVALID / DBP_ERR_UNSUPPORTED name the frame);
+ * n_frames = 0 is a no-op; prec is FP32 only. */
+#define DBP_MAX_BATCH 24
+typedef struct dbp_frame {
+  const void* H;          /* [n_sc][B][U] complex64 */
+  const void* y;          /* [n_sc][n_sym][B] complex64 */
+  void* s_hat;            /* [n_sc][n_sym][U] complex64 */
+  uint8_t* hard;          /* [n_sc][n_sym][U] or NULL */
+  int32_t* status;        /* [n_sc] or NULL */
+  void* workspace;        /* dbp_detect_workspace_bytes(n_sc, U, C) bytes with hard decisions */
+  size_t workspace_bytes;
+  int n_sc, n_sym, B, C, T, reg, qam;
+  float rho, gamma, N0, Es;
+} dbp_frame;
+int dbp_detect_admm_batch(const dbp_frame* frames, int n_frames, int U, void* stream);
+
 /* Launch-plan autotuner.  All clusters of a subcarrier share one workgroup;
  * when they need fewer waves than the plan's minimum, a workgroup holds
  * several subcarriers.  dbp_autotune times the candidate minimums 1, 2, 4

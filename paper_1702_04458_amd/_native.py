@@ -52,6 +52,19 @@ SIGNATURES = {
     "dbp_server_stats": (_i, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_uint64)]),
 }
 
+class Frame(ctypes.Structure):
+    """dbp_frame of include/dbp.h (one frame of a batched detection call)."""
+    _fields_ = [("H", ctypes.c_void_p), ("y", ctypes.c_void_p), ("s_hat", ctypes.c_void_p),
+                ("hard", ctypes.c_void_p), ("status", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t),
+                ("n_sc", ctypes.c_int), ("n_sym", ctypes.c_int), ("B", ctypes.c_int), ("C", ctypes.c_int),
+                ("T", ctypes.c_int), ("reg", ctypes.c_int), ("qam", ctypes.c_int),
+                ("rho", ctypes.c_float), ("gamma", ctypes.c_float), ("N0", ctypes.c_float), ("Es", ctypes.c_float)]
+
+
+SIGNATURES["dbp_detect_admm_batch"] = (ctypes.c_int, [ctypes.POINTER(Frame), ctypes.c_int, ctypes.c_int,
+                                                      ctypes.c_void_p])
+
 _lib = None
 
 

@@ -83,16 +83,26 @@ def workspace(n_sc, U, C, device="cuda"):
 
 
 def _workspace(ws, hd, n_sc, U, C, device):
-    """(pointer, bytes) of the re-slice workspace: needed with hard decisions."""
+    """(pointer, bytes, tensor) of the re-slice workspace, needed with hard
+    decisions.  The caller keeps the tensor referenced until the call that
+    uses it has been queued (a workspace allocated here must not return to
+    the allocator before that)."""
     if hd is None:
-        return None, 0
+        return None, 0, None
     need = _native.lib().dbp_detect_workspace_bytes(n_sc, U, C)
     if ws is None:
         ws = workspace(n_sc, U, C, device)
     _dev(ws, "workspace", torch.uint8)
     if ws.device != device or ws.numel() < need:
         raise ValueError(f"workspace must be a device uint8 tensor of >= {need} bytes on {device}")
-    return ws.data_ptr(), ws.numel()
+    return ws.data_ptr(), ws.numel(), ws
+
+
+def _mark_stream(ws, given, stream):
+    """A workspace allocated here on the current stream but used on another
+    one must not be handed out again before that stream's work is done."""
+    if ws is not None and given is None and stream is not None:
+        ws.record_stream(stream)
 
 
 def _ret(s_hat, hd, stt, status):
@@ -116,7 +126,8 @@ def detect(H, y, N0, C, rho=1.0, T=5, *, algo="admm", reg="mmse", qam=16, Es=1.0
     _dev(y, "y")
     n_sc, n_sym, B, U, y = _shapes(H, y)
     s_hat, hd, stt = _outputs(out, n_sc, n_sym, U, H.device, hard, status)
-    wp, wb = _workspace(workspace, hd, n_sc, U, C, H.device)
+    wp, wb, _ws_keep = _workspace(workspace, hd, n_sc, U, C, H.device)
+    _mark_stream(_ws_keep, workspace, stream)
     L = _native.lib()
     st = _stream(stream)
     hp = hd.data_ptr() if hd is not None else None
@@ -151,6 +162,49 @@ def factor(H, C, rho=1.0, *, prec="fp32", factor=None, out=None, stream=None):
     return f
 
 
+def detect_batch(frames, *, stream=None):
+    """Uneven batch of ADMM detection frames in one launch
+    (``dbp_detect_admm_batch``).  ``frames`` is a list of dicts with keys H
+    [n_sc, B, U], y [n_sc, n_sym, B], N0, C and optionally rho, T, qam, reg,
+    Es, gamma, hard (default True), status (default False), workspace; every
+    frame must have the same U.  Returns a list of (s_hat, hard[, status])
+    per frame, as :func:`detect`."""
+    import ctypes
+
+    if not frames:
+        return []
+    if len(frames) > 24:
+        raise ValueError("at most 24 frames per batch (DBP_MAX_BATCH)")
+    arr = (_native.Frame * len(frames))()
+    results, keep = [], []
+    U = None
+    for i, f in enumerate(frames):
+        H, y = _dev(f["H"], "H"), _dev(f["y"], "y")
+        n_sc, n_sym, B, Uf, y = _shapes(H, y)
+        if U is None:
+            U = Uf
+        elif Uf != U:
+            raise ValueError("every frame of a batch must have the same U")
+        C = int(f["C"])
+        s_hat, hd, stt = _outputs(None, n_sc, n_sym, U, H.device, f.get("hard", True), f.get("status", False))
+        wp, wb, wt = _workspace(f.get("workspace"), hd, n_sc, U, C, H.device)
+        _mark_stream(wt, f.get("workspace"), stream)
+        keep.append((H, y, wt))
+        e = arr[i]
+        e.H, e.y, e.s_hat = H.data_ptr(), y.data_ptr(), s_hat.data_ptr()
+        e.hard = hd.data_ptr() if hd is not None else None
+        e.status = stt.data_ptr() if stt is not None else None
+        e.workspace, e.workspace_bytes = wp, wb
+        e.n_sc, e.n_sym, e.B, e.C, e.T = n_sc, n_sym, B, C, int(f.get("T", 5))
+        e.reg, e.qam = REG[f.get("reg", "mmse")], int(f.get("qam", 16))
+        e.rho, e.gamma, e.N0, e.Es = (float(f.get("rho", 1.0)), float(f.get("gamma", 1.0)), float(f["N0"]),
+                                      float(f.get("Es", 1.0)))
+        results.append(_ret(s_hat, hd, stt, f.get("status", False)))
+    code = _native.lib().dbp_detect_admm_batch(arr, len(frames), U, _stream(stream))
+    _native.check(code)
+    return results
+
+
 def detect_factored(H, factors, y, N0, C, rho=1.0, T=5, *, reg="mmse", qam=16, Es=1.0, gamma=1.0, hard=True,
                     status=False, out=None, workspace=None, stream=None):
     """Algorithm 1's iterations against resident factors from :func:`factor`
@@ -162,7 +216,8 @@ def detect_factored(H, factors, y, N0, C, rho=1.0, T=5, *, reg="mmse", qam=16, E
     if factors.numel() * 8 != _native.lib().dbp_factor_bytes(n_sc, U, C):
         raise ValueError("factors do not match (n_sc, U, C)")
     s_hat, hd, stt = _outputs(out, n_sc, n_sym, U, H.device, hard, status)
-    wp, wb = _workspace(workspace, hd, n_sc, U, C, H.device)
+    wp, wb, _ws_keep = _workspace(workspace, hd, n_sc, U, C, H.device)
+    _mark_stream(_ws_keep, workspace, stream)
     code = _native.lib().dbp_detect_admm_factored(
         H.data_ptr(), factors.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hd.data_ptr() if hd is not None else None,
         stt.data_ptr() if stt is not None else None, wp, wb,

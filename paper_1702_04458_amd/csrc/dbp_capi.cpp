@@ -620,4 +620,103 @@ int dbp_autotune_get(int kind, int U, int C) {
   return min_waves(pk, U, Cp);
 }
 
+int dbp_detect_admm_batch(const dbp_frame* frames, int n_frames, int U, void* stream) {
+  const char* who = "dbp_detect_admm_batch";
+  if (n_frames < 0 || n_frames > DBP_MAX_BATCH)
+    return fail(DBP_ERR_INVALID, "%s: n_frames=%d outside 0..%d", who, n_frames, DBP_MAX_BATCH);
+  if (n_frames > 0 && !frames) return fail(DBP_ERR_INVALID, "%s: null frames", who);
+  if (!supported_u(U)) return fail(DBP_ERR_UNSUPPORTED, "%s: U=%d not built (8, 16, 32, 64)", who, U);
+  // validation of every frame, and the common waves per workgroup
+  int nw = 1, C_max = 1;
+  for (int i = 0; i < n_frames; ++i) {
+    const dbp_frame& fr = frames[i];
+    dbp::UlArgs a;
+    int S = 0;
+    int st = admm_args(who, fr.n_sc, fr.n_sym, fr.B, U, fr.C, fr.T, fr.rho, fr.gamma, fr.N0, fr.Es, fr.reg, fr.qam,
+                       &a, &S);
+    if (st) return st;
+    if (S < U) return fail(DBP_ERR_UNSUPPORTED, "%s: frame %d: S=%d < U=%d (S x S branch) not built", who, i, S, U);
+    if (fr.n_sc > 0 && (!fr.H || !fr.y || !fr.s_hat)) return fail(DBP_ERR_INVALID, "%s: frame %d: null pointer", who, i);
+    if (fr.hard && fr.n_sc > 0) {
+      if (!fr.workspace || fr.workspace_bytes < dbp_detect_workspace_bytes(fr.n_sc, U, fr.C) ||
+          reinterpret_cast<uintptr_t>(fr.workspace) % 256)
+        return fail(DBP_ERR_INVALID, "%s: frame %d: hard decisions need a 256-byte aligned workspace of "
+                    "dbp_detect_workspace_bytes bytes", who, i);
+    }
+    nw = a.nw > nw ? a.nw : nw;
+    C_max = fr.C > C_max ? fr.C : C_max;
+  }
+  dbp::UlBatch b{};
+  dbp::FixBatch fb{};
+  // FP64 slots: in the workspace (after its flags) with the most room
+  const size_t slot = dbp::fix64_slot_bytes(U, C_max);
+  char* slots = nullptr;
+  size_t slot_room = 0;
+  for (int i = 0; i < n_frames; ++i) {
+    const dbp_frame& fr = frames[i];
+    if (!fr.hard || fr.n_sc == 0) continue;
+    const size_t fl = fr.status ? 0 : flags_region(fr.n_sc);
+    if (fr.workspace_bytes - fl > slot_room) {
+      slot_room = fr.workspace_bytes - fl;
+      slots = static_cast<char*>(fr.workspace) + fl;
+    }
+  }
+  int n_slots = (int)(slot_room / slot);
+  if (n_slots > dbp::kFixMaxSlots) n_slots = dbp::kFixMaxSlots;
+  int total = 0;
+  for (int i = 0; i < n_frames; ++i) {
+    const dbp_frame& fr = frames[i];
+    dbp::UlArgs& a = b.f[b.n];
+    int S = 0;
+    (void)admm_args(who, fr.n_sc, fr.n_sym, fr.B, U, fr.C, fr.T, fr.rho, fr.gamma, fr.N0, fr.Es, fr.reg, fr.qam, &a,
+                    &S);
+    if (fr.n_sc == 0) continue;
+    // the frame's plan at the batch's waves per workgroup
+    const Plan pl = make_plan(U, fr.C, kPlanAdmm, nw);
+    a.nw = pl.nw;
+    a.Cp = pl.Cp;
+    a.sc_per_block = pl.scpb;
+    a.H = static_cast<const dbp::c32*>(fr.H);
+    a.y = static_cast<const dbp::c32*>(fr.y);
+    a.shat = static_cast<dbp::c32*>(fr.s_hat);
+    a.hard = fr.hard;
+    a.flags = fr.status;
+    a.guard = 0.f;
+    if (fr.hard) {
+      dbp::FixArgs& f = fb.f[fb.n++];
+      int32_t* flags = fr.status ? fr.status : static_cast<int32_t*>(fr.workspace);
+      a.flags = flags;
+      a.guard = reslice_guard(DBP_PREC_FP32, 0, U);
+      f = dbp::FixArgs{};
+      f.flags = flags;
+      f.ws = slots;
+      f.n_slots = n_slots;
+      f.H = a.H;
+      f.y = a.y;
+      f.shat = a.shat;
+      f.hard = a.hard;
+      f.n_sc = a.n_sc;
+      f.n_sym = a.n_sym;
+      f.B = a.B;
+      f.C = a.C;
+      f.S = a.S;
+      f.T = a.T;
+      f.reg = a.reg;
+      f.L = a.L;
+      fix_params(f, U, fr.rho, fr.gamma, fr.N0, fr.Es, fr.reg, fr.qam, true);
+    }
+    b.first[b.n] = total;
+    total += (fr.n_sc + pl.scpb - 1) / pl.scpb;
+    ++b.n;
+  }
+  b.first[b.n] = total;
+  if (total == 0) return ok();
+  const hipStream_t hs = static_cast<hipStream_t>(stream);
+  // persistent grid: enough workgroups to fill the chip at four waves per SIMD
+  const int cap = 256 * (16 / nw > 0 ? 16 / nw : 1);
+  int st = device_status(who, dbp::launch_admm_ul_f32_batch(b, U, nw, total < cap ? total : cap, hs));
+  if (st || fb.n == 0) return st;
+  return device_status(who, dbp::launch_admm_ul_fix64_batch(fb, U, n_slots, hs));
+}
+
 }  // extern "C"

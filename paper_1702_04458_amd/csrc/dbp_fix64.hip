@@ -151,7 +151,22 @@ __device__ __forceinline__ void write_out(const FixArgs& f, int k, int n, int u,
 // read them.  f.inv_den holds the denominator N0 / (rho Es) + C itself (FP64
 // divides by it).
 template <int U>
+__device__ __forceinline__ void admm_ul_fix64_body(const FixArgs& f);
+
+template <int U>
 __global__ void __launch_bounds__(kFixThreads) admm_ul_fix64(FixArgs f) {
+  admm_ul_fix64_body<U>(f);
+}
+
+// The re-slice of a batch of frames (one U): the frames one after another,
+// each over all workgroups (they share the workspace slots).
+template <int U>
+__global__ void __launch_bounds__(kFixThreads) admm_ul_fix64_batch(FixBatch b) {
+  for (int i = 0; i < b.n; ++i) admm_ul_fix64_body<U>(b.f[i]);
+}
+
+template <int U>
+__device__ __forceinline__ void admm_ul_fix64_body(const FixArgs& f) {
   constexpr int TI = (U >= 32) ? 4 : U / 8;
   constexpr int NT = U / TI;           // tiles per matrix side
   constexpr int T2 = NT * NT;          // tiles per cluster
@@ -461,6 +476,26 @@ hipError_t launch_admm_ul_fix64(const FixArgs& f, hipStream_t st) {
     case 16: hipLaunchKernelGGL(admm_ul_fix64<16>, grid, block, lds, st, f); break;
     case 32: hipLaunchKernelGGL(admm_ul_fix64<32>, grid, block, lds, st, f); break;
     case 64: hipLaunchKernelGGL(admm_ul_fix64<64>, grid, block, lds, st, f); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_admm_ul_fix64_batch(const FixBatch& b, int U, int n_slots, hipStream_t st) {
+  if (b.n < 1) return hipSuccess;
+  int vec = 0, piv = 0;
+  for (int i = 0; i < b.n; ++i) {
+    const int C = b.f[i].C, TI = (U >= 32) ? 4 : U / 8, CG = kFixThreads / ((U / TI) * (U / TI));
+    vec = vec > 3 * C * U + U ? vec : 3 * C * U + U;
+    piv = piv > 2 * CG * U ? piv : 2 * CG * U;
+  }
+  const size_t lds = (size_t)(vec > piv ? vec : piv) * sizeof(d2) + (kListCap + kFixThreads / 64 + 4) * sizeof(int);
+  const dim3 grid((unsigned)n_slots), block(kFixThreads);
+  switch (U) {
+    case 8: hipLaunchKernelGGL(admm_ul_fix64_batch<8>, grid, block, lds, st, b); break;
+    case 16: hipLaunchKernelGGL(admm_ul_fix64_batch<16>, grid, block, lds, st, b); break;
+    case 32: hipLaunchKernelGGL(admm_ul_fix64_batch<32>, grid, block, lds, st, b); break;
+    case 64: hipLaunchKernelGGL(admm_ul_fix64_batch<64>, grid, block, lds, st, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -296,7 +296,7 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
   for (int p = 0; p < 2; ++p) {
     const int lp = wave * 2 + p;
     const int ls = lp / a.Cp, c = lp % a.Cp;
-    const int k = blockIdx.x * a.sc_per_block + ls;
+    const int k = a.blk * a.sc_per_block + ls;
     act[p] = (k < a.n_sc) && (c < a.C);
     Hp[p] = act[p] ? a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32 : a.H;
     yp[p] = act[p] ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
@@ -447,7 +447,7 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
   for (int p = 0; p < 2; ++p) {
     const int lp = wave * 2 + p;
     const int ls = lp / a.Cp, c = lp % a.Cp;
-    const int k = blockIdx.x * a.sc_per_block + ls;
+    const int k = a.blk * a.sc_per_block + ls;
     act[p] = (k < a.n_sc) && (c < a.C);
     Hp[p] = act[p] ? a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32 : a.H;
     yp[p] = act[p] ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
@@ -740,7 +740,7 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
   for (int p = 0; p < 4; ++p) {
     const int lp = wave * 4 + p;
     const int ls = lp / a.Cp, c = lp % a.Cp;
-    const int k = blockIdx.x * a.sc_per_block + ls;
+    const int k = a.blk * a.sc_per_block + ls;
     act[p] = (k < a.n_sc) && (c < a.C);
     Hp[p] = act[p] ? a.H + (size_t)k * a.B * 16 + (size_t)c * a.S * 16 : a.H;
     yp[p] = act[p] ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
@@ -1003,7 +1003,7 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
   f32x16 re[2][2], im[2][2];
   c32 hy0 = cz(), hy1 = cz();
   const int ls = wave / a.Cp, c = wave % a.Cp;
-  const int k = blockIdx.x * a.sc_per_block + ls;
+  const int k = a.blk * a.sc_per_block + ls;
   const bool act = (k < a.n_sc) && (c < a.C);
   const c32* Hk = act ? a.H + (size_t)k * a.B * 64 + (size_t)c * a.S * 64 : a.H;
   const c32* yk = act ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
@@ -1147,7 +1147,7 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
   typedef typename HalfMma<HT>::V V;
   const int h = lane >> 5, col = lane & 31;
   const int ls = wave / a.Cp, c = wave % a.Cp;
-  const int k = blockIdx.x * a.sc_per_block + ls;
+  const int k = a.blk * a.sc_per_block + ls;
   const bool act = (k < a.n_sc) && (c < a.C);
   const c32* Hk = act ? a.H + (size_t)k * a.B * 64 + (size_t)c * a.S * 64 : a.H;
   const c32* yk = act ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
@@ -1283,7 +1283,37 @@ __device__ __forceinline__ c32 consensus(c32 wc, int buf, int ls, int G, int u, 
 // written to a.fac (a static channel factored once); 2 iterations only, B_c^{-1}
 // read from a.fac (every symbol's H_c^H y_c by the VALU pass).
 template <int G, int HALF, int INV, int STAGE>
+__device__ __forceinline__ void admm_ul_body(const UlArgs& a);
+
+template <int G, int HALF, int INV, int STAGE>
 __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
+  a.blk = blockIdx.x;
+  admm_ul_body<G, HALF, INV, STAGE>(a);
+}
+
+// Several frames of the same U in one persistent launch (FP32, one-shot):
+// frame f owns the virtual blocks first[f] .. first[f+1]-1 of its own launch
+// plan (all frames share the waves per workgroup); each workgroup takes
+// virtual blocks in grid stride and finds its frame by binary search over
+// first[].  The frames' argument blocks travel in the kernel arguments.
+template <int G>
+__global__ void __launch_bounds__(512) admm_ul_f32_batch(UlBatch b) {
+  for (int vb = blockIdx.x; vb < b.first[b.n]; vb += gridDim.x) {
+    int lo = 0, hi = b.n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (b.first[mid] <= vb) lo = mid;
+      else hi = mid - 1;
+    }
+    UlArgs a = b.f[lo];
+    a.blk = vb - b.first[lo];
+    admm_ul_body<G, 0, 0, 0>(a);
+    __syncthreads();   // the next virtual block reuses the LDS
+  }
+}
+
+template <int G, int HALF, int INV, int STAGE>
+__device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   constexpr int P = 64 / G;
   extern __shared__ float4 smem_raw[];
   const int nw = blockDim.x >> 6;
@@ -1293,7 +1323,7 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
   const int g = lane / G, u = lane % G;
   const int lp = wave * P + g;
   const int ls = lp / a.Cp, c = lp % a.Cp;
-  const int k = blockIdx.x * a.sc_per_block + ls;
+  const int k = a.blk * a.sc_per_block + ls;
   const bool active = (k < a.n_sc) && (c < a.C);
   const int slot = wave * 64 + lane;
   c32* line = sm.line + wave * 64;
@@ -1405,6 +1435,7 @@ __global__ void __launch_bounds__(512) admm_ul_f32(UlArgs a) {
 // ---------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
+  a.blk = blockIdx.x;
   constexpr int P = 64 / G;
   extern __shared__ float4 smem_raw[];
   const int nw = blockDim.x >> 6;
@@ -1414,7 +1445,7 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   const int g = lane / G, u = lane % G;
   const int lp = wave * P + g;
   const int ls = lp / a.Cp, c = lp % a.Cp;
-  const int k = blockIdx.x * a.sc_per_block + ls;
+  const int k = a.blk * a.sc_per_block + ls;
   const bool active = (k < a.n_sc) && (c < a.C);
   const int slot = wave * 64 + lane;
   c32* line = sm.line + wave * 64;
@@ -1879,6 +1910,19 @@ hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, int inv, int n
   if (U == 64)
     return half == 1 ? launch_mixed_inv<64, 1>(a, inv, nw, st, stage) : launch_mixed_inv<64, 2>(a, inv, nw, st, stage);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_admm_ul_f32_batch(const UlBatch& b, int U, int nw, int grid, hipStream_t st) {
+  if (b.n < 1 || b.first[b.n] == 0) return hipSuccess;
+  const dim3 g((unsigned)grid), blk((unsigned)(64 * nw));
+  switch (U) {
+    case 8: hipLaunchKernelGGL(admm_ul_f32_batch<8>, g, blk, smem_bytes(nw), st, b); break;
+    case 16: hipLaunchKernelGGL(admm_ul_f32_batch<16>, g, blk, smem_bytes(nw), st, b); break;
+    case 32: hipLaunchKernelGGL(admm_ul_f32_batch<32>, g, blk, smem_bytes(nw), st, b); break;
+    case 64: hipLaunchKernelGGL(admm_ul_f32_batch<64>, g, blk, smem_bytes(nw), st, b); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_admm_ul_factored(const UlArgs& a, int U, int nw, hipStream_t st) {

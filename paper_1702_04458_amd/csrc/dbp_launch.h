@@ -35,6 +35,7 @@ struct UlArgs {
   int32_t* flags;     // [n_sc] per-subcarrier status bits written by the detection kernels, or null
   float guard;        // re-slice guard in slicer units t = (kappa x + L) / 2; 0: no re-slice
   int nw;             // waves per workgroup of the call's launch plan
+  int blk;            // block index within this frame's launch (set by the kernel)
 };
 
 // Exact re-slicing: the subcarriers the FP32 kernel flagged (a soft value
@@ -66,7 +67,25 @@ struct DlArgs {
   int h_layout;       // 0: H in the uplink layout [n_sc][B][U]; 1: downlink layout [n_sc][U][B]
 };
 
+// Several frames of one U in one launch: the argument blocks travel by value
+// in the kernel arguments (at most 4 KiB), so a batch needs no device copy.
+constexpr int kMaxBatch = 24;
+struct UlBatch {
+  UlArgs f[kMaxBatch];
+  int first[kMaxBatch + 1];   // first virtual block of each frame, first[n] = total
+  int n;
+};
+struct FixBatch {
+  FixArgs f[kMaxBatch];
+  int n;
+};
+static_assert(sizeof(UlBatch) <= 4096 && sizeof(FixBatch) <= 4096, "kernel argument blocks exceed 4 KiB");
+
 size_t smem_bytes(int nw);
+// persistent launch of grid workgroups (nw waves each) over all frames of b
+hipError_t launch_admm_ul_f32_batch(const UlBatch& b, int U, int nw, int grid, hipStream_t st);
+// FP64 re-slice of the flagged subcarriers of every frame of b
+hipError_t launch_admm_ul_fix64_batch(const FixBatch& b, int U, int n_slots, hipStream_t st);
 // stage: 0 detect, 1 only factor (write B_c^{-1} to a.fac)
 hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st, int stage = 0);
 // inv: 0 FP32 matrix-core inverse, 1 FP64 VALU inverse (U = 32), 2 split-FP16 matrix-core inverse

@@ -188,3 +188,22 @@ def test_autotune_rejects_and_defaults():
     assert L.dbp_autotune_get(1, 32, 8) == 4
     assert L.dbp_autotune_get(2, 32, 16) == 4
     assert L.dbp_autotune_get(0, 12, 8) == -1
+
+
+def test_detect_batch_rejects():
+    import ctypes
+    L = _native.lib()
+    assert L.dbp_detect_admm_batch(None, 0, 32, None) == 0                      # empty: no-op
+    assert L.dbp_detect_admm_batch(None, 25, 32, None) == 1                     # above DBP_MAX_BATCH
+    arr = (_native.Frame * 2)()
+    for e in arr:
+        e.H = e.y = e.s_hat = 1
+        e.n_sc, e.n_sym, e.B, e.C, e.T, e.reg, e.qam = 4, 1, 256, 8, 5, 0, 64
+        e.rho, e.gamma, e.N0, e.Es = 1.0, 1.0, 0.1, 1.0
+    assert L.dbp_detect_admm_batch(arr, 2, 12, None) == 2                       # U not built
+    arr[1].C = 16                                                               # S = 16 < U = 32
+    assert L.dbp_detect_admm_batch(arr, 2, 32, None) == 2
+    assert b"frame 1" in L.dbp_last_error()
+    arr[1].C = 8
+    arr[0].hard = 1                                                             # hard without workspace
+    assert L.dbp_detect_admm_batch(arr, 2, 32, None) == 1

@@ -633,3 +633,31 @@ def test_autotune_keeps_results(kind):
     torch.cuda.synchronize()
     say(f"    chose {best} waves minimum")
     assert torch.equal(before, after) and torch.equal(hb, ha)
+
+
+def test_detect_batch_uneven_frames():
+    """Frames of one U with different B, C, subcarrier counts, symbols, T,
+    QAM and regularisers in one launch: every output bit equals the
+    single-frame call, and decisions equal the oracle's."""
+    say("[gpu] uneven batch")
+    specs = [(256, 32, 8, 300, 64, 25.0, 5, "mmse", 1), (128, 32, 4, 72, 16, 0.0, 5, "mmse", 1),
+             (512, 32, 16, 600, 64, 10.0, 3, "zf", 2), (256, 32, 4, 1, 16, 5.0, 4, "box", 1),
+             (64, 32, 2, 37, 4, 0.0, 5, "mmse", 1)]
+    frames, refs = [], []
+    for i, (B, U, C, n_sc, qam, snr, T, reg, n_sym) in enumerate(specs):
+        fr = inputs.uplink_frame(inputs.frame_seed(60, i, int(snr)), n_sc, B, U, qam, snr, n_sym=n_sym)
+        frames.append(dict(H=to_dev(fr.H), y=to_dev(fr.y), N0=fr.N0, C=C, T=T, qam=qam, reg=reg, status=True))
+        refs.append(fr)
+    out = api.detect_batch(frames)
+    single = [api.detect(f["H"], f["y"], f["N0"], f["C"], 1.0, f["T"], qam=f["qam"], reg=f["reg"], status=True)
+              for f in frames]
+    torch.cuda.synchronize()
+    for (s, h, st), (s1, h1, st1), f, fr in zip(out, single, frames, refs):
+        assert torch.equal(s, s1) and torch.equal(h, h1) and torch.equal(st, st1)
+        ref = O.admm_ul_frame(fr.H, fr.y, f["C"], 1.0, f["T"], n0_f32(fr.N0), reg=f["reg"],
+                              box_r=O.box_radius(fr.qam))
+        assert rel_err(s.cpu().numpy(), ref) <= 1e-5
+        assert np.array_equal(h.cpu().numpy(), O.slice_qam(ref, fr.qam))
+    with pytest.raises(ValueError):
+        api.detect_batch([frames[0], dict(H=to_dev(inputs.uplink_frame(1, 4, 64, 16, 4, 10.0).H),
+                                          y=to_dev(inputs.uplink_frame(1, 4, 64, 16, 4, 10.0).y), N0=0.1, C=4)])
