@@ -323,7 +323,7 @@ def _pctl(v, q):
 
 
 def serve_bench(loads=(0.25, 0.5, 0.7, 0.85, 0.95), frames_per_load=10000, pool=40, n_slots=8,
-                budget_gb=32.0, seed=99, log=sys.stderr):
+                budget_gb=32.0, seed=99, max_batch=8, log=sys.stderr):
     """Continuous-batching serving run: Poisson arrivals of uplink frames whose
     (B, U, C) is uniform over the valid triples with U <= S = B/C, n_sc uniform
     over {72, 300, 600, 1200}, 16/64-QAM, SNR 0..20 dB, ADMM (rho=1, T=5).
@@ -360,6 +360,7 @@ def serve_bench(loads=(0.25, 0.5, 0.7, 0.85, 0.95), frames_per_load=10000, pool=
         frames.append(dict(H=H.contiguous(), y=y, B=B, U=U, C=C, n_sc=n_sc, qam=qam, N0=N0))
     torch.cuda.synchronize()
     srv = api.Server(hbm_budget_bytes=int(budget_gb * 2 ** 30), n_slots=n_slots)
+    srv.set_batching(max_batch)
 
     def outs(f):
         return (torch.empty((f["n_sc"], 1, f["U"]), dtype=torch.complex64, device="cuda"),
@@ -428,7 +429,7 @@ def serve_bench(loads=(0.25, 0.5, 0.7, 0.85, 0.95), frames_per_load=10000, pool=
         print(f"[serve] load {load:.2f}: p50 {p50:.0f} us, p99 {p99:.0f} us", file=log, flush=True)
     st = srv.stats()
     srv.close()
-    return {"saturation_fps": round(sat_fps, 1),
+    return {"saturation_fps": round(sat_fps, 1), "max_batch": max_batch,
             "saturation_vectors_per_s": round(sat_fps * vec_per_frame, 1),
             "mean_subcarriers_per_frame": round(vec_per_frame, 1), "slots": n_slots, "budget_gb": budget_gb,
             "peak_inflight": st["peak_inflight"], "loads": results}
@@ -969,6 +970,9 @@ def main():
     if not args.no_serve and algo == "admm":
         print("[bench] serving run", file=sys.stderr, flush=True)
         serving = serve_bench(frames_per_load=args.serve_frames, pool=40)
+        # the same mix without admission batching (one launch per frame)
+        nb = serve_bench(loads=(0.85,), frames_per_load=max(1000, args.serve_frames // 5), pool=40, max_batch=1)
+        serving["unbatched"] = {"saturation_fps": nb["saturation_fps"], "load_0.85": nb["loads"][0]}
         if U == 32 and args.form == "oneshot":
             serving["served_h16"] = serve_h16_bench(api, B=B, U=U, C=C, qam=qam, snr=snr)
             sat = serving["served_h16"]["saturation_vectors_per_s"]

@@ -373,6 +373,12 @@ int dbp_server_poll(dbp_server* srv, uint64_t ticket, int* done, double* latency
  * admission), and forgets the ticket.  Returns the frame's status. */
 int dbp_server_wait(dbp_server* srv, uint64_t ticket, double* latency_us, double* queue_us);
 int dbp_server_stats(dbp_server* srv, size_t* peak_bytes, int* peak_inflight, uint64_t* completed);
+/* Admission batching: a frame admitted to a free slot takes up to
+ * max_frames - 1 more queued frames of the same U and I/O mode (FP32, not
+ * against a resident channel; the next 64 queued frames are looked at) into
+ * one dbp_detect_admm_batch launch.  max_frames = 1 turns batching off;
+ * the default is 8.  DBP_ERR_INVALID outside 1 .. DBP_MAX_BATCH. */
+int dbp_server_set_batching(dbp_server* srv, int max_frames);
 
 /* Static channels (resident state of the serving loop).  The channel of a
  * coherence interval is loaded once: dbp_channel_load copies H (pinned host

@@ -49,6 +49,7 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_uint64)]),
     "dbp_server_poll": (_i, [_vp, ctypes.c_uint64, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double)]),
     "dbp_server_wait": (_i, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "dbp_server_set_batching": (_i, [_vp, _i]),
     "dbp_server_stats": (_i, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_uint64)]),
 }
 

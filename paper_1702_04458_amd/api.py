@@ -420,6 +420,10 @@ class Server:
         _native.check(_native.lib().dbp_server_wait(self._h, ct.c_uint64(ticket), ct.byref(lat), ct.byref(q)))
         return lat.value, q.value
 
+    def set_batching(self, max_frames: int):
+        """Frames one launch may take at admission (1: no batching)."""
+        _native.check(_native.lib().dbp_server_set_batching(self._h, int(max_frames)))
+
     def stats(self):
         ct = self._ct
         pb, pi, c = ct.c_size_t(), ct.c_int(), ct.c_uint64()

@@ -118,7 +118,8 @@ struct dbp_server {
   Arena* arena = nullptr;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
-  std::vector<uint64_t> slot_frame;   // 0 = free
+  std::vector<std::vector<uint64_t>> slot_frames;   // frames in flight on each slot (empty = free)
+  int max_batch = 8;                  // frames one launch may take (1: no batching)
   std::mutex mu;
   std::condition_variable cv;
   std::deque<uint64_t> queue;
@@ -206,6 +207,58 @@ int launch_frame(dbp_server* s, Frame& f) {
   return DBP_OK;
 }
 
+// The arena block of a frame starts with its re-slice workspace; a host-I/O
+// frame's copies of H, y and the outputs follow.
+struct DevIO {
+  const void* H;
+  const void* y;
+  void* s;
+  uint8_t* hard;
+  void* ws;
+};
+
+DevIO device_io(dbp_server* s, const Frame& f) {
+  char* ws = static_cast<char*>(s->base) + f.off;
+  if (f.flags & DBP_SERVE_DEVICE_IO) return DevIO{f.H, f.y, f.s_out, f.hard_out, f.bytes_ws ? ws : nullptr};
+  auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
+  char* dH = ws + f.bytes_ws;
+  char* dy = dH + al(f.bytes_H);
+  char* ds = dy + al(f.bytes_y);
+  char* dh = ds + al(f.bytes_s);
+  return DevIO{dH, dy, ds, f.hard_out ? reinterpret_cast<uint8_t*>(dh) : nullptr, f.bytes_ws ? ws : nullptr};
+}
+
+// Several admitted frames of one U (FP32, not against a resident channel) in
+// one dbp_detect_admm_batch launch on the slot's stream, with each host-I/O
+// frame's copies before and after it.
+int launch_batch(dbp_server* s, const std::vector<Frame*>& fs, int slot) {
+  hipStream_t st = s->streams[slot];
+  dbp_frame d[DBP_MAX_BATCH];
+  for (size_t i = 0; i < fs.size(); ++i) {
+    const Frame& f = *fs[i];
+    const DevIO io = device_io(s, f);
+    if (!(f.flags & DBP_SERVE_DEVICE_IO)) {
+      if (hipMemcpyAsync(const_cast<void*>(io.H), f.H, f.bytes_H, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(const_cast<void*>(io.y), f.y, f.bytes_y, hipMemcpyHostToDevice, st) != hipSuccess)
+        return DBP_ERR_DEVICE;
+    }
+    d[i] = dbp_frame{io.H, io.y, io.s, io.hard, nullptr, io.ws, f.bytes_ws, f.n_sc, f.n_sym, f.B, f.C, f.T,
+                     f.reg, f.qam, f.rho, 1.0f, f.N0, 1.0f};
+  }
+  int rc = dbp_detect_admm_batch(d, int(fs.size()), fs[0]->U, st);
+  if (rc != DBP_OK) return rc;
+  for (size_t i = 0; i < fs.size(); ++i) {
+    const Frame& f = *fs[i];
+    if (f.flags & DBP_SERVE_DEVICE_IO) continue;
+    if (hipMemcpyAsync(f.s_out, d[i].s_hat, f.bytes_s, hipMemcpyDeviceToHost, st) != hipSuccess) return DBP_ERR_DEVICE;
+    if (f.hard_out && hipMemcpyAsync(f.hard_out, d[i].hard, f.bytes_hard, hipMemcpyDeviceToHost, st) != hipSuccess)
+      return DBP_ERR_DEVICE;
+  }
+  return hipEventRecord(s->events[slot], st) == hipSuccess ? DBP_OK : DBP_ERR_DEVICE;
+}
+
+bool batchable(const Frame& f) { return f.channel == 0 && f.prec == DBP_PREC_FP32; }
+
 void scheduler(dbp_server* s) {
   // dbp_server_create made this device current successfully before starting
   // the thread, so the call cannot fail here
@@ -215,51 +268,77 @@ void scheduler(dbp_server* s) {
     bool progressed = false;
     // completions
     int inflight = 0;
-    for (size_t i = 0; i < s->slot_frame.size(); ++i) {
-      const uint64_t t = s->slot_frame[i];
-      if (!t) continue;
+    for (size_t i = 0; i < s->slot_frames.size(); ++i) {
+      std::vector<uint64_t>& ts = s->slot_frames[i];
+      if (ts.empty()) continue;
       const hipError_t q = hipEventQuery(s->events[i]);
       if (q != hipErrorNotReady) {
-        Frame& f = s->frames[t];
-        f.t_done = Clock::now();
-        f.done = true;
-        if (q != hipSuccess) f.status = DBP_ERR_DEVICE;
-        s->arena->release(f.off, f.footprint);
-        if (f.channel) --s->channels[f.channel].refs;
-        s->slot_frame[i] = 0;
-        ++s->completed;
+        const auto now = Clock::now();
+        for (uint64_t t : ts) {
+          Frame& f = s->frames[t];
+          f.t_done = now;
+          f.done = true;
+          if (q != hipSuccess) f.status = DBP_ERR_DEVICE;
+          s->arena->release(f.off, f.footprint);
+          if (f.channel) --s->channels[f.channel].refs;
+          ++s->completed;
+        }
+        ts.clear();
         progressed = true;
       } else {
-        ++inflight;
+        inflight += int(ts.size());
       }
     }
-    // admissions, in arrival order
+    // admissions, in arrival order; a batchable frame at the head takes up
+    // to max_batch - 1 more batchable frames of the same U and I/O mode from
+    // the next queued ones into its launch
     while (!s->queue.empty()) {
-      auto free_slot = std::find(s->slot_frame.begin(), s->slot_frame.end(), 0);
-      if (free_slot == s->slot_frame.end()) break;
+      auto free_slot = std::find_if(s->slot_frames.begin(), s->slot_frames.end(),
+                                    [](const std::vector<uint64_t>& v) { return v.empty(); });
+      if (free_slot == s->slot_frames.end()) break;
+      const int slot = int(free_slot - s->slot_frames.begin());
       Frame& f = s->frames[s->queue.front()];
       size_t off;
       if (!s->arena->alloc(f.footprint, &off)) break;
       f.off = off;
-      f.slot = int(free_slot - s->slot_frame.begin());
+      f.slot = slot;
       f.t_admit = Clock::now();
       s->queue.pop_front();
-      const int rc = launch_frame(s, f);
+      std::vector<Frame*> batch{&f};
+      if (batchable(f) && s->max_batch > 1) {
+        constexpr size_t kScan = 64;
+        for (auto it = s->queue.begin(); it != s->queue.end() && int(batch.size()) < s->max_batch &&
+                                         size_t(it - s->queue.begin()) < kScan;) {
+          Frame& g = s->frames[*it];
+          if (batchable(g) && g.U == f.U && g.flags == f.flags && s->arena->alloc(g.footprint, &off)) {
+            g.off = off;
+            g.slot = slot;
+            g.t_admit = f.t_admit;
+            batch.push_back(&g);
+            it = s->queue.erase(it);
+          } else {
+            ++it;
+          }
+        }
+      }
+      const int rc = batch.size() > 1 ? launch_batch(s, batch, slot) : launch_frame(s, f);
       if (rc != DBP_OK) {
-        // nothing more of this frame runs: drain what was enqueued before the
-        // failure, then release and report (a failing drain leaves the error
-        // in f.status too)
-        (void)hipStreamSynchronize(s->streams[f.slot]);
-        s->arena->release(f.off, f.footprint);
-        if (f.channel) --s->channels[f.channel].refs;
-        f.status = rc;
-        f.done = true;
-        f.t_done = Clock::now();
-        progressed = true;   // wakes a caller waiting on this ticket
+        // nothing more of these frames runs: drain what was enqueued before
+        // the failure, then release and report (a failing drain leaves the
+        // error in the status too)
+        (void)hipStreamSynchronize(s->streams[slot]);
+        for (Frame* g : batch) {
+          s->arena->release(g->off, g->footprint);
+          if (g->channel) --s->channels[g->channel].refs;
+          g->status = rc;
+          g->done = true;
+          g->t_done = Clock::now();
+        }
+        progressed = true;   // wakes callers waiting on these tickets
         continue;
       }
-      *free_slot = f.ticket;
-      ++inflight;
+      for (Frame* g : batch) free_slot->push_back(g->ticket);
+      inflight += int(batch.size());
       progressed = true;
     }
     s->peak_used = std::max(s->peak_used, s->arena->used());
@@ -313,7 +392,7 @@ int dbp_server_create(int device, size_t hbm_budget_bytes, int n_slots, dbp_serv
   s->arena = new Arena(hbm_budget_bytes);
   s->streams.assign(n_slots, nullptr);
   s->events.assign(n_slots, nullptr);
-  s->slot_frame.assign(n_slots, 0);
+  s->slot_frames.assign(n_slots, {});
   for (int i = 0; i < n_slots; ++i) {
     if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming) != hipSuccess) {
@@ -539,6 +618,13 @@ int dbp_server_wait(dbp_server* s, uint64_t ticket, double* latency_us, double* 
   const int st = it->second.status;
   s->frames.erase(it);
   return st;
+}
+
+int dbp_server_set_batching(dbp_server* s, int max_frames) {
+  if (!s || max_frames < 1 || max_frames > DBP_MAX_BATCH) return DBP_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->max_batch = max_frames;
+  return DBP_OK;
 }
 
 int dbp_server_stats(dbp_server* s, size_t* peak_bytes, int* peak_inflight, uint64_t* completed) {
