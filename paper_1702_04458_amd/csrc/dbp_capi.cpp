@@ -230,6 +230,10 @@ float reslice_guard(int gram_prec, int inv, int U) {
 
 size_t flags_region(int n_sc) { return ((size_t)n_sc * 4 + 255) & ~size_t(255); }
 
+// The list of subcarriers the split FP64 pass recomputes with one workgroup
+// per cluster (one int per workgroup), at the end of the workspace.
+constexpr size_t kList0Room = dbp::kFixMaxSlots * sizeof(int) + 256;
+
 // Status and exact re-slicing of a detection call.  Without hard decisions
 // only the optional status is written (non-finite bit).  With them the FP32
 // kernel flags near-threshold subcarriers into `status` (or, without it, the
@@ -246,10 +250,10 @@ int setup_reslice(const char* who, dbp::UlArgs& a, dbp::FixArgs& f, int32_t* sta
   if (reinterpret_cast<uintptr_t>(ws) % 256)
     return fail(DBP_ERR_INVALID, "%s: workspace must be 256-byte aligned", who);
   int slots = max_slots;
+  const size_t room = ws_bytes > fb + kList0Room ? ws_bytes - fb - kList0Room : 0;
   if (slot_bytes) {
-    const size_t avail = ws_bytes > fb ? ws_bytes - fb : 0;
-    if ((size_t)slots * slot_bytes > avail) slots = (int)(avail / slot_bytes);
-  } else if (ws_bytes < fb) {
+    if ((size_t)slots * slot_bytes > room) slots = (int)(room / slot_bytes);
+  } else if (ws_bytes < fb + kList0Room) {
     slots = 0;
   }
   if (slots < 1) return fail(DBP_ERR_INVALID, "%s: workspace of %zu bytes is too small", who, ws_bytes);
@@ -257,6 +261,10 @@ int setup_reslice(const char* who, dbp::UlArgs& a, dbp::FixArgs& f, int32_t* sta
   a.guard = guard;
   f.flags = a.flags;
   f.ws = static_cast<char*>(ws) + fb;
+  // 256-byte aligned, kFixMaxSlots ints, inside the last kList0Room bytes
+  const uintptr_t end = reinterpret_cast<uintptr_t>(ws) + ws_bytes;
+  f.list0 = reinterpret_cast<int*>((end - dbp::kFixMaxSlots * sizeof(int)) & ~uintptr_t(255));
+  f.split = 0;
   f.n_slots = slots;
   f.H = a.H;
   f.y = a.y;
@@ -299,7 +307,7 @@ extern "C" {
 
 size_t dbp_detect_workspace_bytes(int n_sc, int U, int C) {
   if (n_sc < 0 || U < 1 || C < 1) return 0;
-  return flags_region(n_sc) + (size_t)full_slots(n_sc) * dbp::fix64_slot_bytes(U, C);
+  return flags_region(n_sc) + (size_t)full_slots(n_sc) * dbp::fix64_slot_bytes(U, C) + kList0Room;
 }
 
 }  // extern "C"
@@ -309,7 +317,7 @@ namespace dbp {
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 
 size_t reslice_bytes_min(int n_sc, int U, int C, bool with_status) {
-  return (with_status ? 0 : flags_region(n_sc)) + fix64_slot_bytes(U, C);
+  return (with_status ? 0 : flags_region(n_sc)) + fix64_slot_bytes(U, C) + kList0Room;
 }
 
 // dbp_detect_admm with the re-slice workspace bounded by max_slots FP64 slots
@@ -338,6 +346,7 @@ int detect_admm_impl(const char* who, const void* H, const void* y, void* s_hat,
   st = device_status(who, launch_preprocessing(a, U, gram_prec, inv, hs, 0));
   if (st || !hard) return st;
   fix_params(f, U, rho, gamma, N0, Es, reg, qam, true);
+  f.split = U >= 32;   // large inverses: one workgroup per cluster for each workgroup's first subcarrier
   return device_status(who, dbp::launch_admm_ul_fix64(f, hs));
 }
 
@@ -407,6 +416,7 @@ int dbp_detect_admm_factored(const void* H, const void* factors, const void* y, 
   st = device_status(who, dbp::launch_admm_ul_factored(a, U, a.nw, hs));
   if (st || !hard) return st;
   fix_params(f, U, rho, gamma, N0, Es, reg, qam, true);
+  f.split = U >= 32;
   return device_status(who, dbp::launch_admm_ul_fix64(f, hs));
 }
 
@@ -655,10 +665,10 @@ int dbp_detect_admm_batch(const dbp_frame* frames, int n_frames, int U, void* st
   for (int i = 0; i < n_frames; ++i) {
     const dbp_frame& fr = frames[i];
     if (!fr.hard || fr.n_sc == 0) continue;
-    const size_t fl = fr.status ? 0 : flags_region(fr.n_sc);
+    const size_t fl = (fr.status ? 0 : flags_region(fr.n_sc)) + kList0Room;
     if (fr.workspace_bytes - fl > slot_room) {
       slot_room = fr.workspace_bytes - fl;
-      slots = static_cast<char*>(fr.workspace) + fl;
+      slots = static_cast<char*>(fr.workspace) + fl - kList0Room;
     }
   }
   int n_slots = (int)(slot_room / slot);

@@ -138,20 +138,237 @@ __device__ __forceinline__ void write_out(const FixArgs& f, int k, int n, int u,
 
 }  // namespace
 
-// Algorithm 1 in FP64 for the flagged subcarriers, 1024 threads per
-// workgroup.  The regularised Grams are formed and inverted in registers:
-// thread t owns a TI x TI tile of one cluster's U x U matrix (TI = 1, 2, 4, 4
-// for U = 8, 16, 32, 64), CG = 1024 / (U / TI)^2 clusters at a time (16, or 4
-// at U = 64).  Gram: each thread accumulates its tile over the S rows of H_c
-// straight from memory (the lanes of a wave that share tile rows read the
-// same addresses).  Inverse: Gauss-Jordan elimination without pivoting (HPD)
-// on all CG clusters at once; per pivot p the owners of row p and column p
-// publish them through LDS and every thread updates its tile.  The finished
-// inverses go to the workgroup's slot of the workspace, where the iterations
-// read them.  f.inv_den holds the denominator N0 / (rho Es) + C itself (FP64
-// divides by it).
+// Algorithm 1 in FP64 for the flagged subcarriers.  The regularised Grams
+// are formed and inverted in registers: thread t owns a TI x TI tile of one
+// cluster's U x U matrix, NTH / (U / TI)^2 clusters at a time.  Gram: each
+// thread accumulates its tile over the S rows of H_c straight from memory
+// (the lanes of a wave that share tile rows read the same addresses).
+// Inverse: Gauss-Jordan elimination without pivoting (HPD) on all clusters
+// of the group at once; per pivot p the owners of row p and column p publish
+// them through LDS (colp, rowp: [clusters][U]) and every thread updates its
+// tile.  The inverses go to M ([C][U][U], entry (i, j) at i U + j).
+template <int U, int TI, int NTH>
+__device__ __forceinline__ void fix64_factor_group(const FixArgs& f, const c32* Hk, int cb, d2* M, d2* colp,
+                                                   d2* rowp) {
+  constexpr int NT = U / TI, T2 = NT * NT, UU = U * U;
+  const int tid = threadIdx.x;
+  const int cl = tid / T2, tt = tid % T2, i0 = (tt / NT) * TI, j0 = (tt % NT) * TI;
+  const int c = cb + cl;
+  const bool own = cl < NTH / T2 && c < f.C;   // this thread's cluster exists
+  d2 A[TI][TI];
+#pragma unroll
+  for (int a = 0; a < TI; ++a)
+#pragma unroll
+    for (int b = 0; b < TI; ++b) A[a][b] = dzero();
+  // B_c = H_c^H H_c + rho I, tile rows i0.., columns j0..
+  if (own) {
+    const c32* Hc = Hk + (size_t)c * f.S * U;
+    for (int s = 0; s < f.S; ++s) {
+      const c32* row = Hc + (size_t)s * U;
+      d2 hj[TI];
+#pragma unroll
+      for (int b = 0; b < TI; ++b) hj[b] = dld(row + j0 + b);
+#pragma unroll
+      for (int a = 0; a < TI; ++a) {
+        const d2 hi = dld(row + i0 + a);
+#pragma unroll
+        for (int b = 0; b < TI; ++b) dmacc(A[a][b], hi, hj[b]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < TI; ++a)
+#pragma unroll
+      for (int b = 0; b < TI; ++b)
+        if (i0 + a == j0 + b) A[a][b].re += f.rho;
+  }
+  // Gauss-Jordan: after pivot p, A[p][p] = 1/d, A[p][j] = B[p][j]/d,
+  // A[i][p] = -B[i][p]/d and A[i][j] -= B[i][p] B[p][j]/d elsewhere
+  for (int p = 0; p < U; ++p) {
+    __syncthreads();   // the previous step's readers are done with colp / rowp
+    if (own && j0 <= p && p < j0 + TI) {
+#pragma unroll
+      for (int a = 0; a < TI; ++a)
+#pragma unroll
+        for (int b = 0; b < TI; ++b)
+          if (j0 + b == p) colp[cl * U + i0 + a] = A[a][b];
+    }
+    if (own && i0 <= p && p < i0 + TI) {
+#pragma unroll
+      for (int a = 0; a < TI; ++a)
+#pragma unroll
+        for (int b = 0; b < TI; ++b)
+          if (i0 + a == p) rowp[cl * U + j0 + b] = A[a][b];
+    }
+    __syncthreads();
+    if (own) {
+      const double inv = 1.0 / rowp[cl * U + p].re;
+      d2 rj[TI];
+#pragma unroll
+      for (int b = 0; b < TI; ++b) rj[b] = rowp[cl * U + j0 + b];
+      // the rank-1 update on every entry of the tile (straight-line code);
+      // the entries of pivot row p and column p are then overwritten, by the
+      // few threads whose tile holds them
+      d2 m[TI];
+#pragma unroll
+      for (int a = 0; a < TI; ++a) {
+        const d2 ci = colp[cl * U + i0 + a];
+        m[a] = d2{ci.re * inv, ci.im * inv};   // the multiplier B[i][p] / d
+#pragma unroll
+        for (int b = 0; b < TI; ++b) {
+          A[a][b].re -= m[a].re * rj[b].re - m[a].im * rj[b].im;
+          A[a][b].im -= m[a].re * rj[b].im + m[a].im * rj[b].re;
+        }
+      }
+      if (i0 <= p && p < i0 + TI) {
+#pragma unroll
+        for (int a = 0; a < TI; ++a)
+          if (i0 + a == p) {
+#pragma unroll
+            for (int b = 0; b < TI; ++b) A[a][b] = d2{rj[b].re * inv, rj[b].im * inv};
+          }
+      }
+      if (j0 <= p && p < j0 + TI) {
+#pragma unroll
+        for (int b = 0; b < TI; ++b)
+          if (j0 + b == p) {
+#pragma unroll
+            for (int a = 0; a < TI; ++a) A[a][b] = (i0 + a == p) ? d2{inv, 0.0} : d2{-m[a].re, -m[a].im};
+          }
+      }
+    }
+  }
+  if (own) {
+#pragma unroll
+    for (int a = 0; a < TI; ++a)
+#pragma unroll
+      for (int b = 0; b < TI; ++b) M[(size_t)c * UU + (i0 + a) * U + j0 + b] = A[a][b];
+  }
+}
+
+// Algorithm 1's iterations in FP64 for subcarrier k with the inverses
+// B_c^{-1} in M, all symbols; writes the outputs.  LDS: Y, Z, LM ([C][U])
+// and Sv ([U]).  Ends with a barrier.
+template <int U, int NTH>
+__device__ __forceinline__ void fix64_iterate(const FixArgs& f, int k, const d2* M, d2* Y, d2* Z, d2* LM, d2* Sv) {
+  constexpr int UU = U * U;
+  const int C = f.C, S = f.S, CU = C * U, tid = threadIdx.x;
+  const c32* Hk = f.H + (size_t)k * f.B * U;
+  for (int n = 0; n < f.n_sym; ++n) {
+    const c32* yk = f.y + ((size_t)k * f.n_sym + n) * f.B;
+    // H_c^H y_c
+    for (int e = tid; e < CU; e += NTH) {
+      const int c = e / U, i = e - c * U;
+      const c32* Hc = Hk + (size_t)c * S * U;
+      d2 acc = dzero();
+      for (int s = 0; s < S; ++s) dmacc(acc, dld(Hc + (size_t)s * U + i), dld(yk + (size_t)c * S + s));
+      Z[e] = acc;
+    }
+    __syncthreads();
+    // y_c^reg = B_c^{-1} H_c^H y_c
+    for (int e = tid; e < CU; e += NTH) {
+      const int c = e / U, i = e - c * U;
+      const d2* Mi = M + (size_t)c * UU + i * U;
+      d2 acc = dzero();
+      for (int j = 0; j < U; ++j) dmac(acc, Mi[j], Z[c * U + j]);
+      Y[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < CU; e += NTH) {
+      Z[e] = Y[e];
+      LM[e] = dzero();
+    }
+    __syncthreads();
+    for (int i = tid; i < U; i += NTH) {
+      d2 w = dzero();
+      for (int c = 0; c < C; ++c) {
+        w.re += Z[c * U + i].re;
+        w.im += Z[c * U + i].im;
+      }
+      Sv[i] = prox64(f, w);
+    }
+    __syncthreads();
+    for (int t = 2; t <= f.T; ++t) {
+      // lambda_c += gamma (z_c - s)
+      for (int e = tid; e < CU; e += NTH) {
+        const int i = e % U;
+        LM[e].re += f.gamma * (Z[e].re - Sv[i].re);
+        LM[e].im += f.gamma * (Z[e].im - Sv[i].im);
+      }
+      __syncthreads();
+      // z_c = y_c^reg + rho B_c^{-1} (s - lambda_c)
+      for (int e = tid; e < CU; e += NTH) {
+        const int c = e / U, i = e - c * U;
+        const d2* Mi = M + (size_t)c * UU + i * U;
+        d2 acc = dzero();
+        for (int j = 0; j < U; ++j)
+          dmac(acc, Mi[j], d2{Sv[j].re - LM[c * U + j].re, Sv[j].im - LM[c * U + j].im});
+        Z[e] = d2{Y[e].re + f.rho * acc.re, Y[e].im + f.rho * acc.im};
+      }
+      __syncthreads();
+      // s = prox(sum_c (z_c + lambda_c))
+      for (int i = tid; i < U; i += NTH) {
+        d2 w = dzero();
+        for (int c = 0; c < C; ++c) {
+          w.re += Z[c * U + i].re + LM[c * U + i].re;
+          w.im += Z[c * U + i].im + LM[c * U + i].im;
+        }
+        Sv[i] = prox64(f, w);
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < U; i += NTH) write_out(f, k, n, i, Sv[i]);
+    __syncthreads();
+  }
+}
+
+// Tile side of the whole-workgroup factorisation (1024 threads) and of the
+// per-cluster one (256 threads, one cluster per workgroup).
 template <int U>
-__device__ __forceinline__ void admm_ul_fix64_body(const FixArgs& f);
+constexpr int tile_all() { return (U >= 32) ? 4 : U / 8; }
+template <int U>
+constexpr int tile_one() { return (U >= 16) ? U / 16 : 1; }
+
+// The whole re-slice of the flagged subcarriers of one frame, 1024 threads
+// per workgroup.  With f.split, each workgroup's first subcarrier of the
+// first window is not done here: its index goes to f.list0 (-1 for none),
+// and admm_ul_factor64 / admm_ul_iter64 recompute it with one workgroup per
+// cluster for the inverses.  f.inv_den holds the denominator
+// N0 / (rho Es) + C itself (FP64 divides by it).
+template <int U>
+__device__ __forceinline__ void admm_ul_fix64_body(const FixArgs& f) {
+  constexpr int TI = tile_all<U>();
+  constexpr int CG = kFixThreads / ((U / TI) * (U / TI));   // clusters per group
+  extern __shared__ d2 fsm[];
+  const int C = f.C, CU = C * U;
+  // LDS: the iteration vectors, overlaid during the inversion by the pivot
+  // rows and columns of the group's clusters
+  d2* Y = fsm;            // y_c^reg (first H_c^H y_c)
+  d2* Z = Y + CU;         // z_c
+  d2* LM = Z + CU;        // lambda_c
+  d2* Sv = LM + CU;       // s
+  d2* colp = fsm;         // [CG][U] pivot columns
+  d2* rowp = fsm + CG * U;   // [CG][U] pivot rows
+  int* list = reinterpret_cast<int*>(fsm + (3 * CU + U > 2 * CG * U ? 3 * CU + U : 2 * CG * U));
+  int* wsum = list + kListCap;
+  d2* Mslot = static_cast<d2*>(f.ws) + (size_t)blockIdx.x * C * U * U;   // [C][U][U]
+
+  const long W = fix_window();
+  for (long r = 0; r * W < f.n_sc; ++r) {
+    const int nl = collect_round(f, r, W, list, wsum);
+    int q = 0;
+    if (f.split && r == 0) {
+      if (threadIdx.x == 0) f.list0[blockIdx.x] = nl > 0 ? list[0] : -1;
+      q = 1;
+    }
+    for (; q < nl; ++q) {
+      const int k = list[q];
+      const c32* Hk = f.H + (size_t)k * f.B * U;
+      for (int cb = 0; cb < C; cb += CG) fix64_factor_group<U, TI, kFixThreads>(f, Hk, cb, Mslot, colp, rowp);
+      __syncthreads();   // inverses in the slot; the LDS overlay is free again
+      fix64_iterate<U, kFixThreads>(f, k, Mslot, Y, Z, LM, Sv);
+    }
+  }
+}
 
 template <int U>
 __global__ void __launch_bounds__(kFixThreads) admm_ul_fix64(FixArgs f) {
@@ -165,196 +382,27 @@ __global__ void __launch_bounds__(kFixThreads) admm_ul_fix64_batch(FixBatch b) {
   for (int i = 0; i < b.n; ++i) admm_ul_fix64_body<U>(b.f[i]);
 }
 
+// Split recomputation, step 1: workgroup (g, c) forms and inverts cluster c's
+// regularised Gram of the subcarrier f.list0[g] into slot g.
 template <int U>
-__device__ __forceinline__ void admm_ul_fix64_body(const FixArgs& f) {
-  constexpr int TI = (U >= 32) ? 4 : U / 8;
-  constexpr int NT = U / TI;           // tiles per matrix side
-  constexpr int T2 = NT * NT;          // tiles per cluster
-  constexpr int CG = kFixThreads / T2; // clusters per group
-  constexpr int UU = U * U;
-  extern __shared__ d2 fsm[];
-  const int C = f.C, S = f.S, CU = C * U;
-  // LDS: the iteration vectors, overlaid during the inversion by the pivot
-  // rows and columns of the group's clusters
-  d2* Y = fsm;            // y_c^reg (first H_c^H y_c)
-  d2* Z = Y + CU;         // z_c
-  d2* LM = Z + CU;        // lambda_c
-  d2* Sv = LM + CU;       // s
-  d2* colp = fsm;         // [CG][U] pivot columns
-  d2* rowp = fsm + CG * U;   // [CG][U] pivot rows
-  int* list = reinterpret_cast<int*>(fsm + (3 * CU + U > 2 * CG * U ? 3 * CU + U : 2 * CG * U));
-  int* wsum = list + kListCap;
-  d2* Mslot = static_cast<d2*>(f.ws) + (size_t)blockIdx.x * C * UU;   // [C][U][U]
-  const int tid = threadIdx.x;
-  const int cl = tid / T2, tt = tid % T2, i0 = (tt / NT) * TI, j0 = (tt % NT) * TI;
+__global__ void __launch_bounds__(256) admm_ul_factor64(FixArgs f) {
+  __shared__ d2 piv[2 * U];
+  const int k = f.list0[blockIdx.x];
+  if (k < 0 || (int)blockIdx.y >= f.C) return;   // uniform
+  d2* Mslot = static_cast<d2*>(f.ws) + (size_t)blockIdx.x * f.C * U * U;
+  fix64_factor_group<U, tile_one<U>(), 256>(f, f.H + (size_t)k * f.B * U, blockIdx.y, Mslot, piv, piv + U);
+}
 
-  const long W = fix_window();
-  for (long r = 0; r * W < f.n_sc; ++r) {
-    const int nl = collect_round(f, r, W, list, wsum);
-    for (int q = 0; q < nl; ++q) {
-      const int k = list[q];
-      const c32* Hk = f.H + (size_t)k * f.B * U;
-      for (int cb = 0; cb < C; cb += CG) {
-        const int c = cb + cl;
-        const bool own = c < C;            // this thread's cluster exists
-        d2 M[TI][TI];
-        // B_c = H_c^H H_c + rho I, tile rows i0.., columns j0..
-#pragma unroll
-        for (int a = 0; a < TI; ++a)
-#pragma unroll
-          for (int b = 0; b < TI; ++b) M[a][b] = dzero();
-        if (own) {
-          const c32* Hc = Hk + (size_t)c * S * U;
-          for (int s = 0; s < S; ++s) {
-            const c32* row = Hc + (size_t)s * U;
-            d2 hj[TI];
-#pragma unroll
-            for (int b = 0; b < TI; ++b) hj[b] = dld(row + j0 + b);
-#pragma unroll
-            for (int a = 0; a < TI; ++a) {
-              const d2 hi = dld(row + i0 + a);
-#pragma unroll
-              for (int b = 0; b < TI; ++b) dmacc(M[a][b], hi, hj[b]);
-            }
-          }
-#pragma unroll
-          for (int a = 0; a < TI; ++a)
-#pragma unroll
-            for (int b = 0; b < TI; ++b)
-              if (i0 + a == j0 + b) M[a][b].re += f.rho;
-        }
-        // Gauss-Jordan: after pivot p, M[p][p] = 1/d, M[p][j] = B[p][j]/d,
-        // M[i][p] = -B[i][p]/d and M[i][j] -= B[i][p] B[p][j]/d elsewhere
-        for (int p = 0; p < U; ++p) {
-          __syncthreads();   // the previous step's readers are done with colp / rowp
-          if (own && j0 <= p && p < j0 + TI) {
-#pragma unroll
-            for (int a = 0; a < TI; ++a)
-#pragma unroll
-              for (int b = 0; b < TI; ++b)
-                if (j0 + b == p) colp[cl * U + i0 + a] = M[a][b];
-          }
-          if (own && i0 <= p && p < i0 + TI) {
-#pragma unroll
-            for (int a = 0; a < TI; ++a)
-#pragma unroll
-              for (int b = 0; b < TI; ++b)
-                if (i0 + a == p) rowp[cl * U + j0 + b] = M[a][b];
-          }
-          __syncthreads();
-          if (own) {
-            const double inv = 1.0 / rowp[cl * U + p].re;
-            d2 rj[TI];
-#pragma unroll
-            for (int b = 0; b < TI; ++b) rj[b] = rowp[cl * U + j0 + b];
-            // the rank-1 update on every entry of the tile (straight-line
-            // code); the entries of pivot row p and column p are then
-            // overwritten, by the few threads whose tile holds them
-            d2 m[TI];
-#pragma unroll
-            for (int a = 0; a < TI; ++a) {
-              const d2 ci = colp[cl * U + i0 + a];
-              m[a] = d2{ci.re * inv, ci.im * inv};   // the multiplier B[i][p] / d
-#pragma unroll
-              for (int b = 0; b < TI; ++b) {
-                M[a][b].re -= m[a].re * rj[b].re - m[a].im * rj[b].im;
-                M[a][b].im -= m[a].re * rj[b].im + m[a].im * rj[b].re;
-              }
-            }
-            if (i0 <= p && p < i0 + TI) {
-#pragma unroll
-              for (int a = 0; a < TI; ++a)
-                if (i0 + a == p) {
-#pragma unroll
-                  for (int b = 0; b < TI; ++b) M[a][b] = d2{rj[b].re * inv, rj[b].im * inv};
-                }
-            }
-            if (j0 <= p && p < j0 + TI) {
-#pragma unroll
-              for (int b = 0; b < TI; ++b)
-                if (j0 + b == p) {
-#pragma unroll
-                  for (int a = 0; a < TI; ++a) M[a][b] = (i0 + a == p) ? d2{inv, 0.0} : d2{-m[a].re, -m[a].im};
-                }
-            }
-          }
-        }
-        if (own) {
-#pragma unroll
-          for (int a = 0; a < TI; ++a)
-#pragma unroll
-            for (int b = 0; b < TI; ++b) Mslot[(size_t)c * UU + (i0 + a) * U + j0 + b] = M[a][b];
-        }
-      }
-      __syncthreads();   // inverses in the slot; the LDS overlay is free again
-      for (int n = 0; n < f.n_sym; ++n) {
-        const c32* yk = f.y + ((size_t)k * f.n_sym + n) * f.B;
-        // H_c^H y_c
-        for (int e = tid; e < CU; e += kFixThreads) {
-          const int c = e / U, i = e - c * U;
-          const c32* Hc = Hk + (size_t)c * S * U;
-          d2 acc = dzero();
-          for (int s = 0; s < S; ++s) dmacc(acc, dld(Hc + (size_t)s * U + i), dld(yk + (size_t)c * S + s));
-          Z[e] = acc;
-        }
-        __syncthreads();
-        // y_c^reg = B_c^{-1} H_c^H y_c
-        for (int e = tid; e < CU; e += kFixThreads) {
-          const int c = e / U, i = e - c * U;
-          const d2* Mi = Mslot + (size_t)c * UU + i * U;
-          d2 acc = dzero();
-          for (int j = 0; j < U; ++j) dmac(acc, Mi[j], Z[c * U + j]);
-          Y[e] = acc;
-        }
-        __syncthreads();
-        for (int e = tid; e < CU; e += kFixThreads) {
-          Z[e] = Y[e];
-          LM[e] = dzero();
-        }
-        __syncthreads();
-        for (int i = tid; i < U; i += kFixThreads) {
-          d2 w = dzero();
-          for (int c = 0; c < C; ++c) {
-            w.re += Z[c * U + i].re;
-            w.im += Z[c * U + i].im;
-          }
-          Sv[i] = prox64(f, w);
-        }
-        __syncthreads();
-        for (int t = 2; t <= f.T; ++t) {
-          // lambda_c += gamma (z_c - s)
-          for (int e = tid; e < CU; e += kFixThreads) {
-            const int i = e % U;
-            LM[e].re += f.gamma * (Z[e].re - Sv[i].re);
-            LM[e].im += f.gamma * (Z[e].im - Sv[i].im);
-          }
-          __syncthreads();
-          // z_c = y_c^reg + rho B_c^{-1} (s - lambda_c)
-          for (int e = tid; e < CU; e += kFixThreads) {
-            const int c = e / U, i = e - c * U;
-            const d2* Mi = Mslot + (size_t)c * UU + i * U;
-            d2 acc = dzero();
-            for (int j = 0; j < U; ++j)
-              dmac(acc, Mi[j], d2{Sv[j].re - LM[c * U + j].re, Sv[j].im - LM[c * U + j].im});
-            Z[e] = d2{Y[e].re + f.rho * acc.re, Y[e].im + f.rho * acc.im};
-          }
-          __syncthreads();
-          // s = prox(sum_c (z_c + lambda_c))
-          for (int i = tid; i < U; i += kFixThreads) {
-            d2 w = dzero();
-            for (int c = 0; c < C; ++c) {
-              w.re += Z[c * U + i].re + LM[c * U + i].re;
-              w.im += Z[c * U + i].im + LM[c * U + i].im;
-            }
-            Sv[i] = prox64(f, w);
-          }
-          __syncthreads();
-        }
-        for (int i = tid; i < U; i += kFixThreads) write_out(f, k, n, i, Sv[i]);
-        __syncthreads();
-      }
-    }
-  }
+// Split recomputation, step 2: the iterations of subcarrier f.list0[g] with
+// the inverses of slot g.
+template <int U>
+__global__ void __launch_bounds__(kFixThreads) admm_ul_iter64(FixArgs f) {
+  extern __shared__ d2 fsm[];
+  const int k = f.list0[blockIdx.x];
+  if (k < 0) return;   // uniform
+  const int CU = f.C * U;
+  const d2* Mslot = static_cast<const d2*>(f.ws) + (size_t)blockIdx.x * f.C * U * U;
+  fix64_iterate<U, kFixThreads>(f, k, Mslot, fsm, fsm + CU, fsm + 2 * CU, fsm + 3 * CU);
 }
 
 // Algorithm 2 in FP64 for the flagged subcarriers (f.rho = N0 / Es, or 0 for
@@ -470,12 +518,25 @@ hipError_t launch_admm_ul_fix64(const FixArgs& f, hipStream_t st) {
   const int CG = kFixThreads / ((U / TI) * (U / TI));
   const int vec = 3 * CU + U, piv = 2 * CG * U;
   const size_t lds = (size_t)(vec > piv ? vec : piv) * sizeof(d2) + (kListCap + kFixThreads / 64 + 4) * sizeof(int);
-  const dim3 grid((unsigned)f.n_slots), block(kFixThreads);
+  const size_t lds_iter = (size_t)vec * sizeof(d2);
+  const dim3 grid((unsigned)f.n_slots), block(kFixThreads), grid2((unsigned)f.n_slots, (unsigned)f.C), block2(256);
   switch (U) {
     case 8: hipLaunchKernelGGL(admm_ul_fix64<8>, grid, block, lds, st, f); break;
     case 16: hipLaunchKernelGGL(admm_ul_fix64<16>, grid, block, lds, st, f); break;
-    case 32: hipLaunchKernelGGL(admm_ul_fix64<32>, grid, block, lds, st, f); break;
-    case 64: hipLaunchKernelGGL(admm_ul_fix64<64>, grid, block, lds, st, f); break;
+    case 32:
+      hipLaunchKernelGGL(admm_ul_fix64<32>, grid, block, lds, st, f);
+      if (f.split) {
+        hipLaunchKernelGGL(admm_ul_factor64<32>, grid2, block2, 0, st, f);
+        hipLaunchKernelGGL(admm_ul_iter64<32>, grid, block, lds_iter, st, f);
+      }
+      break;
+    case 64:
+      hipLaunchKernelGGL(admm_ul_fix64<64>, grid, block, lds, st, f);
+      if (f.split) {
+        hipLaunchKernelGGL(admm_ul_factor64<64>, grid2, block2, 0, st, f);
+        hipLaunchKernelGGL(admm_ul_iter64<64>, grid, block, lds_iter, st, f);
+      }
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

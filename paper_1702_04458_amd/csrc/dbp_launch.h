@@ -48,6 +48,8 @@ struct FixArgs {
   uint8_t* hard;      // [n_sc][n_sym][U]
   int32_t* flags;     // [n_sc] status bits of the FP32 pass (read; the re-slice bit is kept)
   void* ws;           // n_slots blocks of C U^2 complex FP64 (ADMM), or null (CG)
+  int* list0;         // [n_slots] subcarriers recomputed with one workgroup per cluster (split)
+  int split;          // 1: each workgroup's first subcarrier goes to the per-cluster kernels
   int n_sc, n_sym, B, U, C, S, T, reg, L, n_slots;
   double rho;         // ADMM penalty (Alg. 1) or N0/Es (Alg. 2)
   double gamma, inv_den, invC, box_r, kappa;
