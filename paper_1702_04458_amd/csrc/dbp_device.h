@@ -265,7 +265,86 @@ __device__ __forceinline__ c32 matvec16(const c32 (&A)[16], c32 q) {
   DBP_MV16_BLOCK(12, 13, 14, 15);
   return cadd(a0, a1);
 }
+// Rows of a 16 x 16 matrix split over the two 16-lane DPP rows of a 32-lane
+// group: lane r of DPP row h holds entries 8h .. 8h+7 of matrix row r (A[i] is
+// column 8h + i).  Every lane of the group holds data, where the lane-row
+// layout leaves half of a 32-lane group idle in the sweep and the products.
+//
+// out_r = sum_j M[r][j] q_j with q_j held by lane j of both DPP rows; both
+// lanes of row r receive out_r.  The odd DPP rows take q rotated by eight
+// lanes (row_ror:8), so that broadcasting lane i gives every lane q_{8h+i}.
+__device__ __forceinline__ c32 matvec_split16(const c32 (&A)[8], c32 q) {
+  q.re = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(q.re), __float_as_int(q.re), 0x128, 0xA, 0xF, false));
+  q.im = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(q.im), __float_as_int(q.im), 0x128, 0xA, 0xF, false));
+  c32 a0 = cz(), a1 = cz();
+  DBP_MV16_BLOCK(0, 1, 2, 3);
+  DBP_MV16_BLOCK(4, 5, 6, 7);
+  c32 acc = cadd(a0, a1);
+  const auto sr = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc.re), __float_as_uint(acc.re), false, false);
+  const auto si = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc.im), __float_as_uint(acc.im), false, false);
+  return c32{__uint_as_float(sr[0]) + __uint_as_float(sr[1]), __uint_as_float(si[0]) + __uint_as_float(si[1])};
+}
 #undef DBP_MV16_BLOCK
+
+// gj_invert_sym for a 16 x 16 matrix in the split-row layout above (r = matrix
+// row of this lane, h = its DPP row within the group; line = the group's 32
+// broadcast slots).  Pivot k publishes column k (slot 16 h_k + r holds S[r][k],
+// h_k = k / 8); a lane reads the eight entries S[8h + i][k] of its half and
+// its own multiplier S[r][k], and updates its eight entries: 8 complex MACs
+// per pivot instead of 16.  Rows past the matrix are identity padding.
+__device__ __forceinline__ void gj_invert_sym_split16(c32 (&A)[8], int r, int h, c32* line) {
+  float pvv = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int hk = k >> 3, kk = k & 7;
+    line[16 * h + r] = A[kk];
+    wave_lds_sync();
+    c32 col[8];
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+      const float4 v = *reinterpret_cast<const float4*>(line + 16 * hk + 8 * h + i);
+      col[i] = c32{v.x, v.y};
+      col[i + 1] = c32{v.z, v.w};
+    }
+    const c32 own = line[16 * hk + r];
+    const float d = line[16 * hk + k].re;
+    wave_lds_sync();
+    const float pv = __builtin_amdgcn_rcpf(d);
+    const bool me = (r == k);
+    // t = -S[r][k] / d (zero on the pivot row, which the sweep leaves alone)
+    const float tr = me ? 0.f : -own.re * pv, ti = me ? 0.f : -own.im * pv;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float ur = tr, ui = ti;
+      if (i == kk) {
+        // column k itself is left alone (it sits in slot kk of half h_k)
+        ur = (h == hk) ? 0.f : tr;
+        ui = (h == hk) ? 0.f : ti;
+      }
+      A[i].re = fmaf(ur, col[i].re, A[i].re);
+      A[i].re = fmaf(ui, col[i].im, A[i].re);
+      A[i].im = fmaf(ui, col[i].re, A[i].im);
+      A[i].im = fmaf(-ur, col[i].im, A[i].im);
+    }
+    if (me && h == hk) A[kk].re = -A[kk].re;
+    if (me) pvv = pv;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) asm volatile("" : "+v"(A[i].re), "+v"(A[i].im));
+  }
+  // B^{-1}[r][j] = -S[r][j] / (d_r d_j): the column factors from half 0's slots
+  if (h == 0) line[r] = c32{pvv, 0.f};
+  wave_lds_sync();
+#pragma unroll
+  for (int i = 0; i < 8; i += 2) {
+    const float4 v = *reinterpret_cast<const float4*>(line + 8 * h + i);
+    const float s0 = -pvv * v.x, s1 = -pvv * v.z;
+    A[i].re *= s0;
+    A[i].im *= s0;
+    A[i + 1].re *= s1;
+    A[i + 1].im *= s1;
+  }
+  wave_lds_sync();
+}
 
 template <int G>
 __device__ __forceinline__ c32 group_matvec(const c32 (&A)[G], c32 q, int u, c32* line, int gbase) {

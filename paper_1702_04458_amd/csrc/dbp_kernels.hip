@@ -832,8 +832,12 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
 // is read from memory once.  The 16x16 result (lane l: column l%16, rows 4(l/16)+r) goes
 // through the wave's stage buffer so that lane b < 16 of each problem's lane
 // group reads row b.
-__device__ __forceinline__ void gram_dl_mfma_s16_u32(const c32 (&hcol)[16], c32 (&A)[16], int lane, int g, int u,
-                                                     c32* stage) {
+// SPLITOUT: the result in the split-row layout of gj_invert_sym_split16 (lane
+// r of DPP row h of the group gets entries 8h .. 8h+7 of row r) instead of
+// one row per lane u < 16.
+template <bool SPLITOUT = false>
+__device__ __forceinline__ void gram_dl_mfma_s16_u32(const c32 (&hcol)[16], c32 (&A)[SPLITOUT ? 8 : 16], int lane,
+                                                     int g, int u, c32* stage) {
   const int q = lane >> 4, r16 = lane & 15;
   f32x4 re[2], im[2];
 #pragma unroll
@@ -865,8 +869,17 @@ __device__ __forceinline__ void gram_dl_mfma_s16_u32(const c32 (&hcol)[16], c32 
   wave_lds_sync();
   // Re A[b][v] = (P P^T)[b][v] - M[b][v] - M[v][b], Im A[b][v] = M[b][v] - M[v][b]
   const int p = lane >> 5, b = lane & 31;
-  if (b < 16) {
-    const float* stf = reinterpret_cast<const float*>(stage + p * 256);
+  const float* stf = reinterpret_cast<const float*>(stage + p * 256);
+  if constexpr (SPLITOUT) {
+    const int r = b & 15, v0 = 8 * (b >> 4);
+    c32 row[8];
+    lds_read_vec<8>(stage + p * 256 + r * 16 + v0, row);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const float mt = stf[2 * ((v0 + v) * 16 + r) + 1];
+      A[v] = c32{row[v].re - row[v].im - mt, row[v].im - mt};
+    }
+  } else if (b < 16) {
 #pragma unroll
     for (int v0 = 0; v0 < 16; v0 += 8) {
       c32 row[8];
@@ -1563,16 +1576,19 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   constexpr int RS = SPLIT ? SG : G;       // row entries held per lane
   const int ra = SPLIT ? (u % SG) : u;     // row of Hu_c held by this lane
   const int r0 = SPLIT ? RS * (u / SG) : 0;
-  c32 hcol[SG], hrow[RS], A[SG];
   // With the matrix-core Gram (U = 32, S <= 16) the row copy hrow is formed
   // only after the inverse, from hcol through LDS, so that it is not live
   // during the Gram and the sweep (register budget of four waves per SIMD).
   constexpr bool LATE_H = (G == 32 && SG == 16);
+  // There (without the budget) A_c and its inverse also take the split-row
+  // layout: lane u holds entries 8 (u / 16) .. + 7 of row u % 16, so that all
+  // 32 lanes of the group share the sweep and the products A_c^{-1} r.
+  constexpr bool ASPLIT = LATE_H && !BUDGET;
+  c32 hcol[SG], hrow[RS], A[ASPLIT ? 8 : SG];
 #pragma unroll
-  for (int i = 0; i < SG; ++i) {
-    hcol[i] = (active && i < S) ? Hk[(size_t)i * sa + (size_t)u * su] : cz();
-    A[i] = cz();
-  }
+  for (int i = 0; i < SG; ++i) hcol[i] = (active && i < S) ? Hk[(size_t)i * sa + (size_t)u * su] : cz();
+#pragma unroll
+  for (int i = 0; i < (ASPLIT ? 8 : SG); ++i) A[i] = cz();
   if constexpr (!LATE_H) {
 #pragma unroll
     for (int i = 0; i < RS; ++i) hrow[i] = (active && ra < S) ? Hk[(size_t)ra * sa + (size_t)(r0 + i) * su] : cz();
@@ -1581,7 +1597,7 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   // M (rows a < S; M must hold zeros).  Every lane of the wave takes part.
   auto gram_into = [&](c32 (&M)[SG]) {
     if constexpr (LATE_H) {
-      gram_dl_mfma_s16_u32(hcol, M, lane, g, u, sm.stage + wave * kStageRows * 64);
+      gram_dl_mfma_s16_u32<false>(hcol, M, lane, g, u, sm.stage + wave * kStageRows * 64);
     } else {
       // Row b of Hu_c is broadcast from the stage buffer of this wave.
       c32* stage = sm.stage + wave * kStageRows * 64;
@@ -1610,12 +1626,21 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
     }
   };
   // A_c = H_c^H H_c + rho^{-1} I_S
-  gram_into(A);
   const float irho = 1.0f / a.rho;
+  if constexpr (ASPLIT) {
+    gram_dl_mfma_s16_u32<true>(hcol, A, lane, g, u, sm.stage + wave * kStageRows * 64);
+    const int h = u >> 4, r = u & 15;
 #pragma unroll
-  for (int v = 0; v < SG; ++v)
-    if (v == u) A[v].re += (u < S) ? irho : 1.0f;
-  gj_invert<SG>(A, u, line, gbase);
+    for (int i = 0; i < 8; ++i)
+      if (8 * h + i == r) A[i].re += (r < S) ? irho : 1.0f;
+    gj_invert_sym_split16(A, r, h, line + gbase);
+  } else {
+    gram_into(A);
+#pragma unroll
+    for (int v = 0; v < SG; ++v)
+      if (v == u) A[v].re += (u < S) ? irho : 1.0f;
+    gj_invert<SG>(A, u, line, gbase);
+  }
   if constexpr (LATE_H) {
     // Transpose the S x G tile of each problem through the wave's stage
     // buffer, one problem at a time: entry (i, w) at i G + ((w + 2 i) mod G).
@@ -1667,6 +1692,8 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
       }
       wave_lds_sync();
       if (SPLIT) acc = c32{pair_sum<SG>(acc.re), pair_sum<SG>(acc.im)};
+      // the split-row product below takes entry a from both lanes of row a
+      if constexpr (ASPLIT) return (ra < S) ? acc : cz();
       return (u < S) ? acc : cz();
     };
     // x_c = A_c^{-1} H_c^H (z + lambda), entry a held by lane a < S.  At
@@ -1677,7 +1704,12 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
     // from H itself, r - H_c^H (H_c x) - x / rho, wins it back.
     auto apply = [&](c32 v) -> c32 {
       const c32 r = hhv(v);
-      c32 xa = group_matvec<SG>(A, r, u, line, gbase);
+      // entry a of x_c on lane a < S (with the split rows, on both lanes of row a)
+      c32 xa;
+      if constexpr (ASPLIT)
+        xa = matvec_split16(A, r);
+      else
+        xa = group_matvec<SG>(A, r, u, line, gbase);
       if constexpr (SG == G) {
         bl[bw] = xa;
         wave_lds_sync();
