@@ -53,8 +53,11 @@ extern "C" {
 #define DBP_PREC_MIXED_BF16 2  /* Gram on BF16 MFMA (FP32 accumulate) + FP32 refinement */
 /* Precision of the regularised inverse in the mixed modes, OR-ed into prec:
  *   DBP_FACTOR_FP32   Gauss-Jordan on the FP32 matrix cores;
- *   DBP_FACTOR_FP64   Gauss-Jordan in FP64 on the vector units (U = 32 only;
- *                     at U = 64 it returns DBP_ERR_UNSUPPORTED);
+ *   DBP_FACTOR_FP64   Gauss-Jordan in FP64 on the vector units at U = 32; at
+ *                     U = 64 the detection calls recompute every subcarrier
+ *                     in FP64 (the FP64 pass below: Gram, inverse and
+ *                     iterations) and dbp_factor_admm returns
+ *                     DBP_ERR_UNSUPPORTED;
  *   DBP_FACTOR_F16X2  Gauss-Jordan on the FP16 matrix cores with every
  *                     operand split into an FP16 hi + lo pair (about 22
  *                     significant bits) and FP32 accumulation; the FP16
@@ -62,10 +65,16 @@ extern "C" {
  *                     accumulation is not correctly rounded under
  *                     cancellation, so the inverse is about 30x less
  *                     accurate than DBP_FACTOR_FP32 (frame error ~5e-5).
- * By default (no flag) the inverse is FP64 when U/S > 0.8 (poorly
- * conditioned regularised Grams) and FP32 otherwise; U = 64 defaults to
- * FP32.  The FP32 mode (DBP_PREC_FP32) always inverts on the FP32 matrix
- * cores and accepts no other factor flag. */
+ * By default (no flag) the inverse is FP32, and FP64 serves the poorly
+ * conditioned regularised Grams, which occur at aspect ratios U/S > 0.8:
+ * there dbp_detect_admm inverts on the FP32 matrix cores, bounds each
+ * cluster's condition number by kappa_hat = tr(B_c) ||B_c^{-1}||_F (at
+ * least kappa_2(B_c), at most U^1.5 times it) and recomputes the subcarriers
+ * with a cluster above 2^14 entirely in FP64 (status DBP_STATUS_ILLCOND; this
+ * needs the workspace even without hard decisions), U = 32 and 64;
+ * dbp_factor_admm takes the FP64 inverse at U = 32 instead.  The FP32 mode
+ * (DBP_PREC_FP32) always inverts on the FP32 matrix cores and accepts no
+ * other factor flag. */
 #define DBP_FACTOR_FP32 0x10
 #define DBP_FACTOR_FP64 0x20
 #define DBP_FACTOR_F16X2 0x30
@@ -73,7 +82,9 @@ extern "C" {
 /* Per-subcarrier status bits (status arrays of the detection calls and of
  * dbp_flag_nonfinite). */
 #define DBP_STATUS_NONFINITE 1   /* a real or imaginary part of an output is NaN or infinite      */
-#define DBP_STATUS_RESLICED 2    /* recomputed in FP64 for exact hard decisions (see below)       */
+#define DBP_STATUS_RESLICED 2    /* recomputed in FP64 (exact hard decisions, see below, or bit 4) */
+#define DBP_STATUS_ILLCOND 4     /* a cluster's regularised Gram exceeded the FP64 factor rule's
+                                    bound (mixed modes, U/S > 0.8): recomputed in FP64            */
 
 /* Exact hard decisions.  Slicing (Section III-A) takes the nearest point of
  * the constellation; an FP32 soft value that lies within rounding distance of
@@ -117,8 +128,10 @@ const char* dbp_last_error(void);
  *   status [n_sc] int32 or NULL  output: DBP_STATUS_* bits of every subcarrier
  *   workspace, workspace_bytes  device workspace of at least
  *          dbp_detect_workspace_bytes(n_sc, U, C) bytes when hard != NULL
- *          (may be NULL when hard == NULL); DBP_ERR_INVALID if missing,
- *          smaller or not 256-byte aligned
+ *          or when the FP64 factor rule applies (mixed modes without a
+ *          factor flag at U/S > 0.8, or DBP_FACTOR_FP64 at U = 64); may be
+ *          NULL otherwise; DBP_ERR_INVALID if missing, smaller or not
+ *          256-byte aligned
  *   T      number of estimates s^(1..T) (T - 1 ADMM iterations after the
  *          initial consensus), T >= 1
  *   rho    ADMM penalty > 0;  gamma  dual step > 0 (the paper uses 1)

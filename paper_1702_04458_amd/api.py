@@ -82,12 +82,12 @@ def workspace(n_sc, U, C, device="cuda"):
     return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
 
 
-def _workspace(ws, hd, n_sc, U, C, device):
-    """(pointer, bytes, tensor) of the re-slice workspace, needed with hard
-    decisions.  The caller keeps the tensor referenced until the call that
-    uses it has been queued (a workspace allocated here must not return to
-    the allocator before that)."""
-    if hd is None:
+def _workspace(ws, need_ws, n_sc, U, C, device):
+    """(pointer, bytes, tensor) of the workspace of the FP64 pass, needed with
+    hard decisions and by the mixed modes' FP64 factor rule.  The caller keeps
+    the tensor referenced until the call that uses it has been queued (a
+    workspace allocated here must not return to the allocator before that)."""
+    if not need_ws:
         return None, 0, None
     need = _native.lib().dbp_detect_workspace_bytes(n_sc, U, C)
     if ws is None:
@@ -126,7 +126,9 @@ def detect(H, y, N0, C, rho=1.0, T=5, *, algo="admm", reg="mmse", qam=16, Es=1.0
     _dev(y, "y")
     n_sc, n_sym, B, U, y = _shapes(H, y)
     s_hat, hd, stt = _outputs(out, n_sc, n_sym, U, H.device, hard, status)
-    wp, wb, _ws_keep = _workspace(workspace, hd, n_sc, U, C, H.device)
+    # the mixed modes may send ill-conditioned subcarriers to the FP64 pass
+    need_ws = hd is not None or (algo == "admm" and prec != "fp32")
+    wp, wb, _ws_keep = _workspace(workspace, need_ws, n_sc, U, C, H.device)
     _mark_stream(_ws_keep, workspace, stream)
     L = _native.lib()
     st = _stream(stream)
@@ -187,7 +189,7 @@ def detect_batch(frames, *, stream=None):
             raise ValueError("every frame of a batch must have the same U")
         C = int(f["C"])
         s_hat, hd, stt = _outputs(None, n_sc, n_sym, U, H.device, f.get("hard", True), f.get("status", False))
-        wp, wb, wt = _workspace(f.get("workspace"), hd, n_sc, U, C, H.device)
+        wp, wb, wt = _workspace(f.get("workspace"), hd is not None, n_sc, U, C, H.device)
         _mark_stream(wt, f.get("workspace"), stream)
         keep.append((H, y, wt))
         e = arr[i]
@@ -216,7 +218,7 @@ def detect_factored(H, factors, y, N0, C, rho=1.0, T=5, *, reg="mmse", qam=16, E
     if factors.numel() * 8 != _native.lib().dbp_factor_bytes(n_sc, U, C):
         raise ValueError("factors do not match (n_sc, U, C)")
     s_hat, hd, stt = _outputs(out, n_sc, n_sym, U, H.device, hard, status)
-    wp, wb, _ws_keep = _workspace(workspace, hd, n_sc, U, C, H.device)
+    wp, wb, _ws_keep = _workspace(workspace, hd is not None, n_sc, U, C, H.device)
     _mark_stream(_ws_keep, workspace, stream)
     code = _native.lib().dbp_detect_admm_factored(
         H.data_ptr(), factors.data_ptr(), y.data_ptr(), s_hat.data_ptr(), hd.data_ptr() if hd is not None else None,

@@ -185,8 +185,24 @@ int admm_args(const char* who, int n_sc, int n_sym, int B, int U, int C, int T, 
   return DBP_OK;
 }
 
-// Precision flags of the ADMM preprocessing -> (gram_prec, inverse kind).
-int admm_prec(const char* who, int prec, int U, int S, int* gram_prec, int* inv) {
+// Threshold of the FP64 factor rule on kappa_hat = tr(B_c) ||B_c^{-1}||_F, an
+// upper bound of kappa_2(B_c) (at most U^1.5 times it): above 2^14 the FP32
+// inverse may lose more than about 1e-3 (relative error of order kappa u,
+// u = 2^-24), the low-precision bar.  i.i.d. Rayleigh clusters at S = U = 32
+// and rho = 1 give kappa_hat of 1.1e3 .. 2.1e3, so the rule costs nothing
+// there; rho = 0.01 flags most clusters.
+constexpr float kCondMax = 16384.f;
+// kappa_hat of the channels the re-slice guards were measured on (i.i.d.
+// Rayleigh, S = U, rho = 1: largest values about 2.0e3 at U = 32 and 9.1e3 at
+// U = 64); the guard of a subcarrier grows by its largest kappa_hat over this.
+inline float cond_ref(int U) { return U >= 64 ? 8192.f : 2048.f; }
+
+// Precision flags of the ADMM preprocessing -> (gram_prec, inverse kind,
+// FP64 factor rule).  one_shot: a detection call, which can recompute flagged
+// subcarriers in FP64; otherwise the factorisation alone (dbp_factor_admm),
+// which keeps the FP64 inverse at U = 32 for the rule.
+int admm_prec(const char* who, int prec, int U, int S, int* gram_prec, int* inv, float* cond = nullptr,
+              bool one_shot = false) {
   *gram_prec = prec & 0xF;
   const int factor = prec & ~0xF;
   if (*gram_prec < DBP_PREC_FP32 || *gram_prec > DBP_PREC_MIXED_BF16 ||
@@ -195,17 +211,29 @@ int admm_prec(const char* who, int prec, int U, int S, int* gram_prec, int* inv)
   if (S < U) return fail(DBP_ERR_UNSUPPORTED, "%s: S=%d < U=%d (S x S branch) not built", who, S, U);
   if (*gram_prec != DBP_PREC_FP32 && U != 32 && U != 64)
     return fail(DBP_ERR_UNSUPPORTED, "%s: mixed precision is built for U=32 and U=64 only", who);
-  if (*gram_prec != DBP_PREC_FP32 && U == 64 && factor == DBP_FACTOR_FP64)
-    return fail(DBP_ERR_UNSUPPORTED, "%s: the FP64 inverse is built for U=32 only (a 64x64 FP64 row set exceeds a "
+  if (*gram_prec != DBP_PREC_FP32 && U == 64 && factor == DBP_FACTOR_FP64 && !one_shot)
+    return fail(DBP_ERR_UNSUPPORTED, "%s: the stored FP64 inverse is built for U=32 only (a 64x64 FP64 row set exceeds a "
                 "wave's registers)", who);
   if (*gram_prec == DBP_PREC_FP32 && (factor == DBP_FACTOR_FP64 || factor == DBP_FACTOR_F16X2))
     return fail(DBP_ERR_UNSUPPORTED, "%s: the FP64 and split-FP16 inverses are built for the mixed modes only", who);
-  // Default rule: FP64 inverse for poorly conditioned regularised Grams
-  // (aspect ratio U/S > 0.8), the FP32 matrix-core inverse otherwise (U = 64
-  // has no FP64 inverse and takes the FP32 one).
+  // Default rule: FP64 for poorly conditioned regularised Grams (aspect
+  // ratio U/S > 0.8), the FP32 matrix-core inverse otherwise.  A detection
+  // call takes the FP32 inverse, estimates each cluster's condition number
+  // and recomputes the subcarriers of clusters above kCondMax entirely in
+  // FP64 (an explicit FP64 request at U = 64 sends every subcarrier there);
+  // the factorisation alone uses the FP64 inverse on the vector units (U = 32).
   *inv = 0;
-  if (factor == DBP_FACTOR_F16X2) *inv = 2;
-  else if (factor == DBP_FACTOR_FP64 || (factor == 0 && 5 * U > 4 * S && U == 32)) *inv = 1;
+  if (cond) *cond = 0.f;
+  const bool rule = factor == 0 && 5 * U > 4 * S && *gram_prec != DBP_PREC_FP32;
+  if (factor == DBP_FACTOR_F16X2) {
+    *inv = 2;
+  } else if (one_shot && rule) {
+    *cond = kCondMax;
+  } else if (one_shot && factor == DBP_FACTOR_FP64 && U == 64) {
+    *cond = -1.f;
+  } else if (factor == DBP_FACTOR_FP64 || (rule && U == 32)) {
+    *inv = 1;
+  }
   return DBP_OK;
 }
 
@@ -244,8 +272,11 @@ int setup_reslice(const char* who, dbp::UlArgs& a, dbp::FixArgs& f, int32_t* sta
   a.flags = status;
   a.guard = 0.f;
   f = dbp::FixArgs{};
-  if (!a.hard) return DBP_OK;
+  if (!a.hard && a.cond_max == 0.f) return DBP_OK;
   const size_t fb = status ? 0 : flags_region(a.n_sc);
+  if (!ws && !a.hard)
+    return fail(DBP_ERR_INVALID, "%s: the FP64 factor rule of the mixed modes (U/S > 0.8) needs a workspace "
+                "(dbp_detect_workspace_bytes)", who);
   if (!ws) return fail(DBP_ERR_INVALID, "%s: hard decisions need a workspace (dbp_detect_workspace_bytes)", who);
   if (reinterpret_cast<uintptr_t>(ws) % 256)
     return fail(DBP_ERR_INVALID, "%s: workspace must be 256-byte aligned", who);
@@ -258,7 +289,7 @@ int setup_reslice(const char* who, dbp::UlArgs& a, dbp::FixArgs& f, int32_t* sta
   }
   if (slots < 1) return fail(DBP_ERR_INVALID, "%s: workspace of %zu bytes is too small", who, ws_bytes);
   a.flags = status ? status : static_cast<int32_t*>(ws);
-  a.guard = guard;
+  a.guard = a.hard ? guard : 0.f;
   f.flags = a.flags;
   f.ws = static_cast<char*>(ws) + fb;
   // 256-byte aligned, kFixMaxSlots ints, inside the last kList0Room bytes
@@ -330,7 +361,8 @@ int detect_admm_impl(const char* who, const void* H, const void* y, void* s_hat,
   int st = admm_args(who, n_sc, n_sym, B, U, C, T, rho, gamma, N0, Es, reg, qam, &a, &S);
   if (st) return st;
   int gram_prec = 0, inv = 0;
-  st = admm_prec(who, prec, U, S, &gram_prec, &inv);
+  float cond = 0.f;
+  st = admm_prec(who, prec, U, S, &gram_prec, &inv, &cond, true);
   if (st) return st;
   if (n_sc > 0 && (!H || !y || !s_hat)) return fail(DBP_ERR_INVALID, "%s: null H, y or s_hat", who);
   if (n_sc == 0) return ok();
@@ -338,13 +370,15 @@ int detect_admm_impl(const char* who, const void* H, const void* y, void* s_hat,
   a.y = static_cast<const dbp::c32*>(y);
   a.shat = static_cast<dbp::c32*>(s_hat);
   a.hard = hard;
+  a.cond_max = cond;
+  a.cond_ref = cond_ref(U);
   dbp::FixArgs f;
   st = setup_reslice(who, a, f, status, workspace, workspace_bytes, reslice_guard(gram_prec, inv, U),
                      dbp::fix64_slot_bytes(U, C), max_slots < full_slots(n_sc) ? max_slots : full_slots(n_sc));
   if (st) return st;
   const hipStream_t hs = static_cast<hipStream_t>(stream);
   st = device_status(who, launch_preprocessing(a, U, gram_prec, inv, hs, 0));
-  if (st || !hard) return st;
+  if (st || (!hard && cond == 0.f)) return st;
   fix_params(f, U, rho, gamma, N0, Es, reg, qam, true);
   f.split = U >= 32;   // large inverses: one workgroup per cluster for each workgroup's first subcarrier
   return device_status(who, dbp::launch_admm_ul_fix64(f, hs));
@@ -357,7 +391,9 @@ extern "C" {
 int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, int32_t* status, void* workspace,
                     size_t workspace_bytes, int n_sc, int n_sym, int B, int U, int C, int T, float rho, float gamma,
                     float N0, float Es, int reg, int qam, int prec, void* stream) {
-  if (hard && workspace && workspace_bytes < dbp_detect_workspace_bytes(n_sc, U, C))
+  // the workspace serves the FP64 pass: hard decisions, or the FP64 factor rule of the mixed modes
+  if ((hard || (prec & 0xF) != DBP_PREC_FP32) && workspace &&
+      workspace_bytes < dbp_detect_workspace_bytes(n_sc, U, C))
     return fail(DBP_ERR_INVALID, "dbp_detect_admm: workspace of %zu bytes, %zu needed", workspace_bytes,
                 dbp_detect_workspace_bytes(n_sc, U, C));
   return dbp::detect_admm_impl("dbp_detect_admm", H, y, s_hat, hard, status, workspace, workspace_bytes,

@@ -395,12 +395,13 @@ __device__ __forceinline__ bool near_threshold(float x, float kappa, int L, floa
 __device__ __forceinline__ bool nonfinite(c32 v) { return !(isfinite(v.re) && isfinite(v.im)); }
 
 // Status bits of one subcarrier from the per-lane bits of the G lanes of lane
-// group g (bit 0 non-finite, bit 1 re-slice); every lane of the wave must call.
+// group g (bit 0 non-finite, bit 1 re-slice, bit 2 poorly conditioned Gram);
+// every lane of the wave must call.
 template <int G>
 __device__ __forceinline__ int group_flags(int fl, int g) {
   const unsigned long long gm = (G == 64) ? ~0ull : (((1ull << G) - 1) << (g * G));
-  const unsigned long long m1 = __ballot(fl & 1), m2 = __ballot(fl & 2);
-  return ((m1 & gm) ? 1 : 0) | ((m2 & gm) ? 2 : 0);
+  const unsigned long long m1 = __ballot(fl & 1), m2 = __ballot(fl & 2), m4 = __ballot(fl & 4);
+  return ((m1 & gm) ? 1 : 0) | ((m2 & gm) ? 2 : 0) | ((m4 & gm) ? 4 : 0);
 }
 
 }  // namespace dbp

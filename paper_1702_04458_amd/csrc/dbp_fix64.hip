@@ -133,7 +133,7 @@ __device__ __forceinline__ d2 prox64(const FixArgs& f, d2 w) {
 __device__ __forceinline__ void write_out(const FixArgs& f, int k, int n, int u, d2 s) {
   const size_t o = ((size_t)k * f.n_sym + n) * f.U + u;
   f.shat[o] = c32{(float)s.re, (float)s.im};
-  f.hard[o] = (uint8_t)(slice64(s.re, f.kappa, f.L) + f.L * slice64(s.im, f.kappa, f.L));
+  if (f.hard) f.hard[o] = (uint8_t)(slice64(s.re, f.kappa, f.L) + f.L * slice64(s.im, f.kappa, f.L));
 }
 
 }  // namespace

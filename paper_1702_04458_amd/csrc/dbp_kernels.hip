@@ -419,6 +419,11 @@ __device__ __forceinline__ float wave_max(float v) {
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
   return v;
 }
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
 
 // Normalisation of the mixed-mode Gram before the FP16 inverse.  H_c is scaled
 // by 2^ex so that its largest entry lies in [2^13, 2^14); the Gram of i.i.d.
@@ -437,7 +442,7 @@ __device__ __forceinline__ int norm_shift(int S) { return 9 + (32 - __builtin_cl
 // problem's scaling exponent either way.
 template <typename HT, bool NORM>
 __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2], f32x16 (&im)[2], c32 (&hyp)[2],
-                                               int lane, int wave, int (&ex)[2], float* stage) {
+                                               int lane, int wave, int (&ex)[2], float* stage, float (&trg)[2]) {
   typedef typename HalfMma<HT>::V V;
   const int h = lane >> 5, col = lane & 31;
   const c32* Hp[2];
@@ -455,18 +460,21 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
     im[p] = f32x16{};
     hyp[p] = cz();
   }
-  // pass 1: largest |Re|, |Im| of each problem -> scale exponent
+  // pass 1: largest |Re|, |Im| of each problem -> scale exponent (and
+  // ||H_c||_F^2 = tr(G_c))
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
-    float m = 0.f;
+    float m = 0.f, ss = 0.f;
     for (int s0 = 0; s0 < a.S; s0 += 16) {
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int s = s0 + 8 * h + t;
         const c32 v = ld_or_zero(Hp[p] + (size_t)min(s, a.S - 1) * 32 + col, act[p] && s < a.S);
         m = fmaxf(m, fmaxf(fabsf(v.re), fabsf(v.im)));
+        ss = fmaf(v.re, v.re, fmaf(v.im, v.im, ss));
       }
     }
+    trg[p] = wave_sum(ss);
     m = wave_max(m);
     int x = 0;
     if (m > 0.f) frexpf(m, &x);      // m < 2^x
@@ -684,12 +692,15 @@ __device__ __forceinline__ void gj_invert_split16_u32(f32x16 (&re)[2], f32x16 (&
 // H_c^H y_c and leaves row u of (G + rho I)^{-1} in A.  INV selects the
 // inverse: 0 FP32 matrix cores, 1 FP64 VALU, 2 split FP16 matrix cores.
 template <typename HT, int INV>
-__device__ __forceinline__ c32 gram_inv_mixed_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave, c64* line64) {
+__device__ __forceinline__ c32 gram_inv_mixed_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave, c64* line64,
+                                                  float& trg) {
   const int h = lane >> 5;
   f32x16 re[2], im[2];
   c32 hyp[2];
   int ex[2];
-  gram_split_u32<HT, INV == 2>(a, re, im, hyp, lane, wave, ex, reinterpret_cast<float*>(line64));
+  float tr[2];
+  gram_split_u32<HT, INV == 2>(a, re, im, hyp, lane, wave, ex, reinterpret_cast<float*>(line64), tr);
+  trg = h ? tr[1] : tr[0];
   if (INV == 0) {
     gj_invert_mfma_u32(re, im, lane, a.rho, reinterpret_cast<float*>(line64));
     acc_to_rows_u32(re, im, A, h);
@@ -1156,7 +1167,7 @@ __device__ __forceinline__ void gj_invert_split16_u64(f32x16 (&re)[2][2], f32x16
 // the normalised Gram (INV = 2).
 template <typename HT, int INV>
 __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave,
-                                                  float* line) {
+                                                  float* line, float& trg) {
   typedef typename HalfMma<HT>::V V;
   const int h = lane >> 5, col = lane & 31;
   const int ls = wave / a.Cp, c = wave % a.Cp;
@@ -1172,8 +1183,8 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
       re[I][J] = f32x16{};
       im[I][J] = f32x16{};
     }
-  // pass 1: scale exponent from the largest |Re|, |Im|
-  float mx = 0.f;
+  // pass 1: scale exponent from the largest |Re|, |Im| (and ||H_c||_F^2 = tr(G_c))
+  float mx = 0.f, ss = 0.f;
   for (int s0 = 0; s0 < a.S; s0 += 16) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -1183,8 +1194,10 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
       const c32 v0 = ld_or_zero(Hk + (size_t)sc * 64 + col, ok);
       const c32 v1 = ld_or_zero(Hk + (size_t)sc * 64 + 32 + col, ok);
       mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v0.re), fabsf(v0.im)), fmaxf(fabsf(v1.re), fabsf(v1.im))));
+      ss = fmaf(v0.re, v0.re, fmaf(v0.im, v0.im, fmaf(v1.re, v1.re, fmaf(v1.im, v1.im, ss))));
     }
   }
+  trg = wave_sum(ss);
   mx = wave_max(mx);
   int x = 0;
   if (mx > 0.f) frexpf(mx, &x);
@@ -1347,6 +1360,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
 #pragma unroll
   for (int v = 0; v < G; ++v) A[v] = cz();
   c32 hy0 = cz();
+  float trg = 0.f;   // tr(G_c) (mixed modes)
   // resident factors of this problem: entry v of lane u's row at v * G + u
   const size_t fo = ((size_t)k * a.C + c) * G * G + u;
   if constexpr (STAGE >= 2) {
@@ -1358,9 +1372,11 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     hy0 = gram_mfma_u32<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
                               reinterpret_cast<float*>(sm.stage + wave * kStageRows * 64));
   } else if constexpr (G == 32 && HALF == 1) {
-    hy0 = gram_inv_mixed_u32<_Float16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
+    hy0 = gram_inv_mixed_u32<_Float16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64),
+                                            trg);
   } else if constexpr (G == 32 && HALF == 2) {
-    hy0 = gram_inv_mixed_u32<__bf16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64));
+    hy0 = gram_inv_mixed_u32<__bf16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64),
+                                          trg);
   } else if constexpr (G == 16) {
     hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
 #pragma unroll
@@ -1371,9 +1387,9 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     hy0 = gram_mfma_u64<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
                               reinterpret_cast<float*>(sm.stage + wave * kStageRows * 64));
   } else if constexpr (G == 64 && HALF == 1) {
-    hy0 = gram_inv_mixed_u64<_Float16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line));
+    hy0 = gram_inv_mixed_u64<_Float16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line), trg);
   } else if constexpr (G == 64 && HALF == 2) {
-    hy0 = gram_inv_mixed_u64<__bf16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line));
+    hy0 = gram_inv_mixed_u64<__bf16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line), trg);
   } else {
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 #pragma unroll
@@ -1389,8 +1405,31 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     return;
   }
 
+  // FP64 factor rule (mixed modes, FP32 inverse): kappa_hat = tr(B_c)
+  // ||B_c^{-1}||_F bounds the condition number kappa_2(B_c) from above (the
+  // largest eigenvalue is at most the trace, and ||B_c^{-1}||_2 at most the
+  // Frobenius norm).  A subcarrier with a cluster above cond_max goes to the
+  // FP64 pass.  Below it the FP32 error grows in proportion to the
+  // conditioning, so the re-slice guard is widened by kappa_hat / cond_ref
+  // (cond_ref: the largest kappa_hat of the channels the guard was measured
+  // on).  Each problem's kappa_hat reaches the output lanes of cluster 0
+  // through one LDS slot, read after the first consensus barrier.
+  constexpr bool COND = (HALF > 0 && INV == 0 && STAGE == 0);
+  float* cond_slot = reinterpret_cast<float*>(sm.aux);
+  float guard = a.guard;
+  if constexpr (COND) {
+    if (a.cond_max != 0.f) {
+      float f2 = 0.f;
+#pragma unroll
+      for (int v = 0; v < G; ++v) f2 = fmaf(A[v].re, A[v].re, fmaf(A[v].im, A[v].im, f2));
+      f2 = group_sum<G>(f2);
+      const float kh = (trg + (float)G * a.rho) * sqrtf(f2);
+      if (u == 0) cond_slot[ls * a.Cp + c] = active ? kh : 0.f;
+    }
+  }
+
   int buf = 0;
-  int fl = 0;   // status bits of this lane's outputs (bit 0 non-finite, bit 1 re-slice)
+  int fl = 0;   // status bits of this lane's outputs (bit 0 non-finite, bit 1 re-slice, bit 2 ill-conditioned)
   for (int n = 0; n < a.n_sym; ++n) {
     c32 hy = hy0;
     if constexpr (STAGE == 3)
@@ -1402,6 +1441,20 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     c32 z = yreg, lam = cz();
     c32 w = consensus<HALF == 0>(active ? z : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
     buf ^= 1;
+    if constexpr (COND) {
+      // the barrier inside the consensus above has made every cluster's estimate visible
+      if (n == 0 && a.cond_max != 0.f && c == 0) {
+        float km = 0.f;
+        bool bad = a.cond_max < 0.f;
+        for (int cc = 0; cc < a.C; ++cc) {
+          const float kc = cond_slot[ls * a.Cp + cc];
+          bad = bad || !(kc <= a.cond_max);   // NaN and infinity fail the comparison
+          km = fmaxf(km, kc);
+        }
+        if (bad) fl |= kStatusReslice | kStatusIllcond;
+        guard = a.guard * fmaxf(1.f, km / a.cond_ref);
+      }
+    }
     c32 s;
     if (a.reg == 2) {
       c32 v = cscale(w, a.invC);
@@ -1430,7 +1483,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       if (a.hard) {
         const int iI = slice_dim(s.re, a.kappa, a.L), iQ = slice_dim(s.im, a.kappa, a.L);
         a.hard[o] = (uint8_t)(iI + a.L * iQ);
-        if (near_threshold(s.re, a.kappa, a.L, a.guard) || near_threshold(s.im, a.kappa, a.L, a.guard)) fl |= 2;
+        if (near_threshold(s.re, a.kappa, a.L, guard) || near_threshold(s.im, a.kappa, a.L, guard)) fl |= 2;
       }
       if (nonfinite(s)) fl |= 1;
     }

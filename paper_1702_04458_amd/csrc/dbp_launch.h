@@ -11,6 +11,7 @@ struct c32;
 // per-subcarrier status bits (the values of DBP_STATUS_NONFINITE / DBP_STATUS_RESLICED)
 constexpr int kStatusNonfinite = 1;
 constexpr int kStatusReslice = 2;
+constexpr int kStatusIllcond = 4;
 // workgroups (FP64 slots) of the re-slice pass at most
 constexpr int kFixMaxSlots = 256;
 
@@ -36,6 +37,12 @@ struct UlArgs {
   float guard;        // re-slice guard in slicer units t = (kappa x + L) / 2; 0: no re-slice
   int nw;             // waves per workgroup of the call's launch plan
   int blk;            // block index within this frame's launch (set by the kernel)
+  // FP64 factor rule of the mixed modes: a subcarrier with a cluster whose
+  // estimate tr(B_c) ||B_c^{-1}||_F exceeds cond_max is flagged for the FP64
+  // pass (kStatusReslice | kStatusIllcond); 0: off; < 0: every subcarrier.
+  // Below it the re-slice guard is scaled by max(1, estimate / cond_ref).
+  float cond_max;
+  float cond_ref;
 };
 
 // Exact re-slicing: the subcarriers the FP32 kernel flagged (a soft value
@@ -45,7 +52,7 @@ struct FixArgs {
   const c32* H;       // [n_sc][B][U]
   const c32* y;       // [n_sc][n_sym][B]
   c32* shat;          // [n_sc][n_sym][U]
-  uint8_t* hard;      // [n_sc][n_sym][U]
+  uint8_t* hard;      // [n_sc][n_sym][U] or null (the FP64 factor rule without hard decisions)
   int32_t* flags;     // [n_sc] status bits of the FP32 pass (read; the re-slice bit is kept)
   void* ws;           // n_slots blocks of C U^2 complex FP64 (ADMM), or null (CG)
   int* list0;         // [n_slots] subcarriers recomputed with one workgroup per cluster (split)

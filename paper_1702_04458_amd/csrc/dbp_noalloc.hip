@@ -66,7 +66,7 @@ int dbp_detect_admm_noalloc(const void* H, const void* y, void* s_hat, uint8_t* 
                                         C, T, rho, gamma, N0, Es, reg, qam, prec, stream);
   if (vrc != DBP_OK || n_sc == 0) return vrc;
   void* ws = nullptr;
-  if (hard) {
+  if (hard || (prec & 0xF) != DBP_PREC_FP32) {   // the FP64 pass: hard decisions or the mixed modes' factor rule
     // the flags (without a status array) and at least one FP64 slot must fit
     const size_t need = dbp::reslice_bytes_min(n_sc, U, C, status != nullptr);
     if (need > kScratchBytes) {

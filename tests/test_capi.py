@@ -55,7 +55,9 @@ def _admm(**kw):
     (dict(prec=9), 1), (dict(H=None), 1), (dict(y=None), 1), (dict(s=None), 1), (dict(n_sc=-1), 1),
     (dict(n_sym=0), 1), (dict(U=12, B=96, C=4), 2), (dict(B=64, C=8, U=16), 2), (dict(C=32, B=512), 2),
     (dict(rho=float("nan")), 1), (dict(prec=1, U=16, B=128, C=8), 2), (dict(prec=0x40), 1),
-    (dict(prec=0x20), 2), (dict(prec=0x13), 1), (dict(prec=0x21, U=64, B=512, C=8), 2),
+    (dict(prec=0x20), 2), (dict(prec=0x13), 1), (dict(prec=0x21, U=64, B=512, C=8), 1),
+    # the FP64 factor rule (mixed, U/S > 0.8; explicit FP64 at U = 64) needs a workspace
+    (dict(prec=1, U=32, B=256, C=8), 1), (dict(prec=2, U=64, B=512, C=8), 1),
 ])
 def test_detect_admm_rejects(kw, code):
     assert _admm(**kw) == code
@@ -137,6 +139,7 @@ def test_factor_entry_points_reject():
     assert L.dbp_factor_admm(1, None, 4, 256, 32, 8, 1.0, 0, None) == 1       # null factors
     assert L.dbp_factor_admm(1, 1, 4, 256, 32, 16, 1.0, 0, None) == 2         # S = 16 < U
     assert L.dbp_factor_admm(1, 1, 4, 256, 32, 8, 1.0, 0x20, None) == 2       # FP64 inverse needs a mixed Gram
+    assert L.dbp_factor_admm(1, 1, 4, 512, 64, 8, 1.0, 0x21, None) == 2       # no stored FP64 inverse at U = 64
     assert L.dbp_factor_admm(None, None, 0, 256, 32, 8, 1.0, 0, None) == 0    # empty is a no-op
     # dbp_detect_admm_factored(H, F, y, s, hard, status, ws, ws_bytes, n_sc, n_sym, B, U, C, T, rho, gamma, N0,
     #                          Es, reg, qam, stream)

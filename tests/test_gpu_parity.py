@@ -411,8 +411,9 @@ def test_precode_shapes(B, U, C):
 # -- mixed precision (split FP16 / BF16 Gram on the matrix cores), U = 32.
 # Bar: frame-level relative error <= 1e-3 and hard decisions as above; the FP16
 # split is expected to be close to the FP32 path, BF16 looser.  Inverses: FP32
-# and split-FP16 matrix cores, FP64 vector units ("auto" is FP64 at C = 8,
-# where U/S = 1 > 0.8, and FP32 at C = 4).
+# and split-FP16 matrix cores, FP64 vector units ("auto" is the FP32 inverse
+# with the FP64 factor rule at C = 8, where U/S = 1 > 0.8: at rho = 1 no
+# cluster is poorly conditioned enough for it; plain FP32 at C = 4).
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 @pytest.mark.parametrize("C,factor", [(8, "auto"), (8, "fp32"), (8, "f16x2"), (4, "auto"), (4, "fp64"), (4, "f16x2")])
 def test_mixed_headline_shape(prec, C, factor):
@@ -495,6 +496,82 @@ def test_cfg4_mixed(prec, corr, factor):
     say(f"    rel_err={err:.2e}")
     assert err <= mixed_bar(prec, factor)
     check_hard(s, h, ref, 64, st, mixed_guard(prec, factor, s.shape[-1]))
+
+
+# -- the FP64 factor rule of the mixed modes (U/S > 0.8): clusters whose bound
+# kappa_hat = tr(B_c) ||B_c^{-1}||_F exceeds 2^14 send their subcarrier to the
+# FP64 pass.  A small ADMM penalty rho makes B_c = G_c + rho I poorly
+# conditioned at S = U; those subcarriers must come out at FP64 accuracy
+# (FP64 result rounded to FP32), the others at the mixed bar.
+def _ill_conditioned_frame(B, U, C):
+    return inputs.uplink_frame(inputs.frame_seed(19, U, C), 24, B, U, 16, 20.0)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("B,U,C", [(256, 32, 8), (512, 64, 8)])
+@pytest.mark.parametrize("hard", [True, False])
+def test_fp64_factor_rule(prec, B, U, C, hard):
+    say(f"[gpu] FP64 factor rule prec={prec} B={B} U={U} C={C} hard={hard}")
+    fr = _ill_conditioned_frame(B, U, C)
+    rho = 0.01
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    s, h, st = api.detect(H, y, fr.N0, C, rho, 5, qam=16, prec=prec, hard=hard, status=True)
+    torch.cuda.synchronize()
+    s, st = s.cpu().numpy(), st.cpu().numpy()
+    ref = O.admm_ul_frame(fr.H, fr.y, C, rho, 5, n0_f32(fr.N0))
+    ill = (st & 4) != 0
+    say(f"    flagged {int(ill.sum())} of {ill.size}")
+    assert ill.any(), "rho = 0.01 at S = U makes some clusters poorly conditioned"
+    assert np.all((st[ill] & 2) != 0), "an ill-conditioned subcarrier is recomputed in FP64"
+    assert per_vec_rel(s[ill], ref[ill]) <= 1e-6
+    assert rel_err(s, ref) <= 1e-3
+    if hard:
+        # exact decisions everywhere: the guard of the unflagged subcarriers
+        # grows with their clusters' kappa_hat, so the FP32 errors that
+        # conditioning brings stay inside it
+        assert np.array_equal(h.cpu().numpy(), O.slice_qam(ref, 16))
+    else:
+        assert h is None
+
+
+@pytest.mark.parametrize("B,U,C", [(256, 32, 8), (512, 64, 8)])
+def test_fp64_factor_rule_idle_at_rho_one(B, U, C):
+    """At the configurations' rho = 1 the i.i.d. clusters stay far below the
+    bound (kappa_hat about 2e3 at U = 32, 8e3 at U = 64): nothing is flagged."""
+    say(f"[gpu] FP64 factor rule idle B={B} U={U}")
+    fr = inputs.uplink_frame(inputs.frame_seed(19, 1, U), 24, B, U, 64, 25.0)
+    s, h, st = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, C, 1.0, 5, qam=64, prec="fp16", status=True)
+    torch.cuda.synchronize()
+    assert not np.any(st.cpu().numpy() & 4)
+
+
+def test_fp64_factor_explicit_u64():
+    """DBP_FACTOR_FP64 at U = 64: every subcarrier recomputed in FP64."""
+    say("[gpu] explicit FP64 factor at U = 64")
+    fr = inputs.uplink_frame(inputs.frame_seed(19, 2, 64), 6, 512, 64, 64, 25.0)
+    s, h, st = api.detect(to_dev(fr.H), to_dev(fr.y), fr.N0, 8, 1.0, 5, qam=64, prec="fp16", factor="fp64",
+                          status=True)
+    torch.cuda.synchronize()
+    s, st = s.cpu().numpy(), st.cpu().numpy()
+    assert np.all((st & 6) == 6)
+    ref = O.admm_ul_frame(fr.H, fr.y, 8, 1.0, 5, n0_f32(fr.N0))
+    assert per_vec_rel(s, ref) <= 1e-6
+    check_hard(s, h.cpu().numpy(), ref, 64, st)
+
+
+def test_fp64_factor_rule_needs_workspace():
+    """Through the C ABI: the rule without hard decisions and without a
+    workspace is refused before any work is queued."""
+    say("[gpu] FP64 factor rule without workspace")
+    from paper_1702_04458_amd import _native
+    fr = _ill_conditioned_frame(256, 32, 8)
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    out = torch.empty((H.shape[0], 1, 32), dtype=torch.complex64, device=DEV)
+    L = _native.lib()
+    code = L.dbp_detect_admm(H.data_ptr(), y.data_ptr(), out.data_ptr(), None, None, None, 0, H.shape[0], 1, 256,
+                             32, 8, 5, 0.01, 1.0, float(fr.N0), 1.0, 0, 16, api.PREC["fp16"], None)
+    assert code == 1   # DBP_ERR_INVALID
+    torch.cuda.synchronize()
 
 
 def test_output_buffers_validated_before_launch():
