@@ -727,6 +727,40 @@ def static_channel_bench(api, frames, C, T, N0, qam, snr_db, out, steps):
                     "(low-precision path, frame error <= 1e-3)"}
 
 
+def reslice_cost(api, shapes=((256, 32, 8, 64, 0.0), (256, 32, 8, 64, 25.0), (512, 64, 8, 64, 0.0),
+                                (128, 16, 8, 16, 0.0)), n_sc=1200, reps=20):
+    """Cost of exact hard decisions: one 1200-subcarrier frame detected with
+    and without hard decisions (the FP64 re-slice of near-threshold
+    subcarriers), and how many subcarriers the FP64 pass recomputed."""
+    import torch
+    res = []
+    for B, U, C, qam, snr in shapes:
+        frames, N0 = make_frames(3, "admm", B, U, qam, snr, n_sc, seed=11)
+        ws = _ws(api, n_sc, U, C)
+        out = (torch.empty((n_sc, 1, U), dtype=torch.complex64, device="cuda"),
+               torch.empty((n_sc, 1, U), dtype=torch.uint8, device="cuda"),
+               torch.empty(n_sc, dtype=torch.int32, device="cuda"))
+        t = {}
+        for hard in (False, True):
+            o = out if hard else (out[0], None, out[2])
+            for i in range(3):
+                api.detect(frames[i][0], frames[i][1], N0, C, 1.0, 5, qam=qam, out=o, workspace=ws, status=True)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(reps):
+                api.detect(frames[i % 3][0], frames[i % 3][1], N0, C, 1.0, 5, qam=qam, out=o, workspace=ws,
+                           status=True)
+            e1.record()
+            torch.cuda.synchronize()
+            t[hard] = e0.elapsed_time(e1) / reps * 1e3
+        n_res = int(((out[2] & 2) != 0).sum().item())
+        res.append({"shape": f"B={B} U={U} C={C} {qam}-QAM {snr:g} dB", "n_sc": n_sc,
+                    "us_soft_only": round(t[False], 1), "us_exact_hard": round(t[True], 1),
+                    "resliced_subcarriers": n_res})
+    return res
+
+
 def copy_bandwidth_gbs(nbytes=1 << 30, reps=10):
     """Device-to-device copy rate measured on this GPU (read + write bytes per
     second), the STREAM-style reference for the kernels' HBM rates.  Kernels
@@ -979,8 +1013,10 @@ def main():
             serving["served_h16"]["vs_fp32_batched"] = round(sat / vectors_per_s, 3)
 
     nsym7 = None
+    reslice = None
     if algo == "admm" and not args.no_compare and args.form == "oneshot" and args.prec == "fp32":
         nsym7 = nsym_bench(api, B, U, C, qam, snr, T)
+        reslice = reslice_cost(api)
 
     budget = None
     if algo == "dl" and not args.no_compare:
@@ -1026,6 +1062,7 @@ def main():
             "static_channel": static,
             "small_frames_graph": graph,
             "n_sym7": nsym7,
+            "exact_hard_cost": reslice,
             "downlink_budgets": budget,
             "serving": serving,
         },
