@@ -147,9 +147,16 @@ __device__ __forceinline__ void write_out(const FixArgs& f, int k, int n, int u,
 // of the group at once; per pivot p the owners of row p and column p publish
 // them through LDS (colp, rowp: [clusters][U]) and every thread updates its
 // tile.  The inverses go to M ([C][U][U], entry (i, j) at i U + j).
+// Rows of H_c per staging step of the one-cluster form.
+constexpr int kStageH = 16;
+
+// hbuf (one-cluster form, NTH = 256, or null): kStageH x U complex values of
+// LDS through which the Gram's rows are staged: every thread loads its share
+// of the next block of rows while the current one is used, so the loads of a
+// whole block are in flight together instead of one row's at a time.
 template <int U, int TI, int NTH>
 __device__ __forceinline__ void fix64_factor_group(const FixArgs& f, const c32* Hk, int cb, d2* M, d2* colp,
-                                                   d2* rowp) {
+                                                   d2* rowp, c32* hbuf = nullptr) {
   constexpr int NT = U / TI, T2 = NT * NT, UU = U * U;
   const int tid = threadIdx.x;
   const int cl = tid / T2, tt = tid % T2, i0 = (tt / NT) * TI, j0 = (tt % NT) * TI;
@@ -161,20 +168,44 @@ __device__ __forceinline__ void fix64_factor_group(const FixArgs& f, const c32* 
 #pragma unroll
     for (int b = 0; b < TI; ++b) A[a][b] = dzero();
   // B_c = H_c^H H_c + rho I, tile rows i0.., columns j0..
-  if (own) {
-    const c32* Hc = Hk + (size_t)c * f.S * U;
-    for (int s = 0; s < f.S; ++s) {
-      const c32* row = Hc + (size_t)s * U;
-      d2 hj[TI];
+  auto gram_row = [&](const c32* row) {
+    d2 hj[TI];
 #pragma unroll
-      for (int b = 0; b < TI; ++b) hj[b] = dld(row + j0 + b);
+    for (int b = 0; b < TI; ++b) hj[b] = dld(row + j0 + b);
 #pragma unroll
-      for (int a = 0; a < TI; ++a) {
-        const d2 hi = dld(row + i0 + a);
+    for (int a = 0; a < TI; ++a) {
+      const d2 hi = dld(row + i0 + a);
 #pragma unroll
-        for (int b = 0; b < TI; ++b) dmacc(A[a][b], hi, hj[b]);
-      }
+      for (int b = 0; b < TI; ++b) dmacc(A[a][b], hi, hj[b]);
     }
+  };
+  const c32* Hc = Hk + (size_t)(c < f.C ? c : 0) * f.S * U;
+  if constexpr (NTH == 256 && (kStageH * U) % NTH == 0) {
+    // one cluster per workgroup, every thread takes part in the staging
+    constexpr int PER = kStageH * U / NTH;
+    const int nblk = (f.S + kStageH - 1) / kStageH;
+    c32 pre[PER];
+    auto fetch = [&](int blk) {
+#pragma unroll
+      for (int t = 0; t < PER; ++t) {
+        const int e = tid + t * NTH, s = blk * kStageH + e / U;
+        pre[t] = (own && s < f.S) ? Hc[(size_t)s * U + e % U] : c32{0.f, 0.f};   // rows past S add nothing
+      }
+    };
+    fetch(0);
+    for (int blk = 0; blk < nblk; ++blk) {
+      __syncthreads();   // the previous block's readers are done with hbuf
+#pragma unroll
+      for (int t = 0; t < PER; ++t) hbuf[tid + t * NTH] = pre[t];
+      __syncthreads();
+      if (blk + 1 < nblk) fetch(blk + 1);
+#pragma unroll 4
+      for (int r = 0; r < kStageH; ++r) gram_row(hbuf + r * U);
+    }
+  } else if (own) {
+    for (int s = 0; s < f.S; ++s) gram_row(Hc + (size_t)s * U);
+  }
+  if (own) {
 #pragma unroll
     for (int a = 0; a < TI; ++a)
 #pragma unroll
@@ -248,7 +279,7 @@ __device__ __forceinline__ void fix64_factor_group(const FixArgs& f, const c32* 
 // Algorithm 1's iterations in FP64 for subcarrier k with the inverses
 // B_c^{-1} in M, all symbols; writes the outputs.  LDS: Y, Z, LM ([C][U])
 // and Sv ([U]).  Ends with a barrier.
-template <int U, int NTH>
+template <int U, int NTH, bool UNROLL = false>
 __device__ __forceinline__ void fix64_iterate(const FixArgs& f, int k, const d2* M, d2* Y, d2* Z, d2* LM, d2* Sv) {
   constexpr int UU = U * U;
   const int C = f.C, S = f.S, CU = C * U, tid = threadIdx.x;
@@ -260,7 +291,13 @@ __device__ __forceinline__ void fix64_iterate(const FixArgs& f, int k, const d2*
       const int c = e / U, i = e - c * U;
       const c32* Hc = Hk + (size_t)c * S * U;
       d2 acc = dzero();
-      for (int s = 0; s < S; ++s) dmacc(acc, dld(Hc + (size_t)s * U + i), dld(yk + (size_t)c * S + s));
+      if constexpr (UNROLL) {
+        // eight rows per step: their loads in flight together
+#pragma unroll 8
+        for (int s = 0; s < S; ++s) dmacc(acc, dld(Hc + (size_t)s * U + i), dld(yk + (size_t)c * S + s));
+      } else {
+        for (int s = 0; s < S; ++s) dmacc(acc, dld(Hc + (size_t)s * U + i), dld(yk + (size_t)c * S + s));
+      }
       Z[e] = acc;
     }
     __syncthreads();
@@ -387,10 +424,11 @@ __global__ void __launch_bounds__(kFixThreads) admm_ul_fix64_batch(FixBatch b) {
 template <int U>
 __global__ void __launch_bounds__(256) admm_ul_factor64(FixArgs f) {
   __shared__ d2 piv[2 * U];
+  __shared__ c32 hbuf[kStageH * U];
   const int k = f.list0[blockIdx.x];
   if (k < 0 || (int)blockIdx.y >= f.C) return;   // uniform
   d2* Mslot = static_cast<d2*>(f.ws) + (size_t)blockIdx.x * f.C * U * U;
-  fix64_factor_group<U, tile_one<U>(), 256>(f, f.H + (size_t)k * f.B * U, blockIdx.y, Mslot, piv, piv + U);
+  fix64_factor_group<U, tile_one<U>(), 256>(f, f.H + (size_t)k * f.B * U, blockIdx.y, Mslot, piv, piv + U, hbuf);
 }
 
 // Split recomputation, step 2: the iterations of subcarrier f.list0[g] with
@@ -402,7 +440,7 @@ __global__ void __launch_bounds__(kFixThreads) admm_ul_iter64(FixArgs f) {
   if (k < 0) return;   // uniform
   const int CU = f.C * U;
   const d2* Mslot = static_cast<const d2*>(f.ws) + (size_t)blockIdx.x * f.C * U * U;
-  fix64_iterate<U, kFixThreads>(f, k, Mslot, fsm, fsm + CU, fsm + 2 * CU, fsm + 3 * CU);
+  fix64_iterate<U, kFixThreads, true>(f, k, Mslot, fsm, fsm + CU, fsm + 2 * CU, fsm + 3 * CU);
 }
 
 // Algorithm 2 in FP64 for the flagged subcarriers (f.rho = N0 / Es, or 0 for
