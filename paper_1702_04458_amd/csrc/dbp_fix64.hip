@@ -443,97 +443,134 @@ __global__ void __launch_bounds__(kFixThreads) admm_ul_iter64(FixArgs f) {
   fix64_iterate<U, kFixThreads, true>(f, k, Mslot, fsm, fsm + CU, fsm + 2 * CU, fsm + 3 * CU);
 }
 
+// Largest B U (complex entries of H[k]) the CG pass keeps in LDS (16 KiB:
+// the pass's LDS stays under 64 KiB).
+constexpr int kCgStage = 2048;
+
+// Sum over the first wave of v (lanes past the data pass 0); lane 0 stores
+// it at *out.  Every thread of the workgroup must call (it ends with a barrier).
+__device__ __forceinline__ void wave0_sum(double v, double* out) {
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (threadIdx.x == 0) *out = v;
+  }
+  __syncthreads();
+}
+
 // Algorithm 2 in FP64 for the flagged subcarriers (f.rho = N0 / Es, or 0 for
-// ZF).  w = sum_c H_c^H (H_c p) is formed cluster by cluster, H_c p in chunks
-// of up to 1024 rows.
+// ZF).  H[k] is staged in LDS when it fits.  w = sum_c H_c^H (H_c p): H p for
+// all B rows by one thread per row (blocks of 1024 rows for larger B), then
+// one partial sum per (cluster, user) and the sum over the clusters in
+// cluster order; the inner products by the first wave.
 __global__ void __launch_bounds__(kFixThreads) dcg_ul_fix64(FixArgs f) {
   extern __shared__ d2 fsm[];
   constexpr int kChunk = 1024;
-  const int U = f.U, C = f.C, S = f.S;
+  const int U = f.U, C = f.C, S = f.S, B = f.B, CU = C * U;
   d2* R = fsm;
   d2* P = R + U;
   d2* X = P + U;
   d2* W = X + U;
-  d2* Hp = W + U;                // kChunk entries
-  double* red = reinterpret_cast<double*>(Hp + kChunk);   // [0] rr, [1] pe / rr_new
+  d2* Hp = W + U;                // kChunk entries: H_c p for a block of rows
+  d2* Wp = Hp + kChunk;          // [C][U] per-cluster partial sums
+  c32* Hs = reinterpret_cast<c32*>(Wp + CU);   // H[k] when B U <= kCgStage
+  double* red = reinterpret_cast<double*>(Hs + kCgStage);   // [0] rr, [1] pe, [2] rr_new
   int* list = reinterpret_cast<int*>(red + 4);
   int* wsum = list + kListCap;
   const int tid = threadIdx.x;
+  const bool staged = B * U <= kCgStage;
+
+  // w = sum_c H_c^H v_c, with v the B entries at vb (stride vs) or, when
+  // vb is null, Hp: per-cluster partial sums by C U threads, then the sum
+  // over the clusters in cluster order.  Ends with a barrier.
+  auto hh_sum = [&](const c32* rows, const c32* yv, d2* out) {
+    for (int e = tid; e < CU; e += kFixThreads) {
+      const int c = e / U, i = e - c * U;
+      d2 acc = dzero();
+      for (int s = 0; s < S; ++s) {
+        const int j = c * S + s;
+        dmacc(acc, dld(rows + (size_t)j * U + i), yv ? dld(yv + j) : Hp[j]);
+      }
+      Wp[e] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < U; i += kFixThreads) {
+      d2 acc = dzero();
+      for (int c = 0; c < C; ++c) {
+        acc.re += Wp[c * U + i].re;
+        acc.im += Wp[c * U + i].im;
+      }
+      out[i] = acc;
+    }
+    __syncthreads();
+  };
 
   const long win = fix_window();
   for (long r = 0; r * win < f.n_sc; ++r) {
     const int nl = collect_round(f, r, win, list, wsum);
     for (int q = 0; q < nl; ++q) {
       const int k = list[q];
-      const c32* Hk = f.H + (size_t)k * f.B * U;
+      const c32* Hk = f.H + (size_t)k * B * U;
+      if (staged) {
+        for (int e = tid; e < B * U; e += kFixThreads) Hs[e] = Hk[e];
+        __syncthreads();
+      }
+      const c32* rows = staged ? Hs : Hk;
       for (int n = 0; n < f.n_sym; ++n) {
-        const c32* yk = f.y + ((size_t)k * f.n_sym + n) * f.B;
+        const c32* yk = f.y + ((size_t)k * f.n_sym + n) * B;
         // y^MRC = sum_c H_c^H y_c; r = p = y^MRC; x = 0
+        hh_sum(rows, yk, R);
         for (int i = tid; i < U; i += kFixThreads) {
-          d2 acc = dzero();
-          for (int c = 0; c < C; ++c) {
-            d2 part = dzero();
-            for (int s = 0; s < S; ++s)
-              dmacc(part, dld(Hk + ((size_t)c * S + s) * U + i), dld(yk + (size_t)c * S + s));
-            acc.re += part.re;
-            acc.im += part.im;
-          }
-          R[i] = acc;
-          P[i] = acc;
+          P[i] = R[i];
           X[i] = dzero();
         }
-        __syncthreads();
-        if (tid == 0) {
-          double rr = 0.0;
-          for (int i = 0; i < U; ++i) rr += R[i].re * R[i].re + R[i].im * R[i].im;
-          red[0] = rr;
-        }
-        __syncthreads();
+        wave0_sum(tid < U ? R[tid].re * R[tid].re + R[tid].im * R[tid].im : 0.0, red);
         for (int t = 1; t <= f.T; ++t) {
           const double rr = red[0];
           if (rr == 0.0) break;   // uniform: every thread read the same value
-          for (int i = tid; i < U; i += kFixThreads) W[i] = dzero();
-          __syncthreads();
-          for (int c = 0; c < C; ++c) {
-            for (int s0 = 0; s0 < S; s0 += kChunk) {
-              const int ns = (S - s0 < kChunk) ? S - s0 : kChunk;
-              for (int s = tid; s < ns; s += kFixThreads) {
-                const c32* row = Hk + ((size_t)c * S + s0 + s) * U;
-                d2 acc = dzero();
-                for (int u = 0; u < U; ++u) dmac(acc, dld(row + u), P[u]);
-                Hp[s] = acc;
+          // H p for all B rows (blocks of kChunk rows when B is larger), then w = sum_c H_c^H (H_c p)
+          if (B <= kChunk) {
+            for (int j = tid; j < B; j += kFixThreads) {
+              d2 acc = dzero();
+              for (int u = 0; u < U; ++u) dmac(acc, dld(rows + (size_t)j * U + u), P[u]);
+              Hp[j] = acc;
+            }
+            __syncthreads();
+            hh_sum(rows, nullptr, W);
+          } else {
+            for (int i = tid; i < U; i += kFixThreads) W[i] = dzero();
+            __syncthreads();
+            for (int c = 0; c < C; ++c) {
+              for (int s0 = 0; s0 < S; s0 += kChunk) {
+                const int ns = (S - s0 < kChunk) ? S - s0 : kChunk;
+                for (int s = tid; s < ns; s += kFixThreads) {
+                  const c32* row = rows + ((size_t)c * S + s0 + s) * U;
+                  d2 acc = dzero();
+                  for (int u = 0; u < U; ++u) dmac(acc, dld(row + u), P[u]);
+                  Hp[s] = acc;
+                }
+                __syncthreads();
+                for (int i = tid; i < U; i += kFixThreads) {
+                  d2 acc = dzero();
+                  for (int s = 0; s < ns; ++s) dmacc(acc, dld(rows + ((size_t)c * S + s0 + s) * U + i), Hp[s]);
+                  W[i].re += acc.re;
+                  W[i].im += acc.im;
+                }
+                __syncthreads();
               }
-              __syncthreads();
-              for (int i = tid; i < U; i += kFixThreads) {
-                d2 acc = dzero();
-                for (int s = 0; s < ns; ++s) dmacc(acc, dld(Hk + ((size_t)c * S + s0 + s) * U + i), Hp[s]);
-                W[i].re += acc.re;
-                W[i].im += acc.im;
-              }
-              __syncthreads();
             }
           }
           // e = rho p + w (kept in W); alpha = ||r||^2 / Re(p^H e)
           for (int i = tid; i < U; i += kFixThreads) W[i] = d2{f.rho * P[i].re + W[i].re, f.rho * P[i].im + W[i].im};
           __syncthreads();
-          if (tid == 0) {
-            double pe = 0.0;
-            for (int i = 0; i < U; ++i) pe += P[i].re * W[i].re + P[i].im * W[i].im;
-            red[1] = pe;
-          }
-          __syncthreads();
+          wave0_sum(tid < U ? P[tid].re * W[tid].re + P[tid].im * W[tid].im : 0.0, red + 1);
           const double alpha = rr / red[1];
           for (int i = tid; i < U; i += kFixThreads) {
             X[i] = d2{X[i].re + alpha * P[i].re, X[i].im + alpha * P[i].im};
             R[i] = d2{R[i].re - alpha * W[i].re, R[i].im - alpha * W[i].im};
           }
           __syncthreads();
-          if (tid == 0) {
-            double rn = 0.0;
-            for (int i = 0; i < U; ++i) rn += R[i].re * R[i].re + R[i].im * R[i].im;
-            red[2] = rn;
-          }
-          __syncthreads();
+          wave0_sum(tid < U ? R[tid].re * R[tid].re + R[tid].im * R[tid].im : 0.0, red + 2);
           const double rr_new = red[2];
           const double beta = rr_new / rr;
           for (int i = tid; i < U; i += kFixThreads) P[i] = d2{R[i].re + beta * P[i].re, R[i].im + beta * P[i].im};
@@ -601,7 +638,8 @@ hipError_t launch_admm_ul_fix64_batch(const FixBatch& b, int U, int n_slots, hip
 }
 
 hipError_t launch_dcg_ul_fix64(const FixArgs& f, hipStream_t st) {
-  const size_t lds = (size_t)(4 * f.U + 1024) * sizeof(d2) + 4 * sizeof(double) + (kListCap + kFixThreads / 64 + 4) * sizeof(int);
+  const size_t lds = (size_t)(4 * f.U + 1024 + f.C * f.U) * sizeof(d2) + kCgStage * sizeof(c32) + 4 * sizeof(double) +
+                    (kListCap + kFixThreads / 64 + 4) * sizeof(int);
   hipLaunchKernelGGL(dcg_ul_fix64, dim3((unsigned)f.n_slots), dim3(kFixThreads), lds, st, f);
   return hipGetLastError();
 }
