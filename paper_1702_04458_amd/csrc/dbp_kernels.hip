@@ -774,27 +774,28 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
       }
     }
   };
-  fetch(0, hv, yv);
-  for (int s0 = 0; s0 < a.S; s0 += 4 * CH) {
-    if (s0 + 4 * CH < a.S) fetch(s0 + 4 * CH, hn, yn);
+  auto accumulate = [&](const c32 (&hd)[4][CH], const c32 (&yd)[4][CH]) {
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const c32 x = hv[p][j];
+        const c32 x = hd[p][j];
         const float pr = x.re + x.im;
         re[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, pr, re[p], 0, 0, 0);       // P^T P, P = Hr + Hi
         im[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.re, x.im, im[p], 0, 0, 0);   // M = Hr^T Hi
-        cmacc(hyp[p], x, yv[p][j]);
+        cmacc(hyp[p], x, yd[p][j]);
       }
     }
-#pragma unroll
-    for (int j = 0; j < CH; ++j)
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        hv[p][j] = hn[p][j];
-        yv[p][j] = yn[p][j];
-      }
+  };
+  // two buffers used in turn (no copies): the next chunk's loads are in
+  // flight while the current one is accumulated
+  fetch(0, hv, yv);
+  for (int s0 = 0; s0 < a.S; s0 += 8 * CH) {
+    if (s0 + 4 * CH < a.S) fetch(s0 + 4 * CH, hn, yn);
+    accumulate(hv, yv);
+    if (s0 + 4 * CH >= a.S) break;
+    if (s0 + 8 * CH < a.S) fetch(s0 + 8 * CH, hv, yv);
+    accumulate(hn, yn);
   }
   // Transpose through LDS, two problems per pass: entry (i, j) of problem pp at
   // (16 pp + i) 16 + (j ^ i) (XOR swizzle: conflict-free for the column read
@@ -1357,8 +1358,11 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
 
   // Preprocessing (Alg. 1, S > U branch): B_c = H_c^H H_c + rho I, B_c^{-1}.
   c32 A[G];
+  // (the U = 16 Gram writes every entry of every lane's row: no clearing)
+  if constexpr (!(G == 16 && STAGE < 2)) {
 #pragma unroll
-  for (int v = 0; v < G; ++v) A[v] = cz();
+    for (int v = 0; v < G; ++v) A[v] = cz();
+  }
   c32 hy0 = cz();
   float trg = 0.f;   // tr(G_c) (mixed modes)
   // resident factors of this problem: entry v of lane u's row at v * G + u
@@ -1518,8 +1522,11 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   const int gbase = g * G;
 
   c32 A[G];
+  // (the U = 16 Gram writes every entry of every lane's row: no clearing)
+  if constexpr (G != 16) {
 #pragma unroll
-  for (int v = 0; v < G; ++v) A[v] = cz();
+    for (int v = 0; v < G; ++v) A[v] = cz();
+  }
   c32 hy0;
   if constexpr (G == 32)
     hy0 = gram_mfma_u32<false>(a, A, lane, wave, reinterpret_cast<float*>(line),
