@@ -103,7 +103,7 @@ extern "C" {
  *
  * dbp_detect_workspace_bytes(n_sc, U, C): bytes of workspace a call with hard
  *   decisions needs (0 for malformed sizes): a flag per subcarrier, up to
- *   256 blocks of C U^2 complex FP64 and 1280 bytes of bookkeeping.  The workspace must be 256-byte aligned;
+ *   256 blocks of C U^2 complex FP64 and 1536 bytes of bookkeeping.  The workspace must be 256-byte aligned;
  *   its contents need no initialisation and are garbage afterwards.  Calls
  *   that share one workspace must not overlap in time.
  */
@@ -163,7 +163,7 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard,
  * clearing between calls.  Returns DBP_ERR_UNSUPPORTED when hard decisions
  * are requested and the flags of n_sc subcarriers (4 n_sc bytes, none when
  * `status` is given) plus one FP64 block of C U^2 complex values (16 C U^2
- * bytes) and 1280 bytes of bookkeeping exceed the array.  Arguments, outputs and errors otherwise as
+ * bytes) and 1536 bytes of bookkeeping exceed the array.  Arguments, outputs and errors otherwise as
  * dbp_detect_admm; the results are bit-identical to it. */
 size_t dbp_noalloc_scratch_bytes(void);
 int dbp_detect_admm_noalloc(const void* H, const void* y, void* s_hat, uint8_t* hard,

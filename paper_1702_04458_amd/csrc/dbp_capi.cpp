@@ -259,8 +259,26 @@ float reslice_guard(int gram_prec, int inv, int U) {
 size_t flags_region(int n_sc) { return ((size_t)n_sc * 4 + 255) & ~size_t(255); }
 
 // The list of subcarriers the split FP64 pass recomputes with one workgroup
-// per cluster (one int per workgroup), at the end of the workspace.
-constexpr size_t kList0Room = dbp::kFixMaxSlots * sizeof(int) + 256;
+// per cluster (one int per workgroup), at the end of the workspace, and 256
+// bytes before it the word where the kernels mark that they flagged
+// anything.
+constexpr size_t kList0Room = dbp::kFixMaxSlots * sizeof(int) + 512;
+
+// A fresh value per call for that mark (never 0).
+std::atomic<uint32_t> g_epoch{0};
+uint32_t next_epoch() {
+  uint32_t e;
+  do e = ++g_epoch; while (e == 0);
+  return e;
+}
+
+// (list0, any) in the last kList0Room bytes of a workspace ending at end.
+void bookkeeping(char* ws, size_t ws_bytes, int** list0, uint32_t** any) {
+  const uintptr_t end = reinterpret_cast<uintptr_t>(ws) + ws_bytes;
+  const uintptr_t l0 = (end - dbp::kFixMaxSlots * sizeof(int)) & ~uintptr_t(255);
+  *list0 = reinterpret_cast<int*>(l0);
+  *any = reinterpret_cast<uint32_t*>(l0 - 256);
+}
 
 // Status and exact re-slicing of a detection call.  Without hard decisions
 // only the optional status is written (non-finite bit).  With them the FP32
@@ -292,9 +310,11 @@ int setup_reslice(const char* who, dbp::UlArgs& a, dbp::FixArgs& f, int32_t* sta
   a.guard = a.hard ? guard : 0.f;
   f.flags = a.flags;
   f.ws = static_cast<char*>(ws) + fb;
-  // 256-byte aligned, kFixMaxSlots ints, inside the last kList0Room bytes
-  const uintptr_t end = reinterpret_cast<uintptr_t>(ws) + ws_bytes;
-  f.list0 = reinterpret_cast<int*>((end - dbp::kFixMaxSlots * sizeof(int)) & ~uintptr_t(255));
+  // 256-byte aligned, inside the last kList0Room bytes
+  bookkeeping(static_cast<char*>(ws), ws_bytes, &f.list0, &a.any);
+  a.epoch = next_epoch();
+  f.any = a.any;
+  f.epoch = a.epoch;
   f.split = 0;
   f.n_slots = slots;
   f.H = a.H;
@@ -734,6 +754,11 @@ int dbp_detect_admm_batch(const dbp_frame* frames, int n_frames, int U, void* st
       a.flags = flags;
       a.guard = reslice_guard(DBP_PREC_FP32, 0, U);
       f = dbp::FixArgs{};
+      int* unused_list0 = nullptr;
+      bookkeeping(static_cast<char*>(fr.workspace), fr.workspace_bytes, &unused_list0, &a.any);
+      a.epoch = next_epoch();
+      f.any = a.any;
+      f.epoch = a.epoch;
       f.flags = flags;
       f.ws = slots;
       f.n_slots = n_slots;

@@ -56,6 +56,12 @@ __device__ __forceinline__ int slice64(double x, double kappa, int L) {
   return (int)i;
 }
 
+// True when the FP32 pass of this call flagged nothing (it stores the call's
+// epoch at f.any when it flags a subcarrier): the pass then neither scans
+// the flags nor recomputes anything.  A stale value from an earlier call
+// differs from this call's epoch, so the test errs only towards scanning.
+__device__ __forceinline__ bool nothing_flagged(const FixArgs& f) { return f.any && *f.any != f.epoch; }
+
 // Flags per thread in one scan of the flag array, and the LDS list capacity.
 constexpr int kPerThread = 16;
 constexpr int kListCap = kFixThreads;
@@ -373,6 +379,7 @@ constexpr int tile_one() { return (U >= 16) ? U / 16 : 1; }
 // N0 / (rho Es) + C itself (FP64 divides by it).
 template <int U>
 __device__ __forceinline__ void admm_ul_fix64_body(const FixArgs& f) {
+  if (nothing_flagged(f)) return;   // uniform
   constexpr int TI = tile_all<U>();
   constexpr int CG = kFixThreads / ((U / TI) * (U / TI));   // clusters per group
   extern __shared__ d2 fsm[];
@@ -425,6 +432,7 @@ template <int U>
 __global__ void __launch_bounds__(256) admm_ul_factor64(FixArgs f) {
   __shared__ d2 piv[2 * U];
   __shared__ c32 hbuf[kStageH * U];
+  if (nothing_flagged(f)) return;   // uniform
   const int k = f.list0[blockIdx.x];
   if (k < 0 || (int)blockIdx.y >= f.C) return;   // uniform
   d2* Mslot = static_cast<d2*>(f.ws) + (size_t)blockIdx.x * f.C * U * U;
@@ -436,6 +444,7 @@ __global__ void __launch_bounds__(256) admm_ul_factor64(FixArgs f) {
 template <int U>
 __global__ void __launch_bounds__(kFixThreads) admm_ul_iter64(FixArgs f) {
   extern __shared__ d2 fsm[];
+  if (nothing_flagged(f)) return;   // uniform
   const int k = f.list0[blockIdx.x];
   if (k < 0) return;   // uniform
   const int CU = f.C * U;
@@ -464,6 +473,7 @@ __device__ __forceinline__ void wave0_sum(double v, double* out) {
 // one partial sum per (cluster, user) and the sum over the clusters in
 // cluster order; the inner products by the first wave.
 __global__ void __launch_bounds__(kFixThreads) dcg_ul_fix64(FixArgs f) {
+  if (nothing_flagged(f)) return;   // uniform
   extern __shared__ d2 fsm[];
   constexpr int kChunk = 1024;
   const int U = f.U, C = f.C, S = f.S, B = f.B, CU = C * U;

@@ -321,27 +321,27 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
       }
     }
   };
-  fetch(0, hv, yv);
-  for (int s0 = 0; s0 < a.S; s0 += 2 * CH) {
-    if (s0 + 2 * CH < a.S) fetch(s0 + 2 * CH, hn, yn);
+  auto accumulate = [&](const c32 (&hd)[2][CH], const c32 (&yd)[2][CH]) {
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        const c32 x = hv[p][q];
+        const c32 x = hd[p][q];
         const float pr = x.re + x.im;
         re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(pr, pr, re[p], 0, 0, 0);       // P^T P, P = Hr + Hi
         im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, x.im, im[p], 0, 0, 0);   // M = Hr^T Hi
-        cmacc(hyp[p], x, yv[p][q]);
+        cmacc(hyp[p], x, yd[p][q]);
       }
     }
-#pragma unroll
-    for (int q = 0; q < CH; ++q)
-#pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        hv[p][q] = hn[p][q];
-        yv[p][q] = yn[p][q];
-      }
+  };
+  // the two buffers in turn (no copies)
+  fetch(0, hv, yv);
+  for (int s0 = 0; s0 < a.S; s0 += 4 * CH) {
+    if (s0 + 2 * CH < a.S) fetch(s0 + 2 * CH, hn, yn);
+    accumulate(hv, yv);
+    if (s0 + 2 * CH >= a.S) break;
+    if (s0 + 4 * CH < a.S) fetch(s0 + 4 * CH, hv, yv);
+    accumulate(hn, yn);
   }
   // re holds P^T P and im holds M = Hr^T Hi; since P^T P = Hr^T Hr + Hi^T Hi
   // + M + M^T, Re G = P^T P - M - M^T and Im G = M - M^T (two MFMAs per row
@@ -1494,7 +1494,10 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   }
   if (a.flags) {
     const int bits = group_flags<G>(fl, g);
-    if (c == 0 && u == 0 && k < a.n_sc) a.flags[k] = bits;
+    if (c == 0 && u == 0 && k < a.n_sc) {
+      a.flags[k] = bits;
+      if ((bits & kStatusReslice) && a.any) *a.any = a.epoch;
+    }
   }
 }
 
@@ -1580,7 +1583,10 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   }
   if (a.flags) {
     const int bits = group_flags<G>(fl, g);
-    if (c == 0 && u == 0 && k < a.n_sc) a.flags[k] = bits;
+    if (c == 0 && u == 0 && k < a.n_sc) {
+      a.flags[k] = bits;
+      if ((bits & kStatusReslice) && a.any) *a.any = a.epoch;
+    }
   }
 }
 

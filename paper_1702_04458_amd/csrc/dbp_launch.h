@@ -43,6 +43,11 @@ struct UlArgs {
   // Below it the re-slice guard is scaled by max(1, estimate / cond_ref).
   float cond_max;
   float cond_ref;
+  // *any is set to epoch by the kernels when they flag a subcarrier for the
+  // FP64 pass; the pass does nothing unless it reads this call's epoch there
+  // (epoch before the pointer: no padding, the batch block stays in 4 KiB).
+  uint32_t epoch;
+  uint32_t* any;
 };
 
 // Exact re-slicing: the subcarriers the FP32 kernel flagged (a soft value
@@ -58,6 +63,8 @@ struct FixArgs {
   int* list0;         // [n_slots] subcarriers recomputed with one workgroup per cluster (split)
   int split;          // 1: each workgroup's first subcarrier goes to the per-cluster kernels
   int n_sc, n_sym, B, U, C, S, T, reg, L, n_slots;
+  const uint32_t* any;   // equals epoch when the FP32 pass flagged any subcarrier of this call
+  uint32_t epoch;
   double rho;         // ADMM penalty (Alg. 1) or N0/Es (Alg. 2)
   double gamma, inv_den, invC, box_r, kappa;
 };

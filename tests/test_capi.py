@@ -74,9 +74,9 @@ def test_workspace_bytes():
     L = _native.lib()
     # a 256-byte aligned flag region of n_sc int32, min(n_sc, 256) blocks of C U^2 complex FP64, and
     # room for 256 aligned int32 (the subcarriers recomputed with one workgroup per cluster)
-    assert L.dbp_detect_workspace_bytes(1200, 32, 8) == 4864 + 256 * 8 * 32 * 32 * 16 + 1280
-    assert L.dbp_detect_workspace_bytes(16, 8, 4) == 256 + 16 * 4 * 8 * 8 * 16 + 1280
-    assert L.dbp_detect_workspace_bytes(0, 8, 4) == 256 * 0 + 1 * 4 * 8 * 8 * 16 + 1280
+    assert L.dbp_detect_workspace_bytes(1200, 32, 8) == 4864 + 256 * 8 * 32 * 32 * 16 + 1536
+    assert L.dbp_detect_workspace_bytes(16, 8, 4) == 256 + 16 * 4 * 8 * 8 * 16 + 1536
+    assert L.dbp_detect_workspace_bytes(0, 8, 4) == 256 * 0 + 1 * 4 * 8 * 8 * 16 + 1536
     assert L.dbp_detect_workspace_bytes(-1, 8, 4) == 0
 
 
