@@ -265,6 +265,41 @@ __device__ __forceinline__ c32 matvec16(const c32 (&A)[16], c32 q) {
   DBP_MV16_BLOCK(12, 13, 14, 15);
   return cadd(a0, a1);
 }
+// The same with conjugated matrix entries: acc = sum_v conj(A[v]) * q_v.
+#define DBP_MV16C_BLOCK(V0, V1, V2, V3)                                                    \
+  asm volatile(                                                                          \
+      "s_nop 1\n\t"                                                                      \
+      "v_fmac_f32_dpp %0, %4, %6 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %0, %5, %7 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %1, %5, %6 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %1, -%4, %7 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %2, %4, %8 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %2, %5, %9 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %3, %5, %8 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %3, -%4, %9 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %0, %4, %10 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %0, %5, %11 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %1, %5, %10 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %1, -%4, %11 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"  \
+      "v_fmac_f32_dpp %2, %4, %12 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %2, %5, %13 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %3, %5, %12 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %3, -%4, %13 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"  \
+      "s_nop 1"                                                                          \
+      : "+v"(a0.re), "+v"(a0.im), "+v"(a1.re), "+v"(a1.im)                               \
+      : "v"(q.re), "v"(q.im), "v"(A[V0].re), "v"(A[V0].im), "v"(A[V1].re), "v"(A[V1].im), \
+        "v"(A[V2].re), "v"(A[V2].im), "v"(A[V3].re), "v"(A[V3].im))
+
+__device__ __forceinline__ c32 matvec16c(const c32 (&A)[16], c32 q) {
+  c32 a0 = cz(), a1 = cz();
+  DBP_MV16C_BLOCK(0, 1, 2, 3);
+  DBP_MV16C_BLOCK(4, 5, 6, 7);
+  DBP_MV16C_BLOCK(8, 9, 10, 11);
+  DBP_MV16C_BLOCK(12, 13, 14, 15);
+  return cadd(a0, a1);
+}
+#undef DBP_MV16C_BLOCK
+
 // Rows of a 16 x 16 matrix split over the two 16-lane DPP rows of a 32-lane
 // group: lane r of DPP row h holds entries 8h .. 8h+7 of matrix row r (A[i] is
 // column 8h + i).  Every lane of the group holds data, where the lane-row

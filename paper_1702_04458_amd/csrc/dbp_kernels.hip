@@ -1746,17 +1746,23 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
     c32 z = cscale(s, a.f0), lam = cz();
     // H_c^H v: entry a held by lane a < S
     auto hhv = [&](c32 v) -> c32 {
-      bl[bw] = v;
-      wave_lds_sync();
       c32 acc = cz();
+      if constexpr (ASPLIT) {
+        // entry r0 + i of v sits in lane i of this lane's own 16-lane DPP row:
+        // broadcast inside the FMAs, no LDS
+        acc = matvec16c(hrow, v);
+      } else {
+        bl[bw] = v;
+        wave_lds_sync();
 #pragma unroll
-      for (int v0 = 0; v0 < RS; v0 += 4) {
-        c32 vv[4];
-        lds_read_vec<4>(bl + br + v0, vv);
+        for (int v0 = 0; v0 < RS; v0 += 4) {
+          c32 vv[4];
+          lds_read_vec<4>(bl + br + v0, vv);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) cmacc(acc, hrow[v0 + i], vv[i]);
+          for (int i = 0; i < 4; ++i) cmacc(acc, hrow[v0 + i], vv[i]);
+        }
+        wave_lds_sync();
       }
-      wave_lds_sync();
       if (SPLIT) acc = c32{pair_sum<SG>(acc.re), pair_sum<SG>(acc.im)};
       // the split-row product below takes entry a from both lanes of row a
       if constexpr (ASPLIT) return (ra < S) ? acc : cz();
@@ -1829,17 +1835,22 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
     c32 x = apply(z);
     for (int t = 2; t <= a.T; ++t) {
       // m_c = H_c x_c: m[u] = sum_a Hu[a][u] x[a]
-      bl[bw] = x;
-      wave_lds_sync();
       c32 m = cz();
+      if constexpr (ASPLIT) {
+        // x[a] sits in lane a of both 16-lane DPP rows of the group
+        m = matvec16(hcol, x);
+      } else {
+        bl[bw] = x;
+        wave_lds_sync();
 #pragma unroll
-      for (int v0 = 0; v0 < SG; v0 += 4) {
-        c32 xv[4];
-        lds_read_vec<4>(bl + v0, xv);
+        for (int v0 = 0; v0 < SG; v0 += 4) {
+          c32 xv[4];
+          lds_read_vec<4>(bl + v0, xv);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) cmac(m, hcol[v0 + i], xv[i]);
+          for (int i = 0; i < 4; ++i) cmac(m, hcol[v0 + i], xv[i]);
+        }
+        wave_lds_sync();
       }
-      wave_lds_sync();
       const c32 wc = csub(m, lam);
       const c32 w = consensus(active ? wc : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
       buf ^= 1;
