@@ -1852,7 +1852,25 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
         wave_lds_sync();
       }
       const c32 wc = csub(m, lam);
-      const c32 w = consensus(active ? wc : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+      c32 w;
+      if (G == 32 && a.Cp >= 2) {
+        // the wave's two problems are clusters 2j and 2j+1 of one subcarrier:
+        // their sum first (lanes l and l ^ 32), then half the LDS slots
+        const c32 wa = active ? wc : cz();
+        const c32 w2 = c32{pair_sum<32>(wa.re), pair_sum<32>(wa.im)};
+        c32* cb = sm.cons + buf * nw * 64;
+        if (g == 0) cb[slot] = w2;
+        __syncthreads();
+        const c32* src = cb + (size_t)ls * a.Cp * G + u;
+        switch (a.Cp) {
+          case 2: w = src[0]; break;
+          case 4: w = sum_slots<2>(src, 2 * G); break;
+          case 8: w = sum_slots<4>(src, 2 * G); break;
+          default: w = sum_slots<8>(src, 2 * G); break;
+        }
+      } else {
+        w = consensus(active ? wc : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+      }
       buf ^= 1;
       // Lemma 2: z_c = w_c + f (s - w) / C, f = max{0, 1 - eps / ||s - w||}
       // (f = 1 at eps = 0); every group holds the same s and w, one user per lane
