@@ -1300,6 +1300,39 @@ __device__ __forceinline__ c32 consensus(c32 wc, int buf, int ls, int G, int u, 
   }
 }
 
+// The consensus of the lane-group layout with P = 64 / G problems per wave.
+// When the padded cluster count Cp is at least P, the wave's P problems are
+// clusters P j .. P j + P - 1 of one subcarrier: their vectors are summed in
+// registers first (pairs of lanes l, l ^ G, then l, l ^ 2G, ...: the same
+// tree on every lane, so every lane holds the same bits), and only the
+// first group of each wave writes its slot; the readers then add Cp / P
+// slots in cluster order.  Otherwise, as consensus().
+template <int G>
+__device__ __forceinline__ c32 consensus_w(c32 wc, int buf, int ls, int u, int g, int C, int Cp, const Smem& sm,
+                                           int slot, int nw) {
+  constexpr int P = 64 / G;
+  if constexpr (P == 1) {
+    (void)g;
+    return consensus<true>(wc, buf, ls, G, u, C, Cp, sm, slot, nw);
+  } else {
+    if (Cp < P) return consensus<true>(wc, buf, ls, G, u, C, Cp, sm, slot, nw);
+    c32 w = wc;
+    if constexpr (P >= 8) w = c32{pair_sum<8>(w.re), pair_sum<8>(w.im)};
+    if constexpr (P >= 4) w = c32{pair_sum<16>(w.re), pair_sum<16>(w.im)};
+    w = c32{pair_sum<32>(w.re), pair_sum<32>(w.im)};
+    c32* cb = sm.cons + buf * nw * 64;
+    if (g == 0) cb[slot] = w;
+    __syncthreads();
+    const c32* src = cb + (size_t)ls * Cp * G + u;
+    switch (Cp / P) {
+      case 1: return src[0];
+      case 2: return sum_slots<2>(src, P * G);
+      case 4: return sum_slots<4>(src, P * G);
+      default: return sum_slots<8>(src, P * G);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Algorithm 1, U x U branch (S >= U), FP32.  Group size G = U.
 // ---------------------------------------------------------------------------
@@ -1443,7 +1476,8 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     // y_c^reg = B_c^{-1} H_c^H y_c; z = y^reg; lambda = 0
     const c32 yreg = group_matvec<G>(A, hy, u, line, gbase);
     c32 z = yreg, lam = cz();
-    c32 w = consensus<HALF == 0>(active ? z : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+    c32 w = (HALF == 0) ? consensus_w<G>(active ? z : cz(), buf, ls, u, g, a.C, a.Cp, sm, slot, nw)
+                        : consensus<false>(active ? z : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
     buf ^= 1;
     if constexpr (COND) {
       // the barrier inside the consensus above has made every cluster's estimate visible
@@ -1472,7 +1506,8 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       const c32 q = csub(s, lam);
       const c32 bq = group_matvec<G>(A, q, u, line, gbase);
       z = c32{fmaf(a.rho, bq.re, yreg.re), fmaf(a.rho, bq.im, yreg.im)};
-      w = consensus<HALF == 0>(active ? cadd(z, lam) : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+      w = (HALF == 0) ? consensus_w<G>(active ? cadd(z, lam) : cz(), buf, ls, u, g, a.C, a.Cp, sm, slot, nw)
+                      : consensus<false>(active ? cadd(z, lam) : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
       buf ^= 1;
       if (a.reg == 2) {
         c32 v = cscale(w, a.invC);
@@ -1548,13 +1583,13 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
     c32 hy = hy0;
     if (n > 0) hy = cluster_pass<G, false>(a.H, a.y, A, k, c, n, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
     // y^MRC = sum_c H_c^H y_c (consensus); r = p = y^MRC; x = 0
-    c32 r = consensus(active ? hy : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+    c32 r = consensus_w<G>(active ? hy : cz(), buf, ls, u, g, a.C, a.Cp, sm, slot, nw);
     buf ^= 1;
     c32 pv = r, x = cz();
     float rr = group_sum<G>(r.re * r.re + r.im * r.im);
     for (int t = 1; t <= a.T; ++t) {
       const c32 wc = group_matvec<G>(A, pv, u, line, gbase);
-      const c32 w = consensus(active ? wc : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
+      const c32 w = consensus_w<G>(active ? wc : cz(), buf, ls, u, g, a.C, a.Cp, sm, slot, nw);
       buf ^= 1;
       const c32 e = c32{fmaf(a.rho, pv.re, w.re), fmaf(a.rho, pv.im, w.im)};
       const float pe = group_sum<G>(pv.re * e.re + pv.im * e.im);
@@ -1852,25 +1887,7 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
         wave_lds_sync();
       }
       const c32 wc = csub(m, lam);
-      c32 w;
-      if (G == 32 && a.Cp >= 2) {
-        // the wave's two problems are clusters 2j and 2j+1 of one subcarrier:
-        // their sum first (lanes l and l ^ 32), then half the LDS slots
-        const c32 wa = active ? wc : cz();
-        const c32 w2 = c32{pair_sum<32>(wa.re), pair_sum<32>(wa.im)};
-        c32* cb = sm.cons + buf * nw * 64;
-        if (g == 0) cb[slot] = w2;
-        __syncthreads();
-        const c32* src = cb + (size_t)ls * a.Cp * G + u;
-        switch (a.Cp) {
-          case 2: w = src[0]; break;
-          case 4: w = sum_slots<2>(src, 2 * G); break;
-          case 8: w = sum_slots<4>(src, 2 * G); break;
-          default: w = sum_slots<8>(src, 2 * G); break;
-        }
-      } else {
-        w = consensus(active ? wc : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
-      }
+      const c32 w = consensus_w<G>(active ? wc : cz(), buf, ls, u, g, a.C, a.Cp, sm, slot, nw);
       buf ^= 1;
       // Lemma 2: z_c = w_c + f (s - w) / C, f = max{0, 1 - eps / ||s - w||}
       // (f = 1 at eps = 0); every group holds the same s and w, one user per lane
