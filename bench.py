@@ -49,14 +49,15 @@ WORKLOADS = {
 
 def algorithmic_bytes(algo, B, U, C, form="oneshot"):
     """HBM bytes one subcarrier-vector must move (complex64 in/out, uint8 hard).
-    The resident forms also read the factors B_c^{-1} (complex64); the FP16
-    channel holds H in 4 bytes per entry plus one float scale per cluster."""
+    The resident forms also read the factors B_c^{-1} (complex64, the upper
+    triangle of each Hermitian block); the FP16 channel holds H in 4 bytes per
+    entry plus one float scale per cluster."""
     if algo == "dl":
         return 8 * B * U + 8 * U + 8 * B
     if form == "resident":
-        return 8 * B * U + 8 * C * U * U + 8 * B + 8 * U + U
+        return 8 * B * U + 8 * C * (U * (U + 1) // 2) + 8 * B + 8 * U + U
     if form == "resident_h16":
-        return 4 * B * U + 4 * C + 8 * C * U * U + 8 * B + 8 * U + U
+        return 4 * B * U + 4 * C + 8 * C * (U * (U + 1) // 2) + 8 * B + 8 * U + U
     return 8 * B * U + 8 * B + 8 * U + U
 
 

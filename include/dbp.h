@@ -177,7 +177,8 @@ int dbp_detect_admm_noalloc(const void* H, const void* y, void* s_hat, uint8_t* 
  * channel.  dbp_factor_admm runs that preprocessing for every (subcarrier,
  * cluster) and writes B_c^{-1} to `factors` (device, caller-owned,
  * dbp_factor_bytes(n_sc, U, C) bytes, an internal layout of n_sc * C blocks
- * of U x U complex64).  dbp_detect_admm_factored then runs Algorithm 1's
+ * of U (U + 1) / 2 complex64: each block's upper triangle, B_c^{-1} being
+ * Hermitian).  dbp_detect_admm_factored then runs Algorithm 1's
  * iterations for any received frame y against that channel: it reads H (for
  * H_c^H y_c) and the factors, and forms no Gram and no inverse.
  *   prec (factor only)  as for dbp_detect_admm: the Gram and inverse

@@ -150,15 +150,18 @@ def detect(H, y, N0, C, rho=1.0, T=5, *, algo="admm", reg="mmse", qam=16, Es=1.0
 def factor(H, C, rho=1.0, *, prec="fp32", factor=None, out=None, stream=None):
     """Algorithm 1's preprocessing for a static channel: B_c^{-1} for every
     (subcarrier, cluster), kept resident for :func:`detect_factored`.  Returns a
-    complex64 device tensor [n_sc, C, U, U] in the library's internal layout."""
+    complex64 device tensor [n_sc, C, U (U + 1) / 2] in the library's internal
+    layout: the upper triangle of each Hermitian block, column by column
+    (entry (i, v), i <= v, at v (v + 1) / 2 + i)."""
     _dev(H, "H")
     n_sc, B, U = H.shape
-    f = out if out is not None else torch.empty((n_sc, C, U, U), dtype=torch.complex64, device=H.device)
+    f = out if out is not None else torch.empty((n_sc, C, U * (U + 1) // 2), dtype=torch.complex64,
+                                                 device=H.device)
     _dev(f, "factors")
     if f.device != H.device:
         raise ValueError(f"factors must be on {H.device}")
     if f.numel() * 8 != _native.lib().dbp_factor_bytes(n_sc, U, C):
-        raise ValueError("factors must hold n_sc * C * U * U complex64")
+        raise ValueError("factors must hold n_sc * C * U (U + 1) / 2 complex64")
     _native.check(_native.lib().dbp_factor_admm(H.data_ptr(), f.data_ptr(), n_sc, B, U, C, float(rho),
                                                 PREC[prec] | FACTOR[factor], _stream(stream)))
     return f

@@ -422,7 +422,7 @@ int dbp_detect_admm(const void* H, const void* y, void* s_hat, uint8_t* hard, in
 
 size_t dbp_factor_bytes(int n_sc, int U, int C) {
   if (n_sc < 0 || U < 1 || C < 1) return 0;
-  return (size_t)n_sc * C * U * U * 8;
+  return (size_t)n_sc * C * (U * (U + 1) / 2) * 8;   // the Hermitian blocks' upper triangles
 }
 
 int dbp_factor_admm(const void* H, void* factors, int n_sc, int B, int U, int C, float rho, int prec, void* stream) {

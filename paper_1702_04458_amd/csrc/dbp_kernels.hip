@@ -1398,12 +1398,22 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   }
   c32 hy0 = cz();
   float trg = 0.f;   // tr(G_c) (mixed modes)
-  // resident factors of this problem: entry v of lane u's row at v * G + u
-  const size_t fo = ((size_t)k * a.C + c) * G * G + u;
+  // Resident factors of this problem: B_c^{-1} is Hermitian, so only its
+  // upper triangle is stored, column by column (entry (i, v), i <= v, at
+  // v (v + 1) / 2 + i; G (G + 1) / 2 values per problem).  Lane u's row
+  // takes entry v from column v (v >= u) or, conjugated, from column u
+  // (v < u): one load per entry, coalesced over the lanes of the first kind.
+  constexpr int NT = G * (G + 1) / 2;
+  const size_t fo = ((size_t)k * a.C + c) * NT;
   if constexpr (STAGE >= 2) {
     if (active) {
+      const int csu = u * (u + 1) / 2;
 #pragma unroll
-      for (int v = 0; v < G; ++v) A[v] = a.fac[fo + (size_t)v * G];
+      for (int v = 0; v < G; ++v) {
+        const bool up = v >= u;
+        const c32 e = a.fac[fo + (up ? (size_t)(v * (v + 1) / 2 + u) : (size_t)(csu + v))];
+        A[v] = up ? e : c32{e.re, -e.im};
+      }
     }
   } else if constexpr (G == 32 && HALF == 0) {
     hy0 = gram_mfma_u32<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
@@ -1437,7 +1447,8 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   if constexpr (STAGE == 1) {
     if (active) {
 #pragma unroll
-      for (int v = 0; v < G; ++v) a.fac[fo + (size_t)v * G] = A[v];
+      for (int v = 0; v < G; ++v)
+        if (v >= u) a.fac[fo + (size_t)(v * (v + 1) / 2 + u)] = A[v];
     }
     return;
   }

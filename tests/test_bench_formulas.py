@@ -23,7 +23,7 @@ def test_one_shot_formulas(algo, B, U, C, T, bytes_vec, mflop):
 def test_resident_forms():
     B, U, C, T = 256, 32, 8, 5
     # the factors add 8 C U^2 bytes; the FP16 channel halves H and adds one float scale per cluster
-    assert bench.algorithmic_bytes("admm", B, U, C, "resident") == 67872 + 8 * C * U * U
-    assert bench.algorithmic_bytes("admm", B, U, C, "resident_h16") == 67872 + 8 * C * U * U - 4 * B * U + 4 * C
+    assert bench.algorithmic_bytes("admm", B, U, C, "resident") == 67872 + 8 * C * U * (U + 1) // 2
+    assert bench.algorithmic_bytes("admm", B, U, C, "resident_h16") == 67872 + 8 * C * U * (U + 1) // 2 - 4 * B * U + 4 * C
     # no Gram and no factorisation: H^H y, then T estimates with one U^2 product each
     assert bench.algorithmic_flops("admm", B, U, C, T, "resident") == 8.0 * (B * U + T * C * U * U)

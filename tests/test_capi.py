@@ -133,7 +133,7 @@ def test_precode_rejects():
 
 def test_factor_entry_points_reject():
     L = _native.lib()
-    assert L.dbp_factor_bytes(1200, 32, 8) == 1200 * 8 * 32 * 32 * 8
+    assert L.dbp_factor_bytes(1200, 32, 8) == 1200 * 8 * (32 * 33 // 2) * 8
     # dbp_factor_admm(H, factors, n_sc, B, U, C, rho, prec, stream)
     assert L.dbp_factor_admm(1, 1, 4, 256, 32, 8, 0.0, 0, None) == 1          # rho <= 0
     assert L.dbp_factor_admm(1, None, 4, 256, 32, 8, 1.0, 0, None) == 1       # null factors

@@ -85,17 +85,23 @@ def test_mixed_precision_factors(prec, factor):
 
 def test_factors_match_oracle_inverse():
     """The stored blocks are B_c^{-1} = (H_c^H H_c + rho I)^{-1}: the library's
-    internal layout holds row u of block (k, c) with entry v at v * U + u."""
+    internal layout holds the upper triangle of block (k, c) column by column,
+    entry (i, v) with i <= v at v (v + 1) / 2 + i."""
     say("[gpu] factors vs oracle inverse")
     B, U, C, n_sc = 128, 16, 8, 6
     fr = inputs.uplink_frame(inputs.frame_seed(23, 0, 10), n_sc, B, U, 16, 10.0)
-    fac = api.factor(to_dev(fr.H), C, 0.7).cpu().numpy()          # [n_sc, C, U, U] as stored
+    fac = api.factor(to_dev(fr.H), C, 0.7).cpu().numpy()          # [n_sc, C, U (U + 1) / 2] as stored
+    assert fac.shape == (n_sc, C, U * (U + 1) // 2)
     S = B // C
     for k in range(n_sc):
         for c in range(C):
             Hc = fr.H[k, c * S:(c + 1) * S].astype(np.complex128)
             Binv = np.linalg.inv(Hc.conj().T @ Hc + 0.7 * np.eye(U))
-            stored = fac[k, c].T                                     # [u][v] = row u, column v
+            stored = np.zeros((U, U), dtype=np.complex128)
+            for v in range(U):
+                for i in range(v + 1):
+                    stored[i, v] = fac[k, c, v * (v + 1) // 2 + i]
+                    stored[v, i] = np.conj(fac[k, c, v * (v + 1) // 2 + i])
             assert np.linalg.norm(stored - Binv) <= 1e-5 * np.linalg.norm(Binv)
 
 

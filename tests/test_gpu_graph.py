@@ -38,7 +38,7 @@ def test_graph_replay_matches_eager():
     H = to_dev(frames[0].H)
     y = to_dev(frames[0].y)
     Hd, sd = to_dev(dl.H), to_dev(dl.s)
-    fac = torch.empty((n_sc, C, U, U), dtype=torch.complex64, device="cuda")
+    fac = torch.empty((n_sc, C, U * (U + 1) // 2), dtype=torch.complex64, device="cuda")
     s_a = torch.empty((n_sc, 1, U), dtype=torch.complex64, device="cuda")
     h_a = torch.empty((n_sc, 1, U), dtype=torch.uint8, device="cuda")
     s_c = torch.empty_like(s_a)
