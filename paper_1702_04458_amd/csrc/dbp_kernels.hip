@@ -18,6 +18,10 @@
 namespace dbp {
 
 constexpr int kStageRows = 8;   // rows of H_c staged per pass through LDS
+// c32 slots of one wave's stage buffer: the staged rows, plus room for a
+// 32 x 32 float tile stored with a row pitch of 33 (transposes without bank
+// conflicts and with compile-time offsets)
+constexpr int kStageWave = kStageRows * 64 + 16;
 
 // Loads in the Gram prologues never branch: a request outside the problem
 // (padding cluster, subcarrier past the end, ragged row past S) reads a valid
@@ -39,7 +43,7 @@ __device__ __forceinline__ c32 ld_or_zero(const c32* p, bool ok) {
 #endif
 
 // LDS carve-up shared by the kernels (all offsets in c32 units):
-//   stage[nw][kStageRows][64]   staged H rows (one slot per lane)
+//   stage[nw][kStageWave]       staged H rows (kStageRows x 64, one slot per lane)
 //   ystage[nw][kStageRows][8]   staged y entries (one per problem of the wave)
 //   line[nw][64]                per-wave broadcast line
 //   cons[2][nw][64]             double-buffered consensus slots (one per lane)
@@ -55,14 +59,14 @@ struct Smem {
 __device__ __forceinline__ Smem carve(c32* base, int nw) {
   Smem s;
   s.stage = base;
-  s.ystage = s.stage + nw * kStageRows * 64;
+  s.ystage = s.stage + nw * kStageWave;
   s.line = s.ystage + nw * kStageRows * 8;
   s.cons = s.line + nw * 64;
   s.aux = s.cons + 2 * nw * 64;
   return s;
 }
 
-size_t smem_bytes(int nw) { return sizeof(c32) * (size_t)nw * (kStageRows * 64 + kStageRows * 8 + 64 + 128 + 64); }
+size_t smem_bytes(int nw) { return sizeof(c32) * (size_t)nw * (kStageWave + kStageRows * 8 + 64 + 128 + 64); }
 
 // One pass over the S rows of H_c (and of y_c for symbol n): accumulates the
 // Gram row A[v] += conj(H[s][u]) H[s][v] when WITH_GRAM, and always
@@ -73,7 +77,7 @@ __device__ __forceinline__ c32 cluster_pass(const c32* __restrict__ H, const c32
                                             int B, int S, int U, int n_sym, const Smem& sm) {
   constexpr int R = kStageRows;
   c32 hy = cz();
-  c32* stage = sm.stage + wave * R * 64;
+  c32* stage = sm.stage + wave * kStageWave;
   c32* yst = sm.ystage + wave * R * 8;
   const c32* Hk = H + (size_t)k * B * U + (size_t)c * S * U;
   const c32* yk = y + ((size_t)k * n_sym + n) * B + (size_t)c * S;
@@ -199,40 +203,48 @@ __device__ __forceinline__ void gj_unscale_u32(f32x16& re, f32x16& im, float pvv
   }
 }
 
+// ADD_RHO: add rho to the diagonal first (false: the caller's accumulators
+// already hold G + rho I).
+template <bool ADD_RHO = true>
 __device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)[2], int lane, float rho, float* line) {
   const int h = lane >> 5, col = lane & 31;
+  if constexpr (ADD_RHO) {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const bool dg = (8 * (r / 4) + 4 * h + (r % 4) == col);
-    re[0][r] += dg ? rho : 0.f;
-    re[1][r] += dg ? rho : 0.f;
+    for (int r = 0; r < 16; ++r) {
+      const bool dg = (8 * (r / 4) + 4 * h + (r % 4) == col);
+      re[0][r] += dg ? rho : 0.f;
+      re[1][r] += dg ? rho : 0.f;
+    }
+  } else {
+    (void)rho;
   }
-  const float hs = h ? 1.f : -1.f;
   float pvv[2] = {0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     const int rr = 4 * (k / 8) + (k % 4);   // register holding row k
     const int hk = (k / 4) & 1;             // lane half holding row k
     const bool isk = (col == k);
-    const float mk = isk ? 0.f : 1.f;       // row and column k are left alone
-    const float dn = (isk && h == hk) ? -1.f : 1.f;
+    const bool dg = isk && h == hk;
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const float sr = re[p][rr], si = im[p][rr];
-      // row k at column col: lanes < 32 get (first, second) = (Re, Im), lanes >= 32 (Im, Re)
-      const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(sr), __float_as_uint(si), false, false);
-      const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(si), __float_as_uint(sr), false, false);
+      // Row k at column col with entry k zeroed (row and column k are left
+      // alone by the update): lanes < 32 get (first, second) = (Re, Im),
+      // lanes >= 32 (Im, Re).  A lane reads the lane of its own column in
+      // either half, so zeroing at the source zeroes column k everywhere.
+      const float srm = isk ? 0.f : sr, sim = isk ? 0.f : si;
+      const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(srm), __float_as_uint(sim), false, false);
+      const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(sim), __float_as_uint(srm), false, false);
       const float first = __uint_as_float(fs[hk]);
       const float second = __uint_as_float(sf[hk]);
       const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sr), k + 32 * hk));
       const float pv = __builtin_amdgcn_rcpf(d);
-      const float t = pv * mk;
-      // Re: -t (Re_i Re_j + Im_i Im_j), Im: -t (Re_i Im_j - Im_i Re_j)
-      const float Are = -t * first;
-      const float Aim = (hs * t) * first;
-      re[p][rr] = sr * dn;
-      re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are, mk * first, re[p], 0, 0, 0);
-      im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim, mk * second, im[p], 0, 0, 0);
+      // Re: -pv (Re_i Re_j + Im_i Im_j), Im: -pv (Re_i Im_j - Im_i Re_j)
+      const float Are = -pv * first;
+      const float Aim = h ? -Are : Are;
+      re[p][rr] = dg ? -sr : sr;
+      re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are, first, re[p], 0, 0, 0);
+      im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim, second, im[p], 0, 0, 0);
       pvv[p] = isk ? pv : pvv[p];
     }
   }
@@ -292,6 +304,9 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
   const c32* Hp[2];
   const c32* yp[2];
   bool act[2];
+  // With INVERT the real part starts from rho I: the diagonal entry (col, col)
+  // sits in register 4 (col / 8) + col % 4 of lane half (col / 4) % 2.
+  const int dr = (INVERT && h == ((col >> 2) & 1)) ? 4 * (col >> 3) + (col & 3) : -1;
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     const int lp = wave * 2 + p;
@@ -300,7 +315,8 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
     act[p] = (k < a.n_sc) && (c < a.C);
     Hp[p] = act[p] ? a.H + (size_t)k * a.B * 32 + (size_t)c * a.S * 32 : a.H;
     yp[p] = act[p] ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
-    re[p] = f32x16{};
+#pragma unroll
+    for (int r = 0; r < 16; ++r) re[p][r] = (r == dr) ? a.rho : 0.f;
     im[p] = f32x16{};
     hyp[p] = cz();
   }
@@ -343,29 +359,30 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
     if (s0 + 4 * CH < a.S) fetch(s0 + 4 * CH, hv, yv);
     accumulate(hn, yn);
   }
-  // re holds P^T P and im holds M = Hr^T Hi; since P^T P = Hr^T Hr + Hi^T Hi
-  // + M + M^T, Re G = P^T P - M - M^T and Im G = M - M^T (two MFMAs per row
-  // pair instead of three).  M goes through the wave's 4 KB stage buffer with
-  // an XOR-swizzled column (entry (i, j) at 32 i + (j ^ i)), conflict-free
-  // both for the row-wise write and the transposed read.
+  // re holds rho I + P^T P and im holds M = Hr^T Hi; since P^T P = Hr^T Hr
+  // + Hi^T Hi + M + M^T, Re G = P^T P - M - M^T and Im G = M - M^T (two MFMAs
+  // per row pair instead of three).  M goes through the wave's stage buffer
+  // with a row pitch of 33 floats (entry (i, j) at 33 i + j), conflict-free
+  // both for the row-wise write and the transposed read, and with a per-lane
+  // base plus a compile-time offset for every register.
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r / 4) + 4 * h + (r % 4);
-      stage[32 * i + (col ^ i)] = im[p][r];
+      stage[33 * i + col] = im[p][r];
     }
     wave_lds_sync();
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r / 4) + 4 * h + (r % 4);
-      const float mt = stage[32 * col + (i ^ col)];
+      const float mt = stage[33 * col + i];
       re[p][r] -= im[p][r] + mt;
       im[p][r] -= mt;
     }
     wave_lds_sync();
   }
-  if (INVERT) gj_invert_mfma_u32(re, im, lane, a.rho, line);
+  if (INVERT) gj_invert_mfma_u32<false>(re, im, lane, a.rho, line);
   // exchange halves: lanes < 32 keep problem 0, lanes >= 32 keep problem 1
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -523,13 +540,13 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r / 4) + 4 * h + (r % 4);
-      stage[32 * i + (col ^ i)] = im[p][r];
+      stage[33 * i + col] = im[p][r];
     }
     wave_lds_sync();
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r / 4) + 4 * h + (r % 4);
-      im[p][r] -= stage[32 * col + (i ^ col)];
+      im[p][r] -= stage[33 * col + i];
     }
     wave_lds_sync();
   }
@@ -952,7 +969,6 @@ __device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&
     re[0][0][r] += dg ? rho : 0.f;
     re[1][1][r] += dg ? rho : 0.f;
   }
-  const float hs = h ? 1.f : -1.f;
   float pvv[2] = {0.f, 0.f};
 #pragma unroll
   for (int kk = 0; kk < 64; ++kk) {
@@ -961,33 +977,31 @@ __device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&
     const int hk = (kr / 4) & 1;
     const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(re[Ik][Ik][rr]), kr + 32 * hk));
     const float pv = __builtin_amdgcn_rcpf(d);
-    float first[2], second[2], mk[2];
+    // row kk with entry kk zeroed at the source lanes, as in gj_invert_mfma_u32
+    float first[2], second[2];
 #pragma unroll
     for (int J = 0; J < 2; ++J) {
       const float sr = re[Ik][J][rr], si = im[Ik][J][rr];
-      const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(sr), __float_as_uint(si), false, false);
-      const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(si), __float_as_uint(sr), false, false);
+      const bool isk = (32 * J + col == kk);
+      const float srm = isk ? 0.f : sr, sim = isk ? 0.f : si;
+      const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(srm), __float_as_uint(sim), false, false);
+      const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(sim), __float_as_uint(srm), false, false);
       first[J] = __uint_as_float(fs[hk]);
       second[J] = __uint_as_float(sf[hk]);
-      const bool isk = (32 * J + col == kk);
-      mk[J] = isk ? 0.f : 1.f;
       re[Ik][J][rr] = (isk && h == hk) ? -sr : sr;
     }
-    float Are[2], Aim[2], Bre[2], Bim[2];
+    float Are[2], Aim[2];
 #pragma unroll
     for (int J = 0; J < 2; ++J) {
-      const float t = pv * mk[J];
-      Are[J] = -t * first[J];
-      Aim[J] = (hs * t) * first[J];
-      Bre[J] = mk[J] * first[J];
-      Bim[J] = mk[J] * second[J];
+      Are[J] = -pv * first[J];
+      Aim[J] = h ? -Are[J] : Are[J];
     }
 #pragma unroll
     for (int I = 0; I < 2; ++I)
 #pragma unroll
       for (int J = 0; J < 2; ++J) {
-        re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are[I], Bre[J], re[I][J], 0, 0, 0);
-        im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim[I], Bim[J], im[I][J], 0, 0, 0);
+        re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are[I], first[J], re[I][J], 0, 0, 0);
+        im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim[I], second[J], im[I][J], 0, 0, 0);
       }
 #pragma unroll
     for (int J = 0; J < 2; ++J) pvv[J] = (32 * J + col == kk) ? pv : pvv[J];
@@ -1070,21 +1084,21 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
   }
   // Tile (I, J) holds P^T P and M = Hr^T Hi restricted to rows 32 I.. and
   // columns 32 J..; Re G_IJ = (P^T P)_IJ - M_IJ - (M_JI)^T and
-  // Im G_IJ = M_IJ - (M_JI)^T.  The transposes go through the wave's 4 KB
-  // stage buffer, one 32 x 32 tile at a time, XOR-swizzled as for U = 32
-  // (entry (i, j) at 32 i + (j ^ i)); both off-diagonal transposes are read
-  // before either off-diagonal tile changes.
+  // Im G_IJ = M_IJ - (M_JI)^T.  The transposes go through the wave's stage
+  // buffer, one 32 x 32 tile at a time, with a row pitch of 33 as for U = 32;
+  // both off-diagonal transposes are read before either off-diagonal tile
+  // changes.
   auto transposed = [&](const f32x16& m, float (&out)[16]) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r / 4) + 4 * h + (r % 4);
-      stage[32 * i + (col ^ i)] = m[r];
+      stage[33 * i + col] = m[r];
     }
     wave_lds_sync();
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r / 4) + 4 * h + (r % 4);
-      out[r] = stage[32 * col + (i ^ col)];
+      out[r] = stage[33 * col + i];
     }
     wave_lds_sync();
   };
@@ -1417,22 +1431,22 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     }
   } else if constexpr (G == 32 && HALF == 0) {
     hy0 = gram_mfma_u32<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
-                              reinterpret_cast<float*>(sm.stage + wave * kStageRows * 64));
+                              reinterpret_cast<float*>(sm.stage + wave * kStageWave));
   } else if constexpr (G == 32 && HALF == 1) {
-    hy0 = gram_inv_mixed_u32<_Float16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64),
+    hy0 = gram_inv_mixed_u32<_Float16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageWave),
                                             trg);
   } else if constexpr (G == 32 && HALF == 2) {
-    hy0 = gram_inv_mixed_u32<__bf16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageRows * 64),
+    hy0 = gram_inv_mixed_u32<__bf16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageWave),
                                           trg);
   } else if constexpr (G == 16) {
-    hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
+    hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageWave);
 #pragma unroll
     for (int v = 0; v < G; ++v)
       if (v == u) A[v].re += a.rho;
     gj_invert<G>(A, u, line, gbase);
   } else if constexpr (G == 64 && HALF == 0) {
     hy0 = gram_mfma_u64<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
-                              reinterpret_cast<float*>(sm.stage + wave * kStageRows * 64));
+                              reinterpret_cast<float*>(sm.stage + wave * kStageWave));
   } else if constexpr (G == 64 && HALF == 1) {
     hy0 = gram_inv_mixed_u64<_Float16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line), trg);
   } else if constexpr (G == 64 && HALF == 2) {
@@ -1579,12 +1593,12 @@ __global__ void __launch_bounds__(512) dcg_ul_f32(UlArgs a) {
   c32 hy0;
   if constexpr (G == 32)
     hy0 = gram_mfma_u32<false>(a, A, lane, wave, reinterpret_cast<float*>(line),
-                               reinterpret_cast<float*>(sm.stage + wave * kStageRows * 64));
+                               reinterpret_cast<float*>(sm.stage + wave * kStageWave));
   else if constexpr (G == 16)
-    hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageRows * 64);
+    hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageWave);
   else if constexpr (G == 64)
     hy0 = gram_mfma_u64<false>(a, A, lane, wave, reinterpret_cast<float*>(line),
-                               reinterpret_cast<float*>(sm.stage + wave * kStageRows * 64));
+                               reinterpret_cast<float*>(sm.stage + wave * kStageWave));
   else
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 
@@ -1709,10 +1723,10 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   // M (rows a < S; M must hold zeros).  Every lane of the wave takes part.
   auto gram_into = [&](c32 (&M)[SG]) {
     if constexpr (LATE_H) {
-      gram_dl_mfma_s16_u32<false>(hcol, M, lane, g, u, sm.stage + wave * kStageRows * 64);
+      gram_dl_mfma_s16_u32<false>(hcol, M, lane, g, u, sm.stage + wave * kStageWave);
     } else {
       // Row b of Hu_c is broadcast from the stage buffer of this wave.
-      c32* stage = sm.stage + wave * kStageRows * 64;
+      c32* stage = sm.stage + wave * kStageWave;
       for (int b = 0; b < S; ++b) {
         // lane u of the group publishes Hu[b][u] = hcol[b]
         c32 hb = cz();
@@ -1740,7 +1754,7 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   // A_c = H_c^H H_c + rho^{-1} I_S
   const float irho = 1.0f / a.rho;
   if constexpr (ASPLIT) {
-    gram_dl_mfma_s16_u32<true>(hcol, A, lane, g, u, sm.stage + wave * kStageRows * 64);
+    gram_dl_mfma_s16_u32<true>(hcol, A, lane, g, u, sm.stage + wave * kStageWave);
     const int h = u >> 4, r = u & 15;
 #pragma unroll
     for (int i = 0; i < 8; ++i)
@@ -1758,7 +1772,7 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
     // buffer, one problem at a time: entry (i, w) at i G + ((w + 2 i) mod G).
     // The rotation keeps column pairs together (16-byte reads) and puts the
     // rows that a read instruction touches into different LDS banks.
-    c32* tile = sm.stage + wave * kStageRows * 64;
+    c32* tile = sm.stage + wave * kStageWave;
     for (int pp = 0; pp < P; ++pp) {
       if (g == pp) {
 #pragma unroll
@@ -1782,7 +1796,7 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   // half of a group 4 entries further on, so that the (up to four) distinct
   // 16-byte addresses a read instruction touches fall into different LDS
   // banks.
-  c32* bl = sm.stage + wave * kStageRows * 64 + g * (G + 8);
+  c32* bl = sm.stage + wave * kStageWave + g * (G + 8);
   const int bw = u + (SPLIT ? 4 * (u / RS) : 0);      // this lane's slot
   const int br = r0 + (SPLIT ? 4 * (r0 / RS) : 0);    // start of the half this lane reads
   int buf = 0;
