@@ -1419,7 +1419,38 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   // (v < u): one load per entry, coalesced over the lanes of the first kind.
   constexpr int NT = G * (G + 1) / 2;
   const size_t fo = ((size_t)k * a.C + c) * NT;
-  if constexpr (STAGE >= 2) {
+  if constexpr (STAGE >= 2 && G == 32) {
+    // The lanes of the other kind would read 32 different cache lines per
+    // load, so each problem's triangle (NT = 528 values, the size of the
+    // wave's stage buffer) first goes through LDS with 16-byte coalesced
+    // loads, one problem of the wave at a time.  Both candidate entries are
+    // inside the triangle for every (u, v) (indices at most NT - 1), so each
+    // lane reads both and keeps one.
+    c32* tri = sm.stage + wave * kStageWave;
+    const int csu = u * (u + 1) / 2;
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+      const int lq = wave * P + pp;
+      const int kq = a.blk * a.sc_per_block + lq / a.Cp, cq = lq % a.Cp;
+      if (kq < a.n_sc && cq < a.C) {
+        const float4* src = reinterpret_cast<const float4*>(a.fac + ((size_t)kq * a.C + cq) * NT);
+        float4* dst = reinterpret_cast<float4*>(tri);
+#pragma unroll
+        for (int i = 0; i < (NT / 2 + 63) / 64; ++i)
+          if (i * 64 + lane < NT / 2) dst[i * 64 + lane] = src[i * 64 + lane];
+      }
+      wave_lds_sync();
+      if (g == pp && active) {
+#pragma unroll
+        for (int v = 0; v < G; ++v) {
+          const c32 e1 = tri[v * (v + 1) / 2 + u];   // entry (u, v), v >= u
+          const c32 e2 = tri[csu + v];               // entry (v, u), v < u
+          A[v] = (v >= u) ? e1 : c32{e2.re, -e2.im};
+        }
+      }
+      wave_lds_sync();
+    }
+  } else if constexpr (STAGE >= 2) {
     if (active) {
       const int csu = u * (u + 1) / 2;
 #pragma unroll
