@@ -18,10 +18,11 @@
 namespace dbp {
 
 constexpr int kStageRows = 8;   // rows of H_c staged per pass through LDS
-// c32 slots of one wave's stage buffer: the staged rows, plus room for a
-// 32 x 32 float tile stored with a row pitch of 33 (transposes without bank
-// conflicts and with compile-time offsets)
-constexpr int kStageWave = kStageRows * 64 + 16;
+// c32 slots of one wave's stage buffer: the staged rows, plus room for the
+// padded transposes (a 32 x 32 float tile with a row pitch of 33, or two
+// 16 x 16 problems as planes of 32 x 17 floats), whose offsets are then
+// compile-time constants
+constexpr int kStageWave = kStageRows * 64 + 32;
 
 // Loads in the Gram prologues never branch: a request outside the problem
 // (padding cluster, subcarrier past the end, ragged row past S) reads a valid
@@ -814,12 +815,15 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
     if (s0 + 8 * CH < a.S) fetch(s0 + 8 * CH, hv, yv);
     accumulate(hn, yn);
   }
-  // Transpose through LDS, two problems per pass: entry (i, j) of problem pp at
-  // (16 pp + i) 16 + (j ^ i) (XOR swizzle: conflict-free for the column read
-  // and for the transposed read).  re holds P^T P and im holds M = Hr^T Hi,
-  // so Re G[v][col] = (P^T P)[v][col] - M[v][col] - M[col][v] and
+  // Transpose through LDS, two problems per pass: the real and imaginary
+  // accumulators go to two float planes, entry (i, j) of problem pp at
+  // (16 pp + i) 17 + j (a row pitch of 17: the column read and the transposed
+  // read are conflict-free, and every offset is a compile-time constant).
+  // re holds P^T P and im holds M = Hr^T Hi, so
+  // Re G[v][col] = (P^T P)[v][col] - M[v][col] - M[col][v] and
   // Im G[v][col] = M[v][col] - M[col][v].
-  float* stf = reinterpret_cast<float*>(stage);
+  float* pre = reinterpret_cast<float*>(stage);
+  float* pim = pre + 32 * 17;
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
 #pragma unroll
@@ -827,29 +831,35 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 4 * q + r;
-        stage[(16 * pp + i) * 16 + (col ^ i)] = c32{re[2 * half + pp][r], im[2 * half + pp][r]};
+        pre[(16 * pp + i) * 17 + col] = re[2 * half + pp][r];
+        pim[(16 * pp + i) * 17 + col] = im[2 * half + pp][r];
       }
     wave_lds_sync();
     if ((q >> 1) == half) {
       const int pp = q & 1;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const c32 g = stage[(16 * pp + v) * 16 + (col ^ v)];
-        const float mt = stf[2 * ((16 * pp + col) * 16 + (v ^ col)) + 1];
-        A[v] = c32{g.re - g.im - mt, mt - g.im};
+        const float gr = pre[(16 * pp + v) * 17 + col], gi = pim[(16 * pp + v) * 17 + col];
+        const float mt = pim[(16 * pp + col) * 17 + v];
+        A[v] = c32{gr - gi - mt, mt - gi};
       }
     }
     wave_lds_sync();
   }
   // H_c^H y_c: sum the four row classes (lanes col, col+16, col+32, col+48)
-  c32 out = cz();
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const float hr = pair_sum<32>(pair_sum<16>(hyp[p].re));
-    const float hi = pair_sum<32>(pair_sum<16>(hyp[p].im));
-    if (p == q) out = c32{hr, hi};
-  }
-  return out;
+  // and hand problem p's sum to row p: v_permlane16_swap of problems (0, 1)
+  // and (2, 3) adds rows in pairs (problem 0 or 2 on even rows, 1 or 3 on odd
+  // rows), v_permlane32_swap then adds the halves, leaving problem q on row q.
+  auto scatter_sum = [](float v0, float v1, float v2, float v3) {
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v0), __float_as_uint(v1), false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(__float_as_uint(v2), __float_as_uint(v3), false, false);
+    const float s01 = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const float s23 = __uint_as_float(b[0]) + __uint_as_float(b[1]);
+    const auto c = __builtin_amdgcn_permlane32_swap(__float_as_uint(s01), __float_as_uint(s23), false, false);
+    return __uint_as_float(c[0]) + __uint_as_float(c[1]);
+  };
+  return c32{scatter_sum(hyp[0].re, hyp[1].re, hyp[2].re, hyp[3].re),
+             scatter_sum(hyp[0].im, hyp[1].im, hyp[2].im, hyp[3].im)};
 }
 
 // Downlink S x S Gram A_c[a][b] = sum_u conj(Hu[a][u]) Hu[b][u] (S <= 16,
@@ -1287,10 +1297,34 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
 // whose register budget the unrolled form would cut into) it is a loop over C.
 template <int N>
 __device__ __forceinline__ c32 sum_slots(const c32* src, int G) {
-  c32 w = cz();
+  c32 w = src[0];
 #pragma unroll
-  for (int cc = 0; cc < N; ++cc) w = cadd(w, src[cc * G]);
+  for (int cc = 1; cc < N; ++cc) w = cadd(w, src[cc * G]);
   return w;
+}
+
+// Sum of a complex value over the P = 64 / G lane groups of a wave (lanes l,
+// l ^ G, l ^ 2G, ...), the same bits on every lane: pairs of groups first,
+// then pairs of pairs.  The real and imaginary parts travel together: one
+// v_permlane16_swap of (re, im) leaves the pair sums of re on the even and of
+// im on the odd rows of 16 lanes, one v_permlane32_swap adds the halves, and a
+// last swap hands every lane both components.
+template <int P>
+__device__ __forceinline__ c32 wave_group_sum(c32 w) {
+  if constexpr (P >= 8) w = c32{pair_sum<8>(w.re), pair_sum<8>(w.im)};
+  if constexpr (P >= 4) {
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(w.re), __float_as_uint(w.im), false, false);
+    const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);   // rows: re01 im01 re23 im23
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+    const float t = __uint_as_float(b[0]) + __uint_as_float(b[1]);   // rows: re im re im (totals)
+    const auto c = __builtin_amdgcn_permlane16_swap(__float_as_uint(t), __float_as_uint(t), false, false);
+    return c32{__uint_as_float(c[0]), __uint_as_float(c[1])};
+  } else {
+    const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(w.re), __float_as_uint(w.im), false, false);
+    const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);   // halves: re | im
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+    return c32{__uint_as_float(b[0]), __uint_as_float(b[1])};
+  }
 }
 
 template <bool UNROLL = true>
@@ -1330,10 +1364,7 @@ __device__ __forceinline__ c32 consensus_w(c32 wc, int buf, int ls, int u, int g
     return consensus<true>(wc, buf, ls, G, u, C, Cp, sm, slot, nw);
   } else {
     if (Cp < P) return consensus<true>(wc, buf, ls, G, u, C, Cp, sm, slot, nw);
-    c32 w = wc;
-    if constexpr (P >= 8) w = c32{pair_sum<8>(w.re), pair_sum<8>(w.im)};
-    if constexpr (P >= 4) w = c32{pair_sum<16>(w.re), pair_sum<16>(w.im)};
-    w = c32{pair_sum<32>(w.re), pair_sum<32>(w.im)};
+    const c32 w = wave_group_sum<P>(wc);
     c32* cb = sm.cons + buf * nw * 64;
     if (g == 0) cb[slot] = w;
     __syncthreads();
