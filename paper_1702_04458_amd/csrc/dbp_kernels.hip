@@ -205,9 +205,12 @@ __device__ __forceinline__ void gj_unscale_u32(f32x16& re, f32x16& im, float pvv
 }
 
 // ADD_RHO: add rho to the diagonal first (false: the caller's accumulators
-// already hold G + rho I).
-template <bool ADD_RHO = true>
-__device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)[2], int lane, float rho, float* line) {
+// already hold G + rho I).  LAZY: leave the swept matrix S with its scales
+// (B^{-1}_ij = -S_ij pv_i pv_j) and return in pvs[p] the reciprocal pivot
+// pv of this lane's column for problem p.
+template <bool ADD_RHO = true, bool LAZY = false>
+__device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)[2], int lane, float rho, float* line,
+                                                   float* pvs = nullptr) {
   const int h = lane >> 5, col = lane & 31;
   if constexpr (ADD_RHO) {
 #pragma unroll
@@ -247,10 +250,19 @@ __device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)
       re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are, first, re[p], 0, 0, 0);
       im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim, second, im[p], 0, 0, 0);
       pvv[p] = isk ? pv : pvv[p];
+      // select in place (otherwise the compiler keeps every pivot's pv live
+      // until the end)
+      asm volatile("" : "+v"(pvv[p]));
     }
   }
+  if constexpr (LAZY) {
+    pvs[0] = pvv[0];
+    pvs[1] = pvv[1];
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
 #pragma unroll
-  for (int p = 0; p < 2; ++p) gj_unscale_u32(re[p], im[p], pvv[p], 1.f, lane, line);
+    for (int p = 0; p < 2; ++p) gj_unscale_u32(re[p], im[p], pvv[p], 1.f, lane, line);
+  }
 }
 
 // Exchange between the wave's two 32-lane halves: v_permlane32_swap(X, Y)
@@ -295,10 +307,12 @@ __device__ __forceinline__ float pair_sum(float v) {
 // accumulators are replaced by (G + rho I)^{-1} on the matrix cores first.
 // One exchange between lanes l and l^32 then gives every lane the full row of
 // its own problem (lane-row layout, problem = l/32).  Returns row u of
-// H_c^H y_c for symbol 0.
-template <bool INVERT>
+// H_c^H y_c for symbol 0.  LAZY (with INVERT): A receives row u of the swept
+// matrix S with its scales left in place, and *pvl the reciprocal pivot pv_u
+// of this lane's row, so that B^{-1} q = -pv_u sum_v S_uv (pv_v q_v).
+template <bool INVERT, bool LAZY = false>
 __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave, float* line,
-                                             float* stage) {
+                                             float* stage, float* pvl = nullptr) {
   const int h = lane >> 5, col = lane & 31;
   f32x16 re[2], im[2];
   c32 hyp[2];
@@ -383,7 +397,13 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
     }
     wave_lds_sync();
   }
-  if (INVERT) gj_invert_mfma_u32<false>(re, im, lane, a.rho, line);
+  if constexpr (INVERT && LAZY) {
+    float pvs[2];
+    gj_invert_mfma_u32<false, true>(re, im, lane, a.rho, line, pvs);
+    *pvl = h ? pvs[1] : pvs[0];
+  } else if constexpr (INVERT) {
+    gj_invert_mfma_u32<false>(re, im, lane, a.rho, line);
+  }
   // exchange halves: lanes < 32 keep problem 0, lanes >= 32 keep problem 1
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -1443,6 +1463,19 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   }
   c32 hy0 = cz();
   float trg = 0.f;   // tr(G_c) (mixed modes)
+  // U = 32, FP32, iterations in the same launch: the inverse keeps its lazy
+  // scales (B^{-1}_uv = -S_uv pv_u pv_v), which every product applies to its
+  // operand and result instead of to the 32 x 32 entries.
+  constexpr bool LAZY = (G == 32 && HALF == 0 && STAGE == 0);
+  float pvl = 1.f;
+  auto bmat = [&](c32 q) -> c32 {
+    if constexpr (LAZY) {
+      const c32 r = group_matvec<G>(A, cscale(q, pvl), u, line, gbase);
+      return cscale(r, -pvl);
+    } else {
+      return group_matvec<G>(A, q, u, line, gbase);
+    }
+  };
   // Resident factors of this problem: B_c^{-1} is Hermitian, so only its
   // upper triangle is stored, column by column (entry (i, v), i <= v, at
   // v (v + 1) / 2 + i; G (G + 1) / 2 values per problem).  Lane u's row
@@ -1492,8 +1525,8 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       }
     }
   } else if constexpr (G == 32 && HALF == 0) {
-    hy0 = gram_mfma_u32<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
-                              reinterpret_cast<float*>(sm.stage + wave * kStageWave));
+    hy0 = gram_mfma_u32<true, LAZY>(a, A, lane, wave, reinterpret_cast<float*>(line),
+                                    reinterpret_cast<float*>(sm.stage + wave * kStageWave), &pvl);
   } else if constexpr (G == 32 && HALF == 1) {
     hy0 = gram_inv_mixed_u32<_Float16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageWave),
                                             trg);
@@ -1561,7 +1594,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     else if (n > 0 || STAGE == 2)
       hy = cluster_pass<G, false>(a.H, a.y, A, k, c, n, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
     // y_c^reg = B_c^{-1} H_c^H y_c; z = y^reg; lambda = 0
-    const c32 yreg = group_matvec<G>(A, hy, u, line, gbase);
+    const c32 yreg = bmat(hy);
     c32 z = yreg, lam = cz();
     c32 w = (HALF == 0) ? consensus_w<G>(active ? z : cz(), buf, ls, u, g, a.C, a.Cp, sm, slot, nw)
                         : consensus<false>(active ? z : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
@@ -1591,7 +1624,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       lam.re = fmaf(a.gamma, z.re - s.re, lam.re);
       lam.im = fmaf(a.gamma, z.im - s.im, lam.im);
       const c32 q = csub(s, lam);
-      const c32 bq = group_matvec<G>(A, q, u, line, gbase);
+      const c32 bq = bmat(q);
       z = c32{fmaf(a.rho, bq.re, yreg.re), fmaf(a.rho, bq.im, yreg.im)};
       w = (HALF == 0) ? consensus_w<G>(active ? cadd(z, lam) : cz(), buf, ls, u, g, a.C, a.Cp, sm, slot, nw)
                       : consensus<false>(active ? cadd(z, lam) : cz(), buf, ls, G, u, a.C, a.Cp, sm, slot, nw);
