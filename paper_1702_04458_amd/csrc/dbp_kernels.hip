@@ -310,7 +310,7 @@ __device__ __forceinline__ float pair_sum(float v) {
 // H_c^H y_c for symbol 0.  LAZY (with INVERT): A receives row u of the swept
 // matrix S with its scales left in place, and *pvl the reciprocal pivot pv_u
 // of this lane's row, so that B^{-1} q = -pv_u sum_v S_uv (pv_v q_v).
-template <bool INVERT, bool LAZY = false>
+template <bool INVERT, bool LAZY = false, bool FLAT = false>
 __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave, float* line,
                                              float* stage, float* pvl = nullptr) {
   const int h = lane >> 5, col = lane & 31;
@@ -365,14 +365,33 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
       }
     }
   };
-  // the two buffers in turn (no copies)
+  // the two buffers in turn (no copies).  FLAT: the loop body always runs
+  // both halves and the rows past the last full double step follow it (with
+  // an exit between the halves the compiler copies the accumulators of the
+  // factor-only kernel on every step; the other kernels are compiled best
+  // with the exit)
   fetch(0, hv, yv);
-  for (int s0 = 0; s0 < a.S; s0 += 4 * CH) {
-    if (s0 + 2 * CH < a.S) fetch(s0 + 2 * CH, hn, yn);
-    accumulate(hv, yv);
-    if (s0 + 2 * CH >= a.S) break;
-    if (s0 + 4 * CH < a.S) fetch(s0 + 4 * CH, hv, yv);
-    accumulate(hn, yn);
+  if constexpr (FLAT) {
+    int s0 = 0;
+    for (; s0 + 4 * CH <= a.S; s0 += 4 * CH) {
+      fetch(s0 + 2 * CH, hn, yn);
+      accumulate(hv, yv);
+      fetch(s0 + 4 * CH, hv, yv);   // zeros past S
+      accumulate(hn, yn);
+    }
+    if (s0 < a.S) {
+      if (s0 + 2 * CH < a.S) fetch(s0 + 2 * CH, hn, yn);
+      accumulate(hv, yv);
+      if (s0 + 2 * CH < a.S) accumulate(hn, yn);
+    }
+  } else {
+    for (int s0 = 0; s0 < a.S; s0 += 4 * CH) {
+      if (s0 + 2 * CH < a.S) fetch(s0 + 2 * CH, hn, yn);
+      accumulate(hv, yv);
+      if (s0 + 2 * CH >= a.S) break;
+      if (s0 + 4 * CH < a.S) fetch(s0 + 4 * CH, hv, yv);
+      accumulate(hn, yn);
+    }
   }
   // re holds rho I + P^T P and im holds M = Hr^T Hi; since P^T P = Hr^T Hr
   // + Hi^T Hi + M + M^T, Re G = P^T P - M - M^T and Im G = M - M^T (two MFMAs
@@ -1525,7 +1544,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       }
     }
   } else if constexpr (G == 32 && HALF == 0) {
-    hy0 = gram_mfma_u32<true, LAZY>(a, A, lane, wave, reinterpret_cast<float*>(line),
+    hy0 = gram_mfma_u32<true, LAZY, STAGE == 1>(a, A, lane, wave, reinterpret_cast<float*>(line),
                                     reinterpret_cast<float*>(sm.stage + wave * kStageWave), &pvl);
   } else if constexpr (G == 32 && HALF == 1) {
     hy0 = gram_inv_mixed_u32<_Float16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageWave),
@@ -1553,7 +1572,34 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       if (v == u) A[v].re += a.rho;
     gj_invert<G>(A, u, line, gbase);
   }
-  if constexpr (STAGE == 1) {
+  if constexpr (STAGE == 1 && G == 32) {
+    // Through the wave's stage buffer, one problem at a time, then 16-byte
+    // coalesced stores.  Lane u writes entry v of its row to v (v + 1) / 2 + u
+    // for every v in increasing order: for v >= u that is entry (u, v) of the
+    // triangle; for v < u the position belongs to a later column w > v, whose
+    // own write (step w, lane u') comes after it and replaces it.  Every
+    // position is inside the triangle (at most NT - 1).
+    c32* tri = sm.stage + wave * kStageWave;
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+      if (g == pp) {
+#pragma unroll
+        for (int v = 0; v < G; ++v) tri[v * (v + 1) / 2 + u] = A[v];
+      }
+      wave_lds_sync();
+      const int lq = wave * P + pp;
+      const int kq = a.blk * a.sc_per_block + lq / a.Cp, cq = lq % a.Cp;
+      if (kq < a.n_sc && cq < a.C) {
+        float4* dst = reinterpret_cast<float4*>(a.fac + ((size_t)kq * a.C + cq) * NT);
+        const float4* src = reinterpret_cast<const float4*>(tri);
+#pragma unroll
+        for (int i = 0; i < (NT / 2 + 63) / 64; ++i)
+          if (i * 64 + lane < NT / 2) dst[i * 64 + lane] = src[i * 64 + lane];
+      }
+      wave_lds_sync();
+    }
+    return;
+  } else if constexpr (STAGE == 1) {
     if (active) {
 #pragma unroll
       for (int v = 0; v < G; ++v)
