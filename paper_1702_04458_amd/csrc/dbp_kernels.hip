@@ -921,15 +921,16 @@ __device__ __forceinline__ void gram_dl_mfma_s16_u32(const c32 (&hcol)[16], c32 
 #pragma unroll
   for (int p = 0; p < 2; ++p) {
     // problem p's tile (from the register copy hcol, zero past S) through
-    // the stage buffer: entry (i, w) at 32 i + ((w + 2 i) mod 32)
+    // the stage buffer: entry (i, w) at 33 i + w (a row pitch of 33 complex
+    // values: conflict-free, and every offset a compile-time constant)
     if (g == p) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) stage[i * 32 + ((u + 2 * i) & 31)] = hcol[i];
+      for (int i = 0; i < 16; ++i) stage[i * 33 + u] = hcol[i];
     }
     wave_lds_sync();
     c32 x[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = stage[r16 * 32 + ((q + 4 * j + 2 * r16) & 31)];
+    for (int j = 0; j < 8; ++j) x[j] = stage[r16 * 33 + q + 4 * j];
     wave_lds_sync();
     re[p] = f32x4{};
     im[p] = f32x4{};
