@@ -1911,20 +1911,23 @@ __device__ __forceinline__ void admm_dl_body(const DlArgs& a) {
   }
   if constexpr (LATE_H) {
     // Transpose the S x G tile of each problem through the wave's stage
-    // buffer, one problem at a time: entry (i, w) at i G + ((w + 2 i) mod G).
-    // The rotation keeps column pairs together (16-byte reads) and puts the
-    // rows that a read instruction touches into different LDS banks.
+    // buffer, one problem at a time: entry (i, w) at i (G + 2) + w.  The
+    // pitch of G + 2 complex values keeps column pairs together and 16-byte
+    // aligned, puts the rows that a read instruction touches into different
+    // LDS banks, and makes every offset a compile-time constant
+    // (SG (G + 2) = 544 values, the size of the stage buffer).
     c32* tile = sm.stage + wave * kStageWave;
+    static_assert(SG * (G + 2) <= kStageWave, "tile exceeds the stage buffer");
     for (int pp = 0; pp < P; ++pp) {
       if (g == pp) {
 #pragma unroll
-        for (int i = 0; i < SG; ++i) tile[i * G + ((u + 2 * i) & (G - 1))] = hcol[i];
+        for (int i = 0; i < SG; ++i) tile[i * (G + 2) + u] = hcol[i];
       }
       wave_lds_sync();
       if (g == pp) {
 #pragma unroll
         for (int m = 0; m < RS / 2; ++m) {
-          const float4 v = *reinterpret_cast<const float4*>(tile + ra * G + ((r0 + 2 * m + 2 * ra) & (G - 1)));
+          const float4 v = *reinterpret_cast<const float4*>(tile + ra * (G + 2) + r0 + 2 * m);
           hrow[2 * m] = c32{v.x, v.y};
           hrow[2 * m + 1] = c32{v.z, v.w};
         }
