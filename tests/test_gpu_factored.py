@@ -27,9 +27,12 @@ def say(msg):
 
 
 # (B, U, C, n_sc, qam, snr): the configurations' shapes, a ragged subcarrier
-# count, and C = 3 / 6 (padding cluster slots in the workgroup)
+# count, C = 3 / 6 (padding cluster slots in the workgroup), and U = 32 with
+# S = 36 and S = 45 antennas per cluster (row counts that end inside the
+# Gram's prefetch chunks)
 SHAPES = [(256, 32, 8, 40, 64, 25.0), (128, 16, 8, 75, 16, 10.0), (64, 8, 4, 16, 4, 10.0),
-          (512, 64, 8, 9, 64, 25.0), (96, 16, 3, 37, 16, 15.0), (384, 32, 6, 11, 64, 20.0)]
+          (512, 64, 8, 9, 64, 25.0), (96, 16, 3, 37, 16, 15.0), (384, 32, 6, 11, 64, 20.0),
+          (72, 32, 2, 5, 16, 15.0), (90, 32, 2, 4, 64, 20.0)]
 
 
 @pytest.mark.parametrize("B,U,C,n_sc,qam,snr", SHAPES)
@@ -83,13 +86,13 @@ def test_mixed_precision_factors(prec, factor):
         assert np.array_equal(h, O.slice_qam(ref, 64))
 
 
-def test_factors_match_oracle_inverse():
+@pytest.mark.parametrize("B,U,C,n_sc", [(128, 16, 8, 6), (256, 32, 8, 3), (72, 32, 2, 3), (90, 32, 2, 3)])
+def test_factors_match_oracle_inverse(B, U, C, n_sc):
     """The stored blocks are B_c^{-1} = (H_c^H H_c + rho I)^{-1}: the library's
     internal layout holds the upper triangle of block (k, c) column by column,
     entry (i, v) with i <= v at v (v + 1) / 2 + i."""
-    say("[gpu] factors vs oracle inverse")
-    B, U, C, n_sc = 128, 16, 8, 6
-    fr = inputs.uplink_frame(inputs.frame_seed(23, 0, 10), n_sc, B, U, 16, 10.0)
+    say(f"[gpu] factors vs oracle inverse B={B} U={U} C={C} n_sc={n_sc}")
+    fr = inputs.uplink_frame(inputs.frame_seed(23, B + U, C), n_sc, B, U, 16, 10.0)
     fac = api.factor(to_dev(fr.H), C, 0.7).cpu().numpy()          # [n_sc, C, U (U + 1) / 2] as stored
     assert fac.shape == (n_sc, C, U * (U + 1) // 2)
     S = B // C
