@@ -15,7 +15,7 @@
 
 namespace dbp {
 
-struct c32 {
+struct alignas(8) c32 {
   float re, im;
 };
 
@@ -255,11 +255,36 @@ __device__ __forceinline__ void gj_invert(c32 (&A)[G], int u, c32* line, int gba
       : "+v"(a0.re), "+v"(a0.im), "+v"(a1.re), "+v"(a1.im)                               \
       : "v"(q.re), "v"(q.im), "v"(A[V0].re), "v"(A[V0].im), "v"(A[V1].re), "v"(A[V1].im), \
         "v"(A[V2].re), "v"(A[V2].im), "v"(A[V3].re), "v"(A[V3].im))
+// The first block of a product: the first product of each accumulator is a
+// v_mul (no zeroed accumulators).
+#define DBP_MV16_FIRST(V0, V1, V2, V3)                                                     \
+  asm volatile(                                                                          \
+      "s_nop 1\n\t"                                                                      \
+      "v_mul_f32_dpp  %0, %4, %6 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %0, -%5, %7 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_mul_f32_dpp  %1, %5, %6 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %1, %4, %7 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_mul_f32_dpp  %2, %4, %8 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %2, -%5, %9 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_mul_f32_dpp  %3, %5, %8 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %3, %4, %9 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %0, %4, %10 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %0, -%5, %11 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"  \
+      "v_fmac_f32_dpp %1, %5, %10 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %1, %4, %11 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %2, %4, %12 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %2, -%5, %13 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"  \
+      "v_fmac_f32_dpp %3, %5, %12 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %3, %4, %13 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "s_nop 1"                                                                          \
+      : "=&v"(a0.re), "=&v"(a0.im), "=&v"(a1.re), "=&v"(a1.im)                               \
+      : "v"(q.re), "v"(q.im), "v"(A[V0].re), "v"(A[V0].im), "v"(A[V1].re), "v"(A[V1].im), \
+        "v"(A[V2].re), "v"(A[V2].im), "v"(A[V3].re), "v"(A[V3].im))
 
 // acc = sum_v A[v] * q_v with q_v held by lane v of the 16-lane row
 __device__ __forceinline__ c32 matvec16(const c32 (&A)[16], c32 q) {
-  c32 a0 = cz(), a1 = cz();
-  DBP_MV16_BLOCK(0, 1, 2, 3);
+  c32 a0, a1;
+  DBP_MV16_FIRST(0, 1, 2, 3);
   DBP_MV16_BLOCK(4, 5, 6, 7);
   DBP_MV16_BLOCK(8, 9, 10, 11);
   DBP_MV16_BLOCK(12, 13, 14, 15);
@@ -289,16 +314,40 @@ __device__ __forceinline__ c32 matvec16(const c32 (&A)[16], c32 q) {
       : "+v"(a0.re), "+v"(a0.im), "+v"(a1.re), "+v"(a1.im)                               \
       : "v"(q.re), "v"(q.im), "v"(A[V0].re), "v"(A[V0].im), "v"(A[V1].re), "v"(A[V1].im), \
         "v"(A[V2].re), "v"(A[V2].im), "v"(A[V3].re), "v"(A[V3].im))
+#define DBP_MV16C_FIRST(V0, V1, V2, V3)                                                    \
+  asm volatile(                                                                          \
+      "s_nop 1\n\t"                                                                      \
+      "v_mul_f32_dpp  %0, %4, %6 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %0, %5, %7 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_mul_f32_dpp  %1, %5, %6 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %1, -%4, %7 row_newbcast:" #V0 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_mul_f32_dpp  %2, %4, %8 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %2, %5, %9 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_mul_f32_dpp  %3, %5, %8 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"    \
+      "v_fmac_f32_dpp %3, -%4, %9 row_newbcast:" #V1 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %0, %4, %10 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %0, %5, %11 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %1, %5, %10 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %1, -%4, %11 row_newbcast:" #V2 " row_mask:0xf bank_mask:0xf\n\t"  \
+      "v_fmac_f32_dpp %2, %4, %12 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %2, %5, %13 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %3, %5, %12 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"   \
+      "v_fmac_f32_dpp %3, -%4, %13 row_newbcast:" #V3 " row_mask:0xf bank_mask:0xf\n\t"  \
+      "s_nop 1"                                                                          \
+      : "=&v"(a0.re), "=&v"(a0.im), "=&v"(a1.re), "=&v"(a1.im)                               \
+      : "v"(q.re), "v"(q.im), "v"(A[V0].re), "v"(A[V0].im), "v"(A[V1].re), "v"(A[V1].im), \
+        "v"(A[V2].re), "v"(A[V2].im), "v"(A[V3].re), "v"(A[V3].im))
 
 __device__ __forceinline__ c32 matvec16c(const c32 (&A)[16], c32 q) {
-  c32 a0 = cz(), a1 = cz();
-  DBP_MV16C_BLOCK(0, 1, 2, 3);
+  c32 a0, a1;
+  DBP_MV16C_FIRST(0, 1, 2, 3);
   DBP_MV16C_BLOCK(4, 5, 6, 7);
   DBP_MV16C_BLOCK(8, 9, 10, 11);
   DBP_MV16C_BLOCK(12, 13, 14, 15);
   return cadd(a0, a1);
 }
 #undef DBP_MV16C_BLOCK
+#undef DBP_MV16C_FIRST
 
 // Rows of a 16 x 16 matrix split over the two 16-lane DPP rows of a 32-lane
 // group: lane r of DPP row h holds entries 8h .. 8h+7 of matrix row r (A[i] is
@@ -311,15 +360,21 @@ __device__ __forceinline__ c32 matvec16c(const c32 (&A)[16], c32 q) {
 __device__ __forceinline__ c32 matvec_split16(const c32 (&A)[8], c32 q) {
   q.re = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(q.re), __float_as_int(q.re), 0x128, 0xA, 0xF, false));
   q.im = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(q.im), __float_as_int(q.im), 0x128, 0xA, 0xF, false));
-  c32 a0 = cz(), a1 = cz();
-  DBP_MV16_BLOCK(0, 1, 2, 3);
+  c32 a0, a1;
+  DBP_MV16_FIRST(0, 1, 2, 3);
   DBP_MV16_BLOCK(4, 5, 6, 7);
   c32 acc = cadd(a0, a1);
-  const auto sr = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc.re), __float_as_uint(acc.re), false, false);
-  const auto si = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc.im), __float_as_uint(acc.im), false, false);
-  return c32{__uint_as_float(sr[0]) + __uint_as_float(sr[1]), __uint_as_float(si[0]) + __uint_as_float(si[1])};
+  // pair sum over the two DPP rows for both parts at once: swapping (re, im)
+  // leaves re + re' on the even and im + im' on the odd rows, a second swap
+  // hands both to every lane (the same sums, in the same order, as two
+  // separate pair sums)
+  const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc.re), __float_as_uint(acc.im), false, false);
+  const float t = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+  const auto tt = __builtin_amdgcn_permlane16_swap(__float_as_uint(t), __float_as_uint(t), false, false);
+  return c32{__uint_as_float(tt[0]), __uint_as_float(tt[1])};
 }
 #undef DBP_MV16_BLOCK
+#undef DBP_MV16_FIRST
 
 // gj_invert_sym for a 16 x 16 matrix in the split-row layout above (r = matrix
 // row of this lane, h = its DPP row within the group; line = the group's 32
