@@ -1009,8 +1009,39 @@ __device__ __forceinline__ void gj_unscale_u64(f32x16 (&re)[2][2], f32x16 (&im)[
   wave_lds_sync();
 }
 
+// dst = src^H for one 32x32 tile pair (real, imaginary) through the wave's
+// stage buffer, a row pitch of 33 floats (as the Gram's transposes).
+__device__ __forceinline__ void tile_conj_transpose(const f32x16& sre, const f32x16& sim, f32x16& dre, f32x16& dim,
+                                                    int h, int col, float* stage) {
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      stage[33 * i + col] = part ? sim[r] : sre[r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      const float t = stage[33 * col + i];
+      if (part)
+        dim[r] = -t;
+      else
+        dre[r] = t;
+    }
+    wave_lds_sync();
+  }
+}
+
+// The swept matrix S stays Hermitian, so tile (1, 0) is tile (0, 1)^H
+// throughout.  While the pivots of the first block column are swept (rows
+// from tiles (0, 0), (0, 1)) tile (1, 0) is not updated; it is formed as
+// (0, 1)^H before the second block's pivots (rows from tiles (1, 0), (1, 1)),
+// which in turn leave tile (0, 1) alone until it is formed as (1, 0)^H at the
+// end: six matrix-core updates per pivot instead of eight.
 __device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&im)[2][2], int lane, float rho,
-                                                   float* line) {
+                                                   float* line, float* stage) {
   const int h = lane >> 5, col = lane & 31;
   // B = G + rho I
 #pragma unroll
@@ -1025,6 +1056,7 @@ __device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&
     const int Ik = kk / 32, kr = kk % 32;
     const int rr = 4 * (kr / 8) + (kr % 4);
     const int hk = (kr / 4) & 1;
+    if (kk == 32) tile_conj_transpose(re[0][1], im[0][1], re[1][0], im[1][0], h, col, stage);
     const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(re[Ik][Ik][rr]), kr + 32 * hk));
     const float pv = __builtin_amdgcn_rcpf(d);
     // row kk with entry kk zeroed at the source lanes, as in gj_invert_mfma_u32
@@ -1050,12 +1082,15 @@ __device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&
     for (int I = 0; I < 2; ++I)
 #pragma unroll
       for (int J = 0; J < 2; ++J) {
+        if (I != J && I != Ik) continue;   // the off-diagonal tile outside the pivot's block row
         re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are[I], first[J], re[I][J], 0, 0, 0);
         im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim[I], second[J], im[I][J], 0, 0, 0);
       }
 #pragma unroll
     for (int J = 0; J < 2; ++J) pvv[J] = (32 * J + col == kk) ? pv : pvv[J];
+    asm volatile("" : "+v"(pvv[0]), "+v"(pvv[1]));
   }
+  tile_conj_transpose(re[1][0], im[1][0], re[0][1], im[0][1], h, col, stage);
   gj_unscale_u64(re, im, pvv, 1.f, lane, line);
 }
 
@@ -1174,7 +1209,7 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
       im[D][D][r] -= td[r];
     }
   }
-  if (INVERT) gj_invert_mfma_u64(re, im, lane, a.rho, line);
+  if (INVERT) gj_invert_mfma_u64(re, im, lane, a.rho, line, stage);
   acc_to_rows_u64(re, im, A, h);
   return combine_hy_u64(hy0, hy1, h);
 }
@@ -1232,7 +1267,7 @@ __device__ __forceinline__ void gj_invert_split16_u64(f32x16 (&re)[2][2], f32x16
 // the normalised Gram (INV = 2).
 template <typename HT, int INV>
 __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64], int lane, int wave,
-                                                  float* line, float& trg) {
+                                                  float* line, float* stage, float& trg) {
   typedef typename HalfMma<HT>::V V;
   const int h = lane >> 5, col = lane & 31;
   const int ls = wave / a.Cp, c = wave % a.Cp;
@@ -1322,7 +1357,7 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
   if (INV == 2)
     gj_invert_split16_u64(re, im, lane, ldexpf(a.rho, 2 * ex - sh), ldexpf(1.f, 2 * ex - sh), line);
   else
-    gj_invert_mfma_u64(re, im, lane, a.rho, line);
+    gj_invert_mfma_u64(re, im, lane, a.rho, line, stage);
   acc_to_rows_u64(re, im, A, h);
   return combine_hy_u64(hy0, hy1, h);
 }
@@ -1563,9 +1598,11 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     hy0 = gram_mfma_u64<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
                               reinterpret_cast<float*>(sm.stage + wave * kStageWave));
   } else if constexpr (G == 64 && HALF == 1) {
-    hy0 = gram_inv_mixed_u64<_Float16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line), trg);
+    hy0 = gram_inv_mixed_u64<_Float16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line),
+                                            reinterpret_cast<float*>(sm.stage + wave * kStageWave), trg);
   } else if constexpr (G == 64 && HALF == 2) {
-    hy0 = gram_inv_mixed_u64<__bf16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line), trg);
+    hy0 = gram_inv_mixed_u64<__bf16, INV>(a, A, lane, wave, reinterpret_cast<float*>(line),
+                                          reinterpret_cast<float*>(sm.stage + wave * kStageWave), trg);
   } else {
     hy0 = cluster_pass<G, true>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
 #pragma unroll
