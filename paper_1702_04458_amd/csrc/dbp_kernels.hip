@@ -1157,7 +1157,10 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
     for (int I = 0; I < 2; ++I)
 #pragma unroll
       for (int J = 0; J < 2; ++J) {
-        re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(ps[I], ps[J], re[I][J], 0, 0, 0);          // P^T P
+        // with INVERT tile (1, 0) of G is never read before the inverse forms
+        // it as tile (0, 1)^H, so its P^T P part is not accumulated
+        if (!(INVERT && I == 1 && J == 0))
+          re[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(ps[I], ps[J], re[I][J], 0, 0, 0);        // P^T P
         im[I][J] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[I].re, xs[J].im, im[I][J], 0, 0, 0);   // M
       }
     // entries col and 32 + col of H_c^H y_c over the rows of this lane's parity
@@ -1188,15 +1191,17 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
     wave_lds_sync();
   };
   {
-    float t01[16], t10[16];
-    transposed(im[0][1], t01);
+    float t01[16] = {}, t10[16];
+    if constexpr (!INVERT) transposed(im[0][1], t01);
     transposed(im[1][0], t10);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       re[0][1][r] -= im[0][1][r] + t10[r];
       im[0][1][r] -= t10[r];
-      re[1][0][r] -= im[1][0][r] + t01[r];
-      im[1][0][r] -= t01[r];
+      if (!INVERT) {
+        re[1][0][r] -= im[1][0][r] + t01[r];
+        im[1][0][r] -= t01[r];
+      }
     }
   }
 #pragma unroll
