@@ -1516,8 +1516,9 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
 
   // Preprocessing (Alg. 1, S > U branch): B_c = H_c^H H_c + rho I, B_c^{-1}.
   c32 A[G];
-  // (the U = 16 Gram writes every entry of every lane's row: no clearing)
-  if constexpr (!(G == 16 && STAGE < 2)) {
+  // (the U = 16 Gram and the U = 32 factor staging write every entry of every
+  // lane's row: no clearing)
+  if constexpr (!(G == 16 && STAGE < 2) && !(G == 32 && STAGE >= 2)) {
 #pragma unroll
     for (int v = 0; v < G; ++v) A[v] = cz();
   }
@@ -1550,21 +1551,39 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     // loads, one problem of the wave at a time.  Both candidate entries are
     // inside the triangle for every (u, v) (indices at most NT - 1), so each
     // lane reads both and keeps one.
+    // Both problems' factor loads are issued first, and symbol 0's
+    // H_c^H y_c is formed while they are in flight.
     c32* tri = sm.stage + wave * kStageWave;
     const int csu = u * (u + 1) / 2;
+    constexpr int NQ = (NT / 2 + 63) / 64;
+    float4 tq[P][NQ];
+    bool tv[P];
 #pragma unroll
     for (int pp = 0; pp < P; ++pp) {
       const int lq = wave * P + pp;
       const int kq = a.blk * a.sc_per_block + lq / a.Cp, cq = lq % a.Cp;
-      if (kq < a.n_sc && cq < a.C) {
-        const float4* src = reinterpret_cast<const float4*>(a.fac + ((size_t)kq * a.C + cq) * NT);
+      tv[pp] = kq < a.n_sc && cq < a.C;
+      const float4* src = reinterpret_cast<const float4*>(a.fac + (tv[pp] ? ((size_t)kq * a.C + cq) * NT : 0));
+#pragma unroll
+      for (int i = 0; i < NQ; ++i)
+        tq[pp][i] = (tv[pp] && i * 64 + lane < NT / 2) ? src[i * 64 + lane] : float4{0.f, 0.f, 0.f, 0.f};
+    }
+    if constexpr (STAGE == 3)
+      hy0 = cluster_hy_direct<G, true>(a, k, c, 0, u, active);
+    else
+      hy0 = cluster_pass<G, false>(a.H, a.y, A, k, c, 0, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+      if (tv[pp]) {
         float4* dst = reinterpret_cast<float4*>(tri);
 #pragma unroll
-        for (int i = 0; i < (NT / 2 + 63) / 64; ++i)
-          if (i * 64 + lane < NT / 2) dst[i * 64 + lane] = src[i * 64 + lane];
+        for (int i = 0; i < NQ; ++i)
+          if (i * 64 + lane < NT / 2) dst[i * 64 + lane] = tq[pp][i];
       }
       wave_lds_sync();
-      if (g == pp && active) {
+      // (an inactive problem reads whatever the buffer holds; its results
+      // are never stored)
+      if (g == pp) {
 #pragma unroll
         for (int v = 0; v < G; ++v) {
           const c32 e1 = tri[v * (v + 1) / 2 + u];   // entry (u, v), v >= u
@@ -1678,10 +1697,13 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   int fl = 0;   // status bits of this lane's outputs (bit 0 non-finite, bit 1 re-slice, bit 2 ill-conditioned)
   for (int n = 0; n < a.n_sym; ++n) {
     c32 hy = hy0;
-    if constexpr (STAGE == 3)
-      hy = cluster_hy_direct<G, true>(a, k, c, n, u, active);
-    else if (n > 0 || STAGE == 2)
+    // (with U = 32 factors, symbol 0's H_c^H y_c was formed with the factor loads)
+    constexpr bool HY0 = (STAGE >= 2 && G == 32);
+    if constexpr (STAGE == 3) {
+      if (!HY0 || n > 0) hy = cluster_hy_direct<G, true>(a, k, c, n, u, active);
+    } else if (n > 0 || (STAGE == 2 && !HY0)) {
       hy = cluster_pass<G, false>(a.H, a.y, A, k, c, n, u, g, lane, wave, active, a.B, a.S, G, a.n_sym, sm);
+    }
     // y_c^reg = B_c^{-1} H_c^H y_c; z = y^reg; lambda = 0
     const c32 yreg = bmat(hy);
     c32 z = yreg, lam = cz();
