@@ -734,6 +734,16 @@ def static_channel_bench(api, frames, C, T, N0, qam, snr_db, out, steps):
     e1.record()
     torch.cuda.synchronize()
     pack_ms = e0.elapsed_time(e1) / 5
+    # the factors and the packed channel from one call (one launch at U = 32)
+    fused = (fac, packed)
+    api.factor_h16(H0, C, 1.0, out=fused)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        api.factor_h16(H0, C, 1.0, out=fused)
+    e1.record()
+    torch.cuda.synchronize()
+    factor_pack_ms = e0.elapsed_time(e1) / 5
     for i in range(3):
         api.detect_factored_h16(packed, fac, frames[i % len(frames)][1], N0, B, U, C, 1.0, T, qam=qam, out=out)
     torch.cuda.synchronize()
@@ -745,7 +755,9 @@ def static_channel_bench(api, frames, C, T, N0, qam, snr_db, out, steps):
     h16_ms = e0.elapsed_time(e1) / steps
     return {"factor_us_per_step": round(factor_ms * 1e3, 2), "detect_factored_us_per_step": round(det_ms * 1e3, 2),
             "detect_factored_vectors_per_s": round(n_sc / (det_ms * 1e-3), 1),
-            "pack_h16_us_per_step": round(pack_ms * 1e3, 2), "detect_h16_us_per_step": round(h16_ms * 1e3, 2),
+            "pack_h16_us_per_step": round(pack_ms * 1e3, 2),
+            "factor_and_pack_h16_us_per_step": round(factor_pack_ms * 1e3, 2),
+            "detect_h16_us_per_step": round(h16_ms * 1e3, 2),
             "detect_h16_vectors_per_s": round(n_sc / (h16_ms * 1e-3), 1),
             "note": "B_c^{-1} formed once per channel; each received frame runs the iterations only. h16: H resident "
                     "as complex FP16 with a power-of-two scale per (subcarrier, cluster), FP32 factors and iterations "
@@ -815,7 +827,7 @@ def served_ratios(static, fp32_batched_us):
     channel's one-time work (factorisation, packing) is spread over F frames."""
     out = {}
     for name, once, per in (("fp32_resident", static["factor_us_per_step"], static["detect_factored_us_per_step"]),
-                            ("h16_resident", static["factor_us_per_step"] + static["pack_h16_us_per_step"],
+                            ("h16_resident", static["factor_and_pack_h16_us_per_step"],
                              static["detect_h16_us_per_step"])):
         out[name] = {f"F={F}": round(fp32_batched_us / (once / F + per), 3) for F in (1, 7, 14, 70)}
         out[name]["F=inf"] = round(fp32_batched_us / per, 3)

@@ -218,7 +218,7 @@ int dbp_flag_nonfinite(const void* x, int n_sc, int per_sc, int32_t* status, voi
  * channel): H is kept in HBM as complex FP16 with one power-of-two scale per
  * (subcarrier, cluster) tile, the factors B_c^{-1} stay FP32, and the
  * iterations run in FP32.  Per subcarrier the iterations then read
- * 4 B U + 8 C U^2 bytes instead of 8 B U + 8 C U^2.
+ * 4 B U + 4 C U (U + 1) bytes instead of 8 B U + 4 C U (U + 1).
  *
  * dbp_channel_h16_bytes(n_sc, B, U, C) = 4 n_sc B U + 4 n_sc C: the size of a
  *   packed channel (0 for malformed sizes).
@@ -229,6 +229,13 @@ int dbp_flag_nonfinite(const void* x, int n_sc, int per_sc, int32_t* status, voi
  *   floats 2^e.  e = floor(log2 m) - 14 for the largest |real or imaginary
  *   part| m of the S x U tile of cluster c on subcarrier k (e >= -126; e = 0
  *   for an all-zero tile), so entries keep 11 significant bits.
+ * dbp_factor_admm_h16(H, factors, packed, ...): dbp_factor_admm and
+ *   dbp_pack_channel_h16 of the same H in one call, with the same outputs bit
+ *   for bit.  At U = 32 with the FP32 preprocessing (prec DBP_PREC_FP32 or
+ *   0) both come from one launch that reads H for the Gram and once more to
+ *   convert it (the tile maxima are taken during the Gram's pass); otherwise
+ *   the two calls run in turn on `stream`.  Arguments and errors as the two
+ *   calls.
  * dbp_detect_admm_factored_h16(packed, factors, y, ...): as
  *   dbp_detect_admm_factored, with H_c^H y_c formed from the packed channel
  *   (entries widened to FP32, FP32 accumulation).  The rounding of H to 11
@@ -240,6 +247,8 @@ int dbp_flag_nonfinite(const void* x, int n_sc, int per_sc, int32_t* status, voi
  * Arguments, requirements and errors otherwise as dbp_detect_admm_factored. */
 size_t dbp_channel_h16_bytes(int n_sc, int B, int U, int C);
 int dbp_pack_channel_h16(const void* H, void* packed, int n_sc, int B, int U, int C, void* stream);
+int dbp_factor_admm_h16(const void* H, void* factors, void* packed, int n_sc, int B, int U, int C,
+                        float rho, int prec, void* stream);
 int dbp_detect_admm_factored_h16(const void* packed, const void* factors, const void* y,
                                  void* s_hat, uint8_t* hard, int32_t* status,
                                  int n_sc, int n_sym, int B, int U, int C, int T,

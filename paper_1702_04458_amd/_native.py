@@ -34,6 +34,7 @@ SIGNATURES = {
     "dbp_channel_h16_bytes": (ctypes.c_size_t, [_i, _i, _i, _i]),
     "dbp_flag_nonfinite": (_i, [_vp, _i, _i, _vp, _vp]),
     "dbp_pack_channel_h16": (_i, [_vp, _vp, _i, _i, _i, _i, _vp]),
+    "dbp_factor_admm_h16": (_i, [_vp, _vp, _vp, _i, _i, _i, _i, _f, _i, _vp]),
     "dbp_detect_admm_factored_h16": (_i, [_vp, _vp, _vp, _vp, _u8p, _vp, _i, _i, _i, _i, _i, _i, _f, _f, _f, _f,
                                           _i, _i, _vp]),
     "dbp_detect_cg": (_i, [_vp, _vp, _vp, _u8p, _vp, _vp, ctypes.c_size_t, _i, _i, _i, _i, _i, _i, _f, _f, _i, _i,

@@ -261,6 +261,33 @@ def pack_channel_h16(H, C, *, out=None, stream=None):
     return p
 
 
+def factor_h16(H, C, rho=1.0, *, prec="fp32", factor=None, out=None, stream=None):
+    """:func:`factor` and :func:`pack_channel_h16` of the same channel in one
+    call (``dbp_factor_admm_h16``; one launch at U = 32 with the FP32
+    preprocessing).  ``out`` is an optional (factors, packed) pair.  Returns
+    (factors, packed), bit for bit those of the two separate calls."""
+    _dev(H, "H")
+    n_sc, B, U = H.shape
+    f, p = out if out is not None else (None, None)
+    if f is None:
+        f = torch.empty((n_sc, C, U * (U + 1) // 2), dtype=torch.complex64, device=H.device)
+    _dev(f, "factors")
+    if f.numel() * 8 != _native.lib().dbp_factor_bytes(n_sc, U, C):
+        raise ValueError("factors must hold n_sc * C * U (U + 1) / 2 complex64")
+    nbytes = _native.lib().dbp_channel_h16_bytes(n_sc, B, U, C)
+    if nbytes == 0 and n_sc > 0:
+        raise ValueError("malformed (n_sc, B, U, C)")
+    if p is None:
+        p = torch.empty(nbytes, dtype=torch.uint8, device=H.device)
+    if p.numel() * p.element_size() != nbytes or not p.is_contiguous() or p.device != H.device:
+        raise ValueError("packed must be a contiguous buffer of dbp_channel_h16_bytes bytes on H's device")
+    if f.device != H.device:
+        raise ValueError(f"factors must be on {H.device}")
+    _native.check(_native.lib().dbp_factor_admm_h16(H.data_ptr(), f.data_ptr(), p.data_ptr(), n_sc, B, U, C,
+                                                    float(rho), PREC[prec] | FACTOR[factor], _stream(stream)))
+    return f, p
+
+
 def detect_factored_h16(packed, factors, y, N0, B, U, C, rho=1.0, T=5, *, reg="mmse", qam=16, Es=1.0, gamma=1.0,
                         hard=True, status=False, out=None, stream=None):
     """Algorithm 1's iterations against resident factors and the packed FP16

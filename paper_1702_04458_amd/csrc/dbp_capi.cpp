@@ -502,6 +502,31 @@ int dbp_pack_channel_h16(const void* H, void* packed, int n_sc, int B, int U, in
                                                  static_cast<hipStream_t>(stream)));
 }
 
+int dbp_factor_admm_h16(const void* H, void* factors, void* packed, int n_sc, int B, int U, int C, float rho,
+                        int prec, void* stream) {
+  const char* who = "dbp_factor_admm_h16";
+  dbp::UlArgs a;
+  int S = 0;
+  int st = admm_args(who, n_sc, 1, B, U, C, 1, rho, 1.0f, 0.0f, 1.0f, DBP_REG_ZF, 4, &a, &S);
+  if (st) return st;
+  int gram_prec = 0, inv = 0;
+  st = admm_prec(who, prec, U, S, &gram_prec, &inv);
+  if (st) return st;
+  if (n_sc > 0 && (!H || !factors || !packed)) return fail(DBP_ERR_INVALID, "%s: null H, factors or packed", who);
+  if (n_sc == 0) return ok();
+  if (U != 32 || gram_prec != DBP_PREC_FP32) {
+    st = dbp_factor_admm(H, factors, n_sc, B, U, C, rho, prec, stream);
+    if (st) return st;
+    return dbp_pack_channel_h16(H, packed, n_sc, B, U, C, stream);
+  }
+  a.H = static_cast<const dbp::c32*>(H);
+  a.y = a.H;   // as in dbp_factor_admm: H stands in for the unused y
+  a.fac = static_cast<dbp::c32*>(factors);
+  a.H16 = static_cast<const uint32_t*>(packed);
+  a.hscale = reinterpret_cast<const float*>(a.H16 + (size_t)n_sc * B * U);
+  return device_status(who, dbp::launch_factor_pack_u32(a, a.nw, static_cast<hipStream_t>(stream)));
+}
+
 int dbp_detect_admm_factored_h16(const void* packed, const void* factors, const void* y, void* s_hat,
                                  uint8_t* hard, int32_t* status, int n_sc, int n_sym, int B, int U, int C, int T,
                                  float rho, float gamma, float N0, float Es, int reg, int qam, void* stream) {

@@ -117,6 +117,30 @@ __device__ __forceinline__ c32 cluster_pass(const c32* __restrict__ H, const c32
 // the low half), widened to FP32 exactly.
 typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
 
+// One complex entry scaled by 2^-e and rounded to complex FP16 (real part in
+// the low half), the packed channel's format.
+__device__ __forceinline__ uint32_t pack_pair(c32 v, int e) {
+  const h16x2 p = {(_Float16)ldexpf(v.re, -e), (_Float16)ldexpf(v.im, -e)};
+  return __builtin_bit_cast(uint32_t, p);
+}
+
+// The packed channel's exponent of a tile whose largest component is m: its
+// largest component lands in [2^14, 2^15).
+__device__ __forceinline__ int pack_exponent(float m) {
+  return (m > 0.f && m <= 3.4028235e38f) ? min(max(ilogbf(m) - 14, -126), 113) : 0;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __device__ __forceinline__ c32 widen_h16(uint32_t w) {
   const h16x2 v = __builtin_bit_cast(h16x2, w);
   return c32{(float)v.x, (float)v.y};
@@ -310,7 +334,10 @@ __device__ __forceinline__ float pair_sum(float v) {
 // H_c^H y_c for symbol 0.  LAZY (with INVERT): A receives row u of the swept
 // matrix S with its scales left in place, and *pvl the reciprocal pivot pv_u
 // of this lane's row, so that B^{-1} q = -pv_u sum_v S_uv (pv_v q_v).
-template <bool INVERT, bool LAZY = false, bool FLAT = false>
+// PACK (factor-only kernel): when a.H16 is set, H is also written as the
+// packed FP16 channel (a.H16, a.hscale; the format of pack_h16, bit for bit):
+// the tile maxima are taken during the Gram's pass and one more pass converts.
+template <bool INVERT, bool LAZY = false, bool FLAT = false, bool PACK = false>
 __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int lane, int wave, float* line,
                                              float* stage, float* pvl = nullptr) {
   const int h = lane >> 5, col = lane & 31;
@@ -352,12 +379,16 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
       }
     }
   };
+  const bool pk = PACK && a.H16 != nullptr;   // uniform
+  float mx[2] = {0.f, 0.f};
   auto accumulate = [&](const c32 (&hd)[2][CH], const c32 (&yd)[2][CH]) {
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         const c32 x = hd[p][q];
+        if constexpr (PACK)
+          if (pk) mx[p] = fmaxf(mx[p], fmaxf(fabsf(x.re), fabsf(x.im)));
         const float pr = x.re + x.im;
         re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(pr, pr, re[p], 0, 0, 0);       // P^T P, P = Hr + Hi
         im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x.re, x.im, im[p], 0, 0, 0);   // M = Hr^T Hi
@@ -391,6 +422,39 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
       if (s0 + 2 * CH >= a.S) break;
       if (s0 + 4 * CH < a.S) fetch(s0 + 4 * CH, hv, yv);
       accumulate(hn, yn);
+    }
+  }
+  if constexpr (PACK) {
+    if (pk) {
+      // rows of this lane's parity, both problems, four rows in flight
+      uint32_t* h16 = const_cast<uint32_t*>(a.H16);
+      int e[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) e[p] = pack_exponent(wave_max(mx[p]));
+      for (int s0 = h; s0 < a.S; s0 += 8) {
+        c32 v[2][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int s = s0 + 2 * t;
+#pragma unroll
+          for (int p = 0; p < 2; ++p) v[p][t] = ld_or_zero(Hp[p] + (size_t)min(s, a.S - 1) * 32 + col, true);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int s = s0 + 2 * t;
+#pragma unroll
+          for (int p = 0; p < 2; ++p)
+            if (act[p] && s < a.S) h16[(Hp[p] - a.H) + (size_t)s * 32 + col] = pack_pair(v[p][t], e[p]);
+        }
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const int lp = wave * 2 + p;
+          const int k = a.blk * a.sc_per_block + lp / a.Cp, c = lp % a.Cp;
+          if (act[p]) const_cast<float*>(a.hscale)[(size_t)k * a.C + c] = ldexpf(1.f, e[p]);
+        }
+      }
     }
   }
   // re holds rho I + P^T P and im holds M = Hr^T Hi; since P^T P = Hr^T Hr
@@ -471,16 +535,6 @@ struct HalfMma<__bf16> {
   }
 };
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Normalisation of the mixed-mode Gram before the FP16 inverse.  H_c is scaled
 // by 2^ex so that its largest entry lies in [2^13, 2^14); the Gram of i.i.d.
@@ -1466,7 +1520,9 @@ __device__ __forceinline__ c32 consensus_w(c32 wc, int buf, int ls, int u, int g
 // 2 split-FP16 matrix-core inverse.
 // STAGE: 0 preprocessing and iterations; 1 preprocessing only, B_c^{-1} is
 // written to a.fac (a static channel factored once); 2 iterations only, B_c^{-1}
-// read from a.fac (every symbol's H_c^H y_c by the VALU pass).
+// read from a.fac (every symbol's H_c^H y_c by the VALU pass); 3 as 2 with H
+// read from the packed FP16 channel; 4 (U = 32, FP32) as 1, and H also
+// written as the packed FP16 channel in the same launch.
 template <int G, int HALF, int INV, int STAGE>
 __device__ __forceinline__ void admm_ul_body(const UlArgs& a);
 
@@ -1500,6 +1556,8 @@ __global__ void __launch_bounds__(512) admm_ul_f32_batch(UlBatch b) {
 template <int G, int HALF, int INV, int STAGE>
 __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   constexpr int P = 64 / G;
+  constexpr bool RESIDENT = (STAGE == 2 || STAGE == 3);   // iterations against stored factors
+  constexpr bool FACTOR = (STAGE == 1 || STAGE == 4);     // preprocessing only
   extern __shared__ float4 smem_raw[];
   const int nw = blockDim.x >> 6;
   Smem sm = carve(reinterpret_cast<c32*>(smem_raw), nw);
@@ -1518,7 +1576,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   c32 A[G];
   // (the U = 16 Gram and the U = 32 factor staging write every entry of every
   // lane's row: no clearing)
-  if constexpr (!(G == 16 && STAGE < 2) && !(G == 32 && STAGE >= 2)) {
+  if constexpr (!(G == 16 && !RESIDENT) && !(G == 32 && RESIDENT)) {
 #pragma unroll
     for (int v = 0; v < G; ++v) A[v] = cz();
   }
@@ -1544,7 +1602,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   // (v < u): one load per entry, coalesced over the lanes of the first kind.
   constexpr int NT = G * (G + 1) / 2;
   const size_t fo = ((size_t)k * a.C + c) * NT;
-  if constexpr (STAGE >= 2 && G == 32) {
+  if constexpr (RESIDENT && G == 32) {
     // The lanes of the other kind would read 32 different cache lines per
     // load, so each problem's triangle (NT = 528 values, the size of the
     // wave's stage buffer) first goes through LDS with 16-byte coalesced
@@ -1593,7 +1651,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       }
       wave_lds_sync();
     }
-  } else if constexpr (STAGE >= 2) {
+  } else if constexpr (RESIDENT) {
     if (active) {
       const int csu = u * (u + 1) / 2;
 #pragma unroll
@@ -1604,7 +1662,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       }
     }
   } else if constexpr (G == 32 && HALF == 0) {
-    hy0 = gram_mfma_u32<true, LAZY, STAGE == 1>(a, A, lane, wave, reinterpret_cast<float*>(line),
+    hy0 = gram_mfma_u32<true, LAZY, FACTOR, STAGE == 4>(a, A, lane, wave, reinterpret_cast<float*>(line),
                                     reinterpret_cast<float*>(sm.stage + wave * kStageWave), &pvl);
   } else if constexpr (G == 32 && HALF == 1) {
     hy0 = gram_inv_mixed_u32<_Float16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageWave),
@@ -1634,7 +1692,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       if (v == u) A[v].re += a.rho;
     gj_invert<G>(A, u, line, gbase);
   }
-  if constexpr (STAGE == 1 && G == 32) {
+  if constexpr (FACTOR && G == 32) {
     // Through the wave's stage buffer, one problem at a time, then 16-byte
     // coalesced stores.  Lane u writes entry v of its row to v (v + 1) / 2 + u
     // for every v in increasing order: for v >= u that is entry (u, v) of the
@@ -1661,7 +1719,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       wave_lds_sync();
     }
     return;
-  } else if constexpr (STAGE == 1) {
+  } else if constexpr (FACTOR) {
     if (active) {
 #pragma unroll
       for (int v = 0; v < G; ++v)
@@ -1698,7 +1756,7 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   for (int n = 0; n < a.n_sym; ++n) {
     c32 hy = hy0;
     // (with U = 32 factors, symbol 0's H_c^H y_c was formed with the factor loads)
-    constexpr bool HY0 = (STAGE >= 2 && G == 32);
+    constexpr bool HY0 = (RESIDENT && G == 32);
     if constexpr (STAGE == 3) {
       if (!HY0 || n > 0) hy = cluster_hy_direct<G, true>(a, k, c, n, u, active);
     } else if (n > 0 || (STAGE == 2 && !HY0)) {
@@ -2183,10 +2241,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) a
 // ---------------------------------------------------------------------------
 constexpr int kPackRegs = 8;
 
-__device__ __forceinline__ uint32_t pack_pair(c32 v, int e) {
-  const h16x2 p = {(_Float16)ldexpf(v.re, -e), (_Float16)ldexpf(v.im, -e)};
-  return __builtin_bit_cast(uint32_t, p);
-}
 
 __global__ void __launch_bounds__(256) pack_h16(const c32* __restrict__ H, uint32_t* __restrict__ H16,
                                                 float* __restrict__ hscale, int B, int U, int C) {
@@ -2216,8 +2270,7 @@ __global__ void __launch_bounds__(256) pack_h16(const c32* __restrict__ H, uint3
   if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
   __syncthreads();
   m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
-  int e = 0;
-  if (m > 0.f && m <= 3.4028235e38f) e = min(max(ilogbf(m) - 14, -126), 113);
+  const int e = pack_exponent(m);
   if (cached) {
 #pragma unroll
     for (int j = 0; j < kPackRegs; ++j) {
@@ -2258,6 +2311,10 @@ static hipError_t launch(K kernel, const Args& a, int nw, hipStream_t st) {
 template <int G, int HALF, int INV>
 static hipError_t launch_stage(const UlArgs& a, int nw, hipStream_t st, int stage) {
   return stage == 1 ? launch(admm_ul_f32<G, HALF, INV, 1>, a, nw, st) : launch(admm_ul_f32<G, HALF, INV, 0>, a, nw, st);
+}
+
+hipError_t launch_factor_pack_u32(const UlArgs& a, int nw, hipStream_t st) {
+  return launch(admm_ul_f32<32, 0, 0, 4>, a, nw, st);
 }
 
 hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st, int stage) {

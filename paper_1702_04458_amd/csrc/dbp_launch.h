@@ -104,6 +104,9 @@ hipError_t launch_admm_ul_f32_batch(const UlBatch& b, int U, int nw, int grid, h
 hipError_t launch_admm_ul_fix64_batch(const FixBatch& b, int U, int n_slots, hipStream_t st);
 // stage: 0 detect, 1 only factor (write B_c^{-1} to a.fac)
 hipError_t launch_admm_ul_f32(const UlArgs& a, int U, int nw, hipStream_t st, int stage = 0);
+// U = 32, FP32: the factors and, in the same launch, H as the packed FP16
+// channel (a.H16 / a.hscale, written)
+hipError_t launch_factor_pack_u32(const UlArgs& a, int nw, hipStream_t st);
 // inv: 0 FP32 matrix-core inverse, 1 FP64 VALU inverse (U = 32), 2 split-FP16 matrix-core inverse
 hipError_t launch_admm_ul_mixed(const UlArgs& a, int U, int half, int inv, int nw, hipStream_t st, int stage = 0);
 // detection against resident factors a.fac (no Gram, no inverse)

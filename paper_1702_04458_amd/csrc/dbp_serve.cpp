@@ -512,8 +512,9 @@ int dbp_channel_load(dbp_server* s, const void* H, int n_sc, int B, int U, int C
       hipMemcpyAsync(d32, H, bytes_H32, kind, s->load_stream) != hipSuccess ||
       hipStreamSynchronize(s->load_stream) != hipSuccess)
     rc = DBP_ERR_DEVICE;
-  if (rc == DBP_OK) rc = dbp_factor_admm(d32, dF, n_sc, B, U, C, rho, prec, s->load_stream);
-  if (rc == DBP_OK && ch.h16) rc = dbp_pack_channel_h16(d32, d, n_sc, B, U, C, s->load_stream);
+  if (rc == DBP_OK)
+    rc = ch.h16 ? dbp_factor_admm_h16(d32, dF, d, n_sc, B, U, C, rho, prec, s->load_stream)
+                : dbp_factor_admm(d32, dF, n_sc, B, U, C, rho, prec, s->load_stream);
   if (rc == DBP_OK && hipEventRecord(ch.ready, s->load_stream) != hipSuccess) rc = DBP_ERR_DEVICE;
   // the temporary block is returned only once the load stream is past it
   if (ch.h16 && hipStreamSynchronize(s->load_stream) != hipSuccess && rc == DBP_OK) rc = DBP_ERR_DEVICE;

@@ -141,6 +141,11 @@ def test_factor_entry_points_reject():
     assert L.dbp_factor_admm(1, 1, 4, 256, 32, 8, 1.0, 0x20, None) == 2       # FP64 inverse needs a mixed Gram
     assert L.dbp_factor_admm(1, 1, 4, 512, 64, 8, 1.0, 0x21, None) == 2       # no stored FP64 inverse at U = 64
     assert L.dbp_factor_admm(None, None, 0, 256, 32, 8, 1.0, 0, None) == 0    # empty is a no-op
+    # dbp_factor_admm_h16(H, factors, packed, n_sc, B, U, C, rho, prec, stream)
+    assert L.dbp_factor_admm_h16(1, 1, None, 4, 256, 32, 8, 1.0, 0, None) == 1   # null packed
+    assert L.dbp_factor_admm_h16(1, 1, 1, 4, 256, 32, 8, 0.0, 0, None) == 1      # rho <= 0
+    assert L.dbp_factor_admm_h16(1, 1, 1, 4, 256, 32, 16, 1.0, 0, None) == 2     # S = 16 < U
+    assert L.dbp_factor_admm_h16(None, None, None, 0, 256, 32, 8, 1.0, 0, None) == 0
     # dbp_detect_admm_factored(H, F, y, s, hard, status, ws, ws_bytes, n_sc, n_sym, B, U, C, T, rho, gamma, N0,
     #                          Es, reg, qam, stream)
     ok = [1, 1, 1, 1, None, None, None, 0, 4, 1, 256, 32, 8, 5, 1.0, 1.0, 0.1, 1.0, 0, 64, None]

@@ -149,6 +149,41 @@ def test_pack_h16_format(B, U, C, n_sc):
             assert np.array_equal(got.imag, want_im.astype(np.float64)), (k, c)
 
 
+@pytest.mark.parametrize("B,U,C,n_sc", [(256, 32, 8, 12), (72, 32, 2, 5), (90, 32, 2, 4), (128, 16, 8, 6),
+                                        (512, 64, 8, 3)])
+def test_factor_h16_one_call(B, U, C, n_sc):
+    """dbp_factor_admm_h16 gives the factors of dbp_factor_admm and the packed
+    channel of dbp_pack_channel_h16 bit for bit (one launch at U = 32, the two
+    calls in turn otherwise)."""
+    say(f"[gpu] factor + pack in one call B={B} U={U} C={C} n_sc={n_sc}")
+    fr = inputs.uplink_frame(inputs.frame_seed(25, B + U, C), n_sc, B, U, 16, 10.0)
+    H = to_dev(fr.H)
+    f1 = api.factor(H, C, 0.8)
+    p1 = api.pack_channel_h16(H, C)
+    f2, p2 = api.factor_h16(H, C, 0.8)
+    torch.cuda.synchronize()
+    assert np.array_equal(f1.cpu().numpy().view(np.uint32), f2.cpu().numpy().view(np.uint32))
+    assert np.array_equal(p1.cpu().numpy(), p2.cpu().numpy())
+
+
+def test_factor_h16_one_call_extreme_tiles():
+    """The packed channel of the one-launch form at tiles spanning 1e-30 ..
+    1e20 and an all-zero tile equals dbp_pack_channel_h16's, byte for byte."""
+    say("[gpu] factor + pack in one call, extreme tiles")
+    B, U, C, n_sc = 256, 32, 8, 6
+    S = B // C
+    fr = inputs.uplink_frame(inputs.frame_seed(26, 0, 10), n_sc, B, U, 16, 10.0)
+    Hn = fr.H.astype(np.complex64)
+    Hn[2, S:2 * S] *= np.float32(1e-30)
+    Hn[3, 0:S] = 0
+    Hn[4, 2 * S:3 * S] *= np.float32(1e20)
+    H = to_dev(Hn)
+    p1 = api.pack_channel_h16(H, C)
+    _, p2 = api.factor_h16(H, C, 1.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(p1.cpu().numpy(), p2.cpu().numpy())
+
+
 @pytest.mark.parametrize("B,U,C,n_sc,qam,snr", SHAPES)
 def test_factored_h16(B, U, C, n_sc, qam, snr):
     """Low-precision bar (frame error <= 1e-3 against the FP64 oracle) and the
