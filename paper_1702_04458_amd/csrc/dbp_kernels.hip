@@ -851,8 +851,12 @@ __device__ __forceinline__ c32 gram_inv_mixed_u32(const UlArgs& a, c32 (&A)[32],
 // of problem p.  Returns row u of H_c^H y_c for symbol 0.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// RHO: the real part starts from rho I (the diagonal entry (col, col) sits in
+// register col - 4 q of lane group q = col / 4), so A leaves as G + rho I.
+template <bool RHO = false>
 __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int lane, int wave, c32* stage) {
   const int q = lane >> 4, col = lane & 15;
+  const int dr = RHO ? col - 4 * q : -1;
   f32x4 re[4], im[4];
   c32 hyp[4];
   const c32* Hp[4];
@@ -866,7 +870,8 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
     act[p] = (k < a.n_sc) && (c < a.C);
     Hp[p] = act[p] ? a.H + (size_t)k * a.B * 16 + (size_t)c * a.S * 16 : a.H;
     yp[p] = act[p] ? a.y + (size_t)k * a.n_sym * a.B + (size_t)c * a.S : a.y;
-    re[p] = f32x4{};
+    #pragma unroll
+    for (int r = 0; r < 4; ++r) re[p][r] = (r == dr) ? a.rho : 0.f;
     im[p] = f32x4{};
     hyp[p] = cz();
   }
@@ -1582,10 +1587,10 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   }
   c32 hy0 = cz();
   float trg = 0.f;   // tr(G_c) (mixed modes)
-  // U = 32, FP32, iterations in the same launch: the inverse keeps its lazy
+  // U = 16 and 32, FP32, iterations in the same launch: the inverse keeps its lazy
   // scales (B^{-1}_uv = -S_uv pv_u pv_v), which every product applies to its
-  // operand and result instead of to the 32 x 32 entries.
-  constexpr bool LAZY = (G == 32 && HALF == 0 && STAGE == 0);
+  // operand and result instead of to the U x U entries.
+  constexpr bool LAZY = ((G == 32 || G == 16) && HALF == 0 && STAGE == 0);
   float pvl = 1.f;
   auto bmat = [&](c32 q) -> c32 {
     if constexpr (LAZY) {
@@ -1671,11 +1676,11 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     hy0 = gram_inv_mixed_u32<__bf16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageWave),
                                           trg);
   } else if constexpr (G == 16) {
-    hy0 = gram_mfma_u16(a, A, lane, wave, sm.stage + wave * kStageWave);
-#pragma unroll
-    for (int v = 0; v < G; ++v)
-      if (v == u) A[v].re += a.rho;
-    gj_invert<G>(A, u, line, gbase);
+    hy0 = gram_mfma_u16<true>(a, A, lane, wave, sm.stage + wave * kStageWave);
+    if constexpr (LAZY)
+      gj_invert_sym<16, true>(A, u, line, gbase, &pvl);
+    else
+      gj_invert<G>(A, u, line, gbase);
   } else if constexpr (G == 64 && HALF == 0) {
     hy0 = gram_mfma_u64<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
                               reinterpret_cast<float*>(sm.stage + wave * kStageWave));
