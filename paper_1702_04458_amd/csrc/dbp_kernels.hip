@@ -230,8 +230,10 @@ __device__ __forceinline__ void gj_unscale_u32(f32x16& re, f32x16& im, float pvv
 
 // ADD_RHO: add rho to the diagonal first (false: the caller's accumulators
 // already hold G + rho I).  LAZY: leave the swept matrix S with its scales
-// (B^{-1}_ij = -S_ij pv_i pv_j) and return in pvs[p] the reciprocal pivot
-// pv of this lane's column for problem p.
+// (B^{-1}_ij = -S_ij pv_i pv_j) and return in pvs[0] the reciprocal pivot of
+// this lane's own row (problem l / 32, row l % 32); the diagonal is also not
+// negated at its pivot, so that S_ii ends 2 d_i above the negated form's
+// (no later update reads it) and B^{-1}_ii = -S_ii pv_i^2 + 2 pv_i.
 template <bool ADD_RHO = true, bool LAZY = false>
 __device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)[2], int lane, float rho, float* line,
                                                    float* pvs = nullptr) {
@@ -270,18 +272,24 @@ __device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)
       // Re: -pv (Re_i Re_j + Im_i Im_j), Im: -pv (Re_i Im_j - Im_i Re_j)
       const float Are = -pv * first;
       const float Aim = h ? -Are : Are;
-      re[p][rr] = dg ? -sr : sr;
+      if constexpr (!LAZY) re[p][rr] = dg ? -sr : sr;
       re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are, first, re[p], 0, 0, 0);
       im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim, second, im[p], 0, 0, 0);
-      pvv[p] = isk ? pv : pvv[p];
-      // select in place (otherwise the compiler keeps every pivot's pv live
-      // until the end)
-      asm volatile("" : "+v"(pvv[p]));
+      if constexpr (LAZY) {
+        // the pivot reciprocals go to LDS (no vector instruction per pivot)
+        if (lane == 0) line[32 * p + k] = pv;
+      } else {
+        pvv[p] = isk ? pv : pvv[p];
+        // select in place (otherwise the compiler keeps every pivot's pv live
+        // until the end)
+        asm volatile("" : "+v"(pvv[p]));
+      }
     }
   }
   if constexpr (LAZY) {
-    pvs[0] = pvv[0];
-    pvs[1] = pvv[1];
+    wave_lds_sync();
+    pvs[0] = line[32 * h + col];   // pv of this lane's own row (problem h, row col)
+    wave_lds_sync();
     __builtin_amdgcn_sched_barrier(0);
   } else {
 #pragma unroll
@@ -481,9 +489,7 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
     wave_lds_sync();
   }
   if constexpr (INVERT && LAZY) {
-    float pvs[2];
-    gj_invert_mfma_u32<false, true>(re, im, lane, a.rho, line, pvs);
-    *pvl = h ? pvs[1] : pvs[0];
+    gj_invert_mfma_u32<false, true>(re, im, lane, a.rho, line, pvl);
   } else if constexpr (INVERT) {
     gj_invert_mfma_u32<false>(re, im, lane, a.rho, line);
   }
@@ -1593,7 +1599,12 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   constexpr bool LAZY = ((G == 32 || G == 16) && HALF == 0 && STAGE == 0);
   float pvl = 1.f;
   auto bmat = [&](c32 q) -> c32 {
-    if constexpr (LAZY) {
+    if constexpr (LAZY && G == 32) {
+      // (the U = 32 sweep leaves the diagonal un-negated: + 2 pv_u q_u)
+      const c32 r = group_matvec<G>(A, cscale(q, pvl), u, line, gbase);
+      const float tp = 2.f * pvl;
+      return c32{fmaf(tp, q.re, -pvl * r.re), fmaf(tp, q.im, -pvl * r.im)};
+    } else if constexpr (LAZY) {
       const c32 r = group_matvec<G>(A, cscale(q, pvl), u, line, gbase);
       return cscale(r, -pvl);
     } else {
