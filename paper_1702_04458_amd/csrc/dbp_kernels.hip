@@ -262,16 +262,18 @@ __device__ __forceinline__ void gj_invert_mfma_u32(f32x16 (&re)[2], f32x16 (&im)
       // alone by the update): lanes < 32 get (first, second) = (Re, Im),
       // lanes >= 32 (Im, Re).  A lane reads the lane of its own column in
       // either half, so zeroing at the source zeroes column k everywhere.
-      const float srm = isk ? 0.f : sr, sim = isk ? 0.f : si;
+      // The imaginary update takes the same A operand and (Im, -Re) as B, so
+      // the real part enters that swap negated.
+      const float srm = isk ? 0.f : sr, sim = isk ? 0.f : si, srn = isk ? 0.f : -sr;
       const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(srm), __float_as_uint(sim), false, false);
-      const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(sim), __float_as_uint(srm), false, false);
+      const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(sim), __float_as_uint(srn), false, false);
       const float first = __uint_as_float(fs[hk]);
       const float second = __uint_as_float(sf[hk]);
       const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sr), k + 32 * hk));
       const float pv = __builtin_amdgcn_rcpf(d);
       // Re: -pv (Re_i Re_j + Im_i Im_j), Im: -pv (Re_i Im_j - Im_i Re_j)
       const float Are = -pv * first;
-      const float Aim = h ? -Are : Are;
+      const float Aim = Are;
       if constexpr (!LAZY) re[p][rr] = dg ? -sr : sr;
       re[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Are, first, re[p], 0, 0, 0);
       im[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(Aim, second, im[p], 0, 0, 0);
@@ -1130,9 +1132,10 @@ __device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&
     for (int J = 0; J < 2; ++J) {
       const float sr = re[Ik][J][rr], si = im[Ik][J][rr];
       const bool isk = (32 * J + col == kk);
-      const float srm = isk ? 0.f : sr, sim = isk ? 0.f : si;
+      // (Im, -Re) as the imaginary update's B operand, as at U = 32
+      const float srm = isk ? 0.f : sr, sim = isk ? 0.f : si, srn = isk ? 0.f : -sr;
       const auto fs = __builtin_amdgcn_permlane32_swap(__float_as_uint(srm), __float_as_uint(sim), false, false);
-      const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(sim), __float_as_uint(srm), false, false);
+      const auto sf = __builtin_amdgcn_permlane32_swap(__float_as_uint(sim), __float_as_uint(srn), false, false);
       first[J] = __uint_as_float(fs[hk]);
       second[J] = __uint_as_float(sf[hk]);
       re[Ik][J][rr] = (isk && h == hk) ? -sr : sr;
@@ -1141,7 +1144,7 @@ __device__ __forceinline__ void gj_invert_mfma_u64(f32x16 (&re)[2][2], f32x16 (&
 #pragma unroll
     for (int J = 0; J < 2; ++J) {
       Are[J] = -pv * first[J];
-      Aim[J] = h ? -Are[J] : Are[J];
+      Aim[J] = Are[J];
     }
 #pragma unroll
     for (int I = 0; I < 2; ++I)
