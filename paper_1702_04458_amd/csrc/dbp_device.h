@@ -161,10 +161,8 @@ __device__ __forceinline__ void gj_invert_rot(c32 (&A)[G], int u, c32* line, int
 // S[u][j] -= S[u][k] conj(S[j][k]) / d; at the end
 // B^{-1}[u][j] = -S[u][j] / (d_u d_j).  Lanes u >= N (a group wider than the
 // matrix) take no part.
-// LAZY: the scales are left in place and *pvl receives this lane's pivot
-// reciprocal (B^{-1}[u][j] = -S[u][j] pv_u pv_j).
-template <int N, bool LAZY = false>
-__device__ __forceinline__ void gj_invert_sym(c32 (&A)[N], int u, c32* line, int gbase, float* pvl = nullptr) {
+template <int N>
+__device__ __forceinline__ void gj_invert_sym(c32 (&A)[N], int u, c32* line, int gbase) {
   float pvv = 0.f;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -200,10 +198,6 @@ __device__ __forceinline__ void gj_invert_sym(c32 (&A)[N], int u, c32* line, int
     // columns of many steps live at once.
 #pragma unroll
     for (int j = 0; j < N; ++j) asm volatile("" : "+v"(A[j].re), "+v"(A[j].im));
-  }
-  if constexpr (LAZY) {
-    *pvl = pvv;
-    return;
   }
   if (u < N) line[gbase + u] = c32{pvv, 0.f};
   wave_lds_sync();

@@ -859,10 +859,107 @@ __device__ __forceinline__ c32 gram_inv_mixed_u32(const UlArgs& a, c32 (&A)[32],
 // of problem p.  Returns row u of H_c^H y_c for symbol 0.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Regularised inverses of the four problems of a U = 16 wave on the matrix
+// cores: v_mfma_f32_16x16x1f32 runs four independent 16 x 16 x 1 products, one
+// per problem (block p of the A and B operands is lane group p, block p of the
+// result is registers 4p .. 4p+3).  On entry re[p] holds P^T P + rho I and
+// im[p] holds M = Hr^T Hi of problem p in the accumulator layout (lane
+// 16 q + col, register r: row 4 q + r, column col), so that B = H^H H + rho I
+// has Re B = P^T P - M - M^T and Im B = M - M^T (M^T through LDS).
+//
+// The sweep is the Hermitian Gauss-Jordan elimination with lazy scales: for
+// each pivot k, S_ij -= conj(w_i) w_j / S_kk for i, j != k, where w is row k;
+// row and column k are left alone and the diagonal is not negated, so that
+// B^{-1} = 2 D - D S D with D = diag(pv) the pivot reciprocals.  One pivot is
+// four rank-1 matrix-core updates of all four problems (real and imaginary
+// parts), against 60 vector FMAs per lane for the same work.  Row k of every
+// problem sits in lane group k / 4, register 4 p + k % 4: it reaches problem
+// p's lane group through the wave's stage buffer.  Entry k of w is zeroed in
+// both operands, which leaves row and column k alone.
+//
+// On return lane 16 p + u holds row u of problem p's S in A (S is Hermitian:
+// read as column u, conjugated) and its pivot reciprocal pv_u in *pvl.
+__device__ __forceinline__ void gj_invert_mfma_u16(f32x4 (&re)[4], f32x4 (&im)[4], c32 (&A)[16], int lane,
+                                                   c32* stage, float* pvl) {
+  const int q = lane >> 4, col = lane & 15;
+  float* pm = reinterpret_cast<float*>(stage);   // M of the four problems, row pitch 17
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pm[(16 * p + 4 * q + r) * 17 + col] = im[p][r];
+  wave_lds_sync();
+  f32x16 sr, si;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float mt = pm[(16 * p + col) * 17 + 4 * q + r];
+      sr[4 * p + r] = re[p][r] - im[p][r] - mt;
+      si[4 * p + r] = im[p][r] - mt;
+    }
+  wave_lds_sync();
+  // row k through two float planes [lane group][problem][column] (the real
+  // and imaginary registers need not be paired for the stores)
+  float* wre = reinterpret_cast<float*>(stage);
+  float* wim = wre + 256;
+  float pvm = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int g = k >> 2, rr = k & 3;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      wre[(4 * q + p) * 16 + col] = sr[4 * p + rr];
+      wim[(4 * q + p) * 16 + col] = si[4 * p + rr];
+    }
+    wave_lds_sync();
+    const c32 w = c32{wre[(4 * g + q) * 16 + col], wim[(4 * g + q) * 16 + col]};   // row k of problem q
+    const float d = wre[(4 * g + q) * 16 + k];                                     // its pivot
+    wave_lds_sync();
+    const float pv = __builtin_amdgcn_rcpf(d);
+    const bool isk = (col == k);
+    const float wr = isk ? 0.f : w.re, wi = isk ? 0.f : w.im, nwr = isk ? 0.f : -w.re;
+    // Re: -pv (wr_i wr_j + wi_i wi_j), Im: -pv (wr_i wi_j - wi_i wr_j)
+    const float ar = -pv * wr, ai = -pv * wi;
+    sr = __builtin_amdgcn_mfma_f32_16x16x1f32(ar, wr, sr, 0, 0, 0);
+    sr = __builtin_amdgcn_mfma_f32_16x16x1f32(ai, wi, sr, 0, 0, 0);
+    si = __builtin_amdgcn_mfma_f32_16x16x1f32(ar, wi, si, 0, 0, 0);
+    si = __builtin_amdgcn_mfma_f32_16x16x1f32(ai, nwr, si, 0, 0, 0);
+    // lane 16 p + u keeps pivot u of problem p (selected in place: otherwise
+    // the compiler keeps every pivot's pv live until the end)
+    pvm = isk ? pv : pvm;
+    asm volatile("" : "+v"(pvm));
+  }
+  *pvl = pvm;
+  // to rows, two problems per pass (two float planes of row pitch 17)
+  float* pre = reinterpret_cast<float*>(stage);
+  float* pim = pre + 32 * 17;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * q + r;
+        pre[(16 * pp + i) * 17 + col] = sr[4 * (2 * half + pp) + r];
+        pim[(16 * pp + i) * 17 + col] = si[4 * (2 * half + pp) + r];
+      }
+    wave_lds_sync();
+    if ((q >> 1) == half) {
+      const int pp = q & 1;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) A[v] = c32{pre[(16 * pp + v) * 17 + col], -pim[(16 * pp + v) * 17 + col]};
+    }
+    wave_lds_sync();
+  }
+}
+
 // RHO: the real part starts from rho I (the diagonal entry (col, col) sits in
 // register col - 4 q of lane group q = col / 4), so A leaves as G + rho I.
-template <bool RHO = false>
-__device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int lane, int wave, c32* stage) {
+// INV (with RHO): A leaves as the lazily scaled inverse S of G + rho I
+// (gj_invert_mfma_u16) and *pvl as the pivot reciprocal of this lane's row.
+template <bool RHO = false, bool INV = false>
+__device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int lane, int wave, c32* stage,
+                                             float* pvl = nullptr) {
   const int q = lane >> 4, col = lane & 15;
   const int dr = RHO ? col - 4 * q : -1;
   f32x4 re[4], im[4];
@@ -930,27 +1027,31 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
   // Im G[v][col] = M[v][col] - M[col][v].
   float* pre = reinterpret_cast<float*>(stage);
   float* pim = pre + 32 * 17;
+  if constexpr (INV) {
+    gj_invert_mfma_u16(re, im, A, lane, stage, pvl);
+  } else {
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
+    for (int half = 0; half < 2; ++half) {
 #pragma unroll
-    for (int pp = 0; pp < 2; ++pp)
+      for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 4 * q + r;
-        pre[(16 * pp + i) * 17 + col] = re[2 * half + pp][r];
-        pim[(16 * pp + i) * 17 + col] = im[2 * half + pp][r];
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * q + r;
+          pre[(16 * pp + i) * 17 + col] = re[2 * half + pp][r];
+          pim[(16 * pp + i) * 17 + col] = im[2 * half + pp][r];
+        }
+      wave_lds_sync();
+      if ((q >> 1) == half) {
+        const int pp = q & 1;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const float gr = pre[(16 * pp + v) * 17 + col], gi = pim[(16 * pp + v) * 17 + col];
+          const float mt = pim[(16 * pp + col) * 17 + v];
+          A[v] = c32{gr - gi - mt, mt - gi};
+        }
       }
-    wave_lds_sync();
-    if ((q >> 1) == half) {
-      const int pp = q & 1;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const float gr = pre[(16 * pp + v) * 17 + col], gi = pim[(16 * pp + v) * 17 + col];
-        const float mt = pim[(16 * pp + col) * 17 + v];
-        A[v] = c32{gr - gi - mt, mt - gi};
-      }
+      wave_lds_sync();
     }
-    wave_lds_sync();
   }
   // H_c^H y_c: sum the four row classes (lanes col, col+16, col+32, col+48)
   // and hand problem p's sum to row p: v_permlane16_swap of problems (0, 1)
@@ -1597,19 +1698,17 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
   c32 hy0 = cz();
   float trg = 0.f;   // tr(G_c) (mixed modes)
   // U = 16 and 32, FP32, iterations in the same launch: the inverse keeps its lazy
-  // scales (B^{-1}_uv = -S_uv pv_u pv_v), which every product applies to its
-  // operand and result instead of to the U x U entries.
+  // scales (B^{-1} = 2 D - D S D, D = diag(pv): off the diagonal
+  // -S_uv pv_u pv_v), which every product applies to its operand and result
+  // instead of to the U x U entries.
   constexpr bool LAZY = ((G == 32 || G == 16) && HALF == 0 && STAGE == 0);
   float pvl = 1.f;
   auto bmat = [&](c32 q) -> c32 {
-    if constexpr (LAZY && G == 32) {
-      // (the U = 32 sweep leaves the diagonal un-negated: + 2 pv_u q_u)
+    if constexpr (LAZY) {
+      // (the sweeps leave the diagonal un-negated: + 2 pv_u q_u)
       const c32 r = group_matvec<G>(A, cscale(q, pvl), u, line, gbase);
       const float tp = 2.f * pvl;
       return c32{fmaf(tp, q.re, -pvl * r.re), fmaf(tp, q.im, -pvl * r.im)};
-    } else if constexpr (LAZY) {
-      const c32 r = group_matvec<G>(A, cscale(q, pvl), u, line, gbase);
-      return cscale(r, -pvl);
     } else {
       return group_matvec<G>(A, q, u, line, gbase);
     }
@@ -1690,11 +1789,12 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
     hy0 = gram_inv_mixed_u32<__bf16, INV>(a, A, lane, wave, reinterpret_cast<c64*>(sm.stage + wave * kStageWave),
                                           trg);
   } else if constexpr (G == 16) {
-    hy0 = gram_mfma_u16<true>(a, A, lane, wave, sm.stage + wave * kStageWave);
-    if constexpr (LAZY)
-      gj_invert_sym<16, true>(A, u, line, gbase, &pvl);
-    else
+    if constexpr (LAZY) {
+      hy0 = gram_mfma_u16<true, true>(a, A, lane, wave, sm.stage + wave * kStageWave, &pvl);
+    } else {
+      hy0 = gram_mfma_u16<true>(a, A, lane, wave, sm.stage + wave * kStageWave);
       gj_invert<G>(A, u, line, gbase);
+    }
   } else if constexpr (G == 64 && HALF == 0) {
     hy0 = gram_mfma_u64<true>(a, A, lane, wave, reinterpret_cast<float*>(line),
                               reinterpret_cast<float*>(sm.stage + wave * kStageWave));
