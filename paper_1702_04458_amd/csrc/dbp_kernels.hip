@@ -33,6 +33,10 @@ __device__ __forceinline__ c32 ld_or_zero(const c32* p, bool ok) {
   return ok ? v : c32{0.f, 0.f};
 }
 
+// Fourth word of a raw buffer descriptor on gfx9-family GPUs (32-bit data
+// format, no swizzle, stride 0: the range check is on bytes).
+constexpr int kBufferWord3 = 0x00020000;
+
 // Prefetch depth of the matrix-core Gram prologues (row pairs for U = 32, row
 // quadruples for U = 16): the loads of the next chunk are in flight while the
 // current chunk's MFMAs run.  Build-time tuning knobs.
@@ -376,16 +380,26 @@ __device__ __forceinline__ c32 gram_mfma_u32(const UlArgs& a, c32 (&A)[32], int 
   // the MFMAs of the current ones run.
   constexpr int CH = DBP_PREFETCH_U32;
   c32 hv[2][CH], yv[2][CH], hn[2][CH], yn[2][CH];
+  // Buffer loads over each problem's S rows of H_c and S entries of y_c (no
+  // bytes for an inactive problem): the hardware range check returns zero
+  // past the end, which pads the last row pair and the inactive problems
+  // without a select, and the per-problem bases stay in scalar registers.
+  // The whole offset is in the vector operand (the scalar offset is outside
+  // the range check).
+  __amdgpu_buffer_rsrc_t hrs[2], yrs[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    hrs[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<c32*>(Hp[p]), 0, act[p] ? a.S * 256 : 0, kBufferWord3);
+    yrs[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<c32*>(yp[p]), 0, act[p] ? a.S * 8 : 0, kBufferWord3);
+  }
   auto fetch = [&](int s0, c32 (&hd)[2][CH], c32 (&yd)[2][CH]) {
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
-      const int s = s0 + 2 * q + h;
+      const int s = s0 + 2 * q + h;   // row s, column col: byte 256 s + 8 col
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        const bool ok = act[p] && s < a.S;
-        const int sc = min(s, a.S - 1);
-        hd[p][q] = ld_or_zero(Hp[p] + (size_t)sc * 32 + col, ok);
-        yd[p][q] = ld_or_zero(yp[p] + sc, ok);
+        hd[p][q] = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(hrs[p], s * 256 + col * 8, 0, 0));
+        yd[p][q] = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(yrs[p], s * 8, 0, 0));
       }
     }
   };
@@ -982,16 +996,21 @@ __device__ __forceinline__ c32 gram_mfma_u16(const UlArgs& a, c32 (&A)[16], int 
   }
   constexpr int CH = DBP_PREFETCH_U16;   // row quadruples per prefetch chunk
   c32 hv[4][CH], yv[4][CH], hn[4][CH], yn[4][CH];
+  // Buffer loads over each problem's S rows (as in gram_mfma_u32).
+  __amdgpu_buffer_rsrc_t hrs[4], yrs[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    hrs[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<c32*>(Hp[p]), 0, act[p] ? a.S * 128 : 0, kBufferWord3);
+    yrs[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<c32*>(yp[p]), 0, act[p] ? a.S * 8 : 0, kBufferWord3);
+  }
   auto fetch = [&](int s0, c32 (&hd)[4][CH], c32 (&yd)[4][CH]) {
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
-      const int s = s0 + 4 * j + q;
+      const int s = s0 + 4 * j + q;   // row s, column col: byte 128 s + 8 col
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const bool ok = act[p] && s < a.S;
-        const int sc = min(s, a.S - 1);
-        hd[p][j] = ld_or_zero(Hp[p] + (size_t)sc * 16 + col, ok);
-        yd[p][j] = ld_or_zero(yp[p] + sc, ok);
+        hd[p][j] = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(hrs[p], s * 128 + col * 8, 0, 0));
+        yd[p][j] = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(yrs[p], s * 8, 0, 0));
       }
     }
   };
