@@ -593,6 +593,13 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
     im[p] = f32x16{};
     hyp[p] = cz();
   }
+  // buffer loads over each problem's S rows (as in gram_mfma_u32)
+  __amdgpu_buffer_rsrc_t hrs[2], yrs[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    hrs[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<c32*>(Hp[p]), 0, act[p] ? a.S * 256 : 0, kBufferWord3);
+    yrs[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<c32*>(yp[p]), 0, act[p] ? a.S * 8 : 0, kBufferWord3);
+  }
   // pass 1: largest |Re|, |Im| of each problem -> scale exponent (and
   // ||H_c||_F^2 = tr(G_c))
 #pragma unroll
@@ -602,7 +609,7 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int s = s0 + 8 * h + t;
-        const c32 v = ld_or_zero(Hp[p] + (size_t)min(s, a.S - 1) * 32 + col, act[p] && s < a.S);
+        const c32 v = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(hrs[p], s * 256 + col * 8, 0, 0));
         m = fmaxf(m, fmaxf(fabsf(v.re), fabsf(v.im)));
         ss = fmaf(v.re, v.re, fmaf(v.im, v.im, ss));
       }
@@ -621,10 +628,8 @@ __device__ __forceinline__ void gram_split_u32(const UlArgs& a, f32x16 (&re)[2],
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int s = s0 + 8 * h + t;
-        const bool ok = act[p] && s < a.S;
-        const int sc = min(s, a.S - 1);
-        v[t] = ld_or_zero(Hp[p] + (size_t)sc * 32 + col, ok);
-        const c32 yv = ld_or_zero(yp[p] + sc, ok);
+        v[t] = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(hrs[p], s * 256 + col * 8, 0, 0));
+        const c32 yv = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(yrs[p], s * 8, 0, 0));
         cmacc(hyp[p], v[t], yv);
       }
       V rh, rl, ih, il;
@@ -1327,13 +1332,14 @@ __device__ __forceinline__ c32 gram_mfma_u64(const UlArgs& a, c32 (&A)[64], int 
       im[I][J] = f32x16{};
     }
   c32 x0 = cz(), x1 = cz(), yv = cz();
+  // buffer loads over the problem's S rows (as in gram_mfma_u32)
+  const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(const_cast<c32*>(Hk), 0, act ? a.S * 512 : 0, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t yrs = __builtin_amdgcn_make_buffer_rsrc(const_cast<c32*>(yk), 0, act ? a.S * 8 : 0, kBufferWord3);
   auto fetch = [&](int s0, c32& o0, c32& o1, c32& oy) {
-    const int s = s0 + h;
-    const bool ok = act && s < a.S;
-    const int sc = min(s, a.S - 1);
-    o0 = ld_or_zero(Hk + (size_t)sc * 64 + col, ok);
-    o1 = ld_or_zero(Hk + (size_t)sc * 64 + 32 + col, ok);
-    oy = ld_or_zero(yk + sc, ok);
+    const int s = s0 + h;   // row s, columns col and 32 + col: bytes 512 s + 8 col (+ 256)
+    o0 = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(hrs, s * 512 + col * 8, 0, 0));
+    o1 = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(hrs, s * 512 + 256 + col * 8, 0, 0));
+    oy = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(yrs, s * 8, 0, 0));
   };
   fetch(0, x0, x1, yv);
   for (int s0 = 0; s0 < a.S; s0 += 2) {
@@ -1476,16 +1482,17 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
       re[I][J] = f32x16{};
       im[I][J] = f32x16{};
     }
+  // buffer loads over the problem's S rows (as in gram_mfma_u32)
+  const __amdgpu_buffer_rsrc_t hrs = __builtin_amdgcn_make_buffer_rsrc(const_cast<c32*>(Hk), 0, act ? a.S * 512 : 0, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t yrs = __builtin_amdgcn_make_buffer_rsrc(const_cast<c32*>(yk), 0, act ? a.S * 8 : 0, kBufferWord3);
   // pass 1: scale exponent from the largest |Re|, |Im| (and ||H_c||_F^2 = tr(G_c))
   float mx = 0.f, ss = 0.f;
   for (int s0 = 0; s0 < a.S; s0 += 16) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int s = s0 + 8 * h + t;
-      const bool ok = act && s < a.S;
-      const int sc = min(s, a.S - 1);
-      const c32 v0 = ld_or_zero(Hk + (size_t)sc * 64 + col, ok);
-      const c32 v1 = ld_or_zero(Hk + (size_t)sc * 64 + 32 + col, ok);
+      const c32 v0 = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(hrs, s * 512 + col * 8, 0, 0));
+      const c32 v1 = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(hrs, s * 512 + 256 + col * 8, 0, 0));
       mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v0.re), fabsf(v0.im)), fmaxf(fabsf(v1.re), fabsf(v1.im))));
       ss = fmaf(v0.re, v0.re, fmaf(v0.im, v0.im, fmaf(v1.re, v1.re, fmaf(v1.im, v1.im, ss))));
     }
@@ -1502,12 +1509,10 @@ __device__ __forceinline__ c32 gram_inv_mixed_u64(const UlArgs& a, c32 (&A)[64],
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int s = s0 + 8 * h + t;
-      const bool ok = act && s < a.S;
-      const int sc = min(s, a.S - 1);
-      const c32 yv = ld_or_zero(yk + sc, ok);
+      const c32 yv = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(yrs, s * 8, 0, 0));
 #pragma unroll
       for (int I = 0; I < 2; ++I) {
-        const c32 v = ld_or_zero(Hk + (size_t)sc * 64 + 32 * I + col, ok);
+        const c32 v = __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(hrs, s * 512 + 256 * I + col * 8, 0, 0));
         cmacc(I ? hy1 : hy0, v, yv);
         const float xr = ldexpf(v.re, ex), xi = ldexpf(v.im, ex);
         const HT hr = (HT)xr, hi = (HT)xi;
