@@ -1763,10 +1763,13 @@ __device__ __forceinline__ void admm_ul_body(const UlArgs& a) {
       const int lq = wave * P + pp;
       const int kq = a.blk * a.sc_per_block + lq / a.Cp, cq = lq % a.Cp;
       tv[pp] = kq < a.n_sc && cq < a.C;
-      const float4* src = reinterpret_cast<const float4*>(a.fac + (tv[pp] ? ((size_t)kq * a.C + cq) * NT : 0));
+      // a buffer load over the problem's NT entries (none when inactive):
+      // the range check zeroes the slots past the triangle without selects
+      const __amdgpu_buffer_rsrc_t frs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<c32*>(a.fac + (tv[pp] ? ((size_t)kq * a.C + cq) * NT : 0)), 0, tv[pp] ? NT * 8 : 0, kBufferWord3);
 #pragma unroll
       for (int i = 0; i < NQ; ++i)
-        tq[pp][i] = (tv[pp] && i * 64 + lane < NT / 2) ? src[i * 64 + lane] : float4{0.f, 0.f, 0.f, 0.f};
+        tq[pp][i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(frs, (i * 64 + lane) * 16, 0, 0));
     }
     if constexpr (STAGE == 3)
       hy0 = cluster_hy_direct<G, true>(a, k, c, 0, u, active);

@@ -30,7 +30,7 @@ struct UlArgs {
   float invC;
   float box_r;
   float kappa;
-  c32* fac;           // [n_sc][C][U][U] resident factors B_c^{-1} (column v of lane u at v*U + u), or null
+  c32* fac;           // [n_sc][C][U(U+1)/2] resident factors B_c^{-1}: upper triangle, entry (i, v), i <= v, at v(v+1)/2 + i; or null
   const uint32_t* H16;  // [n_sc][B][U] packed FP16 channel (real part in the low half), or null
   const float* hscale;  // [n_sc][C] power-of-two scale of each (subcarrier, cluster) tile of H16
   int32_t* flags;     // [n_sc] per-subcarrier status bits written by the detection kernels, or null
