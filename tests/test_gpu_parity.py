@@ -217,7 +217,12 @@ def test_cg_zf():
     check_hard(s, h, ref, 16, st)
 
 
-@pytest.mark.parametrize("B,U,C", [(64, 16, 4), (128, 32, 4), (512, 64, 8), (128, 8, 16), (96, 8, 3)])
+# (54, 16, 3), (99, 32, 3), (195, 64, 3): S = 18, 33, 65 leave a partial last
+# row group in the matrix-core Gram prologues, and C = 3 of 4 cluster slots
+# leaves an inactive problem in the waves (both read as zero by the range
+# check of the buffer loads).
+@pytest.mark.parametrize("B,U,C", [(64, 16, 4), (128, 32, 4), (512, 64, 8), (128, 8, 16), (96, 8, 3),
+                                   (54, 16, 3), (99, 32, 3), (195, 64, 3)])
 @pytest.mark.parametrize("algo", ["admm", "cg"])
 def test_shapes(B, U, C, algo):
     say(f"[gpu] shape B={B} U={U} C={C} {algo}")
@@ -428,6 +433,24 @@ def test_mixed_headline_shape(prec, C, factor):
     say(f"    rel_err={err:.2e}")
     assert err <= mixed_bar(prec, factor)
     check_hard(s, h, ref, 64, st, mixed_guard(prec, factor, s.shape[-1]))
+
+
+# A partial last row group (S = 33, 65) and an inactive cluster slot (C = 3 of
+# 4) in the split-precision Gram prologues (buffer loads read both as zero).
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("B,U", [(99, 32), (195, 64)])
+def test_mixed_ragged_shapes(prec, B, U):
+    say(f"[gpu] mixed ragged prec={prec} B={B} U={U} C=3")
+    fr = inputs.uplink_frame(inputs.frame_seed(6, 50 + U, 25), 13, B, U, 64, 25.0)
+    H, y = to_dev(fr.H), to_dev(fr.y)
+    s, h, st = api.detect(H, y, fr.N0, 3, 1.0, 5, qam=64, prec=prec, factor="auto", status=True)
+    torch.cuda.synchronize()
+    s, h, st = s.cpu().numpy(), h.cpu().numpy(), st.cpu().numpy()
+    ref = O.admm_ul_frame(fr.H, fr.y, 3, 1.0, 5, n0_f32(fr.N0))
+    err = rel_err(s, ref)
+    say(f"    rel_err={err:.2e}")
+    assert err <= mixed_bar(prec, "auto")
+    check_hard(s, h, ref, 64, st, mixed_guard(prec, "auto", U))
 
 
 def mixed_guard(prec, factor, U):
